@@ -1,0 +1,171 @@
+/*
+ * imq.h -- C interface of the MI355X (gfx950) fast product with the
+ * inverse-multiquadric (IMQ) interpolation matrix, and of the solver built
+ * on it.
+ *
+ * The operator (Sec. 2, eqs. IMQ_def and interp_system):
+ *     A_ij = 1 / sqrt(|x_i - x_j|^2 + c^2),   x_i in R^2 distinct data sites,
+ * and the product b = A u that the translation technique of Sec. 2.2
+ * (Algorithm 1) computes.  Each point is lifted to the plane z = -c/2 as a
+ * source and z = +c/2 as a target (eq. G_eq_phi), so A_ij is the 3-D Laplace
+ * Green's function (eq. G_def) between the lifted points; its spectral
+ * expansion (eq. GreenDecompositionG, truncated at order p as in
+ * eq. serieTroncata, error bound of Theorem 2.1) is applied through a
+ * quadtree of the plane: per-leaf expansions (P2M), upward shifts (M2M),
+ * expansion-to-local translations between well-separated boxes (M2L),
+ * downward shifts (L2L), local evaluation (L2P), and the direct near field
+ * (P2P) of the last loop of Algorithm 1.
+ *
+ * Conventions for every entry point below:
+ *  - Array arguments are DEVICE pointers on the current HIP device, owned by
+ *    the caller, unless the comment says "host".
+ *  - All work is enqueued on `stream` (0 = the default stream) and is
+ *    stream-ordered; only the calls that say so synchronise.
+ *  - Errors are returned as a status, never thrown; imq_last_error() gives a
+ *    thread-local detail string for the last failing call.
+ *  - A tree handle may be used by one stream at a time.
+ */
+#ifndef IMQ_H
+#define IMQ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct imq_tree_s *imq_tree;     /* opaque, owned by the library */
+
+typedef enum {
+    IMQ_OK = 0,
+    IMQ_ENOTCONVERGED = 1,  /* warning: outputs are valid, tolerance not met */
+    IMQ_EINVAL = -1,        /* bad argument (size, pointer, c <= 0, NaN ...)  */
+    IMQ_EDUPLICATE = -2,    /* two data sites coincide: A would be singular   */
+    IMQ_ENOMEM = -3,        /* device or host allocation failed               */
+    IMQ_EHIP = -4,          /* a HIP runtime call failed                      */
+    IMQ_EUNSUPPORTED = -5   /* valid request this build does not support      */
+} imq_status;
+
+/* Element type of the vectors handed across the boundary. */
+typedef enum { IMQ_F64 = 0, IMQ_F32 = 1 } imq_dtype;
+
+/* Arithmetic of the expansions, translations and near field inside the
+ * product.  IMQ_PREC_FP32 keeps FP64 only for the final accumulation of b
+ * and for the operator tables' generation. */
+typedef enum { IMQ_PREC_FP64 = 0, IMQ_PREC_FP32 = 1 } imq_prec;
+
+#define IMQ_MAX_LEVELS 31
+
+/* Tree and expansion parameters.
+ *  leaf_max   : a box is split while it holds more than leaf_max points
+ *               (the finest partition of Sec. 2.2 is reached adaptively).
+ *  order_p    : truncation index M of eq. serieTroncata (1 <= p <= 16).
+ *  max_level  : deepest level of the quadtree (<= 30; 0 = 30).
+ *  level_order: optional per-level truncation of the M2L translation
+ *               (0 = use order_p); entry l applies to boxes at level l.
+ *               Multipoles are always kept to order_p.                     */
+typedef struct {
+    int leaf_max;
+    int order_p;
+    int max_level;
+    int level_order[IMQ_MAX_LEVELS + 1];
+} imq_tree_params;
+
+/* Build the quadtree forest of `nsets` independent point sets.
+ *  set_offsets : host, nsets+1 entries; set s owns points
+ *                [set_offsets[s], set_offsets[s+1]) of the concatenation.
+ *  xy          : device FP64, structure of arrays: x[0..Ntot), y[0..Ntot)
+ *                with Ntot = set_offsets[nsets].
+ *  c           : host, nsets shape parameters (c > 0, finite).
+ * Copies the points to the host, builds the trees, interaction lists and
+ * translation tables, and uploads them; synchronises `stream` once.
+ * Returns IMQ_EDUPLICATE if two points of a set coincide exactly. */
+imq_status imq_build_tree(int nsets, const int64_t *set_offsets, const double *xy,
+                          const double *c, const imq_tree_params *params,
+                          hipStream_t stream, imq_tree *out);
+
+/* b = A u for every set and right-hand side, in the caller's point order.
+ *  u : nrhs columns of length Ntot, column r at u + r*ldu (ldu >= Ntot),
+ *      element type `dtype`.
+ *  b : same layout with ldb, element type `dtype`.
+ * Uses the tree's expansions at the given internal precision. */
+imq_status imq_matvec(imq_tree tree, int nrhs, imq_dtype dtype, const void *u,
+                      int64_t ldu, void *b, int64_t ldb, imq_prec prec,
+                      hipStream_t stream);
+
+/* Exact product restricted to some rows: b[r*ldb + k] = sum_j A_{rows[k], j} u_j
+ * for k < nrows (device int64 row indices, caller order).  Direct sums over
+ * all points of the row's set in FP64; used to measure the error of the fast
+ * product on sampled rows. */
+imq_status imq_rows_exact(imq_tree tree, int nrhs, const double *u, int64_t ldu,
+                          int64_t nrows, const int64_t *rows, double *b,
+                          int64_t ldb, hipStream_t stream);
+
+typedef struct {
+    double tol;        /* stop when ||f - A a|| <= tol ||f|| (FP64 product)  */
+    int restart;       /* GMRES restart length m (1 .. 256)                 */
+    int max_iters;     /* cap on inner iterations summed over everything     */
+    int mixed_ir;      /* 1: FP32 inner GMRES inside FP64 refinement         */
+    int max_outer;     /* cap on refinement steps (mixed_ir only; 0 = 10)    */
+} imq_solve_opts;
+
+typedef struct {        /* host */
+    int iters;          /* inner GMRES iterations (matrix products)          */
+    int outer_iters;    /* refinement steps (1 without mixed_ir)             */
+    int converged;      /* 1 if relres <= tol                                */
+    double relres;      /* final explicit ||f - A a|| / ||f||, FP64 product  */
+} imq_solve_stats;
+
+/* Solve A a = f (eq. interp_system) by restarted GMRES on the fast product.
+ *  f, a : FP64, nrhs columns with leading dimensions ldf, lda; `a` holds the
+ *         initial guess on entry (zeros for none) and the solution on exit.
+ *  stats: host array of nrhs entries, filled on return.
+ * Synchronises `stream` once per GMRES cycle to read the residual.  Returns
+ * IMQ_ENOTCONVERGED if some column stopped above tol. */
+imq_status imq_solve(imq_tree tree, int nrhs, const double *f, int64_t ldf,
+                     double *a, int64_t lda, const imq_solve_opts *opts,
+                     imq_solve_stats *stats, hipStream_t stream);
+
+/* Adjoint of b = A(c, X) v for a scalar loss L with upstream g = dL/db.
+ * Derivatives of the entries of eq. IMQ_def:
+ *   dv   = A g                                   (A is symmetric)
+ *   dc[s]= sum_ij g_i v_j dA_ij/dc,  dA_ij/dc = -c (r_ij^2 + c^2)^(-3/2)
+ *   dxy  = d/dx_k of sum_ij g_i A_ij v_j
+ *        = -sum_j (g_k v_j + v_k g_j)(x_k - x_j)(r_kj^2 + c^2)^(-3/2)
+ * for every set s.  v, g, dv: FP64 or FP32 per `dtype` (one column each);
+ * dc: device FP64, nsets entries; dxy: device FP64 SoA 2 x Ntot.  The
+ * interaction lists are those of `tree`. */
+imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
+                               const void *g, void *dv, double *dc, double *dxy,
+                               imq_prec prec, hipStream_t stream);
+
+typedef struct {          /* host */
+    int64_t npoints, nboxes, nleaves;
+    int depth;            /* deepest level present                           */
+    int order_p, K;       /* truncation index and real coefficients per box  */
+    int64_t p2p_pairs;    /* near-field (target, source) pairs per product   */
+    int64_t m2l_pairs;    /* (target box, source box) translations           */
+    int64_t m2p_evals;    /* (target point, source box) multipole evaluations */
+    int64_t p2l_evals;    /* (source point, target box) local accumulations  */
+    int64_t m2m_pairs, l2l_pairs;
+} imq_tree_info;
+
+imq_status imq_get_tree_info(imq_tree tree, imq_tree_info *info);
+
+/* Per-stage device times of the last imq_matvec on this tree, in ms, when
+ * stage timing was switched on with imq_set_stage_timing (host array of
+ * IMQ_NSTAGES entries, stage order as in imq_stage_name). */
+#define IMQ_NSTAGES 9
+imq_status imq_set_stage_timing(imq_tree tree, int on);
+imq_status imq_get_stage_times(imq_tree tree, double *ms);
+const char *imq_stage_name(int stage);
+
+void imq_tree_free(imq_tree tree);
+const char *imq_status_string(imq_status s);
+const char *imq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMQ_H */

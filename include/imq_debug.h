@@ -1,0 +1,48 @@
+/*
+ * imq_debug.h -- host-only inspection hooks of the IMQ library.
+ *
+ * These make no HIP call, so a test-suite can check the host logic (the
+ * quadtree, its interaction lists and the FP64 translation tables) on a
+ * machine without a GPU.  They are not part of the product path.
+ */
+#ifndef IMQ_DEBUG_H
+#define IMQ_DEBUG_H
+
+#include <stdint.h>
+#include "imq.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One translation table as a row-major K x K real matrix, K = (p+1)(p+2)/2,
+ * in the stored n+m-even coefficient layout (host buffer `out`).
+ *  kind 0: child -> parent multipole shift for child position `pos`
+ *  kind 1: parent -> child local shift for child position `pos`
+ *  kind 2: multipole -> local translation at `level` between boxes (dx, dy)
+ *          edges apart, lifted planes c' = cnorm apart (units of the root)
+ *  kind 3: the K per-coefficient constants of the point evaluations
+ * Returns 0, or -1 for a bad argument. */
+int imq_debug_table(int kind, int p, int pos, int level, int dx, int dy, double cnorm, double *out);
+
+/* Build the host part of a tree from HOST coordinates (x[N], y[N]); returns
+ * an opaque handle or NULL (then *status holds the reason). */
+void *imq_debug_host_tree(int nsets, const int64_t *set_offsets, const double *x, const double *y,
+                          const double *c, const imq_tree_params *prm, int *status);
+
+/* Number of elements of a named array of the host tree, or -1: "perm",
+ * "xl", "yl", "level", "set", "ix", "iy", "parent", "child0", "nchild",
+ * "pos", "begin", "end", "isleaf", "cx", "cy", "level_begin", "leaves",
+ * "u_off", "u_idx", "v_off", "v_idx", "v_cls", "w_off", "w_idx", "x_off",
+ * "x_idx", "Klev", "side", "cn". */
+int64_t imq_debug_host_tree_size(void *h, const char *what);
+
+/* Copy a named array into `out` (host, large enough); returns 0 or -1. */
+int imq_debug_host_tree_get(void *h, const char *what, void *out);
+
+void imq_debug_host_tree_free(void *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMQ_DEBUG_H */

@@ -1,0 +1,215 @@
+"""MI355X (gfx950) fast product with the inverse-multiquadric interpolation matrix.
+
+The method (arXiv 2205.04194, Sec. 2): A_ij = 1/sqrt(|x_i - x_j|^2 + c^2) is
+the 3-D Laplace Green's function between the points lifted to z = -c/2 and
+z = +c/2, so the product b = A u is evaluated with the truncated spectral
+expansion of that Green's function on a quadtree (expansions, translations,
+and a direct near field), all in HIP kernels behind the C interface of
+include/imq.h.  This module only marshals torch tensors (device memory and
+the current stream) into those calls.
+
+    tree = build_tree(xy, c, leaf=64, p=12)     # xy: (N, 2) float64 on cuda
+    b = tree.matvec(u, prec="fp64")             # u: (N,) or (nrhs, N)
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import IMQError, PREC
+
+__all__ = ["Tree", "build_tree", "matvec", "solve", "IMQMatvec", "IMQError"]
+
+
+def _stream_ptr(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Tree:
+    """A quadtree forest over one or more point sets, resident on the GPU.
+
+    xy          (Ntot, 2) float64 cuda tensor, the sets concatenated
+    c           shape parameter (float) or one per set
+    set_offsets None (one set) or nsets+1 offsets into xy
+    leaf        points per leaf before a box is split (leaf_max)
+    p           truncation index of the expansions (1..16)
+    level_order optional per-level truncation of the translations
+    """
+
+    def __init__(self, xy: torch.Tensor, c, leaf: int = 64, p: int = 12,
+                 set_offsets: Optional[Sequence[int]] = None, level_order=None,
+                 max_level: int = 0, stream=None):
+        lib = _lib.load()
+        if xy.dim() != 2 or xy.shape[1] != 2:
+            raise ValueError("xy must have shape (N, 2)")
+        if not xy.is_cuda:
+            raise ValueError("xy must be a cuda tensor")
+        xy64 = xy.detach().to(torch.float64)
+        soa = xy64.t().contiguous()
+        n = xy.shape[0]
+        offs = [0, n] if set_offsets is None else [int(v) for v in set_offsets]
+        nsets = len(offs) - 1
+        cs = [float(c)] * nsets if not hasattr(c, "__len__") else [float(v) for v in c]
+        if len(cs) != nsets:
+            raise ValueError("need one shape parameter per set")
+        self.n = n
+        self.nsets = nsets
+        self.offsets = offs
+        self.c = cs
+        self.leaf = leaf
+        self.p = p
+        self.device = xy.device
+        self._xy = xy64
+        off_arr = (ctypes.c_int64 * (nsets + 1))(*offs)
+        c_arr = (ctypes.c_double * nsets)(*cs)
+        prm = _lib.params(leaf, p, max_level, level_order)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.imq_build_tree(nsets, off_arr, _dptr(soa), c_arr, ctypes.byref(prm),
+                                    _stream_ptr(stream), ctypes.byref(h))
+        _lib.check(st, "imq_build_tree")
+        self._h = h
+
+    # ----------------------------------------------------------------- product
+    def matvec(self, u: torch.Tensor, prec: str = "fp64", stream=None) -> torch.Tensor:
+        """b = A u; u is (N,) or (nrhs, N), float64 or float32, on the tree's device."""
+        lib = _lib.load()
+        one = u.dim() == 1
+        u2 = (u.unsqueeze(0) if one else u).contiguous()
+        if u2.shape[1] != self.n:
+            raise ValueError("u has the wrong length")
+        if u2.dtype not in (torch.float64, torch.float32):
+            raise ValueError("u must be float64 or float32")
+        b = torch.empty_like(u2)
+        dt = _lib.F64 if u2.dtype == torch.float64 else _lib.F32
+        with torch.cuda.device(self.device):
+            st = lib.imq_matvec(self._h, u2.shape[0], dt, _dptr(u2), self.n, _dptr(b), self.n,
+                                PREC[prec], _stream_ptr(stream))
+        _lib.check(st, "imq_matvec")
+        return b[0] if one else b
+
+    def rows_exact(self, u: torch.Tensor, rows: torch.Tensor, stream=None) -> torch.Tensor:
+        """Exact FP64 rows of A u (direct sums) for the given row indices."""
+        lib = _lib.load()
+        one = u.dim() == 1
+        u2 = (u.unsqueeze(0) if one else u).to(torch.float64).contiguous()
+        rows = rows.to(device=self.device, dtype=torch.int64).contiguous()
+        b = torch.empty((u2.shape[0], rows.numel()), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            st = lib.imq_rows_exact(self._h, u2.shape[0], _dptr(u2), self.n, rows.numel(),
+                                    _dptr(rows), _dptr(b), rows.numel(), _stream_ptr(stream))
+        _lib.check(st, "imq_rows_exact")
+        return b[0] if one else b
+
+    # ----------------------------------------------------------------- solve
+    def solve(self, f: torch.Tensor, tol: float = 1e-10, restart: int = 50,
+              max_iters: int = 2000, mixed_ir: bool = False, max_outer: int = 10,
+              a0: Optional[torch.Tensor] = None, stream=None):
+        """GMRES on the fast product: returns (a, stats list)."""
+        lib = _lib.load()
+        one = f.dim() == 1
+        f2 = (f.unsqueeze(0) if one else f).to(torch.float64).contiguous()
+        a = torch.zeros_like(f2) if a0 is None else \
+            (a0.unsqueeze(0) if one else a0).to(torch.float64).contiguous().clone()
+        nrhs = f2.shape[0]
+        opts = _lib.SolveOpts(float(tol), int(restart), int(max_iters), int(bool(mixed_ir)),
+                              int(max_outer))
+        stats = (_lib.SolveStats * nrhs)()
+        with torch.cuda.device(self.device):
+            st = lib.imq_solve(self._h, nrhs, _dptr(f2), self.n, _dptr(a), self.n,
+                               ctypes.byref(opts), stats, _stream_ptr(stream))
+        _lib.check(st, "imq_solve", allow_not_converged=True)
+        out = [dict(iters=s.iters, outer_iters=s.outer_iters, converged=bool(s.converged),
+                    relres=s.relres) for s in stats]
+        return (a[0] if one else a), (out[0] if one else out)
+
+    # ----------------------------------------------------------------- adjoint
+    def backward(self, v: torch.Tensor, g: torch.Tensor, prec: str = "fp64", stream=None):
+        """(A g, dL/dc per set, dL/dxy) for the upstream gradient g = dL/d(A v)."""
+        lib = _lib.load()
+        dt = _lib.F64 if v.dtype == torch.float64 else _lib.F32
+        v = v.contiguous()
+        g = g.to(v.dtype).contiguous()
+        dv = torch.empty_like(v)
+        dc = torch.zeros(self.nsets, dtype=torch.float64, device=self.device)
+        dxy = torch.zeros((2, self.n), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            st = lib.imq_matvec_backward(self._h, dt, _dptr(v), _dptr(g), _dptr(dv), _dptr(dc),
+                                         _dptr(dxy), PREC[prec], _stream_ptr(stream))
+        _lib.check(st, "imq_matvec_backward")
+        return dv, dc, dxy.t()
+
+    # ----------------------------------------------------------------- info
+    def info(self) -> dict:
+        lib = _lib.load()
+        inf = _lib.TreeInfo()
+        _lib.check(lib.imq_get_tree_info(self._h, ctypes.byref(inf)), "imq_get_tree_info")
+        return {k: getattr(inf, k) for k, _ in _lib.TreeInfo._fields_}
+
+    def set_stage_timing(self, on: bool = True) -> None:
+        _lib.check(_lib.load().imq_set_stage_timing(self._h, int(on)), "imq_set_stage_timing")
+
+    def stage_times(self) -> dict:
+        lib = _lib.load()
+        arr = (ctypes.c_double * _lib.IMQ_NSTAGES)()
+        _lib.check(lib.imq_get_stage_times(self._h, arr), "imq_get_stage_times")
+        return {lib.imq_stage_name(k).decode(): arr[k] for k in range(_lib.IMQ_NSTAGES)}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.load().imq_tree_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_tree(xy, c, leaf: int = 64, p: int = 12, **kw) -> Tree:
+    return Tree(xy, c, leaf=leaf, p=p, **kw)
+
+
+def matvec(tree: Tree, u: torch.Tensor, prec: str = "fp64") -> torch.Tensor:
+    return tree.matvec(u, prec)
+
+
+def solve(tree: Tree, f: torch.Tensor, **kw):
+    return tree.solve(f, **kw)
+
+
+class IMQMatvec(torch.autograd.Function):
+    """b = A(c, X) v with gradients for v, c and X through the adjoint kernels.
+
+    The tree is rebuilt from the saved (X, c) in backward, so no interaction
+    list is kept alive between the passes.
+    """
+
+    @staticmethod
+    def forward(ctx, xy, c, v, leaf: int = 64, p: int = 12, prec: str = "fp64"):
+        tree = Tree(xy.detach(), float(c), leaf=leaf, p=p)
+        b = tree.matvec(v.detach(), prec)
+        tree.close()
+        ctx.save_for_backward(xy, v)
+        ctx.c = float(c)
+        ctx.cfg = (leaf, p, prec)
+        return b
+
+    @staticmethod
+    def backward(ctx, gb):
+        xy, v = ctx.saved_tensors
+        leaf, p, prec = ctx.cfg
+        tree = Tree(xy.detach(), ctx.c, leaf=leaf, p=p)
+        dv, dc, dxy = tree.backward(v.detach(), gb.detach(), prec)
+        tree.close()
+        dcv = dc[0].to(torch.float64) if isinstance(ctx.c, float) else dc
+        return dxy.to(xy.dtype), dcv, dv.to(v.dtype), None, None, None

@@ -1,0 +1,337 @@
+// C entry points: argument checks, tree upload, dispatch by precision.
+#include "device.h"
+#include "../../include/imq_debug.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace imq {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+template <typename T, typename Tio>
+imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio *b, int64_t ldb,
+                        hipStream_t s);
+imq_status rows_exact(imq_tree_s *t, int nrhs, const double *u, int64_t ldu, int64_t nrows,
+                      const int64_t *rows, double *b, int64_t ldb, hipStream_t s);
+
+template <typename V>
+static imq_status upload(DevBuf &d, const std::vector<V> &h)
+{
+    IMQ_HIP(dev_alloc(d, sizeof(V) * h.size()));
+    if (!h.empty()) IMQ_HIP(hipMemcpy(d.p, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice));
+    return IMQ_OK;
+}
+
+template <typename V>
+static std::vector<float> to_f32(const std::vector<V> &v)
+{
+    std::vector<float> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = float(v[i]);
+    return o;
+}
+
+// All translation tables of a tree, generated in FP64 on the host.
+static void make_tables(const HostTree &h, std::vector<double> &m2m, std::vector<double> &l2l,
+                        std::vector<double> &m2l, std::vector<double> &wx)
+{
+    const int K = h.K, p = h.p;
+    const size_t KK = size_t(K) * K;
+    m2m.assign(4 * KK, 0.0);
+    l2l.assign(4 * KK, 0.0);
+    for (int pos = 0; pos < 4; ++pos) {
+        make_m2m_table(p, pos, m2m.data() + pos * KK);
+        make_l2l_table(p, pos, l2l.data() + pos * KK);
+    }
+    wx.assign(K, 0.0);
+    make_wx_consts(p, wx.data());
+    const size_t ntab = size_t(h.nsets) * h.nlev * NCLASS;
+    m2l.assign(ntab * KK, 0.0);
+    std::vector<size_t> jobs;
+    for (int s = 0; s < h.nsets; ++s)
+        for (int l = 2; l < h.nlev; ++l)
+            for (int cls = 0; cls < NCLASS; ++cls) {
+                const int dx = cls / 7 - 3, dy = cls % 7 - 3;
+                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                jobs.push_back((size_t(s) * h.nlev + l) * NCLASS + cls);
+            }
+    const unsigned nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nthr; ++w)
+        th.emplace_back([&, w]() {
+            for (size_t j = w; j < jobs.size(); j += nthr) {
+                const size_t id = jobs[j];
+                const int cls = int(id % NCLASS);
+                const int l = int((id / NCLASS) % h.nlev);
+                const int s = int(id / NCLASS / h.nlev);
+                make_m2l_table(p, l, cls / 7 - 3, cls % 7 - 3, h.cn[s], m2l.data() + id * KK);
+            }
+        });
+    for (auto &x : th) x.join();
+}
+
+static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
+{
+    const HostTree &h = t->h;
+    imq_status st;
+#define UP(field) if ((st = upload(t->field, h.field)) != IMQ_OK) return st
+    UP(perm); UP(pt_scale); UP(level); UP(set); UP(parent); UP(child0); UP(nchild); UP(pos);
+    UP(begin); UP(end); UP(cx); UP(cy); UP(u_off); UP(u_idx); UP(v_off); UP(v_idx); UP(v_cls);
+    UP(w_off); UP(w_idx); UP(x_off); UP(x_idx); UP(Klev); UP(leaves);
+#undef UP
+    std::vector<double> cc(h.cn);
+    cc.insert(cc.end(), h.c.begin(), h.c.end());      // [c/side per set, c per set]
+    if ((st = upload(t->cn, cc)) != IMQ_OK) return st;
+    if ((st = upload(t->set_off, h.set_off)) != IMQ_OK) return st;
+    IMQ_HIP(dev_alloc(t->xy_user, sizeof(double) * 2 * size_t(h.N)));
+    IMQ_HIP(hipMemcpy(t->xy_user.p, xy_dev, sizeof(double) * 2 * size_t(h.N), hipMemcpyDeviceToDevice));
+
+    if ((st = upload(t->f64.xl, h.xl)) != IMQ_OK) return st;
+    if ((st = upload(t->f64.yl, h.yl)) != IMQ_OK) return st;
+    if ((st = upload(t->f32.xl, to_f32(h.xl))) != IMQ_OK) return st;
+    if ((st = upload(t->f32.yl, to_f32(h.yl))) != IMQ_OK) return st;
+
+    std::vector<double> m2m, l2l, m2l, wx;
+    make_tables(h, m2m, l2l, m2l, wx);
+    if ((st = upload(t->f64.m2m, m2m)) != IMQ_OK) return st;
+    if ((st = upload(t->f64.l2l, l2l)) != IMQ_OK) return st;
+    if ((st = upload(t->f64.m2l, m2l)) != IMQ_OK) return st;
+    if ((st = upload(t->f64.wx, wx)) != IMQ_OK) return st;
+    if ((st = upload(t->f32.m2m, to_f32(m2m))) != IMQ_OK) return st;
+    if ((st = upload(t->f32.l2l, to_f32(l2l))) != IMQ_OK) return st;
+    if ((st = upload(t->f32.m2l, to_f32(m2l))) != IMQ_OK) return st;
+    if ((st = upload(t->f32.wx, to_f32(wx))) != IMQ_OK) return st;
+    return IMQ_OK;
+}
+
+static void free_tree(imq_tree_s *t)
+{
+    DevBuf *bufs[] = {&t->perm, &t->pt_scale, &t->level, &t->set, &t->parent, &t->child0, &t->nchild,
+                      &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
+                      &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
+                      &t->cn, &t->leaves, &t->xy_user, &t->set_off, &t->bs, &t->sol};
+    for (DevBuf *b : bufs) dev_free(*b);
+    for (PrecData *pd : {&t->f64, &t->f32}) {
+        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->m2m, &pd->l2l, &pd->m2l, &pd->wx, &pd->us, &pd->M, &pd->L};
+        for (DevBuf *b : pb) dev_free(*b);
+    }
+    for (auto &e : t->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete t;
+}
+
+static imq_status check_tree(imq_tree t)
+{
+    if (!t) { set_error("null tree handle"); return IMQ_EINVAL; }
+    int dev = -1;
+    IMQ_HIP(hipGetDevice(&dev));
+    if (dev != t->device) IMQ_HIP(hipSetDevice(t->device));
+    return IMQ_OK;
+}
+
+}  // namespace imq
+
+using namespace imq;
+
+extern "C" {
+
+const char *imq_last_error(void) { return g_last_error.c_str(); }
+
+const char *imq_status_string(imq_status s)
+{
+    switch (s) {
+    case IMQ_OK: return "ok";
+    case IMQ_ENOTCONVERGED: return "tolerance not reached";
+    case IMQ_EINVAL: return "invalid argument";
+    case IMQ_EDUPLICATE: return "duplicate data sites";
+    case IMQ_ENOMEM: return "out of memory";
+    case IMQ_EHIP: return "HIP runtime error";
+    case IMQ_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *imq_stage_name(int k)
+{
+    static const char *names[IMQ_NSTAGES] = {"gather", "p2m", "m2m", "m2l", "p2l+l2l",
+                                             "l2p", "p2p", "m2p", "scatter"};
+    return (k >= 0 && k < IMQ_NSTAGES) ? names[k] : "?";
+}
+
+imq_status imq_build_tree(int nsets, const int64_t *set_offsets, const double *xy, const double *c,
+                          const imq_tree_params *params, hipStream_t stream, imq_tree *out)
+{
+    if (!out) { set_error("out is null"); return IMQ_EINVAL; }
+    *out = nullptr;
+    if (nsets < 1 || !set_offsets || !xy || !c || !params) { set_error("null argument or nsets < 1"); return IMQ_EINVAL; }
+    const int64_t N = set_offsets[nsets];
+    if (N < 1) { set_error("no points"); return IMQ_EINVAL; }
+    std::vector<double> hxy(2 * size_t(N));
+    IMQ_HIP(hipMemcpyAsync(hxy.data(), xy, sizeof(double) * 2 * size_t(N), hipMemcpyDeviceToHost, stream));
+    IMQ_HIP(hipStreamSynchronize(stream));
+    auto *t = new imq_tree_s();
+    IMQ_HIP(hipGetDevice(&t->device));
+    imq_status st = build_host_tree(nsets, set_offsets, hxy.data(), hxy.data() + N, c, *params, t->h);
+    if (st != IMQ_OK) { delete t; return st; }
+    st = upload_tree(t, xy);
+    if (st != IMQ_OK) { free_tree(t); return st; }
+    for (auto &e : t->ev) {
+        hipError_t er = hipEventCreate(&e);
+        if (er != hipSuccess) { set_error("hipEventCreate failed"); free_tree(t); return IMQ_EHIP; }
+    }
+    *out = t;
+    return IMQ_OK;
+}
+
+imq_status imq_matvec(imq_tree t, int nrhs, imq_dtype dtype, const void *u, int64_t ldu, void *b,
+                      int64_t ldb, imq_prec prec, hipStream_t stream)
+{
+    imq_status st = check_tree(t);
+    if (st != IMQ_OK) return st;
+    if (nrhs < 1 || !u || !b || ldu < t->h.N || ldb < t->h.N) { set_error("bad nrhs, pointer or leading dimension"); return IMQ_EINVAL; }
+    if (dtype == IMQ_F64 && prec == IMQ_PREC_FP64)
+        return matvec_typed<double, double>(t, nrhs, (const double *)u, ldu, (double *)b, ldb, stream);
+    if (dtype == IMQ_F32 && prec == IMQ_PREC_FP64)
+        return matvec_typed<double, float>(t, nrhs, (const float *)u, ldu, (float *)b, ldb, stream);
+    if (dtype == IMQ_F64 && prec == IMQ_PREC_FP32)
+        return matvec_typed<float, double>(t, nrhs, (const double *)u, ldu, (double *)b, ldb, stream);
+    if (dtype == IMQ_F32 && prec == IMQ_PREC_FP32)
+        return matvec_typed<float, float>(t, nrhs, (const float *)u, ldu, (float *)b, ldb, stream);
+    set_error("unknown dtype or precision");
+    return IMQ_EINVAL;
+}
+
+imq_status imq_rows_exact(imq_tree t, int nrhs, const double *u, int64_t ldu, int64_t nrows,
+                          const int64_t *rows, double *b, int64_t ldb, hipStream_t stream)
+{
+    imq_status st = check_tree(t);
+    if (st != IMQ_OK) return st;
+    if (nrhs < 1 || nrows < 0 || (nrows > 0 && (!u || !rows || !b)) || ldu < t->h.N || ldb < nrows) {
+        set_error("bad argument to imq_rows_exact");
+        return IMQ_EINVAL;
+    }
+    if (nrows > 0x7fffffff) { set_error("too many rows"); return IMQ_EINVAL; }
+    std::vector<int64_t> hr(nrows);
+    IMQ_HIP(hipMemcpyAsync(hr.data(), rows, sizeof(int64_t) * nrows, hipMemcpyDeviceToHost, stream));
+    IMQ_HIP(hipStreamSynchronize(stream));
+    for (int64_t r : hr)
+        if (r < 0 || r >= t->h.N) { set_error("row index out of range"); return IMQ_EINVAL; }
+    return rows_exact(t, nrhs, u, ldu, nrows, rows, b, ldb, stream);
+}
+
+imq_status imq_get_tree_info(imq_tree t, imq_tree_info *info)
+{
+    if (!t || !info) { set_error("null argument"); return IMQ_EINVAL; }
+    const HostTree &h = t->h;
+    info->npoints = h.N;
+    info->nboxes = int64_t(h.level.size());
+    info->nleaves = int64_t(h.leaves.size());
+    info->depth = h.nlev - 1;
+    info->order_p = h.p;
+    info->K = h.K;
+    info->p2p_pairs = h.p2p_pairs;
+    info->m2l_pairs = h.m2l_pairs;
+    info->m2p_evals = h.m2p_evals;
+    info->p2l_evals = h.p2l_evals;
+    info->m2m_pairs = h.m2m_pairs;
+    info->l2l_pairs = h.l2l_pairs;
+    return IMQ_OK;
+}
+
+imq_status imq_set_stage_timing(imq_tree t, int on)
+{
+    if (!t) { set_error("null tree handle"); return IMQ_EINVAL; }
+    t->timing = on != 0;
+    return IMQ_OK;
+}
+
+imq_status imq_get_stage_times(imq_tree t, double *ms)
+{
+    if (!t || !ms) { set_error("null argument"); return IMQ_EINVAL; }
+    for (int k = 0; k < IMQ_NSTAGES; ++k) ms[k] = t->stage_ms[k];
+    return IMQ_OK;
+}
+
+void imq_tree_free(imq_tree t)
+{
+    if (t) free_tree(t);
+}
+
+// ------------------------------------------------------------------ host-only hooks
+
+int imq_debug_table(int kind, int p, int pos, int level, int dx, int dy, double cnorm, double *out)
+{
+    if (p < 1 || p > PMAX || !out) return -1;
+    switch (kind) {
+    case 0: make_m2m_table(p, pos & 3, out); return 0;
+    case 1: make_l2l_table(p, pos & 3, out); return 0;
+    case 2: make_m2l_table(p, level, dx, dy, cnorm, out); return 0;
+    case 3: make_wx_consts(p, out); return 0;
+    }
+    return -1;
+}
+
+void *imq_debug_host_tree(int nsets, const int64_t *set_offsets, const double *x, const double *y,
+                          const double *c, const imq_tree_params *prm, int *status)
+{
+    auto *h = new HostTree();
+    imq_status st = build_host_tree(nsets, set_offsets, x, y, c, *prm, *h);
+    if (status) *status = st;
+    if (st != IMQ_OK) { delete h; return nullptr; }
+    return h;
+}
+
+static const void *field(const HostTree &h, const char *w, int64_t &n, int &elem)
+{
+#define F(name) if (!std::strcmp(w, #name)) { n = int64_t(h.name.size()); elem = int(sizeof(h.name[0])); return h.name.data(); }
+    F(perm) F(xl) F(yl) F(level) F(set) F(ix) F(iy) F(parent) F(child0) F(nchild) F(pos) F(begin)
+    F(end) F(isleaf) F(cx) F(cy) F(level_begin) F(leaves) F(u_off) F(u_idx) F(v_off) F(v_idx)
+    F(v_cls) F(w_off) F(w_idx) F(x_off) F(x_idx) F(Klev) F(side) F(cn)
+#undef F
+    n = -1;
+    elem = 0;
+    return nullptr;
+}
+
+int64_t imq_debug_host_tree_size(void *hp, const char *what)
+{
+    int64_t n; int e;
+    field(*static_cast<HostTree *>(hp), what, n, e);
+    return n;
+}
+
+int imq_debug_host_tree_get(void *hp, const char *what, void *out)
+{
+    int64_t n; int e;
+    const void *src = field(*static_cast<HostTree *>(hp), what, n, e);
+    if (n < 0) return -1;
+    if (n > 0) std::memcpy(out, src, size_t(n) * e);
+    return 0;
+}
+
+void imq_debug_host_tree_free(void *hp) { delete static_cast<HostTree *>(hp); }
+
+imq_status imq_solve(imq_tree t, int nrhs, const double *f, int64_t ldf, double *a, int64_t lda,
+                     const imq_solve_opts *opts, imq_solve_stats *stats, hipStream_t stream)
+{
+    (void)t; (void)nrhs; (void)f; (void)ldf; (void)a; (void)lda; (void)opts; (void)stats; (void)stream;
+    set_error("imq_solve is not available in this build");
+    return IMQ_EUNSUPPORTED;
+}
+
+imq_status imq_matvec_backward(imq_tree t, imq_dtype dtype, const void *v, const void *g, void *dv,
+                               double *dc, double *dxy, imq_prec prec, hipStream_t stream)
+{
+    (void)t; (void)dtype; (void)v; (void)g; (void)dv; (void)dc; (void)dxy; (void)prec; (void)stream;
+    set_error("imq_matvec_backward is not available in this build");
+    return IMQ_EUNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Device-side state of a tree handle and the views handed to kernels.
+#pragma once
+
+#include "imq_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+
+namespace imq {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+hipError_t dev_alloc(DevBuf &b, size_t bytes);
+void dev_free(DevBuf &b);
+
+// Read-only view of the forest for kernels, in arithmetic type T.
+template <typename T>
+struct DTree {
+    int nbox, nsets, nlev, K, P;
+    int64_t N;
+    const int32_t *level, *set, *parent, *child0, *nchild, *pos, *begin, *end;
+    const double *cx, *cy;
+    const int32_t *u_off, *u_idx, *v_off, *v_idx, *v_cls, *w_off, *w_idx, *x_off, *x_idx;
+    const int32_t *Klev;
+    const double *cn;          // per set: c / side
+    const T *xl, *yl;          // leaf-local coordinates, sorted order
+};
+
+struct PrecData {              // everything that exists once per arithmetic type
+    DevBuf xl, yl, m2m, l2l, m2l, wx;
+    DevBuf us, M, L;           // workspace
+    size_t ws_nrhs = 0;
+};
+
+}  // namespace imq
+
+struct imq_tree_s {
+    imq::HostTree h;
+    int device = 0;
+    // topology (shared by both precisions)
+    imq::DevBuf perm, pt_scale, level, set, parent, child0, nchild, pos, begin, end, cx, cy;
+    imq::DevBuf u_off, u_idx, v_off, v_idx, v_cls, w_off, w_idx, x_off, x_idx, Klev, cn, leaves;
+    imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
+    imq::PrecData f64, f32;
+    imq::DevBuf bs;                        // FP64 result accumulator, sorted order
+    size_t bs_nrhs = 0;
+    // solver workspace
+    imq::DevBuf sol;
+    size_t sol_bytes = 0;
+    // stage timing
+    bool timing = false;
+    hipEvent_t ev[IMQ_NSTAGES + 1] = {};
+    double stage_ms[IMQ_NSTAGES] = {};
+};
+
+namespace imq {
+template <typename T> DTree<T> make_view(const imq_tree_s *t);
+template <typename T> PrecData &prec_data(imq_tree_s *t);
+
+// FP64 or FP32 fast product on sorted, already-gathered vectors:
+// us (T, nrhs x N) -> bs (FP64, nrhs x N) in normalised units.
+template <typename T>
+imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s);
+
+template <typename T>
+imq_status ensure_workspace(imq_tree_s *t, int nrhs);
+}  // namespace imq
+
+#define IMQ_HIP(call)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            imq::set_error(std::string(#call) + ": " + hipGetErrorString(e_));        \
+            return e_ == hipErrorOutOfMemory ? IMQ_ENOMEM : IMQ_EHIP;                 \
+        }                                                                             \
+    } while (0)

@@ -1,0 +1,577 @@
+// HIP kernels of the fast product b = A u and their schedule.
+//
+// Stage order (one product):
+//   gather   u -> Morton order, arithmetic type T
+//   P2M      leaf expansions from points (the v_k, w_k sums of Algorithm 1)
+//   M2M      children -> parent, level by level upward
+//   M2L      source box -> target box of the same level (V list)
+//   P2L      points of a coarser leaf -> local expansion (X list)
+//   L2L      parent -> children, level by level downward
+//   L2P      local expansion evaluated at the leaf's points
+//   P2P      direct near field (last loop of Algorithm 1, U list)
+//   M2P      multipole of a finer box evaluated at points (W list)
+//   scatter  FP64 result -> caller order and type, times 1/side
+#include "device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace imq {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int cidx(int n, int m) { return n * (n + 1) / 2 + (m > 0 ? m - 1 : 0); }
+
+__device__ __forceinline__ float rsqrt_t(float x) { return __frsqrt_rn(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+
+template <typename T> __device__ __forceinline__ T pow2i(int l) { return T(ldexp(1.0, l)); }
+
+// Irregular solid harmonics I_n^m(v), 0 <= m <= n <= P, generated column by
+// column in m with the three-term recurrence in n; calls f(n, m, re, im)
+// for every n+m-even pair.
+template <typename T, typename F>
+__device__ __forceinline__ void irregular_even(int P, T vx, T vy, T vz, F &&f)
+{
+    const T r2 = vx * vx + vy * vy + vz * vz;
+    const T inv_r2 = T(1) / r2;
+    T mr = rsqrt_t(r2), mi = T(0);                 // I_m^m
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) {
+            const T a = -T(2 * m - 1) * inv_r2;
+            const T nr = a * (vx * mr - vy * mi);
+            const T ni = a * (vx * mi + vy * mr);
+            mr = nr;
+            mi = ni;
+        }
+        T p2r = 0, p2i = 0, p1r = mr, p1i = mi;   // I_{n-2}^m, I_{n-1}^m
+        f(m, m, mr, mi);
+        for (int n = m + 1; n <= P; ++n) {
+            const T a = T(2 * n - 1) * vz;
+            const T b = T((n + m - 1) * (n - m - 1));
+            const T cr = (a * p1r - b * p2r) * inv_r2;
+            const T ci = (a * p1i - b * p2i) * inv_r2;
+            if (((n + m) & 1) == 0) f(n, m, cr, ci);
+            p2r = p1r; p2i = p1i; p1r = cr; p1i = ci;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <typename Tin, typename T>
+__global__ void k_gather(int64_t N, const int32_t *__restrict__ perm, const Tin *__restrict__ u,
+                         int64_t ldu, T *__restrict__ us)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < N) us[r * N + i] = T(u[r * ldu + perm[i]]);
+}
+
+template <typename Tout>
+__global__ void k_scatter(int64_t N, const int32_t *__restrict__ perm, const double *__restrict__ scale,
+                          const double *__restrict__ bs, Tout *__restrict__ b, int64_t ldb)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < N) b[r * ldb + perm[i]] = Tout(bs[r * N + i] * scale[i]);
+}
+
+// P2M: Mt[n,m] = sum_j u_j |w_j|^(n-m) conj(w_j)^m over a leaf's points.
+// Phase 1: one thread per point writes its monomials to LDS; phase 2: one
+// thread per coefficient sums them.
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restrict__ leaves,
+                                            const T *__restrict__ us, int nrhs, T *__restrict__ M,
+                                            int chunk)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *mono = reinterpret_cast<T *>(smem_raw);
+    const int ld = chunk + 1;
+    const int b = leaves[blockIdx.x];
+    const int beg = t.begin[b], end = t.end[b];
+    const T inv_s = pow2i<T>(t.level[b]);
+    const int P = t.P, K = t.K, tid = threadIdx.x;
+    for (int r = 0; r < nrhs; ++r) {
+        T acc[3] = {T(0), T(0), T(0)};
+        for (int c0 = beg; c0 < end; c0 += chunk) {
+            if (tid < chunk) {
+                const int i = c0 + tid;
+                if (i < end) {
+                    const T wx = t.xl[i] * inv_s, wy = -t.yl[i] * inv_s;   // conj(w)
+                    const T r2 = wx * wx + wy * wy;
+                    T pr = us[r * t.N + i], pi = T(0);
+                    for (int m = 0; m <= P; ++m) {
+                        T tr = pr, ti = pi;
+                        for (int n = m; n <= P; n += 2) {
+                            const int k = cidx(n, m);
+                            mono[k * ld + tid] = tr;
+                            if (m > 0) mono[(k + 1) * ld + tid] = ti;
+                            tr *= r2;
+                            ti *= r2;
+                        }
+                        const T nr = pr * wx - pi * wy;
+                        pi = pr * wy + pi * wx;
+                        pr = nr;
+                    }
+                } else {
+                    for (int k = 0; k < K; ++k) mono[k * ld + tid] = T(0);
+                }
+            }
+            __syncthreads();
+            for (int q = 0; q * 64 + tid < K; ++q) {
+                const int k = q * 64 + tid;
+                T s = T(0);
+                for (int j = 0; j < chunk; ++j) s += mono[k * ld + j];
+                acc[q] += s;
+            }
+            __syncthreads();
+        }
+        for (int q = 0; q * 64 + tid < K; ++q) M[(int64_t(b) * nrhs + r) * K + q * 64 + tid] = acc[q];
+    }
+}
+
+// M2M: parent = sum over children of T_pos(child) * child, for the boxes
+// [b0, b1) of one level.
+template <typename T>
+__global__ void k_m2m(DTree<T> t, int b0, int b1, const T *__restrict__ Tm, int nrhs, T *__restrict__ M)
+{
+    const int b = b0 + blockIdx.x;
+    if (b >= b1) return;
+    const int nc = t.nchild[b];
+    if (nc == 0) return;
+    const int K = t.K, c0 = t.child0[b];
+    for (int r = 0; r < nrhs; ++r)
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            T acc = T(0);
+            for (int c = 0; c < nc; ++c) {
+                const int ch = c0 + c;
+                const T *Tp = Tm + (size_t(t.pos[ch]) * K + k) * K;
+                const T *Mc = M + (size_t(ch) * nrhs + r) * K;
+                for (int j = 0; j < K; ++j) acc += Tp[j] * Mc[j];
+            }
+            M[(size_t(b) * nrhs + r) * K + k] = acc;
+        }
+}
+
+// M2L: L[b] = sum_{s in V(b)} T_{set,level,class} M[s], truncated to the
+// level's order; writes every box (zeros where V(b) is empty).
+template <typename T>
+__global__ void k_m2l(DTree<T> t, const T *__restrict__ Tl, int nrhs, const T *__restrict__ M,
+                      T *__restrict__ L)
+{
+    const int b = blockIdx.x;
+    const int K = t.K, lev = t.level[b];
+    const int Kl = t.Klev[lev];
+    const T *base = Tl + size_t(t.set[b] * t.nlev + lev) * NCLASS * K * K;
+    const int v0 = t.v_off[b], v1 = t.v_off[b + 1];
+    for (int r = 0; r < nrhs; ++r)
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            T acc = T(0);
+            if (k < Kl)
+                for (int v = v0; v < v1; ++v) {
+                    const T *Tp = base + (size_t(t.v_cls[v]) * K + k) * K;
+                    const T *Ms = M + (size_t(t.v_idx[v]) * nrhs + r) * K;
+                    for (int j = 0; j < Kl; ++j) acc += Tp[j] * Ms[j];
+                }
+            L[(size_t(b) * nrhs + r) * K + k] = acc;
+        }
+}
+
+// P2L: points of the X-list leaves of b accumulated into b's local
+// expansion: Lt += (1/s) eps_k c_{jk} u conj(I_j^k((y - z_b)/s)).
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2l(DTree<T> t, const T *__restrict__ us, int nrhs,
+                                            const T *__restrict__ wx, T *__restrict__ L, int chunk)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *mono = reinterpret_cast<T *>(smem_raw);
+    const int ld = chunk + 1;
+    const int b = blockIdx.x;
+    const int x0 = t.x_off[b], x1 = t.x_off[b + 1];
+    if (x0 == x1) return;
+    const int P = t.P, K = t.K, tid = threadIdx.x;
+    const double inv_sd = ldexp(1.0, t.level[b]);
+    const T inv_s = T(inv_sd);
+    const T vz = T(-t.cn[t.set[b]] * inv_sd);
+    for (int r = 0; r < nrhs; ++r) {
+        T acc[3] = {T(0), T(0), T(0)};
+        for (int xi = x0; xi < x1; ++xi) {
+            const int a = t.x_idx[xi];
+            const T ox = T((t.cx[a] - t.cx[b]) * inv_sd), oy = T((t.cy[a] - t.cy[b]) * inv_sd);
+            for (int c0 = t.begin[a]; c0 < t.end[a]; c0 += chunk) {
+                if (tid < chunk) {
+                    const int i = c0 + tid;
+                    if (i < t.end[a]) {
+                        const T u = us[r * t.N + i];
+                        irregular_even<T>(P, t.xl[i] * inv_s + ox, t.yl[i] * inv_s + oy, vz,
+                                          [&](int n, int m, T re, T im) {
+                                              const int k = cidx(n, m);
+                                              mono[k * ld + tid] = u * re;
+                                              if (m > 0) mono[(k + 1) * ld + tid] = -u * im;
+                                          });
+                    } else {
+                        for (int k = 0; k < K; ++k) mono[k * ld + tid] = T(0);
+                    }
+                }
+                __syncthreads();
+                for (int q = 0; q * 64 + tid < K; ++q) {
+                    const int k = q * 64 + tid;
+                    T s = T(0);
+                    for (int j = 0; j < chunk; ++j) s += mono[k * ld + j];
+                    acc[q] += s;
+                }
+                __syncthreads();
+            }
+        }
+        for (int q = 0; q * 64 + tid < K; ++q) {
+            const int k = q * 64 + tid;
+            L[(int64_t(b) * nrhs + r) * K + k] += acc[q] * wx[k] * inv_s;
+        }
+    }
+}
+
+// L2L: child += T_pos(child) * parent for the boxes [b0, b1) of one level.
+template <typename T>
+__global__ void k_l2l(DTree<T> t, int b0, int b1, const T *__restrict__ Tm, int nrhs, T *__restrict__ L)
+{
+    const int b = b0 + blockIdx.x;
+    if (b >= b1) return;
+    const int par = t.parent[b];
+    const int K = t.K;
+    const int Kc = t.Klev[t.level[b]], Kp = t.Klev[t.level[par]];
+    for (int r = 0; r < nrhs; ++r)
+        for (int k = threadIdx.x; k < Kc; k += blockDim.x) {
+            const T *Tp = Tm + (size_t(t.pos[b]) * K + k) * K;
+            const T *Lp = L + (size_t(par) * nrhs + r) * K;
+            T acc = T(0);
+            for (int j = 0; j < Kp; ++j) acc += Tp[j] * Lp[j];
+            L[(size_t(b) * nrhs + r) * K + k] += acc;
+        }
+}
+
+// L2P: potential = sum Re(Lt[n,m] |w|^(n-m) w^m) at each point of a leaf.
+template <typename T>
+__global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restrict__ leaves,
+                                            const T *__restrict__ L, int nrhs, double *__restrict__ bs)
+{
+    const int b = leaves[blockIdx.x];
+    const T inv_s = pow2i<T>(t.level[b]);
+    const int P = t.P, K = t.K;
+    for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+        const T wx = t.xl[i] * inv_s, wy = t.yl[i] * inv_s;
+        const T r2 = wx * wx + wy * wy;
+        for (int r = 0; r < nrhs; ++r) {
+            const T *Lb = L + (size_t(b) * nrhs + r) * K;
+            T acc = T(0), pr = T(1), pi = T(0);
+            for (int m = 0; m <= P; ++m) {
+                T tr = pr, ti = pi;
+                for (int n = m; n <= P; n += 2) {
+                    const int k = cidx(n, m);
+                    acc += Lb[k] * tr;
+                    if (m > 0) acc -= Lb[k + 1] * ti;
+                    tr *= r2;
+                    ti *= r2;
+                }
+                const T nr = pr * wx - pi * wy;
+                pi = pr * wy + pi * wx;
+                pr = nr;
+            }
+            bs[r * t.N + i] = double(acc);
+        }
+    }
+}
+
+// P2P: b_i += sum over U-list leaves a of sum_j u_j / sqrt(|x_i - x_j|^2 + c^2).
+// Partial sums over one source leaf in T, accumulated across leaves in FP64.
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restrict__ leaves,
+                                            const T *__restrict__ us, int nrhs, double *__restrict__ bs)
+{
+    const int b = leaves[blockIdx.x];
+    const double cnd = t.cn[t.set[b]];
+    const T c2 = T(cnd * cnd);
+    const int u0 = t.u_off[b], u1 = t.u_off[b + 1];
+    for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+        const T xi = t.xl[i], yi = t.yl[i];
+        for (int r = 0; r < nrhs; ++r) {
+            double acc = 0.0;
+            for (int uu = u0; uu < u1; ++uu) {
+                const int a = t.u_idx[uu];
+                const T px = xi + T(t.cx[b] - t.cx[a]);
+                const T py = yi + T(t.cy[b] - t.cy[a]);
+                T s = T(0);
+                for (int j = t.begin[a]; j < t.end[a]; ++j) {
+                    const T dx = px - t.xl[j], dy = py - t.yl[j];
+                    s += us[r * t.N + j] * rsqrt_t(dx * dx + dy * dy + c2);
+                }
+                acc += double(s);
+            }
+            bs[r * t.N + i] += acc;
+        }
+    }
+}
+
+// M2P: multipoles of the W-list boxes evaluated at the leaf's points:
+// potential = (1/s_a) sum Re(Mt[n,m] eps_m c_{nm} I_n^m((x - z_a)/s_a)).
+template <typename T>
+__global__ __launch_bounds__(64) void k_m2p(DTree<T> t, const int32_t *__restrict__ leaves,
+                                            const T *__restrict__ M, const T *__restrict__ wx, int nrhs,
+                                            double *__restrict__ bs)
+{
+    const int b = leaves[blockIdx.x];
+    const int w0 = t.w_off[b], w1 = t.w_off[b + 1];
+    if (w0 == w1) return;
+    const int P = t.P, K = t.K;
+    const double cnd = t.cn[t.set[b]];
+    for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+        for (int r = 0; r < nrhs; ++r) {
+            double acc = 0.0;
+            for (int w = w0; w < w1; ++w) {
+                const int a = t.w_idx[w];
+                const double inv_sd = ldexp(1.0, t.level[a]);
+                const T inv_s = T(inv_sd);
+                const T vx = t.xl[i] * inv_s + T((t.cx[b] - t.cx[a]) * inv_sd);
+                const T vy = t.yl[i] * inv_s + T((t.cy[b] - t.cy[a]) * inv_sd);
+                const T vz = T(cnd * inv_sd);
+                const T *Ma = M + (size_t(a) * nrhs + r) * K;
+                T s = T(0);
+                irregular_even<T>(P, vx, vy, vz, [&](int n, int m, T re, T im) {
+                    const int k = cidx(n, m);
+                    T v = Ma[k] * re;
+                    if (m > 0) v -= Ma[k + 1] * im;
+                    s += wx[k] * v;
+                });
+                acc += double(s * inv_s);
+            }
+            bs[r * t.N + i] += acc;
+        }
+    }
+}
+
+// Exact rows: b[r*ldb + k] = sum_j A_{rows[k], j} u_j in FP64 over the row's set.
+__global__ __launch_bounds__(256) void k_rows_exact(int nsets, const int64_t *__restrict__ set_off,
+                                                    const double *__restrict__ c, const double *__restrict__ xy,
+                                                    int64_t N, const double *__restrict__ u, int64_t ldu,
+                                                    const int64_t *__restrict__ rows, double *__restrict__ b,
+                                                    int64_t ldb)
+{
+    __shared__ double red[256];
+    const int64_t row = rows[blockIdx.x];
+    const int r = blockIdx.y;
+    int s = 0;
+    while (s + 1 < nsets && set_off[s + 1] <= row) ++s;
+    const double xi = xy[row], yi = xy[N + row], cc = c[s] * c[s];
+    double acc = 0.0, comp = 0.0;
+    for (int64_t j = set_off[s] + threadIdx.x; j < set_off[s + 1]; j += blockDim.x) {
+        const double dx = xi - xy[j], dy = yi - xy[N + j];
+        const double term = u[r * ldu + j] / sqrt(dx * dx + dy * dy + cc);
+        const double y = term - comp;
+        const double tt = acc + y;
+        comp = (tt - acc) - y;
+        acc = tt;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b[r * ldb + blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------------------------ host side
+
+hipError_t dev_alloc(DevBuf &b, size_t bytes)
+{
+    dev_free(b);
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipSuccess) b.bytes = bytes;
+    else b.p = nullptr;
+    return e;
+}
+
+void dev_free(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T> PrecData &prec_data(imq_tree_s *t);
+template <> PrecData &prec_data<double>(imq_tree_s *t) { return t->f64; }
+template <> PrecData &prec_data<float>(imq_tree_s *t) { return t->f32; }
+
+template <typename T>
+DTree<T> make_view(const imq_tree_s *t)
+{
+    DTree<T> v;
+    const HostTree &h = t->h;
+    v.nbox = int(h.level.size());
+    v.nsets = h.nsets;
+    v.nlev = h.nlev;
+    v.K = h.K;
+    v.P = h.p;
+    v.N = h.N;
+    v.level = t->level.as<int32_t>(); v.set = t->set.as<int32_t>(); v.parent = t->parent.as<int32_t>();
+    v.child0 = t->child0.as<int32_t>(); v.nchild = t->nchild.as<int32_t>(); v.pos = t->pos.as<int32_t>();
+    v.begin = t->begin.as<int32_t>(); v.end = t->end.as<int32_t>();
+    v.cx = t->cx.as<double>(); v.cy = t->cy.as<double>();
+    v.u_off = t->u_off.as<int32_t>(); v.u_idx = t->u_idx.as<int32_t>();
+    v.v_off = t->v_off.as<int32_t>(); v.v_idx = t->v_idx.as<int32_t>(); v.v_cls = t->v_cls.as<int32_t>();
+    v.w_off = t->w_off.as<int32_t>(); v.w_idx = t->w_idx.as<int32_t>();
+    v.x_off = t->x_off.as<int32_t>(); v.x_idx = t->x_idx.as<int32_t>();
+    v.Klev = t->Klev.as<int32_t>();
+    v.cn = t->cn.as<double>();
+    const PrecData &pd = prec_data<T>(const_cast<imq_tree_s *>(t));
+    v.xl = pd.xl.as<T>();
+    v.yl = pd.yl.as<T>();
+    return v;
+}
+
+template <typename T>
+imq_status ensure_workspace(imq_tree_s *t, int nrhs)
+{
+    PrecData &pd = prec_data<T>(t);
+    const size_t nbox = t->h.level.size();
+    if (pd.ws_nrhs < size_t(nrhs)) {
+        IMQ_HIP(dev_alloc(pd.us, sizeof(T) * size_t(t->h.N) * nrhs));
+        IMQ_HIP(dev_alloc(pd.M, sizeof(T) * nbox * nrhs * t->h.K));
+        IMQ_HIP(dev_alloc(pd.L, sizeof(T) * nbox * nrhs * t->h.K));
+        pd.ws_nrhs = nrhs;
+    }
+    if (t->bs_nrhs < size_t(nrhs)) {
+        IMQ_HIP(dev_alloc(t->bs, sizeof(double) * size_t(t->h.N) * nrhs));
+        t->bs_nrhs = nrhs;
+    }
+    return IMQ_OK;
+}
+
+static int lds_chunk(int K, size_t elem)
+{
+    int chunk = 64;
+    while (chunk > 8 && size_t(K) * (chunk + 1) * elem > 64 * 1024) chunk /= 2;
+    return chunk;
+}
+
+static inline void mark(imq_tree_s *t, int stage, hipStream_t s)
+{
+    if (t->timing) (void)hipEventRecord(t->ev[stage], s);
+}
+
+template <typename T>
+imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
+{
+    const HostTree &h = t->h;
+    PrecData &pd = prec_data<T>(t);
+    DTree<T> v = make_view<T>(t);
+    const int nleaves = int(h.leaves.size());
+    const int nbox = int(h.level.size());
+    const int K = h.K;
+    const int chunk = lds_chunk(K, sizeof(T));
+    const size_t lds = size_t(K) * (chunk + 1) * sizeof(T);
+    const int32_t *leaves = t->leaves.as<int32_t>();
+    T *M = pd.M.as<T>(), *L = pd.L.as<T>();
+    const T *us = pd.us.as<T>();
+    double *bs = t->bs.as<double>();
+
+    mark(t, 1, s);
+    hipLaunchKernelGGL(k_p2m<T>, dim3(nleaves), dim3(64), lds, s, v, leaves, us, nrhs, M, chunk);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 2, s);
+    for (int l = h.nlev - 2; l >= 0; --l) {
+        const int b0 = h.level_begin[l], b1 = h.level_begin[l + 1];
+        hipLaunchKernelGGL(k_m2m<T>, dim3(b1 - b0), dim3(64), 0, s, v, b0, b1, pd.m2m.as<T>(), nrhs, M);
+    }
+    IMQ_HIP(hipGetLastError());
+    mark(t, 3, s);
+    hipLaunchKernelGGL(k_m2l<T>, dim3(nbox), dim3(64), 0, s, v, pd.m2l.as<T>(), nrhs, M, L);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 4, s);
+    hipLaunchKernelGGL(k_p2l<T>, dim3(nbox), dim3(64), lds, s, v, us, nrhs, pd.wx.as<T>(), L, chunk);
+    for (int l = 0; l + 1 < h.nlev; ++l) {
+        const int b0 = h.level_begin[l + 1], b1 = h.level_begin[l + 2];
+        hipLaunchKernelGGL(k_l2l<T>, dim3(b1 - b0), dim3(64), 0, s, v, b0, b1, pd.l2l.as<T>(), nrhs, L);
+    }
+    IMQ_HIP(hipGetLastError());
+    mark(t, 5, s);
+    hipLaunchKernelGGL(k_l2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, L, nrhs, bs);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 6, s);
+    hipLaunchKernelGGL(k_p2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, us, nrhs, bs);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 7, s);
+    hipLaunchKernelGGL(k_m2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, M, pd.wx.as<T>(), nrhs, bs);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 8, s);
+    return IMQ_OK;
+}
+
+template imq_status fmm_sorted<double>(imq_tree_s *, int, hipStream_t);
+template imq_status fmm_sorted<float>(imq_tree_s *, int, hipStream_t);
+template imq_status ensure_workspace<double>(imq_tree_s *, int);
+template imq_status ensure_workspace<float>(imq_tree_s *, int);
+template DTree<double> make_view<double>(const imq_tree_s *);
+template DTree<float> make_view<float>(const imq_tree_s *);
+
+template <typename Tin, typename T>
+imq_status launch_gather(imq_tree_s *t, int nrhs, const Tin *u, int64_t ldu, hipStream_t s)
+{
+    const int64_t N = t->h.N;
+    hipLaunchKernelGGL((k_gather<Tin, T>), dim3(unsigned((N + 255) / 256), nrhs), dim3(256), 0, s, N,
+                       t->perm.as<int32_t>(), u, ldu, prec_data<T>(t).us.template as<T>());
+    IMQ_HIP(hipGetLastError());
+    return IMQ_OK;
+}
+
+template <typename Tout>
+imq_status launch_scatter(imq_tree_s *t, int nrhs, Tout *b, int64_t ldb, hipStream_t s)
+{
+    const int64_t N = t->h.N;
+    hipLaunchKernelGGL((k_scatter<Tout>), dim3(unsigned((N + 255) / 256), nrhs), dim3(256), 0, s, N,
+                       t->perm.as<int32_t>(), t->pt_scale.as<double>(), t->bs.as<double>(), b, ldb);
+    IMQ_HIP(hipGetLastError());
+    return IMQ_OK;
+}
+
+template <typename T, typename Tio>
+imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio *b, int64_t ldb,
+                        hipStream_t s)
+{
+    imq_status st = ensure_workspace<T>(t, nrhs);
+    if (st != IMQ_OK) return st;
+    mark(t, 0, s);
+    if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) != IMQ_OK) return st;
+    if ((st = fmm_sorted<T>(t, nrhs, s)) != IMQ_OK) return st;
+    if ((st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) != IMQ_OK) return st;
+    mark(t, 9, s);
+    if (t->timing) {
+        IMQ_HIP(hipEventSynchronize(t->ev[9]));
+        for (int k = 0; k < IMQ_NSTAGES; ++k) {
+            float ms = 0;
+            IMQ_HIP(hipEventElapsedTime(&ms, t->ev[k], t->ev[k + 1]));
+            t->stage_ms[k] = ms;
+        }
+    }
+    return IMQ_OK;
+}
+
+template imq_status matvec_typed<double, double>(imq_tree_s *, int, const double *, int64_t, double *, int64_t, hipStream_t);
+template imq_status matvec_typed<double, float>(imq_tree_s *, int, const float *, int64_t, float *, int64_t, hipStream_t);
+template imq_status matvec_typed<float, double>(imq_tree_s *, int, const double *, int64_t, double *, int64_t, hipStream_t);
+template imq_status matvec_typed<float, float>(imq_tree_s *, int, const float *, int64_t, float *, int64_t, hipStream_t);
+
+imq_status rows_exact(imq_tree_s *t, int nrhs, const double *u, int64_t ldu, int64_t nrows,
+                      const int64_t *rows, double *b, int64_t ldb, hipStream_t s)
+{
+    if (nrows == 0) return IMQ_OK;
+    hipLaunchKernelGGL(k_rows_exact, dim3(unsigned(nrows), nrhs), dim3(256), 0, s, t->h.nsets,
+                       t->set_off.as<int64_t>(), t->cn.as<double>() + t->h.nsets, t->xy_user.as<double>(),
+                       t->h.N, u, ldu, rows, b, ldb);
+    IMQ_HIP(hipGetLastError());
+    return IMQ_OK;
+}
+
+}  // namespace imq

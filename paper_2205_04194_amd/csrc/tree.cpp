@@ -1,0 +1,299 @@
+// Host construction of the quadtree forest and its interaction lists.
+//
+// Sec. 2.2 partitions a square D containing the data into 4^l blocks at
+// level l and, per block, separates the blocks whose points are far enough
+// for the expansion (well separated) from the near ones, whose contribution
+// is summed directly at the finest level.  The paper analyses uniform
+// levels only; here the partition is refined adaptively (a box is split
+// while it holds more than leaf_max points), and the well-separated /
+// near classification becomes the usual adaptive lists:
+//   U(b)  leaves adjacent to leaf b (edge or corner, b included): direct sum
+//   V(b)  children of the neighbours of b's parent that are not adjacent
+//         to b (same level as b): expansion-to-local translation
+//   W(b)  for a leaf b, the largest descendants of b's neighbours that are
+//         not adjacent to b although their parent is: multipole evaluated
+//         at b's points
+//   X(b)  the dual of W: b in W(a) <=> a in X(b): a's points summed into
+//         b's local expansion
+// Every ordered pair of points of a set is covered exactly once by these
+// lists (checked by the test-suite).
+#include "imq_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace imq {
+
+static inline uint64_t spread(uint32_t v)
+{
+    uint64_t x = v & 0x3fffffffu;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+static inline uint64_t morton(uint32_t ix, uint32_t iy) { return spread(ix) | (spread(iy) << 1); }
+
+namespace {
+struct Builder {
+    HostTree &t;
+    std::vector<std::vector<int32_t>> lvl_set_begin;   // [level][set] -> first box
+
+    explicit Builder(HostTree &tt) : t(tt) {}
+
+    int find(int s, int l, int64_t ix, int64_t iy) const
+    {
+        const int64_t n = int64_t(1) << l;
+        if (ix < 0 || iy < 0 || ix >= n || iy >= n) return -1;
+        int lo = lvl_set_begin[l][s], hi = lvl_set_begin[l][s + 1];
+        const uint64_t key = morton(uint32_t(ix), uint32_t(iy));
+        while (lo < hi) {
+            int mid = (lo + hi) / 2;
+            uint64_t km = morton(uint32_t(t.ix[mid]), uint32_t(t.iy[mid]));
+            if (km < key) lo = mid + 1; else hi = mid;
+        }
+        if (lo < lvl_set_begin[l][s + 1] && t.ix[lo] == ix && t.iy[lo] == iy) return lo;
+        return -1;
+    }
+
+    void colleagues(int b, std::vector<int> &out) const
+    {
+        out.clear();
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy) {
+                int c = find(t.set[b], t.level[b], int64_t(t.ix[b]) + dx, int64_t(t.iy[b]) + dy);
+                if (c >= 0) out.push_back(c);
+            }
+    }
+
+    bool adjacent(int a, int b) const
+    {
+        const int L = std::max(t.level[a], t.level[b]);
+        const int sa = L - t.level[a], sb = L - t.level[b];
+        const int64_t ax0 = int64_t(t.ix[a]) << sa, ax1 = int64_t(t.ix[a] + 1) << sa;
+        const int64_t ay0 = int64_t(t.iy[a]) << sa, ay1 = int64_t(t.iy[a] + 1) << sa;
+        const int64_t bx0 = int64_t(t.ix[b]) << sb, bx1 = int64_t(t.ix[b] + 1) << sb;
+        const int64_t by0 = int64_t(t.iy[b]) << sb, by1 = int64_t(t.iy[b] + 1) << sb;
+        return ax0 <= bx1 && bx0 <= ax1 && ay0 <= by1 && by0 <= ay1;
+    }
+};
+}  // namespace
+
+imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const double *y,
+                           const double *c, const imq_tree_params &prm, HostTree &t)
+{
+    if (nsets < 1) { set_error("nsets must be >= 1"); return IMQ_EINVAL; }
+    if (off[0] != 0) { set_error("set_offsets[0] must be 0"); return IMQ_EINVAL; }
+    for (int s = 0; s < nsets; ++s) {
+        if (off[s + 1] <= off[s]) { set_error("every set needs at least one point"); return IMQ_EINVAL; }
+        if (!(c[s] > 0.0) || !std::isfinite(c[s])) { set_error("shape parameter c must be finite and > 0"); return IMQ_EINVAL; }
+    }
+    const int64_t N = off[nsets];
+    if (N > INT32_MAX) { set_error("more than 2^31-1 points"); return IMQ_EINVAL; }
+    if (prm.order_p < 1 || prm.order_p > PMAX) { set_error("order_p must be in [1, 16]"); return IMQ_EINVAL; }
+    if (prm.leaf_max < 1) { set_error("leaf_max must be >= 1"); return IMQ_EINVAL; }
+    int max_level = prm.max_level == 0 ? MORTON_BITS : prm.max_level;
+    if (max_level < 0 || max_level > MORTON_BITS) { set_error("max_level must be in [0, 30]"); return IMQ_EINVAL; }
+    for (int64_t i = 0; i < N; ++i)
+        if (!std::isfinite(x[i]) || !std::isfinite(y[i])) { set_error("non-finite coordinate"); return IMQ_EINVAL; }
+
+    t = HostTree();
+    t.nsets = nsets;
+    t.N = N;
+    t.p = prm.order_p;
+    t.K = Kof(t.p);
+    t.set_off.assign(off, off + nsets + 1);
+    t.c.assign(c, c + nsets);
+    t.side.resize(nsets); t.lox.resize(nsets); t.loy.resize(nsets); t.cn.resize(nsets);
+
+    // ---- normalise, Morton keys, sort per set
+    std::vector<uint64_t> key(N);
+    std::vector<double> xn(N), yn(N);
+    t.perm.resize(N);
+    for (int s = 0; s < nsets; ++s) {
+        double x0 = x[off[s]], x1 = x0, y0 = y[off[s]], y1 = y0;
+        for (int64_t i = off[s]; i < off[s + 1]; ++i) {
+            x0 = std::min(x0, x[i]); x1 = std::max(x1, x[i]);
+            y0 = std::min(y0, y[i]); y1 = std::max(y1, y[i]);
+        }
+        double ext = std::max(x1 - x0, y1 - y0);
+        double side = ext > 0 ? ext * (1.0 + std::ldexp(1.0, -20)) : 1.0;
+        t.side[s] = side; t.lox[s] = x0; t.loy[s] = y0; t.cn[s] = c[s] / side;
+        const double q = std::ldexp(1.0, MORTON_BITS);
+        std::vector<std::pair<uint64_t, int32_t>> kv;
+        kv.reserve(off[s + 1] - off[s]);
+        for (int64_t i = off[s]; i < off[s + 1]; ++i) {
+            double a = (x[i] - x0) / side, b = (y[i] - y0) / side;
+            int64_t qa = std::min<int64_t>(int64_t(a * q), (int64_t(1) << MORTON_BITS) - 1);
+            int64_t qb = std::min<int64_t>(int64_t(b * q), (int64_t(1) << MORTON_BITS) - 1);
+            qa = std::max<int64_t>(qa, 0); qb = std::max<int64_t>(qb, 0);
+            kv.emplace_back(morton(uint32_t(qa), uint32_t(qb)), int32_t(i));
+        }
+        std::sort(kv.begin(), kv.end());
+        for (size_t k = 0; k < kv.size(); ++k) {
+            int64_t i = off[s] + int64_t(k);
+            key[i] = kv[k].first;
+            t.perm[i] = kv[k].second;
+            xn[i] = (x[kv[k].second] - x0) / side;
+            yn[i] = (y[kv[k].second] - y0) / side;
+        }
+        // exact duplicates can only share a Morton key
+        for (int64_t i = off[s]; i < off[s + 1];) {
+            int64_t j = i + 1;
+            while (j < off[s + 1] && key[j] == key[i]) ++j;
+            for (int64_t a = i; a < j; ++a)
+                for (int64_t b = a + 1; b < j; ++b)
+                    if (x[t.perm[a]] == x[t.perm[b]] && y[t.perm[a]] == y[t.perm[b]]) {
+                        set_error("duplicate data sites: points " + std::to_string(t.perm[a]) +
+                                  " and " + std::to_string(t.perm[b]));
+                        return IMQ_EDUPLICATE;
+                    }
+            i = j;
+        }
+    }
+
+    // ---- breadth-first adaptive split: boxes come out in (level, set, Morton) order
+    auto push_box = [&](int l, int s, int64_t bx, int64_t by, int64_t b, int64_t e, int par) {
+        t.level.push_back(l); t.set.push_back(s);
+        t.ix.push_back(int32_t(bx)); t.iy.push_back(int32_t(by));
+        t.parent.push_back(par); t.child0.push_back(-1); t.nchild.push_back(0);
+        t.pos.push_back(int32_t((bx & 1) | ((by & 1) << 1)));
+        t.begin.push_back(int32_t(b)); t.end.push_back(int32_t(e));
+        t.isleaf.push_back(1);
+        const double sz = std::ldexp(1.0, -l);
+        t.cx.push_back((double(bx) + 0.5) * sz); t.cy.push_back((double(by) + 0.5) * sz);
+    };
+    t.level_begin.push_back(0);
+    for (int s = 0; s < nsets; ++s) push_box(0, s, 0, 0, off[s], off[s + 1], -1);
+    int lvl_lo = 0, lvl_hi = nsets;
+    for (int l = 0;; ++l) {
+        t.level_begin.push_back(lvl_hi);
+        if (l >= max_level) break;
+        const int shift = 2 * (MORTON_BITS - l - 1);
+        for (int b = lvl_lo; b < lvl_hi; ++b) {
+            if (t.end[b] - t.begin[b] <= prm.leaf_max) continue;
+            int64_t lo = t.begin[b];
+            const int64_t hi = t.end[b];
+            const int first = int(t.level.size());
+            int cnt = 0;
+            for (int ch = 0; ch < 4; ++ch) {
+                int64_t e = std::partition_point(key.begin() + lo, key.begin() + hi,
+                                                 [&](uint64_t k) { return int((k >> shift) & 3) <= ch; }) -
+                            key.begin();
+                if (e > lo) {
+                    push_box(l + 1, t.set[b], 2 * int64_t(t.ix[b]) + (ch & 1),
+                             2 * int64_t(t.iy[b]) + (ch >> 1), lo, e, b);
+                    ++cnt;
+                }
+                lo = e;
+            }
+            t.child0[b] = first; t.nchild[b] = cnt; t.isleaf[b] = 0;
+        }
+        lvl_lo = lvl_hi;
+        lvl_hi = int(t.level.size());
+        if (lvl_hi == lvl_lo) break;
+    }
+    const int nbox = int(t.level.size());
+    t.nlev = int(t.level_begin.size()) - 1;
+    t.Klev.resize(t.nlev);
+    for (int l = 0; l < t.nlev; ++l) {
+        int pl = (l <= IMQ_MAX_LEVELS && prm.level_order[l] > 0) ? prm.level_order[l] : t.p;
+        pl = std::min(pl, t.p);
+        t.Klev[l] = Kof(pl);
+    }
+
+    // ---- points: leaf-local coordinates
+    t.xl.resize(N); t.yl.resize(N); t.pt_scale.resize(N); t.pt_leaf.resize(N);
+    for (int b = 0; b < nbox; ++b) {
+        if (!t.isleaf[b]) continue;
+        t.leaves.push_back(b);
+        for (int i = t.begin[b]; i < t.end[b]; ++i) {
+            t.xl[i] = xn[i] - t.cx[b];
+            t.yl[i] = yn[i] - t.cy[b];
+            t.pt_scale[i] = 1.0 / t.side[t.set[b]];
+            t.pt_leaf[i] = b;
+        }
+    }
+
+    // ---- lookup structure
+    Builder B(t);
+    B.lvl_set_begin.assign(t.nlev, std::vector<int32_t>(nsets + 1, 0));
+    for (int l = 0; l < t.nlev; ++l) {
+        int b = t.level_begin[l];
+        for (int s = 0; s <= nsets; ++s) {
+            while (b < t.level_begin[l + 1] && t.set[b] < s) ++b;
+            B.lvl_set_begin[l][s] = b;
+        }
+        B.lvl_set_begin[l][nsets] = t.level_begin[l + 1];
+    }
+
+    // ---- lists
+    std::vector<std::vector<int32_t>> U(nbox), V(nbox), Vc(nbox), W(nbox), X(nbox);
+    std::vector<int> col, pcol, stack;
+    for (int b = 0; b < nbox; ++b) {
+        if (t.parent[b] >= 0) {
+            B.colleagues(t.parent[b], pcol);
+            for (int pc : pcol)
+                for (int ch = t.child0[pc]; ch >= 0 && ch < t.child0[pc] + t.nchild[pc]; ++ch) {
+                    int dx = t.ix[b] - t.ix[ch], dy = t.iy[b] - t.iy[ch];
+                    if (std::abs(dx) > 1 || std::abs(dy) > 1) {
+                        V[b].push_back(ch);
+                        Vc[b].push_back(class_of(dx, dy));
+                    }
+                }
+        }
+        if (!t.isleaf[b]) continue;
+        B.colleagues(b, col);
+        stack.assign(col.begin(), col.end());
+        while (!stack.empty()) {
+            int cb = stack.back();
+            stack.pop_back();
+            if (t.isleaf[cb]) { U[b].push_back(cb); continue; }
+            for (int ch = t.child0[cb]; ch < t.child0[cb] + t.nchild[cb]; ++ch) {
+                if (B.adjacent(b, ch)) stack.push_back(ch);
+                else W[b].push_back(ch);
+            }
+        }
+        for (int a = t.parent[b]; a >= 0; a = t.parent[a]) {
+            B.colleagues(a, pcol);
+            for (int cb : pcol)
+                if (cb != a && t.isleaf[cb] && B.adjacent(b, cb)) U[b].push_back(cb);
+        }
+        std::sort(U[b].begin(), U[b].end());
+        std::sort(W[b].begin(), W[b].end());
+    }
+    for (int b = 0; b < nbox; ++b)
+        for (int w : W[b]) X[w].push_back(b);
+
+    auto flatten = [&](const std::vector<std::vector<int32_t>> &L, std::vector<int32_t> &offv,
+                       std::vector<int32_t> &idx) {
+        offv.assign(nbox + 1, 0);
+        for (int b = 0; b < nbox; ++b) offv[b + 1] = offv[b] + int32_t(L[b].size());
+        idx.resize(offv[nbox]);
+        for (int b = 0; b < nbox; ++b) std::copy(L[b].begin(), L[b].end(), idx.begin() + offv[b]);
+    };
+    flatten(U, t.u_off, t.u_idx);
+    flatten(V, t.v_off, t.v_idx);
+    {
+        std::vector<int32_t> dummy;
+        flatten(Vc, dummy, t.v_cls);
+    }
+    flatten(W, t.w_off, t.w_idx);
+    flatten(X, t.x_off, t.x_idx);
+
+    auto npts = [&](int b) { return int64_t(t.end[b] - t.begin[b]); };
+    for (int b = 0; b < nbox; ++b) {
+        for (int u : U[b]) t.p2p_pairs += npts(b) * npts(u);
+        t.m2l_pairs += int64_t(V[b].size());
+        for (int w : W[b]) { (void)w; t.m2p_evals += npts(b); }
+        for (int xsrc : X[b]) t.p2l_evals += npts(xsrc);
+        if (t.parent[b] >= 0) { t.m2m_pairs++; t.l2l_pairs++; }
+    }
+    return IMQ_OK;
+}
+
+}  // namespace imq

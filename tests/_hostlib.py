@@ -1,0 +1,83 @@
+"""Helpers for the CPU tests of the library's host logic (no GPU calls)."""
+import ctypes
+
+import numpy as np
+
+from paper_2205_04194_amd import _lib
+
+
+def host_tree(xy_list, c_list, leaf, p=4, max_level=0, level_order=None):
+    """Build the host part of a tree; returns (handle, status)."""
+    lib = _lib.load()
+    xy = np.concatenate(xy_list, axis=0)
+    offs = np.concatenate([[0], np.cumsum([len(a) for a in xy_list])]).astype(np.int64)
+    x = np.ascontiguousarray(xy[:, 0], dtype=np.float64)
+    y = np.ascontiguousarray(xy[:, 1], dtype=np.float64)
+    c = np.ascontiguousarray(c_list, dtype=np.float64)
+    prm = _lib.params(leaf, p, max_level, level_order)
+    st = ctypes.c_int(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = lib.imq_debug_host_tree(len(xy_list), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                x.ctypes.data_as(dp), y.ctypes.data_as(dp), c.ctypes.data_as(dp),
+                                ctypes.byref(prm), ctypes.byref(st))
+    return h, st.value
+
+
+_DTYPES = {"xl": np.float64, "yl": np.float64, "cx": np.float64, "cy": np.float64,
+           "side": np.float64, "cn": np.float64}
+
+
+def get(h, name):
+    lib = _lib.load()
+    n = lib.imq_debug_host_tree_size(h, name.encode())
+    assert n >= 0, name
+    out = np.empty(n, dtype=_DTYPES.get(name, np.int32))
+    assert lib.imq_debug_host_tree_get(h, name.encode(), out.ctypes.data_as(ctypes.c_void_p)) == 0
+    return out
+
+
+def free(h):
+    _lib.load().imq_debug_host_tree_free(h)
+
+
+def table(kind, p, pos=0, level=0, dx=0, dy=0, cnorm=0.0):
+    K = (p + 1) * (p + 2) // 2
+    out = np.zeros(K if kind == 3 else K * K)
+    rc = _lib.load().imq_debug_table(kind, p, pos, level, dx, dy, cnorm,
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert rc == 0
+    return out if kind == 3 else out.reshape(K, K)
+
+
+# ---- the stored representation, written from its definition -----------------
+# coefficient layout: degree n = 0..p, m ascending with n+m even, (Re, Im)
+
+def layout(p):
+    lay = []
+    for n in range(p + 1):
+        for m in range(n % 2, n + 1, 2):
+            lay.append((n, m, 0))
+            if m > 0:
+                lay.append((n, m, 1))
+    return lay
+
+
+def moments(p, pts, u, z, s):
+    """Mt[n,m] = sum u |w|^(n-m) conj(w)^m, w = (y - z)/s."""
+    w = ((pts[:, 0] - z[0]) + 1j * (pts[:, 1] - z[1])) / s
+    out = []
+    for n, m, ri in layout(p):
+        v = np.sum(u * np.abs(w) ** (n - m) * np.conj(w) ** m)
+        out.append(v.real if ri == 0 else v.imag)
+    return np.array(out)
+
+
+def local_eval(p, Lt, pts, z, s):
+    """sum Re(Lt[n,m] |w|^(n-m) w^m), w = (x - z)/s."""
+    w = ((pts[:, 0] - z[0]) + 1j * (pts[:, 1] - z[1])) / s
+    phi = np.zeros(len(pts))
+    lay = layout(p)
+    for i, (n, m, ri) in enumerate(lay):
+        mono = np.abs(w) ** (n - m) * w ** m
+        phi += Lt[i] * (mono.real if ri == 0 else -mono.imag)
+    return phi

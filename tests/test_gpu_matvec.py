@@ -1,0 +1,130 @@
+"""GPU parity of the fast product against the FP64 oracle (through the C ABI).
+
+Tolerances (relative 2-norm over the compared entries):
+  FP64 expansions: 1e-6   FP32 path: 1e-5      (the targets of the method)
+  a tree with a single leaf is the plain dense product: 1e-13 (FP64) and
+  1e-6 (FP32: one rounding per entry and per partial sum).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def imq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_04194_amd as m
+    from paper_2205_04194_amd import _lib
+    _lib.load()
+    return m
+
+
+def _dev(a):
+    return torch.tensor(a, device="cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+def test_single_leaf_tree_is_the_dense_product(imq):
+    d = W.small(700)
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=1000, p=4)
+    assert tree.info()["nboxes"] == 1
+    ref = oracle.matvec(d["xy"], d["c"], d["u"])
+    u = _dev(d["u"])
+    assert _rel(tree.matvec(u, "fp64").cpu().numpy(), ref) < 1e-13
+    assert _rel(tree.matvec(u, "fp32").cpu().numpy(), ref) < 1e-6
+
+
+@pytest.mark.parametrize("p,tol64", [(8, 1e-5), (10, 1e-6), (12, 2e-7)])
+def test_small_workload_fp64_and_fp32(imq, p, tol64):
+    d = W.small()
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=32, p=p)
+    ref = oracle.matvec(d["xy"], d["c"], d["u"])
+    u = _dev(d["u"])
+    e64 = _rel(tree.matvec(u, "fp64").cpu().numpy(), ref)
+    e32 = _rel(tree.matvec(u, "fp32").cpu().numpy(), ref)
+    assert e64 < tol64
+    assert e32 < max(tol64, 1e-5)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 65, 129, 1000])
+def test_ragged_sizes_and_tiny_sets(imq, n):
+    xy = W.uniform_points(n, W.rng(66, n))
+    u = W.uniform_vector(n, W.rng(66, n + 1))
+    tree = imq.build_tree(_dev(xy), 0.05, leaf=8, p=10)
+    ref = oracle.matvec(xy, 0.05, u)
+    assert _rel(tree.matvec(_dev(u), "fp64").cpu().numpy(), ref) < 1e-6
+
+
+def test_many_rhs_and_fp32_io(imq):
+    d = W.small(3000)
+    U = W.uniform_vector(3000, W.rng(66, 5), nrhs=5)
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=32, p=12)
+    ref = oracle.matvec(d["xy"], d["c"], U)
+    B = tree.matvec(_dev(U), "fp64").cpu().numpy()
+    for r in range(5):
+        assert _rel(B[r], ref[r]) < 1e-6
+    B32 = tree.matvec(_dev(U).float(), "fp32").cpu().numpy().astype(np.float64)
+    assert B32.dtype == np.float64
+    for r in range(5):
+        assert _rel(B32[r], ref[r]) < 1e-5
+
+
+def test_several_sets_in_one_forest(imq):
+    g = W.rng(66, 9)
+    sizes = [500, 1, 1800, 37]
+    cs = [0.1, 0.05, 0.02, 0.2]
+    sets = [W.uniform_points(k, g) * (i + 1) for i, k in enumerate(sizes)]
+    xy = np.concatenate(sets)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    u = W.uniform_vector(len(xy), g)
+    tree = imq.build_tree(_dev(xy), cs, leaf=16, p=12, set_offsets=list(offs))
+    b = tree.matvec(_dev(u), "fp64").cpu().numpy()
+    for s in range(4):
+        a, e = offs[s], offs[s + 1]
+        ref = oracle.matvec(xy[a:e], cs[s], u[a:e])
+        assert _rel(b[a:e], ref) < 1e-6, s
+
+
+def test_clustered_points(imq):
+    xy = W.mixture_points(20000, W.rng("mixture1m", 3), W.rng(66, 11))
+    u = W.uniform_vector(20000, W.rng(66, 12))
+    tree = imq.build_tree(_dev(xy), 0.02, leaf=64, p=12)
+    inf = tree.info()
+    assert inf["m2p_evals"] > 0 and inf["p2l_evals"] > 0      # adaptive W/X lists exercised
+    ref = oracle.matvec(xy, 0.02, u)
+    assert _rel(tree.matvec(_dev(u), "fp64").cpu().numpy(), ref) < 1e-6
+    assert _rel(tree.matvec(_dev(u), "fp32").cpu().numpy(), ref) < 1e-5
+
+
+def test_exact_rows_match_the_oracle(imq):
+    d = W.uniform100k()
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=64, p=12)
+    rows = np.sort(W.rng(66, 13).choice(len(d["xy"]), 300, replace=False))
+    ex = tree.rows_exact(_dev(d["u"]), _dev(rows)).cpu().numpy()
+    ref = oracle.matvec(d["xy"], d["c"], d["u"], xy_targets=d["xy"][rows])
+    assert _rel(ex, ref) < 1e-13
+    b = tree.matvec(_dev(d["u"]), "fp64").cpu().numpy()
+    assert _rel(b[rows], ref) < 1e-6
+    b32 = tree.matvec(_dev(d["u"]), "fp32").cpu().numpy()
+    assert _rel(b32[rows], ref) < 1e-5
+
+
+def test_invalid_arguments_raise(imq):
+    xy = W.uniform_points(10, W.rng(66, 14))
+    with pytest.raises(imq.IMQError):
+        imq.build_tree(_dev(np.concatenate([xy, xy[:1]])), 0.1, leaf=4, p=4)
+    with pytest.raises(imq.IMQError):
+        imq.build_tree(_dev(xy), -1.0, leaf=4, p=4)
+    tree = imq.build_tree(_dev(xy), 0.1, leaf=4, p=4)
+    with pytest.raises(ValueError):
+        tree.matvec(_dev(np.zeros(11)))

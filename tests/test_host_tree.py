@@ -1,0 +1,190 @@
+"""CPU tests of the quadtree and its interaction lists (host logic, no GPU)."""
+import re
+import os
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests import _hostlib as H
+from paper_2205_04194_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = set()
+    for hdr in ("imq.h", "imq_debug.h"):
+        src = open(os.path.join(ROOT, "include", hdr)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(imq_\w+)\s*\(", src))
+    assert "imq_matvec" in names and "imq_build_tree" in names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(_lib.SIGNATURES) <= names
+
+
+def _coverage(h, n):
+    """Count how often each ordered (target, source) point pair is covered."""
+    begin, end = H.get(h, "begin"), H.get(h, "end")
+    cnt = np.zeros((n, n), dtype=np.int32)
+
+    def add(lst, off, b):
+        for k in range(off[b], off[b + 1]):
+            a = lst[k]
+            cnt[begin[b]:end[b], begin[a]:end[a]] += 1
+
+    lists = [(H.get(h, f"{x}_idx"), H.get(h, f"{x}_off")) for x in "uvwx"]
+    for b in range(len(begin)):
+        for idx, off in lists:
+            add(idx, off, b)
+    return cnt
+
+
+@pytest.mark.parametrize("kind,n,leaf", [("uniform", 400, 8), ("uniform", 333, 5),
+                                         ("mixture", 600, 6), ("line", 300, 4)])
+def test_lists_cover_every_pair_exactly_once(kind, n, leaf):
+    g = W.rng(77, n)
+    if kind == "uniform":
+        xy = W.uniform_points(n, g)
+    elif kind == "mixture":
+        xy = W.mixture_points(n, W.rng(77, 1), g)
+    else:
+        t = g.random(n)
+        xy = np.stack([t, 0.3 + 0.01 * t ** 2], axis=1)      # strongly anisotropic
+    h, st = H.host_tree([xy], [0.05], leaf)
+    assert st == 0
+    try:
+        cnt = _coverage(h, n)
+        assert cnt.min() == 1 and cnt.max() == 1
+    finally:
+        H.free(h)
+
+
+def test_lists_of_several_sets_never_cross():
+    g = W.rng(77, 2)
+    sets = [W.uniform_points(k, g) for k in (150, 1, 40, 220)]
+    h, st = H.host_tree(sets, [0.1, 0.2, 0.05, 0.3], 6)
+    assert st == 0
+    try:
+        n = sum(len(s) for s in sets)
+        cnt = _coverage(h, n)
+        offs = np.concatenate([[0], np.cumsum([len(s) for s in sets])])
+        block = np.zeros_like(cnt)
+        for a, b in zip(offs[:-1], offs[1:]):
+            block[a:b, a:b] = 1
+        assert np.array_equal(cnt, block)
+    finally:
+        H.free(h)
+
+
+def test_tree_invariants_morton_order_leaves_and_levels():
+    d = W.small()
+    xy = d["xy"]
+    h, st = H.host_tree([xy], [d["c"]], 32, p=10)
+    assert st == 0
+    try:
+        perm = H.get(h, "perm")
+        assert np.array_equal(np.sort(perm), np.arange(len(xy)))
+        begin, end = H.get(h, "begin"), H.get(h, "end")
+        isleaf, level = H.get(h, "isleaf"), H.get(h, "level")
+        leaves = H.get(h, "leaves")
+        # leaves partition the points and hold at most leaf_max of them
+        owner = np.zeros(len(xy), dtype=int)
+        for b in leaves:
+            owner[begin[b]:end[b]] += 1
+            assert end[b] - begin[b] <= 32
+        assert np.all(owner == 1)
+        # (level, Morton) ordering: levels non-decreasing, children contiguous
+        assert np.all(np.diff(level) >= 0)
+        child0, nchild, parent = H.get(h, "child0"), H.get(h, "nchild"), H.get(h, "parent")
+        for b in range(len(level)):
+            if nchild[b]:
+                kids = range(child0[b], child0[b] + nchild[b])
+                assert all(parent[k] == b for k in kids)
+                assert begin[child0[b]] == begin[b] and end[child0[b] + nchild[b] - 1] == end[b]
+        # leaf-local coordinates lie inside the leaf box
+        xl, yl = H.get(h, "xl"), H.get(h, "yl")
+        for b in leaves:
+            half = 0.5 * 2.0 ** -level[b]
+            assert np.all(np.abs(xl[begin[b]:end[b]]) <= half)
+            assert np.all(np.abs(yl[begin[b]:end[b]]) <= half)
+        # V lists: same level, offsets in [-3,3]^2 but not adjacent
+        ix, iy = H.get(h, "ix"), H.get(h, "iy")
+        voff, vidx, vcls = H.get(h, "v_off"), H.get(h, "v_idx"), H.get(h, "v_cls")
+        for b in range(len(level)):
+            assert voff[b + 1] - voff[b] <= 27
+            for k in range(voff[b], voff[b + 1]):
+                a = vidx[k]
+                dx, dy = ix[b] - ix[a], iy[b] - iy[a]
+                assert level[a] == level[b]
+                assert max(abs(dx), abs(dy)) in (2, 3)
+                assert vcls[k] == (dx + 3) * 7 + (dy + 3)
+    finally:
+        H.free(h)
+
+
+def test_uniform_grid_list_counts_match_the_paper():
+    """On a full uniform partition the interior counts are those of Sec. 2.3:
+    at most 27 well-separated blocks per block and 9 near blocks."""
+    m = 32
+    g = (np.arange(m) + 0.5) / m
+    xy = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    h, st = H.host_tree([xy], [0.1], 1)
+    assert st == 0
+    try:
+        level, leaves = H.get(h, "level"), H.get(h, "leaves")
+        uoff = H.get(h, "u_off")
+        voff = H.get(h, "v_off")
+        ix, iy = H.get(h, "ix"), H.get(h, "iy")
+        assert len(leaves) == m * m and np.all(level[leaves] == 5)
+        nu = np.array([uoff[b + 1] - uoff[b] for b in leaves])
+        nv = np.array([voff[b + 1] - voff[b] for b in leaves])
+        interior = [(ix[b] >= 2) & (ix[b] < m - 2) & (iy[b] >= 2) & (iy[b] < m - 2) for b in leaves]
+        assert np.all(nu <= 9) and np.all(nu[np.array(interior)] == 9)
+        assert np.all(nv <= 27) and np.all(nv[np.array(interior)] == 27)
+        assert H.get(h, "w_idx").size == 0 and H.get(h, "x_idx").size == 0
+    finally:
+        H.free(h)
+
+
+def test_duplicates_and_bad_arguments_are_rejected():
+    xy = W.uniform_points(50, W.rng(77, 3))
+    dup = np.concatenate([xy, xy[7:8]], axis=0)
+    h, st = H.host_tree([dup], [0.1], 8)
+    assert h is None and st == -2
+    h, st = H.host_tree([xy], [0.0], 8)
+    assert h is None and st == -1
+    h, st = H.host_tree([xy], [float("nan")], 8)
+    assert h is None and st == -1
+    bad = xy.copy()
+    bad[3, 1] = float("inf")
+    h, st = H.host_tree([bad], [0.1], 8)
+    assert h is None and st == -1
+    h, st = H.host_tree([xy], [0.1], 8, p=17)
+    assert h is None and st == -1
+
+
+def test_single_point_and_single_leaf_sets():
+    h, st = H.host_tree([np.array([[0.3, 0.7]])], [0.1], 8)
+    assert st == 0
+    assert list(H.get(h, "leaves")) == [0] and list(H.get(h, "u_idx")) == [0]
+    H.free(h)
+    xy = W.uniform_points(40, W.rng(77, 4))
+    h, st = H.host_tree([xy], [0.1], 64)
+    assert st == 0
+    assert H.get(h, "level").size == 1 and H.get(h, "v_idx").size == 0
+    H.free(h)
+
+
+def test_level_orders_are_clamped_to_p():
+    xy = W.uniform_points(3000, W.rng(77, 5))
+    h, st = H.host_tree([xy], [0.05], 16, p=8, level_order=[0, 0, 12, 6, 4])
+    assert st == 0
+    Klev = H.get(h, "Klev")
+    K = lambda p: (p + 1) * (p + 2) // 2
+    assert Klev[0] == K(8) and Klev[2] == K(8) and Klev[3] == K(6) and Klev[4] == K(4)
+    assert all(k == K(8) for k in Klev[5:])
+    H.free(h)
