@@ -149,13 +149,20 @@ typedef struct {          /* host */
     int64_t m2p_evals;    /* (target point, source box) multipole evaluations */
     int64_t p2l_evals;    /* (source point, target box) local accumulations  */
     int64_t m2m_pairs, l2l_pairs;
+    int nlevels;                            /* levels 0 .. nlevels-1       */
+    int64_t level_boxes[IMQ_MAX_LEVELS + 1];
+    int64_t level_m2l_pairs[IMQ_MAX_LEVELS + 1];
+    int level_K[IMQ_MAX_LEVELS + 1];        /* translation size per level  */
 } imq_tree_info;
 
 imq_status imq_get_tree_info(imq_tree tree, imq_tree_info *info);
 
-/* Per-stage device times of the last imq_matvec on this tree, in ms, when
- * stage timing was switched on with imq_set_stage_timing (host array of
- * IMQ_NSTAGES entries, stage order as in imq_stage_name). */
+/* Per-stage device times of the products run on this tree since stage
+ * timing was (re)started with imq_set_stage_timing(tree, 1): event pairs are
+ * recorded on the product's stream around every stage (no synchronisation
+ * inside the product), and imq_get_stage_times synchronises on them and
+ * returns the mean per stage in ms (host array of IMQ_NSTAGES entries, stage
+ * order as in imq_stage_name).  At most 256 products are recorded. */
 #define IMQ_NSTAGES 9
 imq_status imq_set_stage_timing(imq_tree tree, int on);
 imq_status imq_get_stage_times(imq_tree tree, double *ms);

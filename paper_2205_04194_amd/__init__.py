@@ -152,7 +152,11 @@ class Tree:
         lib = _lib.load()
         inf = _lib.TreeInfo()
         _lib.check(lib.imq_get_tree_info(self._h, ctypes.byref(inf)), "imq_get_tree_info")
-        return {k: getattr(inf, k) for k, _ in _lib.TreeInfo._fields_}
+        out = {}
+        for k, _ in _lib.TreeInfo._fields_:
+            v = getattr(inf, k)
+            out[k] = list(v)[:inf.nlevels] if k.startswith("level_") else v
+        return out
 
     def set_stage_timing(self, on: bool = True) -> None:
         _lib.check(_lib.load().imq_set_stage_timing(self._h, int(on)), "imq_set_stage_timing")

@@ -39,7 +39,11 @@ class TreeInfo(ctypes.Structure):
                 ("depth", ctypes.c_int), ("order_p", ctypes.c_int), ("K", ctypes.c_int),
                 ("p2p_pairs", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("m2p_evals", ctypes.c_int64), ("p2l_evals", ctypes.c_int64),
-                ("m2m_pairs", ctypes.c_int64), ("l2l_pairs", ctypes.c_int64)]
+                ("m2m_pairs", ctypes.c_int64), ("l2l_pairs", ctypes.c_int64),
+                ("nlevels", ctypes.c_int),
+                ("level_boxes", ctypes.c_int64 * (IMQ_MAX_LEVELS + 1)),
+                ("level_m2l_pairs", ctypes.c_int64 * (IMQ_MAX_LEVELS + 1)),
+                ("level_K", ctypes.c_int * (IMQ_MAX_LEVELS + 1))]
 
 
 _lib = None

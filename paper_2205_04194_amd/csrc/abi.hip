@@ -140,6 +140,12 @@ static imq_status check_tree(imq_tree t)
 
 using namespace imq;
 
+hipEvent_t *imq_tree_s::stage_events()
+{
+    if (!timing || ev_used >= TIMING_RING || ev.empty()) return nullptr;
+    return ev.data() + size_t(ev_used++) * (IMQ_NSTAGES + 1);
+}
+
 extern "C" {
 
 const char *imq_last_error(void) { return g_last_error.c_str(); }
@@ -182,10 +188,6 @@ imq_status imq_build_tree(int nsets, const int64_t *set_offsets, const double *x
     if (st != IMQ_OK) { delete t; return st; }
     st = upload_tree(t, xy);
     if (st != IMQ_OK) { free_tree(t); return st; }
-    for (auto &e : t->ev) {
-        hipError_t er = hipEventCreate(&e);
-        if (er != hipSuccess) { set_error("hipEventCreate failed"); free_tree(t); return IMQ_EHIP; }
-    }
     *out = t;
     return IMQ_OK;
 }
@@ -242,20 +244,49 @@ imq_status imq_get_tree_info(imq_tree t, imq_tree_info *info)
     info->p2l_evals = h.p2l_evals;
     info->m2m_pairs = h.m2m_pairs;
     info->l2l_pairs = h.l2l_pairs;
+    info->nlevels = h.nlev;
+    for (int l = 0; l <= IMQ_MAX_LEVELS; ++l) {
+        info->level_boxes[l] = 0;
+        info->level_m2l_pairs[l] = 0;
+        info->level_K[l] = 0;
+    }
+    for (int l = 0; l < h.nlev && l <= IMQ_MAX_LEVELS; ++l) {
+        info->level_K[l] = h.Klev[l];
+        info->level_boxes[l] = h.level_begin[l + 1] - h.level_begin[l];
+        info->level_m2l_pairs[l] = h.v_off[h.level_begin[l + 1]] - h.v_off[h.level_begin[l]];
+    }
     return IMQ_OK;
 }
 
 imq_status imq_set_stage_timing(imq_tree t, int on)
 {
-    if (!t) { set_error("null tree handle"); return IMQ_EINVAL; }
+    imq_status st = check_tree(t);
+    if (st != IMQ_OK) return st;
+    if (on && t->ev.empty()) {
+        t->ev.assign(size_t(imq_tree_s::TIMING_RING) * (IMQ_NSTAGES + 1), nullptr);
+        for (auto &e : t->ev) IMQ_HIP(hipEventCreate(&e));
+    }
     t->timing = on != 0;
+    t->ev_used = 0;
     return IMQ_OK;
 }
 
 imq_status imq_get_stage_times(imq_tree t, double *ms)
 {
-    if (!t || !ms) { set_error("null argument"); return IMQ_EINVAL; }
-    for (int k = 0; k < IMQ_NSTAGES; ++k) ms[k] = t->stage_ms[k];
+    imq_status st = check_tree(t);
+    if (st != IMQ_OK) return st;
+    if (!ms) { set_error("null argument"); return IMQ_EINVAL; }
+    for (int k = 0; k < IMQ_NSTAGES; ++k) ms[k] = 0.0;
+    const int n = t->ev_used;
+    for (int r = 0; r < n; ++r) {
+        hipEvent_t *e = t->ev.data() + size_t(r) * (IMQ_NSTAGES + 1);
+        IMQ_HIP(hipEventSynchronize(e[IMQ_NSTAGES]));
+        for (int k = 0; k < IMQ_NSTAGES; ++k) {
+            float v = 0;
+            IMQ_HIP(hipEventElapsedTime(&v, e[k], e[k + 1]));
+            ms[k] += v / n;
+        }
+    }
     return IMQ_OK;
 }
 

@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <string>
+#include <vector>
 
 namespace imq {
 
@@ -53,10 +54,13 @@ struct imq_tree_s {
     // solver workspace
     imq::DevBuf sol;
     size_t sol_bytes = 0;
-    // stage timing
+    // stage timing: one set of IMQ_NSTAGES+1 events per recorded product,
+    // read back (and summed) only when the caller asks for the times
+    static constexpr int TIMING_RING = 256;
     bool timing = false;
-    hipEvent_t ev[IMQ_NSTAGES + 1] = {};
-    double stage_ms[IMQ_NSTAGES] = {};
+    std::vector<hipEvent_t> ev;          // TIMING_RING * (IMQ_NSTAGES + 1)
+    int ev_used = 0;                     // products recorded since the last reset
+    hipEvent_t *stage_events();          // events of the product being launched, or null
 };
 
 namespace imq {

@@ -456,9 +456,11 @@ static int lds_chunk(int K, size_t elem)
     return chunk;
 }
 
-static inline void mark(imq_tree_s *t, int stage, hipStream_t s)
+static thread_local hipEvent_t *g_cur_events = nullptr;
+
+static inline void mark(imq_tree_s *, int stage, hipStream_t s)
 {
-    if (t->timing) (void)hipEventRecord(t->ev[stage], s);
+    if (g_cur_events) (void)hipEventRecord(g_cur_events[stage], s);
 }
 
 template <typename T>
@@ -542,20 +544,14 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
 {
     imq_status st = ensure_workspace<T>(t, nrhs);
     if (st != IMQ_OK) return st;
+    g_cur_events = t->stage_events();
     mark(t, 0, s);
-    if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) != IMQ_OK) return st;
-    if ((st = fmm_sorted<T>(t, nrhs, s)) != IMQ_OK) return st;
-    if ((st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) != IMQ_OK) return st;
-    mark(t, 9, s);
-    if (t->timing) {
-        IMQ_HIP(hipEventSynchronize(t->ev[9]));
-        for (int k = 0; k < IMQ_NSTAGES; ++k) {
-            float ms = 0;
-            IMQ_HIP(hipEventElapsedTime(&ms, t->ev[k], t->ev[k + 1]));
-            t->stage_ms[k] = ms;
-        }
-    }
-    return IMQ_OK;
+    if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) == IMQ_OK &&
+        (st = fmm_sorted<T>(t, nrhs, s)) == IMQ_OK &&
+        (st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) == IMQ_OK)
+        mark(t, 9, s);
+    g_cur_events = nullptr;
+    return st;
 }
 
 template imq_status matvec_typed<double, double>(imq_tree_s *, int, const double *, int64_t, double *, int64_t, hipStream_t);
