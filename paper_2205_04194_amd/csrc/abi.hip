@@ -100,6 +100,32 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
 
     std::vector<double> m2m, l2l, m2l, wx;
     make_tables(h, m2m, l2l, m2l, wx);
+    // zero-pad every K x K table to KP x KP for the MFMA tiles
+    const int K = h.K, KP = (K + 15) & ~15;
+    t->KP = KP;
+    auto pad = [&](std::vector<double> &v) {
+        const size_t n = v.size() / (size_t(K) * K);
+        std::vector<double> o(n * size_t(KP) * KP, 0.0);
+        for (size_t tb = 0; tb < n; ++tb)
+            for (int r = 0; r < K; ++r)
+                std::copy(v.begin() + (tb * K + r) * K, v.begin() + (tb * K + r + 1) * K,
+                          o.begin() + (tb * KP + r) * KP);
+        v.swap(o);
+    };
+    pad(m2m);
+    pad(l2l);
+    pad(m2l);
+    for (auto pr : {std::make_pair(&h.m2m, &t->g_m2m), std::make_pair(&h.m2l, &t->g_m2l),
+                    std::make_pair(&h.l2l, &t->g_l2l)}) {
+        const GemmList &g = *pr.first;
+        DevGemm &d = *pr.second;
+        if ((st = upload(d.tasks, g.tasks)) != IMQ_OK) return st;
+        if ((st = upload(d.tbox, g.tbox)) != IMQ_OK) return st;
+        if ((st = upload(d.tab, g.tab)) != IMQ_OK) return st;
+        if ((st = upload(d.src, g.src)) != IMQ_OK) return st;
+        d.level_task_begin = g.level_task_begin;
+        d.ntasks = int(g.tasks.size());
+    }
     if ((st = upload(t->f64.m2m, m2m)) != IMQ_OK) return st;
     if ((st = upload(t->f64.l2l, l2l)) != IMQ_OK) return st;
     if ((st = upload(t->f64.m2l, m2l)) != IMQ_OK) return st;
@@ -118,6 +144,9 @@ static void free_tree(imq_tree_s *t)
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
                       &t->cn, &t->leaves, &t->xy_user, &t->set_off, &t->bs, &t->sol};
     for (DevBuf *b : bufs) dev_free(*b);
+    for (DevGemm *g : {&t->g_m2m, &t->g_m2l, &t->g_l2l}) {
+        dev_free(g->tasks); dev_free(g->tbox); dev_free(g->tab); dev_free(g->src);
+    }
     for (PrecData *pd : {&t->f64, &t->f32}) {
         DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->m2m, &pd->l2l, &pd->m2l, &pd->wx, &pd->us, &pd->M, &pd->L};
         for (DevBuf *b : pb) dev_free(*b);

@@ -34,9 +34,16 @@ struct DTree {
 };
 
 struct PrecData {              // everything that exists once per arithmetic type
-    DevBuf xl, yl, m2m, l2l, m2l, wx;
+    DevBuf xl, yl, wx;
+    DevBuf m2m, l2l, m2l;      // translation tables, zero-padded to KP x KP each
     DevBuf us, M, L;           // workspace
     size_t ws_nrhs = 0;
+};
+
+struct DevGemm {               // device copy of a GemmList
+    DevBuf tasks, tbox, tab, src;
+    std::vector<int32_t> level_task_begin;
+    int ntasks = 0;
 };
 
 }  // namespace imq
@@ -49,6 +56,8 @@ struct imq_tree_s {
     imq::DevBuf u_off, u_idx, v_off, v_idx, v_cls, w_off, w_idx, x_off, x_idx, Klev, cn, leaves;
     imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
     imq::PrecData f64, f32;
+    imq::DevGemm g_m2m, g_m2l, g_l2l;
+    int KP = 0;                            // K rounded up to the MFMA tile (16)
     imq::DevBuf bs;                        // FP64 result accumulator, sorted order
     size_t bs_nrhs = 0;
     // solver workspace

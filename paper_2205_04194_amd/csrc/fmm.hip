@@ -132,53 +132,6 @@ __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restric
     }
 }
 
-// M2M: parent = sum over children of T_pos(child) * child, for the boxes
-// [b0, b1) of one level.
-template <typename T>
-__global__ void k_m2m(DTree<T> t, int b0, int b1, const T *__restrict__ Tm, int nrhs, T *__restrict__ M)
-{
-    const int b = b0 + blockIdx.x;
-    if (b >= b1) return;
-    const int nc = t.nchild[b];
-    if (nc == 0) return;
-    const int K = t.K, c0 = t.child0[b];
-    for (int r = 0; r < nrhs; ++r)
-        for (int k = threadIdx.x; k < K; k += blockDim.x) {
-            T acc = T(0);
-            for (int c = 0; c < nc; ++c) {
-                const int ch = c0 + c;
-                const T *Tp = Tm + (size_t(t.pos[ch]) * K + k) * K;
-                const T *Mc = M + (size_t(ch) * nrhs + r) * K;
-                for (int j = 0; j < K; ++j) acc += Tp[j] * Mc[j];
-            }
-            M[(size_t(b) * nrhs + r) * K + k] = acc;
-        }
-}
-
-// M2L: L[b] = sum_{s in V(b)} T_{set,level,class} M[s], truncated to the
-// level's order; writes every box (zeros where V(b) is empty).
-template <typename T>
-__global__ void k_m2l(DTree<T> t, const T *__restrict__ Tl, int nrhs, const T *__restrict__ M,
-                      T *__restrict__ L)
-{
-    const int b = blockIdx.x;
-    const int K = t.K, lev = t.level[b];
-    const int Kl = t.Klev[lev];
-    const T *base = Tl + size_t(t.set[b] * t.nlev + lev) * NCLASS * K * K;
-    const int v0 = t.v_off[b], v1 = t.v_off[b + 1];
-    for (int r = 0; r < nrhs; ++r)
-        for (int k = threadIdx.x; k < K; k += blockDim.x) {
-            T acc = T(0);
-            if (k < Kl)
-                for (int v = v0; v < v1; ++v) {
-                    const T *Tp = base + (size_t(t.v_cls[v]) * K + k) * K;
-                    const T *Ms = M + (size_t(t.v_idx[v]) * nrhs + r) * K;
-                    for (int j = 0; j < Kl; ++j) acc += Tp[j] * Ms[j];
-                }
-            L[(size_t(b) * nrhs + r) * K + k] = acc;
-        }
-}
-
 // P2L: points of the X-list leaves of b accumulated into b's local
 // expansion: Lt += (1/s) eps_k c_{jk} u conj(I_j^k((y - z_b)/s)).
 template <typename T>
@@ -232,23 +185,122 @@ __global__ __launch_bounds__(64) void k_p2l(DTree<T> t, const T *__restrict__ us
     }
 }
 
-// L2L: child += T_pos(child) * parent for the boxes [b0, b1) of one level.
+// ------------------------------------------------------------------ MFMA translations
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// 16x16x4 matrix-core step: lane l supplies A[l%16][l/16] and B[l/16][l%16]
+// and holds D[4(l/16)+v][l%16], v = 0..3.
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    using acc_t = f32x4;
+    static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    using acc_t = f64x4;
+    static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int GEMM_MAXRB = 10;        // row blocks of 16: KP <= 160 (p <= 16)
+
+// One task = one workgroup of 4 waves: out[:, col] (+)= sum_s T_s in[:, src(col, s)]
+// for the 64 columns (target box, rhs) of blockIdx.y.  Wave w owns columns
+// [16w, 16w+16) and every row block; the source columns are staged in LDS in
+// chunks of KC coefficients, the table rows are read from L2.
 template <typename T>
-__global__ void k_l2l(DTree<T> t, int b0, int b1, const T *__restrict__ Tm, int nrhs, T *__restrict__ L)
+__global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__ tasks, int task0,
+                                                    const int32_t *__restrict__ tbox,
+                                                    const int32_t *__restrict__ tab,
+                                                    const int32_t *__restrict__ src,
+                                                    const T *__restrict__ tables, int KP, int K, int nrhs,
+                                                    const T *__restrict__ in, T *__restrict__ out,
+                                                    int accumulate)
 {
-    const int b = b0 + blockIdx.x;
-    if (b >= b1) return;
-    const int par = t.parent[b];
-    const int K = t.K;
-    const int Kc = t.Klev[t.level[b]], Kp = t.Klev[t.level[par]];
-    for (int r = 0; r < nrhs; ++r)
-        for (int k = threadIdx.x; k < Kc; k += blockDim.x) {
-            const T *Tp = Tm + (size_t(t.pos[b]) * K + k) * K;
-            const T *Lp = L + (size_t(par) * nrhs + r) * K;
-            T acc = T(0);
-            for (int j = 0; j < Kp; ++j) acc += Tp[j] * Lp[j];
-            L[(size_t(b) * nrhs + r) * K + k] += acc;
+    constexpr int KC = sizeof(T) == 4 ? 96 : 48;
+    constexpr int LDB = KC + 1;
+    __shared__ T Bs[GEMM_TILE * LDB];
+    __shared__ int s_col[GEMM_TILE];
+    using acc_t = typename Mfma<T>::acc_t;
+    const GemmTask tk = tasks[task0 + blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int ncols = tk.nbox * nrhs;
+    const int col0 = blockIdx.y * GEMM_TILE;
+    if (col0 >= ncols) return;
+    const int nrb = (tk.kout + 15) >> 4;
+    const int kin4 = (tk.kin + 3) & ~3;
+    acc_t acc[GEMM_MAXRB];
+#pragma unroll
+    for (int i = 0; i < GEMM_MAXRB; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][v] = T(0);
+
+    for (int s = 0; s < tk.nslot; ++s) {
+        __syncthreads();
+        int has = 0;
+        if (tid < GEMM_TILE) {
+            const int gc = col0 + tid;
+            int ci = -1;
+            if (gc < ncols) {
+                const int bl = gc / nrhs, r = gc - bl * nrhs;
+                const int sb = src[tk.src0 + bl * tk.nslot + s];
+                if (sb >= 0) ci = sb * nrhs + r;
+            }
+            s_col[tid] = ci;
+            has = ci >= 0;
         }
+        if (!__syncthreads_or(has)) continue;
+        const T *A = tables + size_t(tab[tk.tab0 + s]) * KP * KP;
+        for (int kc0 = 0; kc0 < kin4; kc0 += KC) {
+            const int kcn = min(KC, kin4 - kc0);
+            for (int e = tid; e < GEMM_TILE * kcn; e += 256) {
+                const int c = e / kcn, k = e - c * kcn;
+                const int ci = s_col[c];
+                const int kk = kc0 + k;
+                Bs[c * LDB + k] = (ci >= 0 && kk < tk.kin) ? in[size_t(ci) * K + kk] : T(0);
+            }
+            __syncthreads();
+            const T *Bw = Bs + (wave * 16 + r16) * LDB;
+            const T *Ar = A + size_t(r16) * KP + kc0 + q;
+            for (int k0 = 0; k0 < kcn; k0 += 4) {
+                const T b = Bw[k0 + q];
+#pragma unroll
+                for (int rb = 0; rb < GEMM_MAXRB; ++rb)
+                    if (rb < nrb) acc[rb] = Mfma<T>::mac(Ar[size_t(rb) * 16 * KP + k0], b, acc[rb]);
+            }
+            __syncthreads();
+        }
+    }
+    const int gc = col0 + wave * 16 + r16;
+    if (gc < ncols) {
+        const int bl = gc / nrhs, r = gc - bl * nrhs;
+        T *o = out + (size_t(tbox[tk.box0 + bl]) * nrhs + r) * K;
+#pragma unroll
+        for (int rb = 0; rb < GEMM_MAXRB; ++rb)
+            if (rb < nrb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rb * 16 + q * 4 + v;
+                    if (row < tk.kout) {
+                        if (accumulate) o[row] += acc[rb][v];
+                        else o[row] = acc[rb][v];
+                    }
+                }
+    }
+}
+
+template <typename T>
+__global__ void k_fill(size_t n, T *__restrict__ p, T v)
+{
+    const size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // L2P: potential = sum Re(Lt[n,m] |w|^(n-m) w^m) at each point of a leaf.
@@ -483,20 +535,29 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     hipLaunchKernelGGL(k_p2m<T>, dim3(nleaves), dim3(64), lds, s, v, leaves, us, nrhs, M, chunk);
     IMQ_HIP(hipGetLastError());
     mark(t, 2, s);
-    for (int l = h.nlev - 2; l >= 0; --l) {
-        const int b0 = h.level_begin[l], b1 = h.level_begin[l + 1];
-        hipLaunchKernelGGL(k_m2m<T>, dim3(b1 - b0), dim3(64), 0, s, v, b0, b1, pd.m2m.as<T>(), nrhs, M);
-    }
+    const int KP = t->KP;
+    auto gemm = [&](const DevGemm &g, int t0, int t1, const T *tables, const T *in, T *out, int acc) {
+        if (t1 <= t0) return;
+        hipLaunchKernelGGL(k_gemm_tasks<T>, dim3(t1 - t0, nrhs), dim3(256), 0, s,
+                           g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
+                           g.src.as<int32_t>(), tables, KP, K, nrhs, in, out, acc);
+    };
+    for (int l = h.nlev - 2; l >= 0; --l)
+        gemm(t->g_m2m, t->g_m2m.level_task_begin[l], t->g_m2m.level_task_begin[l + 1], pd.m2m.as<T>(),
+             M, M, 0);
     IMQ_HIP(hipGetLastError());
     mark(t, 3, s);
-    hipLaunchKernelGGL(k_m2l<T>, dim3(nbox), dim3(64), 0, s, v, pd.m2l.as<T>(), nrhs, M, L);
+    {
+        const size_t nL = size_t(nbox) * nrhs * K;
+        hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, L, T(0));
+    }
+    gemm(t->g_m2l, 0, t->g_m2l.ntasks, pd.m2l.as<T>(), M, L, 0);
     IMQ_HIP(hipGetLastError());
     mark(t, 4, s);
     hipLaunchKernelGGL(k_p2l<T>, dim3(nbox), dim3(64), lds, s, v, us, nrhs, pd.wx.as<T>(), L, chunk);
-    for (int l = 0; l + 1 < h.nlev; ++l) {
-        const int b0 = h.level_begin[l + 1], b1 = h.level_begin[l + 2];
-        hipLaunchKernelGGL(k_l2l<T>, dim3(b1 - b0), dim3(64), 0, s, v, b0, b1, pd.l2l.as<T>(), nrhs, L);
-    }
+    for (int l = 1; l < h.nlev; ++l)
+        gemm(t->g_l2l, t->g_l2l.level_task_begin[l], t->g_l2l.level_task_begin[l + 1], pd.l2l.as<T>(),
+             L, L, 1);
     IMQ_HIP(hipGetLastError());
     mark(t, 5, s);
     hipLaunchKernelGGL(k_l2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, L, nrhs, bs);

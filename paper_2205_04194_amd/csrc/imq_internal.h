@@ -58,6 +58,32 @@ void make_wx_consts(int p, double *w);
 double legendre_at_zero(int n, int m);     // P_n^m(0), Condon-Shortley sign
 
 // ------------------------------------------------------------------ tree
+
+// A batch of the dense translations y[:, t] (+)= sum_s T_s x[:, src(t, s)]
+// for up to GEMM_TILE target boxes t that share every slot's table T_s
+// (same set, level and child position).  Columns are (box, right-hand side)
+// pairs; one task is one workgroup's tile.
+constexpr int GEMM_TILE = 64;
+struct GemmTask {
+    int32_t box0;     // first target in GemmList::tbox
+    int32_t nbox;     // targets in this task (<= GEMM_TILE)
+    int32_t nslot;    // source slots per target
+    int32_t kin;      // coefficients read from each source
+    int32_t kout;     // coefficients written to each target
+    int32_t tab0;     // first table index in GemmList::tab (nslot entries)
+    int32_t src0;     // first source in GemmList::src (nbox * nslot entries, -1 = none)
+    int32_t level;    // level of the targets
+};
+
+struct GemmList {
+    std::vector<GemmTask> tasks;
+    std::vector<int32_t> tbox, tab, src;
+    std::vector<int32_t> level_task_begin;   // tasks of level l: [begin[l], begin[l+1])
+};
+
+struct HostTree;
+void build_gemm_lists(HostTree &t);
+
 struct HostTree {
     int nsets = 0;
     int64_t N = 0;
@@ -83,6 +109,11 @@ struct HostTree {
     std::vector<int32_t> v_off, v_idx, v_cls; // same-level translations
     std::vector<int32_t> w_off, w_idx;       // multipole -> target points (leaves)
     std::vector<int32_t> x_off, x_idx;       // source points -> local
+
+    // translation batches: multipole shift (targets = parents), expansion-to-
+    // local translation (targets = boxes with a V list), local shift
+    // (targets = children).  M2L tables are indexed (set*nlev + level)*NCLASS + class.
+    GemmList m2m, m2l, l2l;
 
     int64_t p2p_pairs = 0, m2l_pairs = 0, m2p_evals = 0, p2l_evals = 0;
     int64_t m2m_pairs = 0, l2l_pairs = 0;

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <numeric>
 
 namespace imq {
@@ -285,6 +286,8 @@ imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const
     flatten(W, t.w_off, t.w_idx);
     flatten(X, t.x_off, t.x_idx);
 
+    build_gemm_lists(t);
+
     auto npts = [&](int b) { return int64_t(t.end[b] - t.begin[b]); };
     for (int b = 0; b < nbox; ++b) {
         for (int u : U[b]) t.p2p_pairs += npts(b) * npts(u);
@@ -294,6 +297,109 @@ imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const
         if (t.parent[b] >= 0) { t.m2m_pairs++; t.l2l_pairs++; }
     }
     return IMQ_OK;
+}
+
+// ---- translation batches
+//
+// For a box at child position (px, py) of its parent, the sources of its V
+// list lie at offsets (dx, dy) with dx in [px-3, px+2], dy in [py-3, py+2]
+// and max(|dx|, |dy|) >= 2: 27 classes, fixed per position.  Grouping the
+// targets of a (set, level, position) makes every slot's table uniform
+// across a task.
+static void v_classes(int pos, std::vector<int> &cls)
+{
+    cls.clear();
+    const int px = pos & 1, py = (pos >> 1) & 1;
+    for (int dx = px - 3; dx <= px + 2; ++dx)
+        for (int dy = py - 3; dy <= py + 2; ++dy)
+            if (std::max(std::abs(dx), std::abs(dy)) >= 2) cls.push_back(class_of(dx, dy));
+}
+
+static void add_tasks(GemmList &g, const std::vector<int32_t> &boxes, int nslot, int kin, int kout,
+                      int level, const std::vector<int32_t> &tabs,
+                      const std::function<int32_t(int32_t, int)> &source)
+{
+    for (size_t b0 = 0; b0 < boxes.size(); b0 += GEMM_TILE) {
+        GemmTask k;
+        k.box0 = int32_t(g.tbox.size());
+        k.nbox = int32_t(std::min<size_t>(GEMM_TILE, boxes.size() - b0));
+        k.nslot = nslot;
+        k.kin = kin;
+        k.kout = kout;
+        k.tab0 = int32_t(g.tab.size());
+        k.src0 = int32_t(g.src.size());
+        k.level = level;
+        g.tab.insert(g.tab.end(), tabs.begin(), tabs.end());
+        for (int i = 0; i < k.nbox; ++i) {
+            const int32_t b = boxes[b0 + i];
+            g.tbox.push_back(b);
+            for (int s = 0; s < nslot; ++s) g.src.push_back(source(b, s));
+        }
+        g.tasks.push_back(k);
+    }
+}
+
+void build_gemm_lists(HostTree &t)
+{
+    const int nbox = int(t.level.size());
+    const int L = t.nlev;
+    t.m2m = GemmList();
+    t.m2l = GemmList();
+    t.l2l = GemmList();
+    // child of box b at position s, or -1
+    auto child_at = [&](int32_t b, int s) -> int32_t {
+        for (int c = t.child0[b]; c >= 0 && c < t.child0[b] + t.nchild[b]; ++c)
+            if (t.pos[c] == s) return c;
+        return -1;
+    };
+    // multipole shift: parents level by level, slots = child positions
+    t.m2m.level_task_begin.assign(L + 1, 0);
+    for (int l = 0; l < L; ++l) {
+        t.m2m.level_task_begin[l] = int32_t(t.m2m.tasks.size());
+        std::vector<int32_t> parents;
+        for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
+            if (t.nchild[b] > 0) parents.push_back(b);
+        add_tasks(t.m2m, parents, 4, t.K, t.K, l, {0, 1, 2, 3}, child_at);
+    }
+    t.m2m.level_task_begin[L] = int32_t(t.m2m.tasks.size());
+    // local shift: children grouped by position, one slot (the parent)
+    t.l2l.level_task_begin.assign(L + 1, 0);
+    for (int l = 0; l < L; ++l) {
+        t.l2l.level_task_begin[l] = int32_t(t.l2l.tasks.size());
+        if (l == 0) continue;
+        for (int pos = 0; pos < 4; ++pos) {
+            std::vector<int32_t> kids;
+            for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
+                if (t.pos[b] == pos) kids.push_back(b);
+            add_tasks(t.l2l, kids, 1, t.Klev[l - 1], t.Klev[l], l, {pos},
+                      [&](int32_t b, int) { return t.parent[b]; });
+        }
+    }
+    t.l2l.level_task_begin[L] = int32_t(t.l2l.tasks.size());
+    // expansion-to-local: (set, level, position) groups, 27 slots
+    std::vector<int> cls;
+    t.m2l.level_task_begin.assign(L + 1, 0);
+    for (int l = 0; l < L; ++l) {
+        t.m2l.level_task_begin[l] = int32_t(t.m2l.tasks.size());
+        for (int s = 0; s < t.nsets; ++s)
+            for (int pos = 0; pos < 4; ++pos) {
+                std::vector<int32_t> tgt;
+                for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
+                    if (t.set[b] == s && t.pos[b] == pos && t.v_off[b + 1] > t.v_off[b]) tgt.push_back(b);
+                if (tgt.empty()) continue;
+                v_classes(pos, cls);
+                std::vector<int32_t> tabs;
+                for (int c : cls) tabs.push_back((s * L + l) * NCLASS + c);
+                add_tasks(t.m2l, tgt, int(cls.size()), t.Klev[l], t.Klev[l], l, tabs,
+                          [&](int32_t b, int slot) -> int32_t {
+                              for (int v = t.v_off[b]; v < t.v_off[b + 1]; ++v)
+                                  if (t.v_cls[v] == cls[slot]) return t.v_idx[v];
+                              return -1;
+                          });
+            }
+    }
+    t.m2l.level_task_begin[L] = int32_t(t.m2l.tasks.size());
+    (void)nbox;
 }
 
 }  // namespace imq
