@@ -190,8 +190,9 @@ __global__ __launch_bounds__(64) void k_p2l(DTree<T> t, const T *__restrict__ us
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// 16x16x4 matrix-core step: lane l supplies A[l%16][l/16] and B[l/16][l%16]
-// and holds D[4(l/16)+v][l%16], v = 0..3.
+// 16x16x4 matrix-core step: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// item v of lane l holds D[row(l/16, v)][l%16], where the FP32 form keeps four
+// consecutive rows per lane group and the FP64 form interleaves them.
 template <typename T> struct Mfma;
 template <> struct Mfma<float> {
     using acc_t = f32x4;
@@ -199,6 +200,7 @@ template <> struct Mfma<float> {
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
 };
 template <> struct Mfma<double> {
     using acc_t = f64x4;
@@ -206,6 +208,7 @@ template <> struct Mfma<double> {
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int q, int v) { return 4 * v + q; }
 };
 
 constexpr int GEMM_MAXRB = 10;        // row blocks of 16: KP <= 160 (p <= 16)
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
             if (rb < nrb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int row = rb * 16 + q * 4 + v;
+                    const int row = rb * 16 + Mfma<T>::row(q, v);
                     if (row < tk.kout) {
                         if (accumulate) o[row] += acc[rb][v];
                         else o[row] = acc[rb][v];
