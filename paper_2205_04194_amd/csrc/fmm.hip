@@ -212,11 +212,22 @@ template <> struct Mfma<double> {
 };
 
 constexpr int GEMM_MAXRB = 10;        // row blocks of 16: KP <= 160 (p <= 16)
+constexpr int GEMM_MAXSLOT = 27;
 
 // One task = one workgroup of 4 waves: out[:, col] (+)= sum_s T_s in[:, src(col, s)]
 // for the 64 columns (target box, rhs) of blockIdx.y.  Wave w owns columns
-// [16w, 16w+16) and every row block; the source columns are staged in LDS in
-// chunks of KC coefficients, the table rows are read from L2.
+// [16w, 16w+16) and every row block.  The contraction runs over a sequence of
+// (slot, k-chunk) steps; each step's table chunk (rows x KC) and source
+// chunk (KC x 64 columns) are staged in LDS, and the next step's are loaded
+// into registers while the matrix cores work on the current one.
+template <typename T>
+struct GemmStage {
+    static constexpr int KC = sizeof(T) == 4 ? 32 : 16;            // k per step
+    static constexpr int LD = KC + (sizeof(T) == 4 ? 1 : 2);       // LDS row stride
+    static constexpr int NA = GEMM_MAXRB * 16 * KC / 256;          // table elems / thread
+    static constexpr int NB = GEMM_TILE * KC / 256;                // source elems / thread
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__ tasks, int task0,
                                                     const int32_t *__restrict__ tbox,
@@ -226,10 +237,13 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
                                                     const T *__restrict__ in, T *__restrict__ out,
                                                     int accumulate)
 {
-    constexpr int KC = sizeof(T) == 4 ? 96 : 48;
-    constexpr int LDB = KC + 1;
-    __shared__ T Bs[GEMM_TILE * LDB];
-    __shared__ int s_col[GEMM_TILE];
+    using S = GemmStage<T>;
+    constexpr int KC = S::KC, LD = S::LD;
+    __shared__ T As[GEMM_MAXRB * 16 * LD];
+    __shared__ T Bs[GEMM_TILE * LD];
+    __shared__ int s_col[GEMM_MAXSLOT][GEMM_TILE];
+    __shared__ int s_step[GEMM_MAXSLOT];
+    __shared__ int s_nstep;
     using acc_t = typename Mfma<T>::acc_t;
     const GemmTask tk = tasks[task0 + blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -239,48 +253,89 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     if (col0 >= ncols) return;
     const int nrb = (tk.kout + 15) >> 4;
     const int kin4 = (tk.kin + 3) & ~3;
+    const int nkc = (kin4 + KC - 1) / KC;
+    const int arows = nrb * 16;
+
+    // source column of every (slot, column); slots without any source are skipped
+    for (int e = tid; e < tk.nslot * GEMM_TILE; e += 256) {
+        const int sl = e / GEMM_TILE, c = e - sl * GEMM_TILE;
+        const int gc = col0 + c;
+        int ci = -1;
+        if (gc < ncols) {
+            const int bl = gc / nrhs, r = gc - bl * nrhs;
+            const int sb = src[tk.src0 + bl * tk.nslot + sl];
+            if (sb >= 0) ci = sb * nrhs + r;
+        }
+        s_col[sl][c] = ci;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int n = 0;
+        for (int sl = 0; sl < tk.nslot; ++sl) {
+            bool any = false;
+            for (int c = 0; c < GEMM_TILE && !any; ++c) any = s_col[sl][c] >= 0;
+            if (any) s_step[n++] = sl;
+        }
+        s_nstep = n;
+    }
+    __syncthreads();
+    const int nstep = s_nstep * nkc;
+
+    T ra[S::NA], rb_[S::NB];
+    auto fetch = [&](int step) {
+        const int sl = s_step[step / nkc];
+        const int kc0 = (step % nkc) * KC;
+        const T *A = tables + size_t(tab[tk.tab0 + sl]) * KP * KP;
+#pragma unroll
+        for (int i = 0; i < S::NA; ++i) {
+            const int e = tid + i * 256;
+            const int r = e / KC, k = e % KC;
+            ra[i] = (r < arows && kc0 + k < kin4) ? A[size_t(r) * KP + kc0 + k] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < S::NB; ++i) {
+            const int e = tid + i * 256;
+            const int c = e / KC, k = e % KC;
+            const int ci = s_col[sl][c];
+            const int kk = kc0 + k;
+            rb_[i] = (ci >= 0 && kk < tk.kin) ? in[size_t(ci) * K + kk] : T(0);
+        }
+    };
+
     acc_t acc[GEMM_MAXRB];
 #pragma unroll
     for (int i = 0; i < GEMM_MAXRB; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[i][v] = T(0);
 
-    for (int s = 0; s < tk.nslot; ++s) {
+    if (nstep > 0) fetch(0);
+    for (int step = 0; step < nstep; ++step) {
         __syncthreads();
-        int has = 0;
-        if (tid < GEMM_TILE) {
-            const int gc = col0 + tid;
-            int ci = -1;
-            if (gc < ncols) {
-                const int bl = gc / nrhs, r = gc - bl * nrhs;
-                const int sb = src[tk.src0 + bl * tk.nslot + s];
-                if (sb >= 0) ci = sb * nrhs + r;
-            }
-            s_col[tid] = ci;
-            has = ci >= 0;
-        }
-        if (!__syncthreads_or(has)) continue;
-        const T *A = tables + size_t(tab[tk.tab0 + s]) * KP * KP;
-        for (int kc0 = 0; kc0 < kin4; kc0 += KC) {
-            const int kcn = min(KC, kin4 - kc0);
-            for (int e = tid; e < GEMM_TILE * kcn; e += 256) {
-                const int c = e / kcn, k = e - c * kcn;
-                const int ci = s_col[c];
-                const int kk = kc0 + k;
-                Bs[c * LDB + k] = (ci >= 0 && kk < tk.kin) ? in[size_t(ci) * K + kk] : T(0);
-            }
-            __syncthreads();
-            const T *Bw = Bs + (wave * 16 + r16) * LDB;
-            const T *Ar = A + size_t(r16) * KP + kc0 + q;
-            for (int k0 = 0; k0 < kcn; k0 += 4) {
-                const T b = Bw[k0 + q];
 #pragma unroll
-                for (int rb = 0; rb < GEMM_MAXRB; ++rb)
-                    if (rb < nrb) acc[rb] = Mfma<T>::mac(Ar[size_t(rb) * 16 * KP + k0], b, acc[rb]);
-            }
-            __syncthreads();
+        for (int i = 0; i < S::NA; ++i) {
+            const int e = tid + i * 256;
+            const int r = e / KC, k = e % KC;
+            if (r < arows) As[r * LD + k] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < S::NB; ++i) {
+            const int e = tid + i * 256;
+            const int c = e / KC, k = e % KC;
+            Bs[c * LD + k] = rb_[i];
+        }
+        __syncthreads();
+        if (step + 1 < nstep) fetch(step + 1);
+        const T *Bw = Bs + (wave * 16 + r16) * LD + q;
+        const T *Aw = As + r16 * LD + q;
+#pragma unroll
+        for (int k0 = 0; k0 < KC; k0 += 4) {
+            const T b = Bw[k0];
+#pragma unroll
+            for (int rb = 0; rb < GEMM_MAXRB; ++rb)
+                if (rb < nrb) acc[rb] = Mfma<T>::mac(Aw[rb * 16 * LD + k0], b, acc[rb]);
         }
     }
+
     const int gc = col0 + wave * 16 + r16;
     if (gc < ncols) {
         const int bl = gc / nrhs, r = gc - bl * nrhs;
@@ -338,32 +393,96 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restric
     }
 }
 
+// Reciprocal square root for the direct sums: the hardware estimate in
+// FP32; in FP64 the estimate refined by two Newton steps
+// y <- y (3 - x y^2) / 2, each roughly doubling the number of correct bits.
+__device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_fast(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+
+constexpr int P2P_CHUNK = 256;                 // sources staged per round
+constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 per lane group
+
 // P2P: b_i += sum over U-list leaves a of sum_j u_j / sqrt(|x_i - x_j|^2 + c^2).
-// Partial sums over one source leaf in T, accumulated across leaves in FP64.
+// One wave per target leaf.  Lane l takes target l % TP (TP = the leaf's
+// point count rounded up to a power of two, at least 4) in lane group
+// l / TP of G = 64 / TP groups.  The U-list sources are staged, relative to
+// the target leaf's centre, in LDS chunks of up to 256 (padded with zero
+// weights to a multiple of 4 G); each group sums a contiguous quarter-aligned
+// run of the chunk, 4 sources per step, and the G partial sums of a target
+// are combined with shuffles.  Partial sums over one chunk are kept in T,
+// the running sum in FP64.
 template <typename T>
 __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restrict__ leaves,
                                             const T *__restrict__ us, int nrhs, double *__restrict__ bs)
 {
+    using V4 = typename Vec4<T>::type;
+    __shared__ V4 sx4[P2P_LDS / 4], sy4[P2P_LDS / 4], su4[P2P_LDS / 4];
+    T *sx = reinterpret_cast<T *>(sx4), *sy = reinterpret_cast<T *>(sy4), *su = reinterpret_cast<T *>(su4);
     const int b = leaves[blockIdx.x];
+    const int lane = threadIdx.x;
     const double cnd = t.cn[t.set[b]];
     const T c2 = T(cnd * cnd);
     const int u0 = t.u_off[b], u1 = t.u_off[b + 1];
-    for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+    for (int t0 = t.begin[b]; t0 < t.end[b]; t0 += 64) {
+        const int ntc = min(64, t.end[b] - t0);
+        int TP = 4;
+        while (TP < ntc) TP <<= 1;
+        const int G = 64 / TP, grp = lane / TP, ti = lane % TP;
+        const bool valid = ti < ntc;
+        const int i = t0 + (valid ? ti : 0);
         const T xi = t.xl[i], yi = t.yl[i];
         for (int r = 0; r < nrhs; ++r) {
             double acc = 0.0;
+            int pos = 0;
+            auto flush = [&]() {
+                const int per = ((pos + G - 1) / G + 3) & ~3;   // sources per group, multiple of 4
+                for (int j = pos + lane; j < per * G; j += 64) {
+                    sx[j] = T(0); sy[j] = T(0); su[j] = T(0);
+                }
+                __syncthreads();
+                T part = T(0);
+                const int q0 = grp * per / 4, q1 = q0 + per / 4;
+                for (int qv = q0; qv < q1; ++qv) {
+                    const V4 X = sx4[qv], Y = sy4[qv], U = su4[qv];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const T dx = xi - X[k], dy = yi - Y[k];
+                        part += U[k] * rsqrt_fast(fma(dx, dx, fma(dy, dy, c2)));
+                    }
+                }
+                acc += double(part);
+                __syncthreads();
+                pos = 0;
+            };
             for (int uu = u0; uu < u1; ++uu) {
                 const int a = t.u_idx[uu];
-                const T px = xi + T(t.cx[b] - t.cx[a]);
-                const T py = yi + T(t.cy[b] - t.cy[a]);
-                T s = T(0);
-                for (int j = t.begin[a]; j < t.end[a]; ++j) {
-                    const T dx = px - t.xl[j], dy = py - t.yl[j];
-                    s += us[r * t.N + j] * rsqrt_t(dx * dx + dy * dy + c2);
+                const T ox = T(t.cx[a] - t.cx[b]), oy = T(t.cy[a] - t.cy[b]);
+                for (int j0 = t.begin[a]; j0 < t.end[a]; j0 += 64) {
+                    const int ns = min(64, t.end[a] - j0);
+                    if (pos + ns > P2P_CHUNK) flush();
+                    if (lane < ns) {
+                        const int j = j0 + lane;
+                        sx[pos + lane] = t.xl[j] + ox;
+                        sy[pos + lane] = t.yl[j] + oy;
+                        su[pos + lane] = us[r * t.N + j];
+                    }
+                    pos += ns;
                 }
-                acc += double(s);
             }
-            bs[r * t.N + i] += acc;
+            if (pos > 0) flush();
+            for (int off = TP; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
+            if (grp == 0 && valid) bs[r * t.N + i] += acc;
         }
     }
 }
