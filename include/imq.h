@@ -70,6 +70,9 @@ typedef struct {
     int order_p;
     int max_level;
     int level_order[IMQ_MAX_LEVELS + 1];
+    int direct_max;      /* adaptive W/X interactions whose finer box holds at
+                            most this many points are summed directly instead
+                            of through an expansion (0 = 2*leaf_max, < 0 = never) */
 } imq_tree_params;
 
 /* Build the quadtree forest of `nsets` independent point sets.

@@ -42,11 +42,13 @@ class Tree:
     leaf        points per leaf before a box is split (leaf_max)
     p           truncation index of the expansions (1..16)
     level_order optional per-level truncation of the translations
+    direct_max  W/X interactions with at most this many points in the finer
+                box are summed directly (0: 2*leaf, negative: never)
     """
 
     def __init__(self, xy: torch.Tensor, c, leaf: int = 64, p: int = 12,
                  set_offsets: Optional[Sequence[int]] = None, level_order=None,
-                 max_level: int = 0, stream=None):
+                 max_level: int = 0, direct_max: int = 0, stream=None):
         lib = _lib.load()
         if xy.dim() != 2 or xy.shape[1] != 2:
             raise ValueError("xy must have shape (N, 2)")
@@ -70,7 +72,7 @@ class Tree:
         self._xy = xy64
         off_arr = (ctypes.c_int64 * (nsets + 1))(*offs)
         c_arr = (ctypes.c_double * nsets)(*cs)
-        prm = _lib.params(leaf, p, max_level, level_order)
+        prm = _lib.params(leaf, p, max_level, level_order, direct_max)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = lib.imq_build_tree(nsets, off_arr, _dptr(soa), c_arr, ctypes.byref(prm),

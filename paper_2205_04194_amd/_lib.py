@@ -21,7 +21,8 @@ PREC = {"fp64": 0, "fp32": 1}
 
 class TreeParams(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int), ("order_p", ctypes.c_int), ("max_level", ctypes.c_int),
-                ("level_order", ctypes.c_int * (IMQ_MAX_LEVELS + 1))]
+                ("level_order", ctypes.c_int * (IMQ_MAX_LEVELS + 1)),
+                ("direct_max", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -104,11 +105,12 @@ def check(status: int, where: str, allow_not_converged: bool = False) -> int:
     raise IMQError(status, where)
 
 
-def params(leaf: int, p: int, max_level: int = 0, level_order=None) -> TreeParams:
+def params(leaf: int, p: int, max_level: int = 0, level_order=None, direct_max: int = 0) -> TreeParams:
     prm = TreeParams()
     prm.leaf_max = int(leaf)
     prm.order_p = int(p)
     prm.max_level = int(max_level)
+    prm.direct_max = int(direct_max)
     for i in range(IMQ_MAX_LEVELS + 1):
         prm.level_order[i] = 0
     if level_order is not None:

@@ -222,7 +222,7 @@ constexpr int GEMM_MAXSLOT = 27;
 // into registers while the matrix cores work on the current one.
 template <typename T>
 struct GemmStage {
-    static constexpr int KC = sizeof(T) == 4 ? 32 : 16;            // k per step
+    static constexpr int KC = sizeof(T) == 4 ? 64 : 32;            // k per step
     static constexpr int LD = KC + (sizeof(T) == 4 ? 1 : 2);       // LDS row stride
     static constexpr int NA = GEMM_MAXRB * 16 * KC / 256;          // table elems / thread
     static constexpr int NB = GEMM_TILE * KC / 256;                // source elems / thread
@@ -242,6 +242,8 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     __shared__ T As[GEMM_MAXRB * 16 * LD];
     __shared__ T Bs[GEMM_TILE * LD];
     __shared__ int s_col[GEMM_MAXSLOT][GEMM_TILE];
+    __shared__ int s_tab[GEMM_MAXSLOT];
+    __shared__ int s_has[GEMM_MAXSLOT];
     __shared__ int s_step[GEMM_MAXSLOT];
     __shared__ int s_nstep;
     using acc_t = typename Mfma<T>::acc_t;
@@ -257,6 +259,11 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     const int arows = nrb * 16;
 
     // source column of every (slot, column); slots without any source are skipped
+    if (tid < tk.nslot) {
+        s_tab[tid] = tab[tk.tab0 + tid];
+        s_has[tid] = 0;
+    }
+    __syncthreads();
     for (int e = tid; e < tk.nslot * GEMM_TILE; e += 256) {
         const int sl = e / GEMM_TILE, c = e - sl * GEMM_TILE;
         const int gc = col0 + c;
@@ -267,15 +274,13 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
             if (sb >= 0) ci = sb * nrhs + r;
         }
         s_col[sl][c] = ci;
+        if (ci >= 0) s_has[sl] = 1;
     }
     __syncthreads();
     if (tid == 0) {
         int n = 0;
-        for (int sl = 0; sl < tk.nslot; ++sl) {
-            bool any = false;
-            for (int c = 0; c < GEMM_TILE && !any; ++c) any = s_col[sl][c] >= 0;
-            if (any) s_step[n++] = sl;
-        }
+        for (int sl = 0; sl < tk.nslot; ++sl)
+            if (s_has[sl]) s_step[n++] = sl;
         s_nstep = n;
     }
     __syncthreads();
@@ -285,7 +290,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     auto fetch = [&](int step) {
         const int sl = s_step[step / nkc];
         const int kc0 = (step % nkc) * KC;
-        const T *A = tables + size_t(tab[tk.tab0 + sl]) * KP * KP;
+        const T *A = tables + size_t(s_tab[sl]) * KP * KP;
 #pragma unroll
         for (int i = 0; i < S::NA; ++i) {
             const int e = tid + i * 256;

@@ -270,6 +270,45 @@ imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const
     for (int b = 0; b < nbox; ++b)
         for (int w : W[b]) X[w].push_back(b);
 
+    // W/X interactions whose finer box is small are cheaper as direct sums:
+    // move them to the near list of every leaf under the target box.
+    const int dmax = prm.direct_max == 0 ? 2 * prm.leaf_max : prm.direct_max;
+    if (dmax > 0) {
+        std::vector<int> under;
+        auto leaves_under = [&](int box) {
+            under.clear();
+            stack.assign(1, box);
+            while (!stack.empty()) {
+                int q = stack.back();
+                stack.pop_back();
+                if (t.isleaf[q]) under.push_back(q);
+                else for (int ch = t.child0[q]; ch < t.child0[q] + t.nchild[q]; ++ch) stack.push_back(ch);
+            }
+        };
+        std::vector<std::vector<int32_t>> Wk(nbox), Xk(nbox);
+        for (int b = 0; b < nbox; ++b) {
+            for (int w : W[b]) {               // targets b (leaf), sources w
+                if (t.end[w] - t.begin[w] <= dmax) {
+                    leaves_under(w);
+                    U[b].insert(U[b].end(), under.begin(), under.end());
+                } else {
+                    Wk[b].push_back(w);
+                }
+            }
+            for (int a : X[b]) {               // targets b, sources a (leaf)
+                if (t.end[b] - t.begin[b] <= dmax) {
+                    leaves_under(b);
+                    for (int l : under) U[l].push_back(a);
+                } else {
+                    Xk[b].push_back(a);
+                }
+            }
+        }
+        W.swap(Wk);
+        X.swap(Xk);
+        for (int b = 0; b < nbox; ++b) std::sort(U[b].begin(), U[b].end());
+    }
+
     auto flatten = [&](const std::vector<std::vector<int32_t>> &L, std::vector<int32_t> &offv,
                        std::vector<int32_t> &idx) {
         offv.assign(nbox + 1, 0);

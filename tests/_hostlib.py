@@ -6,7 +6,7 @@ import numpy as np
 from paper_2205_04194_amd import _lib
 
 
-def host_tree(xy_list, c_list, leaf, p=4, max_level=0, level_order=None):
+def host_tree(xy_list, c_list, leaf, p=4, max_level=0, level_order=None, direct_max=0):
     """Build the host part of a tree; returns (handle, status)."""
     lib = _lib.load()
     xy = np.concatenate(xy_list, axis=0)
@@ -14,7 +14,7 @@ def host_tree(xy_list, c_list, leaf, p=4, max_level=0, level_order=None):
     x = np.ascontiguousarray(xy[:, 0], dtype=np.float64)
     y = np.ascontiguousarray(xy[:, 1], dtype=np.float64)
     c = np.ascontiguousarray(c_list, dtype=np.float64)
-    prm = _lib.params(leaf, p, max_level, level_order)
+    prm = _lib.params(leaf, p, max_level, level_order, direct_max)
     st = ctypes.c_int(0)
     dp = ctypes.POINTER(ctypes.c_double)
     h = lib.imq_debug_host_tree(len(xy_list), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

@@ -95,12 +95,14 @@ def test_several_sets_in_one_forest(imq):
         assert _rel(b[a:e], ref) < 1e-6, s
 
 
-def test_clustered_points(imq):
+@pytest.mark.parametrize("direct_max", [-1, 0])
+def test_clustered_points(imq, direct_max):
     xy = W.mixture_points(20000, W.rng("mixture1m", 3), W.rng(66, 11))
     u = W.uniform_vector(20000, W.rng(66, 12))
-    tree = imq.build_tree(_dev(xy), 0.02, leaf=64, p=12)
+    tree = imq.build_tree(_dev(xy), 0.02, leaf=64, p=12, direct_max=direct_max)
     inf = tree.info()
-    assert inf["m2p_evals"] > 0 and inf["p2l_evals"] > 0      # adaptive W/X lists exercised
+    if direct_max < 0:
+        assert inf["m2p_evals"] > 0 and inf["p2l_evals"] > 0   # W/X through expansions
     ref = oracle.matvec(xy, 0.02, u)
     assert _rel(tree.matvec(_dev(u), "fp64").cpu().numpy(), ref) < 1e-6
     assert _rel(tree.matvec(_dev(u), "fp32").cpu().numpy(), ref) < 1e-5

@@ -43,9 +43,10 @@ def _coverage(h, n):
     return cnt
 
 
+@pytest.mark.parametrize("direct_max", [0, -1, 1000])
 @pytest.mark.parametrize("kind,n,leaf", [("uniform", 400, 8), ("uniform", 333, 5),
                                          ("mixture", 600, 6), ("line", 300, 4)])
-def test_lists_cover_every_pair_exactly_once(kind, n, leaf):
+def test_lists_cover_every_pair_exactly_once(kind, n, leaf, direct_max):
     g = W.rng(77, n)
     if kind == "uniform":
         xy = W.uniform_points(n, g)
@@ -54,11 +55,14 @@ def test_lists_cover_every_pair_exactly_once(kind, n, leaf):
     else:
         t = g.random(n)
         xy = np.stack([t, 0.3 + 0.01 * t ** 2], axis=1)      # strongly anisotropic
-    h, st = H.host_tree([xy], [0.05], leaf)
+    h, st = H.host_tree([xy], [0.05], leaf, direct_max=direct_max)
     assert st == 0
     try:
         cnt = _coverage(h, n)
         assert cnt.min() == 1 and cnt.max() == 1
+        nw, nx = H.get(h, "w_idx").size, H.get(h, "x_idx").size
+        if direct_max > 0 and direct_max >= n:
+            assert nw == 0 and nx == 0          # every W/X interaction summed directly
     finally:
         H.free(h)
 
