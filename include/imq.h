@@ -143,6 +143,19 @@ imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
                                const void *g, void *dv, double *dc, double *dxy,
                                imq_prec prec, hipStream_t stream);
 
+/* Launch shape of the batched translations (the M2L tile shape and that of
+ * the shifts), chosen by the autotuner or by hand; 0 = default.
+ *  *_kc    : coefficients staged per pipeline step (16, 32 or 64 in FP32;
+ *            16 or 32 in FP64)
+ *  *_split : the output rows of one tile are spread over this many
+ *            workgroups (1 .. 10)                                          */
+typedef struct {
+    int m2l_kc, m2l_split;
+    int shift_kc, shift_split;
+} imq_kernel_config;
+
+imq_status imq_set_kernel_config(imq_tree tree, const imq_kernel_config *cfg);
+
 typedef struct {          /* host */
     int64_t npoints, nboxes, nleaves;
     int depth;            /* deepest level present                           */

@@ -35,6 +35,11 @@ class SolveStats(ctypes.Structure):
                 ("relres", ctypes.c_double)]
 
 
+class KernelConfig(ctypes.Structure):
+    _fields_ = [("m2l_kc", ctypes.c_int), ("m2l_split", ctypes.c_int),
+                ("shift_kc", ctypes.c_int), ("shift_split", ctypes.c_int)]
+
+
 class TreeInfo(ctypes.Structure):
     _fields_ = [("npoints", ctypes.c_int64), ("nboxes", ctypes.c_int64), ("nleaves", ctypes.c_int64),
                 ("depth", ctypes.c_int), ("order_p", ctypes.c_int), ("K", ctypes.c_int),
@@ -62,6 +67,7 @@ SIGNATURES = {
     "imq_solve": (_int, [_vp, _int, _vp, _i64, _vp, _i64, _p(SolveOpts), _p(SolveStats), _vp]),
     "imq_matvec_backward": (_int, [_vp, _int, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
     "imq_get_tree_info": (_int, [_vp, _p(TreeInfo)]),
+    "imq_set_kernel_config": (_int, [_vp, _p(KernelConfig)]),
     "imq_set_stage_timing": (_int, [_vp, _int]),
     "imq_get_stage_times": (_int, [_vp, _p(_dbl)]),
     "imq_stage_name": (ctypes.c_char_p, [_int]),

@@ -287,6 +287,19 @@ imq_status imq_get_tree_info(imq_tree t, imq_tree_info *info)
     return IMQ_OK;
 }
 
+imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
+{
+    if (!t || !cfg) { set_error("null argument"); return IMQ_EINVAL; }
+    auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
+    if (!ok_kc(cfg->m2l_kc) || !ok_kc(cfg->shift_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
+        cfg->shift_split < 0 || cfg->shift_split > 10) {
+        set_error("kernel config out of range");
+        return IMQ_EINVAL;
+    }
+    t->kcfg = *cfg;
+    return IMQ_OK;
+}
+
 imq_status imq_set_stage_timing(imq_tree t, int on)
 {
     imq_status st = check_tree(t);

@@ -57,6 +57,7 @@ struct imq_tree_s {
     imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
     imq::PrecData f64, f32;
     imq::DevGemm g_m2m, g_m2l, g_l2l;
+    imq_kernel_config kcfg = {};
     int KP = 0;                            // K rounded up to the MFMA tile (16)
     imq::DevBuf bs;                        // FP64 result accumulator, sorted order
     size_t bs_nrhs = 0;

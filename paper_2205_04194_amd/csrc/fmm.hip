@@ -215,20 +215,21 @@ constexpr int GEMM_MAXRB = 10;        // row blocks of 16: KP <= 160 (p <= 16)
 constexpr int GEMM_MAXSLOT = 27;
 
 // One task = one workgroup of 4 waves: out[:, col] (+)= sum_s T_s in[:, src(col, s)]
-// for the 64 columns (target box, rhs) of blockIdx.y.  Wave w owns columns
-// [16w, 16w+16) and every row block.  The contraction runs over a sequence of
-// (slot, k-chunk) steps; each step's table chunk (rows x KC) and source
-// chunk (KC x 64 columns) are staged in LDS, and the next step's are loaded
-// into registers while the matrix cores work on the current one.
-template <typename T>
+// for the 64 columns (target box, rhs) of blockIdx.y and the row blocks of
+// split blockIdx.z.  Wave w owns columns [16w, 16w+16).  The contraction runs
+// over a sequence of (slot, k-chunk) steps; each step's table chunk
+// (rows x KC) and source chunk (KC x 64 columns) are staged in LDS, and the
+// next step's are loaded into registers while the matrix cores work on the
+// current one.
+template <typename T, int KC_>
 struct GemmStage {
-    static constexpr int KC = sizeof(T) == 4 ? 64 : 32;            // k per step
+    static constexpr int KC = KC_;                                  // k per step
     static constexpr int LD = KC + (sizeof(T) == 4 ? 1 : 2);       // LDS row stride
     static constexpr int NA = GEMM_MAXRB * 16 * KC / 256;          // table elems / thread
     static constexpr int NB = GEMM_TILE * KC / 256;                // source elems / thread
 };
 
-template <typename T>
+template <typename T, int KC_>
 __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__ tasks, int task0,
                                                     const int32_t *__restrict__ tbox,
                                                     const int32_t *__restrict__ tab,
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
                                                     const T *__restrict__ in, T *__restrict__ out,
                                                     int accumulate)
 {
-    using S = GemmStage<T>;
+    using S = GemmStage<T, KC_>;
     constexpr int KC = S::KC, LD = S::LD;
     __shared__ T As[GEMM_MAXRB * 16 * LD];
     __shared__ T Bs[GEMM_TILE * LD];
@@ -253,12 +254,16 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     const int ncols = tk.nbox * nrhs;
     const int col0 = blockIdx.y * GEMM_TILE;
     if (col0 >= ncols) return;
-    const int nrb = (tk.kout + 15) >> 4;
+    const int nrb_all = (tk.kout + 15) >> 4;
+    const int per = (nrb_all + gridDim.z - 1) / gridDim.z;
+    const int rb0 = blockIdx.z * per;
+    const int nrb = min(nrb_all - rb0, per);          // row blocks of this split
+    if (nrb <= 0) return;
     const int kin4 = (tk.kin + 3) & ~3;
     const int nkc = (kin4 + KC - 1) / KC;
     const int arows = nrb * 16;
+    const int row0 = rb0 * 16;
 
-    // source column of every (slot, column); slots without any source are skipped
     if (tid < tk.nslot) {
         s_tab[tid] = tab[tk.tab0 + tid];
         s_has[tid] = 0;
@@ -290,7 +295,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     auto fetch = [&](int step) {
         const int sl = s_step[step / nkc];
         const int kc0 = (step % nkc) * KC;
-        const T *A = tables + size_t(s_tab[sl]) * KP * KP;
+        const T *A = tables + size_t(s_tab[sl]) * KP * KP + size_t(row0) * KP;
 #pragma unroll
         for (int i = 0; i < S::NA; ++i) {
             const int e = tid + i * 256;
@@ -350,12 +355,40 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
             if (rb < nrb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int row = rb * 16 + Mfma<T>::row(q, v);
+                    const int row = row0 + rb * 16 + Mfma<T>::row(q, v);
                     if (row < tk.kout) {
                         if (accumulate) o[row] += acc[rb][v];
                         else o[row] = acc[rb][v];
                     }
                 }
+    }
+}
+
+// Launch one batch of translation tasks with the chunk depth and row split
+// of the tree's kernel configuration.
+template <typename T>
+static void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks,
+                        int t0, const int32_t *tbox, const int32_t *tab, const int32_t *src,
+                        const T *tables, int KP, int K, const T *in, T *out, int acc)
+{
+    const dim3 grid(ntask, nrhs, split);
+    if constexpr (sizeof(T) == 4) {
+        if (kc >= 64)
+            hipLaunchKernelGGL((k_gemm_tasks<T, 64>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
+                               tables, KP, K, nrhs, in, out, acc);
+        else if (kc >= 32)
+            hipLaunchKernelGGL((k_gemm_tasks<T, 32>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
+                               tables, KP, K, nrhs, in, out, acc);
+        else
+            hipLaunchKernelGGL((k_gemm_tasks<T, 16>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
+                               tables, KP, K, nrhs, in, out, acc);
+    } else {
+        if (kc >= 32)
+            hipLaunchKernelGGL((k_gemm_tasks<T, 32>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
+                               tables, KP, K, nrhs, in, out, acc);
+        else
+            hipLaunchKernelGGL((k_gemm_tasks<T, 16>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
+                               tables, KP, K, nrhs, in, out, acc);
     }
 }
 
@@ -494,37 +527,44 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
 
 // M2P: multipoles of the W-list boxes evaluated at the leaf's points:
 // potential = (1/s_a) sum Re(Mt[n,m] eps_m c_{nm} I_n^m((x - z_a)/s_a)).
+// One wave per target leaf; each W box's multipole, premultiplied by the
+// constants, is staged in LDS and read back as a broadcast.
 template <typename T>
 __global__ __launch_bounds__(64) void k_m2p(DTree<T> t, const int32_t *__restrict__ leaves,
                                             const T *__restrict__ M, const T *__restrict__ wx, int nrhs,
                                             double *__restrict__ bs)
 {
+    __shared__ T mw[KMAX + 1];
     const int b = leaves[blockIdx.x];
     const int w0 = t.w_off[b], w1 = t.w_off[b + 1];
     if (w0 == w1) return;
-    const int P = t.P, K = t.K;
+    const int P = t.P, K = t.K, lane = threadIdx.x;
     const double cnd = t.cn[t.set[b]];
-    for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+    for (int i0 = t.begin[b]; i0 < t.end[b]; i0 += 64) {
+        const int i = i0 + lane;
+        const bool valid = i < t.end[b];
+        const T xi = valid ? t.xl[i] : T(0), yi = valid ? t.yl[i] : T(0);
         for (int r = 0; r < nrhs; ++r) {
             double acc = 0.0;
             for (int w = w0; w < w1; ++w) {
                 const int a = t.w_idx[w];
                 const double inv_sd = ldexp(1.0, t.level[a]);
+                __syncthreads();
+                for (int k = lane; k < K; k += 64) mw[k] = M[(size_t(a) * nrhs + r) * K + k] * wx[k];
+                __syncthreads();
                 const T inv_s = T(inv_sd);
-                const T vx = t.xl[i] * inv_s + T((t.cx[b] - t.cx[a]) * inv_sd);
-                const T vy = t.yl[i] * inv_s + T((t.cy[b] - t.cy[a]) * inv_sd);
+                const T vx = xi * inv_s + T((t.cx[b] - t.cx[a]) * inv_sd);
+                const T vy = yi * inv_s + T((t.cy[b] - t.cy[a]) * inv_sd);
                 const T vz = T(cnd * inv_sd);
-                const T *Ma = M + (size_t(a) * nrhs + r) * K;
                 T s = T(0);
                 irregular_even<T>(P, vx, vy, vz, [&](int n, int m, T re, T im) {
                     const int k = cidx(n, m);
-                    T v = Ma[k] * re;
-                    if (m > 0) v -= Ma[k + 1] * im;
-                    s += wx[k] * v;
+                    s += mw[k] * re;
+                    if (m > 0) s -= mw[k + 1] * im;
                 });
                 acc += double(s * inv_s);
             }
-            bs[r * t.N + i] += acc;
+            if (valid) bs[r * t.N + i] += acc;
         }
     }
 }
@@ -663,28 +703,31 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     IMQ_HIP(hipGetLastError());
     mark(t, 2, s);
     const int KP = t->KP;
-    auto gemm = [&](const DevGemm &g, int t0, int t1, const T *tables, const T *in, T *out, int acc) {
+    const imq_kernel_config &kc = t->kcfg;
+    const int kc_def = sizeof(T) == 4 ? 32 : 16;
+    auto gemm = [&](const DevGemm &g, int t0, int t1, const T *tables, const T *in, T *out, int acc,
+                    int kcv, int split) {
         if (t1 <= t0) return;
-        hipLaunchKernelGGL(k_gemm_tasks<T>, dim3(t1 - t0, nrhs), dim3(256), 0, s,
-                           g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
-                           g.src.as<int32_t>(), tables, KP, K, nrhs, in, out, acc);
+        launch_gemm<T>(s, kcv > 0 ? kcv : kc_def, split > 0 ? split : 1, t1 - t0, nrhs,
+                       g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
+                       g.src.as<int32_t>(), tables, KP, K, in, out, acc);
     };
     for (int l = h.nlev - 2; l >= 0; --l)
         gemm(t->g_m2m, t->g_m2m.level_task_begin[l], t->g_m2m.level_task_begin[l + 1], pd.m2m.as<T>(),
-             M, M, 0);
+             M, M, 0, kc.shift_kc, kc.shift_split);
     IMQ_HIP(hipGetLastError());
     mark(t, 3, s);
     {
         const size_t nL = size_t(nbox) * nrhs * K;
         hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, L, T(0));
     }
-    gemm(t->g_m2l, 0, t->g_m2l.ntasks, pd.m2l.as<T>(), M, L, 0);
+    gemm(t->g_m2l, 0, t->g_m2l.ntasks, pd.m2l.as<T>(), M, L, 0, kc.m2l_kc, kc.m2l_split);
     IMQ_HIP(hipGetLastError());
     mark(t, 4, s);
     hipLaunchKernelGGL(k_p2l<T>, dim3(nbox), dim3(64), lds, s, v, us, nrhs, pd.wx.as<T>(), L, chunk);
     for (int l = 1; l < h.nlev; ++l)
         gemm(t->g_l2l, t->g_l2l.level_task_begin[l], t->g_l2l.level_task_begin[l + 1], pd.l2l.as<T>(),
-             L, L, 1);
+             L, L, 1, kc.shift_kc, kc.shift_split);
     IMQ_HIP(hipGetLastError());
     mark(t, 5, s);
     hipLaunchKernelGGL(k_l2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, L, nrhs, bs);
