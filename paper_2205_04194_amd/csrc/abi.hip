@@ -86,6 +86,31 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     UP(begin); UP(end); UP(cx); UP(cy); UP(u_off); UP(u_idx); UP(v_off); UP(v_idx); UP(v_cls);
     UP(w_off); UP(w_idx); UP(x_off); UP(x_idx); UP(Klev); UP(leaves);
 #undef UP
+    {   // W and X lists as flat pairs
+        std::vector<int32_t> w_tgt, w_scr, w_leaves, x_tgt, x_boxes;
+        int32_t scr = 0;
+        const int nbox = int(h.level.size());
+        for (int b = 0; b < nbox; ++b) {
+            if (h.w_off[b + 1] > h.w_off[b]) w_leaves.push_back(b);
+            for (int k = h.w_off[b]; k < h.w_off[b + 1]; ++k) {
+                w_tgt.push_back(b);
+                w_scr.push_back(scr);
+                scr += h.end[b] - h.begin[b];
+            }
+            if (h.x_off[b + 1] > h.x_off[b]) x_boxes.push_back(b);
+            for (int k = h.x_off[b]; k < h.x_off[b + 1]; ++k) x_tgt.push_back(b);
+        }
+        t->nwpairs = int(w_tgt.size());
+        t->nwleaves = int(w_leaves.size());
+        t->nwscr = scr;
+        t->nxpairs = int(x_tgt.size());
+        t->nxboxes = int(x_boxes.size());
+        if ((st = upload(t->w_tgt, w_tgt)) != IMQ_OK) return st;
+        if ((st = upload(t->w_scr, w_scr)) != IMQ_OK) return st;
+        if ((st = upload(t->w_leaves, w_leaves)) != IMQ_OK) return st;
+        if ((st = upload(t->x_tgt, x_tgt)) != IMQ_OK) return st;
+        if ((st = upload(t->x_boxes, x_boxes)) != IMQ_OK) return st;
+    }
     std::vector<double> cc(h.cn);
     cc.insert(cc.end(), h.c.begin(), h.c.end());      // [c/side per set, c per set]
     if ((st = upload(t->cn, cc)) != IMQ_OK) return st;
@@ -142,13 +167,15 @@ static void free_tree(imq_tree_s *t)
     DevBuf *bufs[] = {&t->perm, &t->pt_scale, &t->level, &t->set, &t->parent, &t->child0, &t->nchild,
                       &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
-                      &t->cn, &t->leaves, &t->xy_user, &t->set_off, &t->bs, &t->sol};
+                      &t->cn, &t->leaves, &t->xy_user, &t->set_off, &t->bs, &t->sol,
+                      &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw};
     for (DevBuf *b : bufs) dev_free(*b);
     for (DevGemm *g : {&t->g_m2m, &t->g_m2l, &t->g_l2l}) {
         dev_free(g->tasks); dev_free(g->tbox); dev_free(g->tab); dev_free(g->src);
     }
     for (PrecData *pd : {&t->f64, &t->f32}) {
-        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->m2m, &pd->l2l, &pd->m2l, &pd->wx, &pd->us, &pd->M, &pd->L};
+        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->m2m, &pd->l2l, &pd->m2l, &pd->wx, &pd->us, &pd->M, &pd->L,
+                        &pd->Lx};
         for (DevBuf *b : pb) dev_free(*b);
     }
     for (auto &e : t->ev)

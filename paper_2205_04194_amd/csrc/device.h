@@ -38,6 +38,8 @@ struct PrecData {              // everything that exists once per arithmetic typ
     DevBuf m2m, l2l, m2l;      // translation tables, zero-padded to KP x KP each
     DevBuf us, M, L;           // workspace
     size_t ws_nrhs = 0;
+    DevBuf Lx;                 // per-pair local expansions of the X lists
+    size_t lx_nrhs = 0;
 };
 
 struct DevGemm {               // device copy of a GemmList
@@ -61,6 +63,10 @@ struct imq_tree_s {
     int KP = 0;                            // K rounded up to the MFMA tile (16)
     imq::DevBuf bs;                        // FP64 result accumulator, sorted order
     size_t bs_nrhs = 0;
+    // W and X lists as pairs: target of every pair, per-pair scratch offsets,
+    // and the boxes that own at least one pair
+    imq::DevBuf w_tgt, w_scr, w_leaves, x_tgt, x_boxes, Pw;
+    int nwpairs = 0, nwleaves = 0, nwscr = 0, nxpairs = 0, nxboxes = 0;
     // solver workspace
     imq::DevBuf sol;
     size_t sol_bytes = 0;

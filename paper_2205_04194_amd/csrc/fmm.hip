@@ -78,111 +78,140 @@ __global__ void k_scatter(int64_t N, const int32_t *__restrict__ perm, const dou
     if (i < N) b[r * ldb + perm[i]] = Tout(bs[r * N + i] * scale[i]);
 }
 
-// P2M: Mt[n,m] = sum_j u_j |w_j|^(n-m) conj(w_j)^m over a leaf's points.
-// Phase 1: one thread per point writes its monomials to LDS; phase 2: one
-// thread per coefficient sums them.
-template <typename T>
-__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ us, int nrhs, T *__restrict__ M,
-                                            int chunk)
+// Monomials of one point for every stored coefficient: f(k, value) with
+// value = |w|^(n-m) w^m split into real and imaginary parts (the caller
+// passes conj(w) for multipoles).
+template <typename T, typename F>
+__device__ __forceinline__ void monomials(int P, T wx, T wy, F &&f)
 {
-    extern __shared__ unsigned char smem_raw[];
-    T *mono = reinterpret_cast<T *>(smem_raw);
-    const int ld = chunk + 1;
-    const int b = leaves[blockIdx.x];
-    const int beg = t.begin[b], end = t.end[b];
-    const T inv_s = pow2i<T>(t.level[b]);
-    const int P = t.P, K = t.K, tid = threadIdx.x;
-    for (int r = 0; r < nrhs; ++r) {
-        T acc[3] = {T(0), T(0), T(0)};
-        for (int c0 = beg; c0 < end; c0 += chunk) {
-            if (tid < chunk) {
-                const int i = c0 + tid;
-                if (i < end) {
-                    const T wx = t.xl[i] * inv_s, wy = -t.yl[i] * inv_s;   // conj(w)
-                    const T r2 = wx * wx + wy * wy;
-                    T pr = us[r * t.N + i], pi = T(0);
-                    for (int m = 0; m <= P; ++m) {
-                        T tr = pr, ti = pi;
-                        for (int n = m; n <= P; n += 2) {
-                            const int k = cidx(n, m);
-                            mono[k * ld + tid] = tr;
-                            if (m > 0) mono[(k + 1) * ld + tid] = ti;
-                            tr *= r2;
-                            ti *= r2;
-                        }
-                        const T nr = pr * wx - pi * wy;
-                        pi = pr * wy + pi * wx;
-                        pr = nr;
-                    }
-                } else {
-                    for (int k = 0; k < K; ++k) mono[k * ld + tid] = T(0);
-                }
-            }
-            __syncthreads();
-            for (int q = 0; q * 64 + tid < K; ++q) {
-                const int k = q * 64 + tid;
-                T s = T(0);
-                for (int j = 0; j < chunk; ++j) s += mono[k * ld + j];
-                acc[q] += s;
-            }
-            __syncthreads();
+    const T r2 = wx * wx + wy * wy;
+    T pr = T(1), pi = T(0);
+    for (int m = 0; m <= P; ++m) {
+        T tr = pr, ti = pi;
+        for (int n = m; n <= P; n += 2) {
+            const int k = cidx(n, m);
+            f(k, tr);
+            if (m > 0) f(k + 1, ti);
+            tr *= r2;
+            ti *= r2;
         }
-        for (int q = 0; q * 64 + tid < K; ++q) M[(int64_t(b) * nrhs + r) * K + q * 64 + tid] = acc[q];
+        const T nr = pr * wx - pi * wy;
+        pi = pr * wy + pi * wx;
+        pr = nr;
     }
 }
 
-// P2L: points of the X-list leaves of b accumulated into b's local
-// expansion: Lt += (1/s) eps_k c_{jk} u conj(I_j^k((y - z_b)/s)).
+// Column sums of an LDS matrix: sum_{j < n} a[j*ld + k] * w[j], unrolled so
+// that several reads are in flight.
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2l(DTree<T> t, const T *__restrict__ us, int nrhs,
-                                            const T *__restrict__ wx, T *__restrict__ L, int chunk)
+__device__ __forceinline__ T lds_dot(const T *a, int ld, int k, const T *w, int n)
+{
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+        s0 += a[j * ld + k] * w[j];
+        s1 += a[(j + 1) * ld + k] * w[j + 1];
+        s2 += a[(j + 2) * ld + k] * w[j + 2];
+        s3 += a[(j + 3) * ld + k] * w[j + 3];
+    }
+    for (; j < n; ++j) s0 += a[j * ld + k] * w[j];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// P2M: Mt[n,m] = sum_j u_j |w_j|^(n-m) conj(w_j)^m over a leaf's points.
+// One wave per leaf: each lane writes its point's monomials as one row of
+// an LDS matrix (odd row stride), then each lane sums one coefficient's
+// column against the weights of every right-hand side.
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restrict__ leaves,
+                                            const T *__restrict__ us, int nrhs, T *__restrict__ M, int ld)
 {
     extern __shared__ unsigned char smem_raw[];
-    T *mono = reinterpret_cast<T *>(smem_raw);
-    const int ld = chunk + 1;
-    const int b = blockIdx.x;
-    const int x0 = t.x_off[b], x1 = t.x_off[b + 1];
-    if (x0 == x1) return;
-    const int P = t.P, K = t.K, tid = threadIdx.x;
+    T *mono = reinterpret_cast<T *>(smem_raw);   // [64][ld]
+    T *su = mono + 64 * ld;                      // [64]
+    const int b = leaves[blockIdx.x];
+    const int beg = t.begin[b], end = t.end[b];
+    const T inv_s = pow2i<T>(t.level[b]);
+    const int P = t.P, K = t.K, lane = threadIdx.x;
+    for (int c0 = beg; c0 < end; c0 += 64) {
+        const int n = min(64, end - c0);
+        __syncthreads();
+        if (lane < n) {
+            T *row = mono + lane * ld;
+            monomials<T>(P, t.xl[c0 + lane] * inv_s, -t.yl[c0 + lane] * inv_s,
+                         [&](int k, T v) { row[k] = v; });
+        }
+        for (int r = 0; r < nrhs; ++r) {
+            __syncthreads();
+            if (lane < n) su[lane] = us[r * t.N + c0 + lane];
+            __syncthreads();
+            for (int k = lane; k < K; k += 64) {
+                const T v = lds_dot(mono, ld, k, su, n);
+                T &dst = M[(int64_t(b) * nrhs + r) * K + k];
+                dst = (c0 == beg) ? v : dst + v;
+            }
+        }
+    }
+}
+
+// P2L, one workgroup per (target box b, X-list leaf a) pair k: the local
+// expansion of a's points about b's centre,
+//     Lx[k] = (1/s) sum_j u_j eps_k c_{jk} conj(I_j^k((y_j - z_b)/s)),
+// written to scratch and summed per box afterwards in list order.
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2l_pairs(DTree<T> t, const int32_t *__restrict__ x_tgt,
+                                                  const T *__restrict__ us, int nrhs,
+                                                  const T *__restrict__ wx, T *__restrict__ Lx, int ld,
+                                                  int npairs)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *mono = reinterpret_cast<T *>(smem_raw);   // [64][ld]
+    T *su = mono + 64 * ld;
+    const int kp = blockIdx.x;
+    const int b = x_tgt[kp], a = t.x_idx[kp];
+    const int P = t.P, K = t.K, lane = threadIdx.x;
     const double inv_sd = ldexp(1.0, t.level[b]);
     const T inv_s = T(inv_sd);
     const T vz = T(-t.cn[t.set[b]] * inv_sd);
-    for (int r = 0; r < nrhs; ++r) {
-        T acc[3] = {T(0), T(0), T(0)};
-        for (int xi = x0; xi < x1; ++xi) {
-            const int a = t.x_idx[xi];
-            const T ox = T((t.cx[a] - t.cx[b]) * inv_sd), oy = T((t.cy[a] - t.cy[b]) * inv_sd);
-            for (int c0 = t.begin[a]; c0 < t.end[a]; c0 += chunk) {
-                if (tid < chunk) {
-                    const int i = c0 + tid;
-                    if (i < t.end[a]) {
-                        const T u = us[r * t.N + i];
-                        irregular_even<T>(P, t.xl[i] * inv_s + ox, t.yl[i] * inv_s + oy, vz,
-                                          [&](int n, int m, T re, T im) {
-                                              const int k = cidx(n, m);
-                                              mono[k * ld + tid] = u * re;
-                                              if (m > 0) mono[(k + 1) * ld + tid] = -u * im;
-                                          });
-                    } else {
-                        for (int k = 0; k < K; ++k) mono[k * ld + tid] = T(0);
-                    }
-                }
-                __syncthreads();
-                for (int q = 0; q * 64 + tid < K; ++q) {
-                    const int k = q * 64 + tid;
-                    T s = T(0);
-                    for (int j = 0; j < chunk; ++j) s += mono[k * ld + j];
-                    acc[q] += s;
-                }
-                __syncthreads();
+    const T ox = T((t.cx[a] - t.cx[b]) * inv_sd), oy = T((t.cy[a] - t.cy[b]) * inv_sd);
+    for (int c0 = t.begin[a]; c0 < t.end[a]; c0 += 64) {
+        const int n = min(64, t.end[a] - c0);
+        __syncthreads();
+        if (lane < n) {
+            T *row = mono + lane * ld;
+            irregular_even<T>(P, t.xl[c0 + lane] * inv_s + ox, t.yl[c0 + lane] * inv_s + oy, vz,
+                              [&](int nn, int m, T re, T im) {
+                                  const int k = cidx(nn, m);
+                                  row[k] = re;
+                                  if (m > 0) row[k + 1] = -im;
+                              });
+        }
+        for (int r = 0; r < nrhs; ++r) {
+            __syncthreads();
+            if (lane < n) su[lane] = us[r * t.N + c0 + lane];
+            __syncthreads();
+            for (int k = lane; k < K; k += 64) {
+                const T v = lds_dot(mono, ld, k, su, n) * wx[k] * inv_s;
+                T &dst = Lx[(size_t(r) * npairs + kp) * K + k];
+                dst = (c0 == t.begin[a]) ? v : dst + v;
             }
         }
-        for (int q = 0; q * 64 + tid < K; ++q) {
-            const int k = q * 64 + tid;
-            L[(int64_t(b) * nrhs + r) * K + k] += acc[q] * wx[k] * inv_s;
-        }
     }
+}
+
+// L[b] += sum of the pair expansions of b's X list, in list order.
+template <typename T>
+__global__ void k_p2l_reduce(DTree<T> t, const int32_t *__restrict__ xboxes, int nrhs,
+                             const T *__restrict__ Lx, int npairs, T *__restrict__ L)
+{
+    const int b = xboxes[blockIdx.x];
+    const int K = t.K;
+    for (int r = 0; r < nrhs; ++r)
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            T s = T(0);
+            for (int kp = t.x_off[b]; kp < t.x_off[b + 1]; ++kp) s += Lx[(size_t(r) * npairs + kp) * K + k];
+            L[(size_t(b) * nrhs + r) * K + k] += s;
+        }
 }
 
 // ------------------------------------------------------------------ MFMA translations
@@ -525,48 +554,58 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
     }
 }
 
-// M2P: multipoles of the W-list boxes evaluated at the leaf's points:
-// potential = (1/s_a) sum Re(Mt[n,m] eps_m c_{nm} I_n^m((x - z_a)/s_a)).
-// One wave per target leaf; each W box's multipole, premultiplied by the
-// constants, is staged in LDS and read back as a broadcast.
+// M2P, one wave per (target leaf b, W-list box a) pair k: the multipole of
+// a evaluated at b's points,
+//     potential = (1/s_a) sum Re(Mt[n,m] eps_m c_{nm} I_n^m((x - z_a)/s_a)),
+// written to scratch (offset w_scr[k]) and summed per point afterwards in
+// list order.  The multipole, premultiplied by the constants, is staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(64) void k_m2p(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ M, const T *__restrict__ wx, int nrhs,
-                                            double *__restrict__ bs)
+__global__ __launch_bounds__(64) void k_m2p_pairs(DTree<T> t, const int32_t *__restrict__ w_tgt,
+                                                  const int32_t *__restrict__ w_scr,
+                                                  const T *__restrict__ M, const T *__restrict__ wx,
+                                                  int nrhs, double *__restrict__ Pw, int nscr)
 {
     __shared__ T mw[KMAX + 1];
-    const int b = leaves[blockIdx.x];
-    const int w0 = t.w_off[b], w1 = t.w_off[b + 1];
-    if (w0 == w1) return;
+    const int kp = blockIdx.x;
+    const int b = w_tgt[kp], a = t.w_idx[kp];
     const int P = t.P, K = t.K, lane = threadIdx.x;
     const double cnd = t.cn[t.set[b]];
-    for (int i0 = t.begin[b]; i0 < t.end[b]; i0 += 64) {
-        const int i = i0 + lane;
-        const bool valid = i < t.end[b];
-        const T xi = valid ? t.xl[i] : T(0), yi = valid ? t.yl[i] : T(0);
-        for (int r = 0; r < nrhs; ++r) {
-            double acc = 0.0;
-            for (int w = w0; w < w1; ++w) {
-                const int a = t.w_idx[w];
-                const double inv_sd = ldexp(1.0, t.level[a]);
-                __syncthreads();
-                for (int k = lane; k < K; k += 64) mw[k] = M[(size_t(a) * nrhs + r) * K + k] * wx[k];
-                __syncthreads();
-                const T inv_s = T(inv_sd);
-                const T vx = xi * inv_s + T((t.cx[b] - t.cx[a]) * inv_sd);
-                const T vy = yi * inv_s + T((t.cy[b] - t.cy[a]) * inv_sd);
-                const T vz = T(cnd * inv_sd);
-                T s = T(0);
-                irregular_even<T>(P, vx, vy, vz, [&](int n, int m, T re, T im) {
-                    const int k = cidx(n, m);
-                    s += mw[k] * re;
-                    if (m > 0) s -= mw[k + 1] * im;
-                });
-                acc += double(s * inv_s);
-            }
-            if (valid) bs[r * t.N + i] += acc;
+    const double inv_sd = ldexp(1.0, t.level[a]);
+    const T inv_s = T(inv_sd);
+    const T ox = T((t.cx[b] - t.cx[a]) * inv_sd), oy = T((t.cy[b] - t.cy[a]) * inv_sd);
+    const T vz = T(cnd * inv_sd);
+    for (int r = 0; r < nrhs; ++r) {
+        __syncthreads();
+        for (int k = lane; k < K; k += 64) mw[k] = M[(size_t(a) * nrhs + r) * K + k] * wx[k];
+        __syncthreads();
+        for (int i = t.begin[b] + lane; i < t.end[b]; i += 64) {
+            T s = T(0);
+            irregular_even<T>(P, t.xl[i] * inv_s + ox, t.yl[i] * inv_s + oy, vz,
+                              [&](int n, int m, T re, T im) {
+                                  const int k = cidx(n, m);
+                                  s += mw[k] * re;
+                                  if (m > 0) s -= mw[k + 1] * im;
+                              });
+            Pw[size_t(r) * nscr + w_scr[kp] + (i - t.begin[b])] = double(s * inv_s);
         }
     }
+}
+
+// b_i += sum over the W-list pairs of i's leaf, in list order.
+template <typename T>
+__global__ __launch_bounds__(64) void k_m2p_reduce(DTree<T> t, const int32_t *__restrict__ wleaves,
+                                                   const int32_t *__restrict__ w_scr, int nrhs,
+                                                   const double *__restrict__ Pw, int nscr,
+                                                   double *__restrict__ bs)
+{
+    const int b = wleaves[blockIdx.x];
+    for (int r = 0; r < nrhs; ++r)
+        for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+            double s = 0.0;
+            for (int kp = t.w_off[b]; kp < t.w_off[b + 1]; ++kp)
+                s += Pw[size_t(r) * nscr + w_scr[kp] + (i - t.begin[b])];
+            bs[r * t.N + i] += s;
+        }
 }
 
 // Exact rows: b[r*ldb + k] = sum_j A_{rows[k], j} u_j in FP64 over the row's set.
@@ -661,18 +700,16 @@ imq_status ensure_workspace(imq_tree_s *t, int nrhs)
         IMQ_HIP(dev_alloc(pd.L, sizeof(T) * nbox * nrhs * t->h.K));
         pd.ws_nrhs = nrhs;
     }
+    if (pd.lx_nrhs < size_t(nrhs)) {
+        IMQ_HIP(dev_alloc(pd.Lx, sizeof(T) * size_t(t->nxpairs) * nrhs * t->h.K));
+        pd.lx_nrhs = nrhs;
+    }
     if (t->bs_nrhs < size_t(nrhs)) {
         IMQ_HIP(dev_alloc(t->bs, sizeof(double) * size_t(t->h.N) * nrhs));
+        IMQ_HIP(dev_alloc(t->Pw, sizeof(double) * size_t(t->nwscr) * nrhs));
         t->bs_nrhs = nrhs;
     }
     return IMQ_OK;
-}
-
-static int lds_chunk(int K, size_t elem)
-{
-    int chunk = 64;
-    while (chunk > 8 && size_t(K) * (chunk + 1) * elem > 64 * 1024) chunk /= 2;
-    return chunk;
 }
 
 static thread_local hipEvent_t *g_cur_events = nullptr;
@@ -691,43 +728,49 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     const int nleaves = int(h.leaves.size());
     const int nbox = int(h.level.size());
     const int K = h.K;
-    const int chunk = lds_chunk(K, sizeof(T));
-    const size_t lds = size_t(K) * (chunk + 1) * sizeof(T);
+    const int ld = K | 1;                                      // odd LDS row stride
+    const size_t lds = (size_t(64) * ld + 64) * sizeof(T);
     const int32_t *leaves = t->leaves.as<int32_t>();
     T *M = pd.M.as<T>(), *L = pd.L.as<T>();
     const T *us = pd.us.as<T>();
     double *bs = t->bs.as<double>();
 
     mark(t, 1, s);
-    hipLaunchKernelGGL(k_p2m<T>, dim3(nleaves), dim3(64), lds, s, v, leaves, us, nrhs, M, chunk);
+    hipLaunchKernelGGL(k_p2m<T>, dim3(nleaves), dim3(64), lds, s, v, leaves, us, nrhs, M, ld);
     IMQ_HIP(hipGetLastError());
     mark(t, 2, s);
     const int KP = t->KP;
     const imq_kernel_config &kc = t->kcfg;
-    const int kc_def = sizeof(T) == 4 ? 32 : 16;
     auto gemm = [&](const DevGemm &g, int t0, int t1, const T *tables, const T *in, T *out, int acc,
                     int kcv, int split) {
         if (t1 <= t0) return;
-        launch_gemm<T>(s, kcv > 0 ? kcv : kc_def, split > 0 ? split : 1, t1 - t0, nrhs,
+        launch_gemm<T>(s, kcv, split, t1 - t0, nrhs,
                        g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
                        g.src.as<int32_t>(), tables, KP, K, in, out, acc);
     };
     for (int l = h.nlev - 2; l >= 0; --l)
         gemm(t->g_m2m, t->g_m2m.level_task_begin[l], t->g_m2m.level_task_begin[l + 1], pd.m2m.as<T>(),
-             M, M, 0, kc.shift_kc, kc.shift_split);
+             M, M, 0, kc.shift_kc > 0 ? kc.shift_kc : 16, kc.shift_split > 0 ? kc.shift_split : 2);
     IMQ_HIP(hipGetLastError());
     mark(t, 3, s);
     {
         const size_t nL = size_t(nbox) * nrhs * K;
         hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, L, T(0));
     }
-    gemm(t->g_m2l, 0, t->g_m2l.ntasks, pd.m2l.as<T>(), M, L, 0, kc.m2l_kc, kc.m2l_split);
+    gemm(t->g_m2l, 0, t->g_m2l.ntasks, pd.m2l.as<T>(), M, L, 0, kc.m2l_kc > 0 ? kc.m2l_kc : 32,
+         kc.m2l_split > 0 ? kc.m2l_split : 1);
     IMQ_HIP(hipGetLastError());
     mark(t, 4, s);
-    hipLaunchKernelGGL(k_p2l<T>, dim3(nbox), dim3(64), lds, s, v, us, nrhs, pd.wx.as<T>(), L, chunk);
+    if (t->nxpairs > 0) {
+        T *Lx = pd.Lx.as<T>();
+        hipLaunchKernelGGL(k_p2l_pairs<T>, dim3(t->nxpairs), dim3(64), lds, s, v, t->x_tgt.as<int32_t>(), us,
+                           nrhs, pd.wx.as<T>(), Lx, ld, t->nxpairs);
+        hipLaunchKernelGGL(k_p2l_reduce<T>, dim3(t->nxboxes), dim3(64), 0, s, v, t->x_boxes.as<int32_t>(),
+                           nrhs, Lx, t->nxpairs, L);
+    }
     for (int l = 1; l < h.nlev; ++l)
         gemm(t->g_l2l, t->g_l2l.level_task_begin[l], t->g_l2l.level_task_begin[l + 1], pd.l2l.as<T>(),
-             L, L, 1, kc.shift_kc, kc.shift_split);
+             L, L, 1, kc.shift_kc > 0 ? kc.shift_kc : 16, kc.shift_split > 0 ? kc.shift_split : 2);
     IMQ_HIP(hipGetLastError());
     mark(t, 5, s);
     hipLaunchKernelGGL(k_l2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, L, nrhs, bs);
@@ -736,7 +779,13 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     hipLaunchKernelGGL(k_p2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, us, nrhs, bs);
     IMQ_HIP(hipGetLastError());
     mark(t, 7, s);
-    hipLaunchKernelGGL(k_m2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, M, pd.wx.as<T>(), nrhs, bs);
+    if (t->nwpairs > 0) {
+        double *Pw = t->Pw.as<double>();
+        hipLaunchKernelGGL(k_m2p_pairs<T>, dim3(t->nwpairs), dim3(64), 0, s, v, t->w_tgt.as<int32_t>(),
+                           t->w_scr.as<int32_t>(), M, pd.wx.as<T>(), nrhs, Pw, t->nwscr);
+        hipLaunchKernelGGL(k_m2p_reduce<T>, dim3(t->nwleaves), dim3(64), 0, s, v, t->w_leaves.as<int32_t>(),
+                           t->w_scr.as<int32_t>(), nrhs, Pw, t->nwscr, bs);
+    }
     IMQ_HIP(hipGetLastError());
     mark(t, 8, s);
     return IMQ_OK;
