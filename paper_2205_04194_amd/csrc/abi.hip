@@ -21,6 +21,8 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
                         hipStream_t s);
 imq_status rows_exact(imq_tree_s *t, int nrhs, const double *u, int64_t ldu, int64_t nrows,
                       const int64_t *rows, double *b, int64_t ldb, hipStream_t s);
+imq_status solve_one(imq_tree_s *t, const double *f_user, double *a_user, const imq_solve_opts &o,
+                     imq_solve_stats &stats, hipStream_t s);
 
 template <typename V>
 static imq_status upload(DevBuf &d, const std::vector<V> &h)
@@ -421,9 +423,24 @@ void imq_debug_host_tree_free(void *hp) { delete static_cast<HostTree *>(hp); }
 imq_status imq_solve(imq_tree t, int nrhs, const double *f, int64_t ldf, double *a, int64_t lda,
                      const imq_solve_opts *opts, imq_solve_stats *stats, hipStream_t stream)
 {
-    (void)t; (void)nrhs; (void)f; (void)ldf; (void)a; (void)lda; (void)opts; (void)stats; (void)stream;
-    set_error("imq_solve is not available in this build");
-    return IMQ_EUNSUPPORTED;
+    imq_status st = check_tree(t);
+    if (st != IMQ_OK) return st;
+    if (nrhs < 1 || !f || !a || !opts || !stats || ldf < t->h.N || lda < t->h.N) {
+        set_error("bad argument to imq_solve");
+        return IMQ_EINVAL;
+    }
+    if (!(opts->tol > 0.0) || opts->restart < 1 || opts->restart > 256 || opts->max_iters < 1 ||
+        opts->max_outer < 0) {
+        set_error("solve options out of range (tol > 0, 1 <= restart <= 256, max_iters >= 1)");
+        return IMQ_EINVAL;
+    }
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+        st = solve_one(t, f + size_t(r) * ldf, a + size_t(r) * lda, *opts, stats[r], stream);
+        if (st != IMQ_OK) return st;
+        all = all && stats[r].converged;
+    }
+    return all ? IMQ_OK : IMQ_ENOTCONVERGED;
 }
 
 imq_status imq_matvec_backward(imq_tree t, imq_dtype dtype, const void *v, const void *g, void *dv,
