@@ -138,7 +138,10 @@ imq_status imq_solve(imq_tree tree, int nrhs, const double *f, int64_t ldf,
  *        = -sum_j (g_k v_j + v_k g_j)(x_k - x_j)(r_kj^2 + c^2)^(-3/2)
  * for every set s.  v, g, dv: FP64 or FP32 per `dtype` (one column each);
  * dc: device FP64, nsets entries; dxy: device FP64 SoA 2 x Ntot.  The
- * interaction lists are those of `tree`. */
+ * interaction lists are those of `tree`, which must sum its adaptive W/X
+ * interactions directly (built with direct_max >= Ntot), else
+ * IMQ_EUNSUPPORTED.  The vertical derivative uses translation tables to the
+ * n+m-odd local coefficients, generated on the first call. */
 imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
                                const void *g, void *dv, double *dc, double *dxy,
                                imq_prec prec, hipStream_t stream);

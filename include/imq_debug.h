@@ -22,6 +22,9 @@ extern "C" {
  *  kind 2: multipole -> local translation at `level` between boxes (dx, dy)
  *          edges apart, lifted planes c' = cnorm apart (units of the root)
  *  kind 3: the K per-coefficient constants of the point evaluations
+ *  kind 4: as kind 2, to the p(p+1)/2 n+m-odd local coefficients that give
+ *          the vertical derivative at the target plane (first rows of K x K)
+ *  kind 5: parent -> child shift of those odd coefficients (leading block)
  * Returns 0, or -1 for a bad argument. */
 int imq_debug_table(int kind, int p, int pos, int level, int dx, int dy, double cnorm, double *out);
 

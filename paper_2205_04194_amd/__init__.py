@@ -221,8 +221,9 @@ class IMQMatvec(torch.autograd.Function):
     def backward(ctx, gb):
         xy, v = ctx.saved_tensors
         leaf, p, prec = ctx.cfg
-        tree = Tree(xy.detach(), ctx.c, leaf=leaf, p=p)
+        # the lists are rebuilt here (not kept from forward), with every
+        # adaptive W/X interaction in the direct near field
+        tree = Tree(xy.detach(), ctx.c, leaf=leaf, p=p, direct_max=1 << 30)
         dv, dc, dxy = tree.backward(v.detach(), gb.detach(), prec)
         tree.close()
-        dcv = dc[0].to(torch.float64) if isinstance(ctx.c, float) else dc
-        return dxy.to(xy.dtype), dcv, dv.to(v.dtype), None, None, None
+        return dxy.to(xy.dtype), dc[0].to(torch.float64), dv.to(v.dtype), None, None, None

@@ -23,6 +23,9 @@ imq_status rows_exact(imq_tree_s *t, int nrhs, const double *u, int64_t ldu, int
                       const int64_t *rows, double *b, int64_t ldb, hipStream_t s);
 imq_status solve_one(imq_tree_s *t, const double *f_user, double *a_user, const imq_solve_opts &o,
                      imq_solve_stats &stats, hipStream_t s);
+template <typename T, typename Tio>
+imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, double *dc, double *dxy,
+                          hipStream_t s);
 
 template <typename V>
 static imq_status upload(DevBuf &d, const std::vector<V> &h)
@@ -170,14 +173,14 @@ static void free_tree(imq_tree_s *t)
                       &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
                       &t->cn, &t->leaves, &t->xy_user, &t->set_off, &t->bs, &t->sol,
-                      &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw};
+                      &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw, &t->adj};
     for (DevBuf *b : bufs) dev_free(*b);
     for (DevGemm *g : {&t->g_m2m, &t->g_m2l, &t->g_l2l}) {
         dev_free(g->tasks); dev_free(g->tbox); dev_free(g->tab); dev_free(g->src);
     }
     for (PrecData *pd : {&t->f64, &t->f32}) {
         DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->m2m, &pd->l2l, &pd->m2l, &pd->wx, &pd->us, &pd->M, &pd->L,
-                        &pd->Lx};
+                        &pd->Lx, &pd->m2l_odd, &pd->l2l_odd, &pd->Lodd};
         for (DevBuf *b : pb) dev_free(*b);
     }
     for (auto &e : t->ev)
@@ -376,6 +379,8 @@ int imq_debug_table(int kind, int p, int pos, int level, int dx, int dy, double 
     case 1: make_l2l_table(p, pos & 3, out); return 0;
     case 2: make_m2l_table(p, level, dx, dy, cnorm, out); return 0;
     case 3: make_wx_consts(p, out); return 0;
+    case 4: make_m2l_odd_table(p, level, dx, dy, cnorm, out); return 0;
+    case 5: make_l2l_odd_table(p, pos & 3, out); return 0;
     }
     return -1;
 }
@@ -446,9 +451,24 @@ imq_status imq_solve(imq_tree t, int nrhs, const double *f, int64_t ldf, double 
 imq_status imq_matvec_backward(imq_tree t, imq_dtype dtype, const void *v, const void *g, void *dv,
                                double *dc, double *dxy, imq_prec prec, hipStream_t stream)
 {
-    (void)t; (void)dtype; (void)v; (void)g; (void)dv; (void)dc; (void)dxy; (void)prec; (void)stream;
-    set_error("imq_matvec_backward is not available in this build");
-    return IMQ_EUNSUPPORTED;
+    imq_status st = check_tree(t);
+    if (st != IMQ_OK) return st;
+    if (!v || !g || !dv || !dc || !dxy) { set_error("null argument to imq_matvec_backward"); return IMQ_EINVAL; }
+    if (t->nwpairs > 0 || t->nxpairs > 0) {
+        set_error("the adjoint needs a tree whose adaptive W/X interactions are summed directly "
+                  "(build it with direct_max >= the number of points)");
+        return IMQ_EUNSUPPORTED;
+    }
+    if (dtype == IMQ_F64 && prec == IMQ_PREC_FP64)
+        return backward_typed<double, double>(t, (const double *)v, (const double *)g, (double *)dv, dc, dxy, stream);
+    if (dtype == IMQ_F32 && prec == IMQ_PREC_FP64)
+        return backward_typed<double, float>(t, (const float *)v, (const float *)g, (float *)dv, dc, dxy, stream);
+    if (dtype == IMQ_F64 && prec == IMQ_PREC_FP32)
+        return backward_typed<float, double>(t, (const double *)v, (const double *)g, (double *)dv, dc, dxy, stream);
+    if (dtype == IMQ_F32 && prec == IMQ_PREC_FP32)
+        return backward_typed<float, float>(t, (const float *)v, (const float *)g, (float *)dv, dc, dxy, stream);
+    set_error("unknown dtype or precision");
+    return IMQ_EINVAL;
 }
 
 }  // extern "C"

@@ -1,0 +1,279 @@
+// Adjoint of the fast product b = A(c, X) v for a scalar loss with upstream
+// gradient g = dL/db.  From the entries of eq. IMQ_def,
+//     phi = (r^2 + c^2)^(-1/2),  grad_x phi = -(x_i - x_j) (r^2+c^2)^(-3/2),
+//     d phi / dc = -c (r^2 + c^2)^(-3/2),
+// and, with the fields F_w(x) = sum_j w_j grad_x phi(x - x_j) and
+// Z_w(x) = sum_j w_j dphi/dc(x - x_j),
+//     dL/dv   = A g                          (A is symmetric)
+//     dL/dx_k = g_k F_v(x_k) + v_k F_g(x_k)
+//     dL/dc   = sum_i g_i Z_v(x_i).
+// All of it comes from one expansion pass over the two weight vectors v and
+// g: the n+m-even local coefficients give the potential and its in-plane
+// gradient, the n+m-odd ones (extra translation tables) the vertical
+// derivative, which is d/dc in the lifted picture.  The near field is summed
+// directly with the same formulas.  Adaptive W/X lists are not expanded
+// here: the tree must route them to the direct sum (direct_max >= N).
+#include "device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+namespace imq {
+
+template <typename T>
+void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks, int t0,
+                 const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *tables, int KP,
+                 int K, const T *in, T *out, int acc, int kin_ovr, int kout_ovr);
+template <typename T> imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s);
+template <typename T> imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s);
+
+namespace {
+
+__device__ __forceinline__ int cidx_e(int n, int m) { return n * (n + 1) / 2 + (m > 0 ? m - 1 : 0); }
+__device__ __forceinline__ int cidx_o(int j, int k) { return j * (j - 1) / 2 + (k > 0 ? k - 1 : 0); }
+
+template <typename T>
+__global__ void k_zero(size_t n, T *__restrict__ p)
+{
+    const size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = T(0);
+}
+
+template <typename Tin, typename T>
+__global__ void k_gather2(int64_t N, const int32_t *__restrict__ perm, const Tin *__restrict__ v,
+                          const Tin *__restrict__ g, T *__restrict__ us)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i < N) {
+        us[i] = T(v[perm[i]]);
+        us[N + i] = T(g[perm[i]]);
+    }
+}
+
+// Per target (normalised units): out[0] = potential of g, out[1..2] = grad of
+// the v field, out[3..4] = grad of the g field, out[5] = d/dc of the v field.
+template <typename T>
+__global__ __launch_bounds__(64) void k_adjoint_eval(DTree<T> t, const int32_t *__restrict__ leaves,
+                                                     const T *__restrict__ L, const T *__restrict__ Lo,
+                                                     const T *__restrict__ us, double *__restrict__ out)
+{
+    const int b = leaves[blockIdx.x];
+    const int P = t.P, K = t.K;
+    const double inv_sd = ldexp(1.0, t.level[b]);
+    const T inv_s = T(inv_sd);
+    const double cnd = t.cn[t.set[b]];
+    const T cc = T(cnd), c2 = T(cnd * cnd);
+    const T *Lv = L + (size_t(b) * 2 + 0) * K;
+    const T *Lg = L + (size_t(b) * 2 + 1) * K;
+    const T *Lov = Lo + (size_t(b) * 2 + 0) * K;
+    const int64_t N = t.N;
+    for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+        const T xi = t.xl[i], yi = t.yl[i];
+        // far field from the local expansions
+        const T wx = xi * inv_s, wy = yi * inv_s;
+        const T r2 = wx * wx + wy * wy;
+        T potg = 0, gvx = 0, gvy = 0, ggx = 0, ggy = 0, dzv = 0;
+        T pmr = 1, pmi = 0, p1r = 0, p1i = 0;              // W^m, W^(m-1)
+        for (int m = 0; m <= P; ++m) {
+            T tr = pmr, ti = pmi;                            // r2^q W^m
+            T sr = p1r, si = p1i;                            // r2^q W^(m-1)
+            T qr = 0, qi = 0;                                // r2^(q-1) W^m
+            for (int n = m, q = 0; n <= P; n += 2, ++q) {
+                const int k = cidx_e(n, m);
+                const T dxr = T(2 * q) * wx * qr + T(m) * sr, dxi = T(2 * q) * wx * qi + T(m) * si;
+                const T dyr = T(2 * q) * wy * qr - T(m) * si, dyi = T(2 * q) * wy * qi + T(m) * sr;
+                const T lvr = Lv[k], lvi = m > 0 ? Lv[k + 1] : T(0);
+                const T lgr = Lg[k], lgi = m > 0 ? Lg[k + 1] : T(0);
+                potg += lgr * tr - lgi * ti;
+                ggx += lgr * dxr - lgi * dxi;
+                ggy += lgr * dyr - lgi * dyi;
+                gvx += lvr * dxr - lvi * dxi;
+                gvy += lvr * dyr - lvi * dyi;
+                if (n + 1 <= P) {
+                    const int ko = cidx_o(n + 1, m);
+                    const T lor = Lov[ko], loi = m > 0 ? Lov[ko + 1] : T(0);
+                    dzv += lor * tr - loi * ti;
+                }
+                qr = tr; qi = ti;
+                tr *= r2; ti *= r2;
+                sr *= r2; si *= r2;
+            }
+            p1r = pmr; p1i = pmi;
+            const T nr = pmr * wx - pmi * wy;
+            pmi = pmr * wy + pmi * wx;
+            pmr = nr;
+        }
+        double o0 = double(potg), o1 = double(gvx * inv_s), o2 = double(gvy * inv_s);
+        double o3 = double(ggx * inv_s), o4 = double(ggy * inv_s), o5 = double(dzv);
+        // near field, summed directly
+        for (int uu = t.u_off[b]; uu < t.u_off[b + 1]; ++uu) {
+            const int a = t.u_idx[uu];
+            const T px = xi + T(t.cx[b] - t.cx[a]), py = yi + T(t.cy[b] - t.cy[a]);
+            T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+            for (int j = t.begin[a]; j < t.end[a]; ++j) {
+                const T dx = px - t.xl[j], dy = py - t.yl[j];
+                const T ir = T(1) / sqrt(dx * dx + dy * dy + c2);
+                const T ir3 = ir * ir * ir;
+                const T vj = us[j], gj = us[N + j];
+                s0 += gj * ir;
+                s1 -= vj * dx * ir3;
+                s2 -= vj * dy * ir3;
+                s3 -= gj * dx * ir3;
+                s4 -= gj * dy * ir3;
+                s5 -= cc * vj * ir3;
+            }
+            o0 += double(s0); o1 += double(s1); o2 += double(s2);
+            o3 += double(s3); o4 += double(s4); o5 += double(s5);
+        }
+        out[0 * N + i] = o0;
+        out[1 * N + i] = o1;
+        out[2 * N + i] = o2;
+        out[3 * N + i] = o3;
+        out[4 * N + i] = o4;
+        out[5 * N + i] = o5;
+    }
+}
+
+template <typename T, typename Tout>
+__global__ void k_adjoint_final(int64_t N, const int32_t *__restrict__ perm, const double *__restrict__ scale,
+                                const T *__restrict__ us, const double *__restrict__ out,
+                                Tout *__restrict__ dv, double *__restrict__ dxy, double *__restrict__ dcpart)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= N) return;
+    const double s1 = scale[i], s2 = s1 * s1;
+    const double v = double(us[i]), g = double(us[N + i]);
+    const int32_t k = perm[i];
+    dv[k] = Tout(out[i] * s1);
+    dxy[k] = (g * out[1 * N + i] + v * out[3 * N + i]) * s2;
+    dxy[N + k] = (g * out[2 * N + i] + v * out[4 * N + i]) * s2;
+    dcpart[i] = g * out[5 * N + i] * s2;
+}
+
+// dc[s] = sum of dcpart over the set's points, in a fixed order.
+__global__ __launch_bounds__(256) void k_set_sum(const int64_t *__restrict__ set_off,
+                                                 const double *__restrict__ part, double *__restrict__ dc)
+{
+    __shared__ double red[256];
+    const int s = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = set_off[s] + threadIdx.x; i < set_off[s + 1]; i += blockDim.x) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dc[s] = red[0];
+}
+
+template <typename V>
+imq_status upload_vec(DevBuf &d, const std::vector<V> &h)
+{
+    IMQ_HIP(dev_alloc(d, sizeof(V) * h.size()));
+    if (!h.empty()) IMQ_HIP(hipMemcpy(d.p, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice));
+    return IMQ_OK;
+}
+
+// Odd-coefficient tables, generated once per tree on first use.
+imq_status ensure_odd_tables(imq_tree_s *t)
+{
+    if (t->odd_ready) return IMQ_OK;
+    const HostTree &h = t->h;
+    const int K = h.K, KP = t->KP, p = h.p;
+    const size_t KK = size_t(K) * K, PP = size_t(KP) * KP;
+    const size_t ntab = size_t(h.nsets) * h.nlev * NCLASS;
+    std::vector<double> m2l(ntab * PP, 0.0), l2l(4 * PP, 0.0), tmp(KK);
+    auto pad_into = [&](const std::vector<double> &src, double *dst) {
+        for (int r = 0; r < K; ++r) std::copy(src.begin() + size_t(r) * K, src.begin() + size_t(r + 1) * K, dst + size_t(r) * KP);
+    };
+    for (int pos = 0; pos < 4; ++pos) {
+        make_l2l_odd_table(p, pos, tmp.data());
+        pad_into(tmp, l2l.data() + pos * PP);
+    }
+    for (int s = 0; s < h.nsets; ++s)
+        for (int l = 2; l < h.nlev; ++l)
+            for (int cls = 0; cls < NCLASS; ++cls) {
+                const int dx = cls / 7 - 3, dy = cls % 7 - 3;
+                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                make_m2l_odd_table(p, l, dx, dy, h.cn[s], tmp.data());
+                pad_into(tmp, m2l.data() + ((size_t(s) * h.nlev + l) * NCLASS + cls) * PP);
+            }
+    std::vector<float> m2l32(m2l.begin(), m2l.end()), l2l32(l2l.begin(), l2l.end());
+    imq_status st;
+    if ((st = upload_vec(t->f64.m2l_odd, m2l)) != IMQ_OK) return st;
+    if ((st = upload_vec(t->f64.l2l_odd, l2l)) != IMQ_OK) return st;
+    if ((st = upload_vec(t->f32.m2l_odd, m2l32)) != IMQ_OK) return st;
+    if ((st = upload_vec(t->f32.l2l_odd, l2l32)) != IMQ_OK) return st;
+    t->odd_ready = true;
+    return IMQ_OK;
+}
+
+inline dim3 grid1(int64_t n) { return dim3(unsigned((n + 255) / 256)); }
+
+}  // namespace
+
+template <typename T, typename Tio>
+imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, double *dc, double *dxy,
+                          hipStream_t s)
+{
+    const HostTree &h = t->h;
+    const int64_t N = h.N;
+    const int K = h.K, KP = t->KP;
+    const int nbox = int(h.level.size());
+    imq_status st;
+    if ((st = ensure_workspace<T>(t, 2)) != IMQ_OK) return st;
+    if ((st = ensure_odd_tables(t)) != IMQ_OK) return st;
+    PrecData &pd = prec_data<T>(t);
+    const size_t lo_bytes = sizeof(T) * size_t(nbox) * 2 * K;
+    if (pd.Lodd.bytes < lo_bytes) IMQ_HIP(dev_alloc(pd.Lodd, lo_bytes));
+    if (t->adj.bytes < sizeof(double) * 7 * size_t(N)) IMQ_HIP(dev_alloc(t->adj, sizeof(double) * 7 * size_t(N)));
+    T *us = pd.us.as<T>();
+    double *out = t->adj.as<double>();
+    double *dcpart = out + 6 * N;
+
+    hipLaunchKernelGGL((k_gather2<Tio, T>), grid1(N), dim3(256), 0, s, N, t->perm.as<int32_t>(), v, g, us);
+    IMQ_HIP(hipGetLastError());
+    if ((st = fmm_upward<T>(t, 2, s)) != IMQ_OK) return st;
+    if ((st = fmm_translate<T>(t, 2, s)) != IMQ_OK) return st;
+    // odd (vertical-derivative) coefficients: same batches, other tables
+    T *Lo = pd.Lodd.as<T>();
+    const int Ko = Kodd(h.p);
+    {
+        const size_t n = size_t(nbox) * 2 * K;
+        hipLaunchKernelGGL(k_zero<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, Lo);
+    }
+    if (t->g_m2l.ntasks > 0)
+        launch_gemm<T>(s, 32, 1, t->g_m2l.ntasks, 2, t->g_m2l.tasks.as<GemmTask>(), 0, t->g_m2l.tbox.as<int32_t>(),
+                       t->g_m2l.tab.as<int32_t>(), t->g_m2l.src.as<int32_t>(), pd.m2l_odd.as<T>(), KP, K,
+                       pd.M.as<T>(), Lo, 0, 0, Ko);
+    for (int l = 1; l < h.nlev; ++l) {
+        const DevGemm &gl = t->g_l2l;
+        const int t0 = gl.level_task_begin[l], t1 = gl.level_task_begin[l + 1];
+        if (t1 <= t0) continue;
+        launch_gemm<T>(s, 16, 2, t1 - t0, 2, gl.tasks.as<GemmTask>(), t0, gl.tbox.as<int32_t>(),
+                       gl.tab.as<int32_t>(), gl.src.as<int32_t>(), pd.l2l_odd.as<T>(), KP, K, Lo, Lo, 1, Ko, Ko);
+    }
+    IMQ_HIP(hipGetLastError());
+    DTree<T> view = make_view<T>(t);
+    hipLaunchKernelGGL(k_adjoint_eval<T>, dim3(unsigned(h.leaves.size())), dim3(64), 0, s, view,
+                       t->leaves.as<int32_t>(), pd.L.as<T>(), Lo, us, out);
+    hipLaunchKernelGGL((k_adjoint_final<T, Tio>), grid1(N), dim3(256), 0, s, N, t->perm.as<int32_t>(),
+                       t->pt_scale.as<double>(), us, out, dv, dxy, dcpart);
+    hipLaunchKernelGGL(k_set_sum, dim3(h.nsets), dim3(256), 0, s, t->set_off.as<int64_t>(), dcpart, dc);
+    IMQ_HIP(hipGetLastError());
+    return IMQ_OK;
+}
+
+template imq_status backward_typed<double, double>(imq_tree_s *, const double *, const double *, double *,
+                                                   double *, double *, hipStream_t);
+template imq_status backward_typed<double, float>(imq_tree_s *, const float *, const float *, float *,
+                                                  double *, double *, hipStream_t);
+template imq_status backward_typed<float, double>(imq_tree_s *, const double *, const double *, double *,
+                                                  double *, double *, hipStream_t);
+template imq_status backward_typed<float, float>(imq_tree_s *, const float *, const float *, float *,
+                                                 double *, double *, hipStream_t);
+
+}  // namespace imq

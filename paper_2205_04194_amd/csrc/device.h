@@ -40,6 +40,8 @@ struct PrecData {              // everything that exists once per arithmetic typ
     size_t ws_nrhs = 0;
     DevBuf Lx;                 // per-pair local expansions of the X lists
     size_t lx_nrhs = 0;
+    DevBuf m2l_odd, l2l_odd;   // adjoint: tables to the n+m-odd local coefficients
+    DevBuf Lodd;               // adjoint: odd local coefficients
 };
 
 struct DevGemm {               // device copy of a GemmList
@@ -70,6 +72,9 @@ struct imq_tree_s {
     // solver workspace
     imq::DevBuf sol;
     size_t sol_bytes = 0;
+    // adjoint: per-point fields and partial sums; odd tables generated on first use
+    imq::DevBuf adj;
+    bool odd_ready = false;
     // stage timing: one set of IMQ_NSTAGES+1 events per recorded product,
     // read back (and summed) only when the caller asks for the times
     static constexpr int TIMING_RING = 256;

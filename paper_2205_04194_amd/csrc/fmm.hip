@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
                                                     const int32_t *__restrict__ src,
                                                     const T *__restrict__ tables, int KP, int K, int nrhs,
                                                     const T *__restrict__ in, T *__restrict__ out,
-                                                    int accumulate)
+                                                    int accumulate, int kin_ovr, int kout_ovr)
 {
     using S = GemmStage<T, KC_>;
     constexpr int KC = S::KC, LD = S::LD;
@@ -277,7 +277,9 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     __shared__ int s_step[GEMM_MAXSLOT];
     __shared__ int s_nstep;
     using acc_t = typename Mfma<T>::acc_t;
-    const GemmTask tk = tasks[task0 + blockIdx.x];
+    GemmTask tk = tasks[task0 + blockIdx.x];
+    if (kin_ovr > 0) tk.kin = kin_ovr;
+    if (kout_ovr > 0) tk.kout = kout_ovr;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, q = lane >> 4;
     const int ncols = tk.nbox * nrhs;
@@ -396,28 +398,28 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
 // Launch one batch of translation tasks with the chunk depth and row split
 // of the tree's kernel configuration.
 template <typename T>
-static void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks,
-                        int t0, const int32_t *tbox, const int32_t *tab, const int32_t *src,
-                        const T *tables, int KP, int K, const T *in, T *out, int acc)
+void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks,
+                 int t0, const int32_t *tbox, const int32_t *tab, const int32_t *src,
+                 const T *tables, int KP, int K, const T *in, T *out, int acc, int kin_ovr, int kout_ovr)
 {
     const dim3 grid(ntask, nrhs, split);
     if constexpr (sizeof(T) == 4) {
         if (kc >= 64)
             hipLaunchKernelGGL((k_gemm_tasks<T, 64>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc);
+                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
         else if (kc >= 32)
             hipLaunchKernelGGL((k_gemm_tasks<T, 32>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc);
+                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
         else
             hipLaunchKernelGGL((k_gemm_tasks<T, 16>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc);
+                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
     } else {
         if (kc >= 32)
             hipLaunchKernelGGL((k_gemm_tasks<T, 32>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc);
+                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
         else
             hipLaunchKernelGGL((k_gemm_tasks<T, 16>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc);
+                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
     }
 }
 
@@ -719,6 +721,80 @@ static inline void mark(imq_tree_s *, int stage, hipStream_t s)
     if (g_cur_events) (void)hipEventRecord(g_cur_events[stage], s);
 }
 
+// Upward pass: leaf expansions and multipole shifts (stages P2M, M2M).
+template <typename T>
+imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s)
+{
+    const HostTree &h = t->h;
+    PrecData &pd = prec_data<T>(t);
+    DTree<T> v = make_view<T>(t);
+    const int nleaves = int(h.leaves.size());
+    const int K = h.K;
+    const int ld = K | 1;                                      // odd LDS row stride
+    const size_t lds = (size_t(64) * ld + 64) * sizeof(T);
+    T *M = pd.M.as<T>();
+    mark(t, 1, s);
+    hipLaunchKernelGGL(k_p2m<T>, dim3(nleaves), dim3(64), lds, s, v, t->leaves.as<int32_t>(),
+                       pd.us.as<T>(), nrhs, M, ld);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 2, s);
+    const imq_kernel_config &kc = t->kcfg;
+    for (int l = h.nlev - 2; l >= 0; --l) {
+        const DevGemm &g = t->g_m2m;
+        const int t0 = g.level_task_begin[l], t1 = g.level_task_begin[l + 1];
+        if (t1 <= t0) continue;
+        launch_gemm<T>(s, kc.shift_kc > 0 ? kc.shift_kc : 16, kc.shift_split > 0 ? kc.shift_split : 2,
+                       t1 - t0, nrhs, g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
+                       g.src.as<int32_t>(), pd.m2m.as<T>(), t->KP, K, M, M, 0, 0, 0);
+    }
+    IMQ_HIP(hipGetLastError());
+    return IMQ_OK;
+}
+
+// Translations and downward pass into L (stages M2L, P2L, L2L).
+template <typename T>
+imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
+{
+    const HostTree &h = t->h;
+    PrecData &pd = prec_data<T>(t);
+    DTree<T> v = make_view<T>(t);
+    const int nbox = int(h.level.size());
+    const int K = h.K, KP = t->KP;
+    const int ld = K | 1;
+    const size_t lds = (size_t(64) * ld + 64) * sizeof(T);
+    T *M = pd.M.as<T>(), *L = pd.L.as<T>();
+    const imq_kernel_config &kc = t->kcfg;
+    mark(t, 3, s);
+    {
+        const size_t nL = size_t(nbox) * nrhs * K;
+        hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, L, T(0));
+    }
+    if (t->g_m2l.ntasks > 0)
+        launch_gemm<T>(s, kc.m2l_kc > 0 ? kc.m2l_kc : 32, kc.m2l_split > 0 ? kc.m2l_split : 1,
+                       t->g_m2l.ntasks, nrhs, t->g_m2l.tasks.as<GemmTask>(), 0, t->g_m2l.tbox.as<int32_t>(),
+                       t->g_m2l.tab.as<int32_t>(), t->g_m2l.src.as<int32_t>(), pd.m2l.as<T>(), KP, K, M, L,
+                       0, 0, 0);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 4, s);
+    if (t->nxpairs > 0) {
+        T *Lx = pd.Lx.as<T>();
+        hipLaunchKernelGGL(k_p2l_pairs<T>, dim3(t->nxpairs), dim3(64), lds, s, v, t->x_tgt.as<int32_t>(),
+                           pd.us.as<T>(), nrhs, pd.wx.as<T>(), Lx, ld, t->nxpairs);
+        hipLaunchKernelGGL(k_p2l_reduce<T>, dim3(t->nxboxes), dim3(64), 0, s, v, t->x_boxes.as<int32_t>(),
+                           nrhs, Lx, t->nxpairs, L);
+    }
+    for (int l = 1; l < h.nlev; ++l) {
+        const DevGemm &g = t->g_l2l;
+        const int t0 = g.level_task_begin[l], t1 = g.level_task_begin[l + 1];
+        if (t1 <= t0) continue;
+        launch_gemm<T>(s, kc.shift_kc > 0 ? kc.shift_kc : 16, kc.shift_split > 0 ? kc.shift_split : 2,
+                       t1 - t0, nrhs, g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
+                       g.src.as<int32_t>(), pd.l2l.as<T>(), KP, K, L, L, 1, 0, 0);
+    }
+    IMQ_HIP(hipGetLastError());
+    return IMQ_OK;
+}
+
 template <typename T>
 imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
 {
@@ -726,63 +802,22 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     PrecData &pd = prec_data<T>(t);
     DTree<T> v = make_view<T>(t);
     const int nleaves = int(h.leaves.size());
-    const int nbox = int(h.level.size());
-    const int K = h.K;
-    const int ld = K | 1;                                      // odd LDS row stride
-    const size_t lds = (size_t(64) * ld + 64) * sizeof(T);
     const int32_t *leaves = t->leaves.as<int32_t>();
-    T *M = pd.M.as<T>(), *L = pd.L.as<T>();
-    const T *us = pd.us.as<T>();
     double *bs = t->bs.as<double>();
-
-    mark(t, 1, s);
-    hipLaunchKernelGGL(k_p2m<T>, dim3(nleaves), dim3(64), lds, s, v, leaves, us, nrhs, M, ld);
-    IMQ_HIP(hipGetLastError());
-    mark(t, 2, s);
-    const int KP = t->KP;
-    const imq_kernel_config &kc = t->kcfg;
-    auto gemm = [&](const DevGemm &g, int t0, int t1, const T *tables, const T *in, T *out, int acc,
-                    int kcv, int split) {
-        if (t1 <= t0) return;
-        launch_gemm<T>(s, kcv, split, t1 - t0, nrhs,
-                       g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
-                       g.src.as<int32_t>(), tables, KP, K, in, out, acc);
-    };
-    for (int l = h.nlev - 2; l >= 0; --l)
-        gemm(t->g_m2m, t->g_m2m.level_task_begin[l], t->g_m2m.level_task_begin[l + 1], pd.m2m.as<T>(),
-             M, M, 0, kc.shift_kc > 0 ? kc.shift_kc : 16, kc.shift_split > 0 ? kc.shift_split : 2);
-    IMQ_HIP(hipGetLastError());
-    mark(t, 3, s);
-    {
-        const size_t nL = size_t(nbox) * nrhs * K;
-        hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, L, T(0));
-    }
-    gemm(t->g_m2l, 0, t->g_m2l.ntasks, pd.m2l.as<T>(), M, L, 0, kc.m2l_kc > 0 ? kc.m2l_kc : 32,
-         kc.m2l_split > 0 ? kc.m2l_split : 1);
-    IMQ_HIP(hipGetLastError());
-    mark(t, 4, s);
-    if (t->nxpairs > 0) {
-        T *Lx = pd.Lx.as<T>();
-        hipLaunchKernelGGL(k_p2l_pairs<T>, dim3(t->nxpairs), dim3(64), lds, s, v, t->x_tgt.as<int32_t>(), us,
-                           nrhs, pd.wx.as<T>(), Lx, ld, t->nxpairs);
-        hipLaunchKernelGGL(k_p2l_reduce<T>, dim3(t->nxboxes), dim3(64), 0, s, v, t->x_boxes.as<int32_t>(),
-                           nrhs, Lx, t->nxpairs, L);
-    }
-    for (int l = 1; l < h.nlev; ++l)
-        gemm(t->g_l2l, t->g_l2l.level_task_begin[l], t->g_l2l.level_task_begin[l + 1], pd.l2l.as<T>(),
-             L, L, 1, kc.shift_kc > 0 ? kc.shift_kc : 16, kc.shift_split > 0 ? kc.shift_split : 2);
-    IMQ_HIP(hipGetLastError());
+    imq_status st;
+    if ((st = fmm_upward<T>(t, nrhs, s)) != IMQ_OK) return st;
+    if ((st = fmm_translate<T>(t, nrhs, s)) != IMQ_OK) return st;
     mark(t, 5, s);
-    hipLaunchKernelGGL(k_l2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, L, nrhs, bs);
+    hipLaunchKernelGGL(k_l2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs);
     IMQ_HIP(hipGetLastError());
     mark(t, 6, s);
-    hipLaunchKernelGGL(k_p2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, us, nrhs, bs);
+    hipLaunchKernelGGL(k_p2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, pd.us.as<T>(), nrhs, bs);
     IMQ_HIP(hipGetLastError());
     mark(t, 7, s);
     if (t->nwpairs > 0) {
         double *Pw = t->Pw.as<double>();
         hipLaunchKernelGGL(k_m2p_pairs<T>, dim3(t->nwpairs), dim3(64), 0, s, v, t->w_tgt.as<int32_t>(),
-                           t->w_scr.as<int32_t>(), M, pd.wx.as<T>(), nrhs, Pw, t->nwscr);
+                           t->w_scr.as<int32_t>(), pd.M.as<T>(), pd.wx.as<T>(), nrhs, Pw, t->nwscr);
         hipLaunchKernelGGL(k_m2p_reduce<T>, dim3(t->nwleaves), dim3(64), 0, s, v, t->w_leaves.as<int32_t>(),
                            t->w_scr.as<int32_t>(), nrhs, Pw, t->nwscr, bs);
     }
@@ -791,6 +826,16 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     return IMQ_OK;
 }
 
+template void launch_gemm<double>(hipStream_t, int, int, int, int, const GemmTask *, int, const int32_t *,
+                                  const int32_t *, const int32_t *, const double *, int, int,
+                                  const double *, double *, int, int, int);
+template void launch_gemm<float>(hipStream_t, int, int, int, int, const GemmTask *, int, const int32_t *,
+                                 const int32_t *, const int32_t *, const float *, int, int, const float *,
+                                 float *, int, int, int);
+template imq_status fmm_upward<double>(imq_tree_s *, int, hipStream_t);
+template imq_status fmm_upward<float>(imq_tree_s *, int, hipStream_t);
+template imq_status fmm_translate<double>(imq_tree_s *, int, hipStream_t);
+template imq_status fmm_translate<float>(imq_tree_s *, int, hipStream_t);
 template imq_status fmm_sorted<double>(imq_tree_s *, int, hipStream_t);
 template imq_status fmm_sorted<float>(imq_tree_s *, int, hipStream_t);
 template imq_status ensure_workspace<double>(imq_tree_s *, int);

@@ -200,4 +200,69 @@ void make_wx_consts(int p, double *w)
         }
 }
 
+// ---- vertical derivative (adjoint with respect to the shape parameter)
+//
+// Moving a target vertically changes its lifted separation from the sources,
+// so d/dc of the potential is the z-derivative of the local expansion at the
+// target plane.  With d/dz R_j^k = R_{j-1}^k, only the n+m-odd local
+// coefficients contribute there:
+//     dphi/dz (x) = sum_{j+k odd} Re(Lo[j,k] |w|^(j-1-k) w^k),  w = (x - z)/s,
+// stored in the odd layout  idx_odd(j, k) = j(j-1)/2 + max(k-1, 0)  (j >= 1),
+// p(p+1)/2 real numbers.  Rows of these tables are odd coefficients; the
+// K x K buffers are filled in their first p(p+1)/2 rows (and, for the local
+// shift, columns).
+static inline int iro(int j, int k) { return j * (j - 1) / 2 + (k > 0 ? k - 1 : 0); }
+
+static void put2(double *T, int K, int r, bool rim, int c, bool cim, cplx A1, cplx A2, double so)
+{
+    const cplx sum = A1 + A2, dif = A1 - A2;
+    T[r * K + c] += so * sum.real();
+    if (cim) T[r * K + c + 1] += -so * dif.imag();
+    if (rim) {
+        T[(r + 1) * K + c] += so * sum.imag();
+        if (cim) T[(r + 1) * K + c + 1] += so * dif.real();
+    }
+}
+
+void make_m2l_odd_table(int p, int level, int dx, int dy, double cnorm, double *T)
+{
+    const int K = Kof(p);
+    for (int i = 0; i < K * K; ++i) T[i] = 0.0;
+    const double scale = std::ldexp(1.0, level);
+    std::vector<cplx> I;
+    irregular_all(2 * p, double(dx), double(dy), cnorm * scale, I);
+    for (int j = 1; j <= p; ++j)
+        for (int k = (j + 1) & 1; k <= j - 1; k += 2) {
+            const double so = eps(k) * cnm(j - 1, k) * scale * scale;
+            for (int n = 0; n <= p; ++n)
+                for (int m = n & 1; m <= n; m += 2) {
+                    const double si = cnm(n, m) * sgn(j + k);
+                    cplx A1 = si * at(I, 2 * p, n + j, m - k);
+                    cplx A2 = (m > 0) ? sgn(m) * si * at(I, 2 * p, n + j, -m - k) : cplx(0, 0);
+                    put2(T, K, iro(j, k), k > 0, ire(n, m), m > 0, A1, A2, so);
+                }
+        }
+}
+
+void make_l2l_odd_table(int p, int pos, double *T)
+{
+    const int K = Kof(p);
+    for (int i = 0; i < K * K; ++i) T[i] = 0.0;
+    double dx, dy;
+    child_offset(pos, dx, dy);
+    std::vector<cplx> R;
+    regular_all(p, dx, dy, 0.0, R);
+    for (int j = 1; j <= p; ++j)
+        for (int k = (j + 1) & 1; k <= j - 1; k += 2) {
+            const double so = eps(k) * cnm(j - 1, k) * std::ldexp(1.0, -(j - 1));
+            for (int n = j; n <= p; ++n)
+                for (int m = (n + 1) & 1; m <= n - 1; m += 2) {
+                    const double si = 1.0 / (eps(m) * cnm(n - 1, m));
+                    cplx C1 = si * at(R, p, n - j, m - k);
+                    cplx C2 = (m > 0) ? sgn(m) * si * at(R, p, n - j, -m - k) : cplx(0, 0);
+                    put2(T, K, iro(j, k), k > 0, iro(n, m), m > 0, C1, C2, so);
+                }
+        }
+}
+
 }  // namespace imq

@@ -55,6 +55,12 @@ void make_m2m_table(int p, int pos, double *T);
 void make_l2l_table(int p, int pos, double *T);
 void make_m2l_table(int p, int level, int dx, int dy, double cnorm, double *T);
 void make_wx_consts(int p, double *w);
+// n+m-odd local coefficients (vertical derivative at the target plane):
+// translation with the same inputs as make_m2l_table (already including the
+// 1/s^2 of the level), and the parent -> child shift of odd coefficients.
+void make_m2l_odd_table(int p, int level, int dx, int dy, double cnorm, double *T);
+void make_l2l_odd_table(int p, int pos, double *T);
+inline int Kodd(int p) { return p * (p + 1) / 2; }
 double legendre_at_zero(int n, int m);     // P_n^m(0), Condon-Shortley sign
 
 // ------------------------------------------------------------------ tree

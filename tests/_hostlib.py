@@ -81,3 +81,24 @@ def local_eval(p, Lt, pts, z, s):
         mono = np.abs(w) ** (n - m) * w ** m
         phi += Lt[i] * (mono.real if ri == 0 else -mono.imag)
     return phi
+
+
+def odd_layout(p):
+    """n+m-odd local coefficients (j >= 1, k = j-1, j-3, ... >= 0), (Re, Im)."""
+    lay = []
+    for j in range(1, p + 1):
+        for k in range((j + 1) % 2, j, 2):
+            lay.append((j, k, 0))
+            if k > 0:
+                lay.append((j, k, 1))
+    return lay
+
+
+def vertical_eval(p, Lo, pts, z, s):
+    """sum Re(Lo[j,k] |w|^(j-1-k) w^k), w = (x - z)/s: the z-derivative at the plane."""
+    w = ((pts[:, 0] - z[0]) + 1j * (pts[:, 1] - z[1])) / s
+    out = np.zeros(len(pts))
+    for i, (j, k, ri) in enumerate(odd_layout(p)):
+        mono = np.abs(w) ** (j - 1 - k) * w ** k
+        out += Lo[i] * (mono.real if ri == 0 else -mono.imag)
+    return out

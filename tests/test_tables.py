@@ -124,3 +124,40 @@ def test_point_evaluation_constants_point_to_local(p):
     phi = H.local_eval(p, Lt, tgt, zt, s)
     ex = oracle.matvec(src, cn, u, xy_targets=tgt)
     assert np.abs(phi - ex).max() / np.abs(ex).max() < 10 * 0.4 ** (p + 1)
+
+
+@pytest.mark.parametrize("p", [4, 10, 16])
+@pytest.mark.parametrize("pos", [1, 2])
+def test_l2l_odd_shift_is_exact_on_the_plane(p, pos):
+    g = W.rng(88, 200 + p + pos)
+    Ko = p * (p + 1) // 2
+    lay = H.odd_layout(p)
+    Lo = g.standard_normal(Ko) * np.array([0.5 ** j for j, k, ri in lay])
+    zc = np.array([0.25 if pos & 1 else -0.25, 0.25 if pos & 2 else -0.25])
+    pts = zc + (g.random((25, 2)) - 0.5) * 0.5
+    T = H.table(5, p, pos=pos)[:Ko, :Ko]
+    a = H.vertical_eval(p, Lo, pts, np.zeros(2), 1.0)
+    b = H.vertical_eval(p, T @ Lo, pts, zc, 0.5)
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(a).max())
+
+
+@pytest.mark.parametrize("level,dx,dy,cn", [(3, 2, 1, 0.05), (6, -3, 3, 0.02), (9, 2, -2, 0.02)])
+def test_m2l_odd_gives_the_vertical_derivative(level, dx, dy, cn):
+    """d/dc of sum_j u_j / sqrt(r^2 + c^2) is -c sum_j u_j (r^2 + c^2)^(-3/2)."""
+    g = W.rng(92, level)
+    s = 2.0 ** -level
+    zs = np.array([3.5, 4.5]) * s
+    zt = zs + np.array([dx, dy]) * s
+    src = zs + (g.random((40, 2)) - 0.5) * s
+    tgt = zt + (g.random((30, 2)) - 0.5) * s
+    u = g.uniform(-1, 1, 40)
+    d2 = ((tgt[:, None, :] - src[None, :, :]) ** 2).sum(-1)
+    exact = -cn * (u[None, :] * (d2 + cn * cn) ** -1.5).sum(1)
+    errs = []
+    for p in (4, 8, 12, 16):
+        Ko = p * (p + 1) // 2
+        T = H.table(4, p, level=level, dx=dx, dy=dy, cnorm=cn)[:Ko, :]
+        dz = H.vertical_eval(p, T @ H.moments(p, src, u, zs, s), tgt, zt, s)
+        errs.append(np.abs(dz - exact).max() / np.abs(exact).max())
+    assert errs[-1] < 1e-6
+    assert errs[-1] < errs[0]
