@@ -149,9 +149,10 @@ imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
 /* Launch shape of the batched translations (the M2L tile shape and that of
  * the shifts), chosen by the autotuner or by hand; 0 = default.
  *  *_kc    : coefficients staged per pipeline step (16, 32 or 64 in FP32;
- *            16 or 32 in FP64)
+ *            16 or 32 in FP64); for the shifts 0 means one step per source
+ *            slot with at most two row blocks per workgroup (the default)
  *  *_split : the output rows of one tile are spread over this many
- *            workgroups (1 .. 10)                                          */
+ *            workgroups (1 .. 10; ignored when shift_kc is 0)             */
 typedef struct {
     int m2l_kc, m2l_split;
     int shift_kc, shift_split;

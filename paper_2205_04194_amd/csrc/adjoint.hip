@@ -253,7 +253,7 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
         const DevGemm &gl = t->g_l2l;
         const int t0 = gl.level_task_begin[l], t1 = gl.level_task_begin[l + 1];
         if (t1 <= t0) continue;
-        launch_gemm<T>(s, 16, 2, t1 - t0, 2, gl.tasks.as<GemmTask>(), t0, gl.tbox.as<int32_t>(),
+        launch_gemm<T>(s, 0, 0, t1 - t0, 2, gl.tasks.as<GemmTask>(), t0, gl.tbox.as<int32_t>(),
                        gl.tab.as<int32_t>(), gl.src.as<int32_t>(), pd.l2l_odd.as<T>(), KP, K, Lo, Lo, 1, Ko, Ko);
     }
     IMQ_HIP(hipGetLastError());

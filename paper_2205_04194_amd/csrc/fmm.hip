@@ -250,15 +250,15 @@ constexpr int GEMM_MAXSLOT = 27;
 // (rows x KC) and source chunk (KC x 64 columns) are staged in LDS, and the
 // next step's are loaded into registers while the matrix cores work on the
 // current one.
-template <typename T, int KC_>
+template <typename T, int KC_, int MAXRB_>
 struct GemmStage {
     static constexpr int KC = KC_;                                  // k per step
     static constexpr int LD = KC + (sizeof(T) == 4 ? 1 : 2);       // LDS row stride
-    static constexpr int NA = GEMM_MAXRB * 16 * KC / 256;          // table elems / thread
+    static constexpr int NA = MAXRB_ * 16 * KC / 256;              // table elems / thread
     static constexpr int NB = GEMM_TILE * KC / 256;                // source elems / thread
 };
 
-template <typename T, int KC_>
+template <typename T, int KC_, int MAXRB>
 __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__ tasks, int task0,
                                                     const int32_t *__restrict__ tbox,
                                                     const int32_t *__restrict__ tab,
@@ -267,9 +267,9 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
                                                     const T *__restrict__ in, T *__restrict__ out,
                                                     int accumulate, int kin_ovr, int kout_ovr)
 {
-    using S = GemmStage<T, KC_>;
+    using S = GemmStage<T, KC_, MAXRB>;
     constexpr int KC = S::KC, LD = S::LD;
-    __shared__ T As[GEMM_MAXRB * 16 * LD];
+    __shared__ T As[MAXRB * 16 * LD];
     __shared__ T Bs[GEMM_TILE * LD];
     __shared__ int s_col[GEMM_MAXSLOT][GEMM_TILE];
     __shared__ int s_tab[GEMM_MAXSLOT];
@@ -343,9 +343,9 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
         }
     };
 
-    acc_t acc[GEMM_MAXRB];
+    acc_t acc[MAXRB];
 #pragma unroll
-    for (int i = 0; i < GEMM_MAXRB; ++i)
+    for (int i = 0; i < MAXRB; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[i][v] = T(0);
 
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
         for (int k0 = 0; k0 < KC; k0 += 4) {
             const T b = Bw[k0];
 #pragma unroll
-            for (int rb = 0; rb < GEMM_MAXRB; ++rb)
+            for (int rb = 0; rb < MAXRB; ++rb)
                 if (rb < nrb) acc[rb] = Mfma<T>::mac(Aw[rb * 16 * LD + k0], b, acc[rb]);
         }
     }
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
         const int bl = gc / nrhs, r = gc - bl * nrhs;
         T *o = out + (size_t(tbox[tk.box0 + bl]) * nrhs + r) * K;
 #pragma unroll
-        for (int rb = 0; rb < GEMM_MAXRB; ++rb)
+        for (int rb = 0; rb < MAXRB; ++rb)
             if (rb < nrb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -395,32 +395,36 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     }
 }
 
-// Launch one batch of translation tasks with the chunk depth and row split
-// of the tree's kernel configuration.
+// Launch one batch of translation tasks.  kc > 0: that many coefficients
+// per pipeline step and the rows of a tile spread over `split` workgroups.
+// kc == 0 ("whole" mode, for the short level-by-level shifts): every slot
+// is staged in one step and each workgroup takes at most two row blocks, so
+// a task is one memory round trip per slot.
 template <typename T>
 void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks,
                  int t0, const int32_t *tbox, const int32_t *tab, const int32_t *src,
                  const T *tables, int KP, int K, const T *in, T *out, int acc, int kin_ovr, int kout_ovr)
 {
-    const dim3 grid(ntask, nrhs, split);
-    if constexpr (sizeof(T) == 4) {
-        if (kc >= 64)
-            hipLaunchKernelGGL((k_gemm_tasks<T, 64>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
-        else if (kc >= 32)
-            hipLaunchKernelGGL((k_gemm_tasks<T, 32>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
-        else
-            hipLaunchKernelGGL((k_gemm_tasks<T, 16>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
-    } else {
-        if (kc >= 32)
-            hipLaunchKernelGGL((k_gemm_tasks<T, 32>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
-        else
-            hipLaunchKernelGGL((k_gemm_tasks<T, 16>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,
-                               tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr);
+#define IMQ_GEMM(KCV, RB)                                                                            \
+    hipLaunchKernelGGL((k_gemm_tasks<T, KCV, RB>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,  \
+                       tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr)
+    if (kc == 0) {
+        const int nrb = KP / 16;
+        const dim3 grid(ntask, nrhs, (nrb + 1) / 2);
+        if (KP <= 96) IMQ_GEMM(96, 2);
+        else IMQ_GEMM(160, 2);
+        return;
     }
+    const dim3 grid(ntask, nrhs, split > 0 ? split : 1);
+    if constexpr (sizeof(T) == 4) {
+        if (kc >= 64) IMQ_GEMM(64, GEMM_MAXRB);
+        else if (kc >= 32) IMQ_GEMM(32, GEMM_MAXRB);
+        else IMQ_GEMM(16, GEMM_MAXRB);
+    } else {
+        if (kc >= 32) IMQ_GEMM(32, GEMM_MAXRB);
+        else IMQ_GEMM(16, GEMM_MAXRB);
+    }
+#undef IMQ_GEMM
 }
 
 template <typename T>
@@ -743,9 +747,9 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s)
         const DevGemm &g = t->g_m2m;
         const int t0 = g.level_task_begin[l], t1 = g.level_task_begin[l + 1];
         if (t1 <= t0) continue;
-        launch_gemm<T>(s, kc.shift_kc > 0 ? kc.shift_kc : 16, kc.shift_split > 0 ? kc.shift_split : 2,
-                       t1 - t0, nrhs, g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
-                       g.src.as<int32_t>(), pd.m2m.as<T>(), t->KP, K, M, M, 0, 0, 0);
+        launch_gemm<T>(s, kc.shift_kc, kc.shift_split, t1 - t0, nrhs, g.tasks.as<GemmTask>(), t0,
+                       g.tbox.as<int32_t>(), g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.m2m.as<T>(),
+                       t->KP, K, M, M, 0, 0, 0);
     }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
@@ -787,9 +791,9 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
         const DevGemm &g = t->g_l2l;
         const int t0 = g.level_task_begin[l], t1 = g.level_task_begin[l + 1];
         if (t1 <= t0) continue;
-        launch_gemm<T>(s, kc.shift_kc > 0 ? kc.shift_kc : 16, kc.shift_split > 0 ? kc.shift_split : 2,
-                       t1 - t0, nrhs, g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
-                       g.src.as<int32_t>(), pd.l2l.as<T>(), KP, K, L, L, 1, 0, 0);
+        launch_gemm<T>(s, kc.shift_kc, kc.shift_split, t1 - t0, nrhs, g.tasks.as<GemmTask>(), t0,
+                       g.tbox.as<int32_t>(), g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.l2l.as<T>(), KP,
+                       K, L, L, 1, 0, 0);
     }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
