@@ -161,7 +161,8 @@ def main():
     flops = {"m2l": m2l_flops(info), "p2p": p2p_flops(info)}
     if dom in flops:
         achieved = flops[dom] / (st[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[head],
+        roof = {"kernel": dom, "bound": "mfma" if dom == "m2l" else "alu", "achieved": achieved,
+                "peak": PEAK_TFLOPS[head],
                 "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[head], "traffic": None,
                 "algorithmic_flops_per_launch": flops[dom], "launch_ms": st[dom]}
     else:

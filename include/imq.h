@@ -160,6 +160,14 @@ typedef struct {
 
 imq_status imq_set_kernel_config(imq_tree tree, const imq_kernel_config *cfg);
 
+/* Change the per-level truncation of the M2L translations (and of the local
+ * shifts that follow them) on an existing tree: orders[l] for l < nlevels
+ * (levels beyond are left as they are), each in [1, order_p] or 0 for
+ * order_p.  The truncated translation is the leading block of the full
+ * table, so nothing is regenerated; the batches' sizes are re-uploaded with a
+ * synchronous copy.  Multipoles stay at order_p. */
+imq_status imq_set_level_orders(imq_tree tree, int nlevels, const int *orders);
+
 typedef struct {          /* host */
     int64_t npoints, nboxes, nleaves;
     int depth;            /* deepest level present                           */

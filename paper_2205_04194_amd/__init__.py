@@ -167,6 +167,11 @@ class Tree:
         _lib.check(_lib.load().imq_set_kernel_config(self._h, ctypes.byref(cfg)),
                    "imq_set_kernel_config")
 
+    def set_level_orders(self, orders) -> None:
+        """Per-level truncation of the translations (0 = order p)."""
+        arr = (ctypes.c_int * max(1, len(orders)))(*[int(o) for o in orders])
+        _lib.check(_lib.load().imq_set_level_orders(self._h, len(orders), arr), "imq_set_level_orders")
+
     def set_stage_timing(self, on: bool = True) -> None:
         _lib.check(_lib.load().imq_set_stage_timing(self._h, int(on)), "imq_set_stage_timing")
 

@@ -68,6 +68,7 @@ SIGNATURES = {
     "imq_matvec_backward": (_int, [_vp, _int, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
     "imq_get_tree_info": (_int, [_vp, _p(TreeInfo)]),
     "imq_set_kernel_config": (_int, [_vp, _p(KernelConfig)]),
+    "imq_set_level_orders": (_int, [_vp, _int, _p(_int)]),
     "imq_set_stage_timing": (_int, [_vp, _int]),
     "imq_get_stage_times": (_int, [_vp, _p(_dbl)]),
     "imq_stage_name": (ctypes.c_char_p, [_int]),

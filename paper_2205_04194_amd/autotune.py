@@ -1,0 +1,122 @@
+"""Autotuner for the fast product: translation orders per level, precision
+and the launch shape of the translation batches.
+
+The error of a configuration is measured, never modelled: the product is
+compared on a sample of rows with exact FP64 direct sums computed on the GPU
+(``Tree.rows_exact``).  The cost model of Sec. 2.3 is not used; the time of a
+configuration is measured with events.
+
+Search (all on one tree, no rebuild):
+  1. for each precision, the uniform order p is lowered from the tree's order
+     while the sampled error stays within the target;
+  2. per level, deepest first, the translation order is lowered while the
+     error stays within the target (the lifted vertical offset c makes deep
+     levels, whose boxes are small next to c, converge fastest);
+  3. the M2L pipeline depth and row split are timed and the fastest kept.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+
+@dataclass
+class TuneResult:
+    precision: str
+    level_orders: List[int]
+    m2l_kc: int
+    m2l_split: int
+    error: float
+    ms: float
+    trials: List[dict] = field(default_factory=list)
+
+
+def _error(tree, u, rows, exact, prec):
+    b = tree.matvec(u, prec)
+    return float(torch.linalg.norm(b[rows] - exact) / torch.linalg.norm(exact))
+
+
+def _time(tree, u, prec, reps=5):
+    tree.matvec(u, prec)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        tree.matvec(u, prec)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"),
+         nrows: int = 1000, safety: float = 0.8, seed: int = 0,
+         kcs=(16, 32, 64), splits=(1, 2)) -> TuneResult:
+    """Fastest configuration of ``tree`` whose sampled-row relative 2-norm
+    error is at most ``safety * target``; the tree is left configured."""
+    n = tree.n
+    g = np.random.default_rng(seed)
+    rows = torch.tensor(np.sort(g.choice(n, min(nrows, n), replace=False)), device=tree.device)
+    exact = tree.rows_exact(u, rows)
+    info = tree.info()
+    nlev = info["nlevels"]
+    pmax = info["order_p"]
+    active = [l for l in range(nlev) if info["level_m2l_pairs"][l] > 0]
+    budget = safety * target
+    best: Optional[TuneResult] = None
+    trials = []
+    for prec in precisions:
+        orders = [pmax] * nlev
+        tree.set_level_orders(orders)
+        tree.set_kernel_config()
+        err = _error(tree, u, rows, exact, prec)
+        trials.append({"prec": prec, "orders": list(orders), "err": err})
+        if err > budget:
+            continue
+        # 1. lower the uniform order
+        while orders[0] > 2:
+            trial = [o - 1 for o in orders]
+            tree.set_level_orders(trial)
+            e = _error(tree, u, rows, exact, prec)
+            trials.append({"prec": prec, "orders": list(trial), "err": e})
+            if e > budget:
+                break
+            orders, err = trial, e
+        tree.set_level_orders(orders)
+        # 2. lower the deep levels further
+        for l in reversed(active):
+            while orders[l] > 1:
+                trial = list(orders)
+                trial[l] -= 1
+                tree.set_level_orders(trial)
+                e = _error(tree, u, rows, exact, prec)
+                trials.append({"prec": prec, "orders": list(trial), "err": e})
+                if e > budget:
+                    break
+                orders, err = trial, e
+        tree.set_level_orders(orders)
+        # 3. launch shape of the translations
+        shape, ms = (0, 0), float("inf")
+        for kc in kcs:
+            if prec == "fp64" and kc > 32:
+                continue
+            for sp in splits:
+                tree.set_kernel_config(m2l_kc=kc, m2l_split=sp)
+                t = _time(tree, u, prec)
+                trials.append({"prec": prec, "m2l_kc": kc, "m2l_split": sp, "ms": t})
+                if t < ms:
+                    shape, ms = (kc, sp), t
+        res = TuneResult(prec, list(orders), shape[0], shape[1], err, ms)
+        if best is None or res.ms < best.ms:
+            best = res
+    if best is None:
+        raise RuntimeError(f"no precision reaches the target {target:g} at order {pmax}")
+    tree.set_level_orders(best.level_orders)
+    tree.set_kernel_config(m2l_kc=best.m2l_kc, m2l_split=best.m2l_split)
+    best.error = _error(tree, u, rows, exact, best.precision)
+    best.trials = trials
+    return best

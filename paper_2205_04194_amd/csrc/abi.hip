@@ -332,6 +332,27 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
     return IMQ_OK;
 }
 
+imq_status imq_set_level_orders(imq_tree t, int nlevels, const int *orders)
+{
+    imq_status st = check_tree(t);
+    if (st != IMQ_OK) return st;
+    if (nlevels < 0 || (nlevels > 0 && !orders)) { set_error("bad level orders"); return IMQ_EINVAL; }
+    HostTree &h = t->h;
+    for (int l = 0; l < nlevels && l < h.nlev; ++l)
+        if (orders[l] < 0 || orders[l] > h.p) { set_error("level order out of [0, order_p]"); return IMQ_EINVAL; }
+    for (int l = 0; l < nlevels && l < h.nlev; ++l) h.Klev[l] = Kof(orders[l] > 0 ? orders[l] : h.p);
+    for (GemmTask &k : h.m2l.tasks) k.kin = k.kout = h.Klev[k.level];
+    for (GemmTask &k : h.l2l.tasks) {
+        k.kin = h.Klev[k.level - 1];
+        k.kout = h.Klev[k.level];
+    }
+    IMQ_HIP(hipDeviceSynchronize());
+    if ((st = upload(t->Klev, h.Klev)) != IMQ_OK) return st;
+    if ((st = upload(t->g_m2l.tasks, h.m2l.tasks)) != IMQ_OK) return st;
+    if ((st = upload(t->g_l2l.tasks, h.l2l.tasks)) != IMQ_OK) return st;
+    return IMQ_OK;
+}
+
 imq_status imq_set_stage_timing(imq_tree t, int on)
 {
     imq_status st = check_tree(t);
