@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-iters", type=int, default=150,
                     help="GMRES products per solve (0: skip the solve comparison)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="uniform order p and default launch shapes instead of the autotuner")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -145,17 +147,38 @@ def main():
                         device=dev)
     exact = tree.rows_exact(u, rows)
     results = {}
-    for prec in (["fp32", "fp64"] if args.prec == "auto" else [args.prec]):
+    precs = ["fp32", "fp64"] if args.prec == "auto" else [args.prec]
+    # reference: uniform order p, default launch shapes
+    for prec in precs:
         b = tree.matvec(u, prec)
         err = float(torch.linalg.norm(b[rows] - exact) / torch.linalg.norm(exact))
         ms, stages = time_products(tree, u, prec, args.steps, args.warmup)
         results[prec] = {"ms": ms, "err": err, "stages": stages}
-        log(f"{prec}: {ms:.3f} ms/product, rel err {err:.2e}, stages " +
+        log(f"{prec} uniform p={args.p}: {ms:.3f} ms/product, rel err {err:.2e}, stages " +
+            " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
+    tuned = None
+    if not args.no_tune:
+        from paper_2205_04194_amd import autotune
+        t0 = time.perf_counter()
+        res = autotune.tune(tree, u, target=1e-6, precisions=precs, seed=1)
+        t_tune = time.perf_counter() - t0
+        b = tree.matvec(u, res.precision)
+        err = float(torch.linalg.norm(b[rows] - exact) / torch.linalg.norm(exact))
+        ms, stages = time_products(tree, u, res.precision, args.steps, args.warmup)
+        tuned = {"ms": ms, "err": err, "stages": stages, "prec": res.precision,
+                 "level_orders": res.level_orders, "m2l_kc": res.m2l_kc, "m2l_split": res.m2l_split,
+                 "tune_s": t_tune}
+        info = tree.info()
+        log(f"tuned {res.precision} orders {res.level_orders} kc {res.m2l_kc} split {res.m2l_split}: "
+            f"{ms:.3f} ms/product, rel err {err:.2e}, stages " +
             " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
 
-    ok = [p for p in results if results[p]["err"] <= 1e-6]
-    head = min(ok, key=lambda p: results[p]["ms"]) if ok else "fp64"
-    r = results[head]
+    if tuned is not None and tuned["err"] <= 1e-6:
+        head, r = tuned["prec"], tuned
+    else:
+        ok = [p for p in results if results[p]["err"] <= 1e-6]
+        head = min(ok, key=lambda p: results[p]["ms"]) if ok else "fp64"
+        r = results[head]
     st = r["stages"]
     dom = max(st, key=st.get)
     flops = {"m2l": m2l_flops(info), "p2p": p2p_flops(info)}
@@ -183,12 +206,14 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32"}[head],
         "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "c": d["c"], "leaf": args.leaf, "p": args.p,
-                   "nrhs": 1, "precision": head},
+                   "nrhs": 1, "precision": head,
+                   "level_orders": r.get("level_orders"), "m2l_kc": r.get("m2l_kc"),
+                   "m2l_split": r.get("m2l_split")},
         "rel_err_sampled_rows": r["err"],
         "tree_build_s": t_build,
         "stage_ms": st,
-        "other_precisions": {p: {"ms_per_step": v["ms"], "rel_err": v["err"]}
-                             for p, v in results.items() if p != head},
+        "uniform_order": {p: {"ms_per_step": v["ms"], "rel_err": v["err"]} for p, v in results.items()},
+        "tune_s": r.get("tune_s"),
         "roofline": roof,
     }
     if args.solve_iters > 0:

@@ -78,20 +78,23 @@ __global__ void k_scatter(int64_t N, const int32_t *__restrict__ perm, const dou
     if (i < N) b[r * ldb + perm[i]] = Tout(bs[r * N + i] * scale[i]);
 }
 
-// Monomials of one point for every stored coefficient: f(k, value) with
-// value = |w|^(n-m) w^m split into real and imaginary parts (the caller
-// passes conj(w) for multipoles).
-template <typename T, typename F>
-__device__ __forceinline__ void monomials(int P, T wx, T wy, F &&f)
+// Monomials of one point for every stored coefficient: f(k, value, imag)
+// with value the real (imag = false) or imaginary part of |w|^(n-m) w^m (the
+// caller passes conj(w) for multipoles).  P is a compile-time order, so every
+// coefficient index is a constant.
+template <int P, typename T, typename F>
+__device__ __forceinline__ void monomials(T wx, T wy, F &&f)
 {
     const T r2 = wx * wx + wy * wy;
     T pr = T(1), pi = T(0);
+#pragma unroll
     for (int m = 0; m <= P; ++m) {
         T tr = pr, ti = pi;
+#pragma unroll
         for (int n = m; n <= P; n += 2) {
-            const int k = cidx(n, m);
-            f(k, tr);
-            if (m > 0) f(k + 1, ti);
+            const int k = n * (n + 1) / 2 + (m > 0 ? m - 1 : 0);
+            f(k, tr, false);
+            if (m > 0) f(k + 1, ti, true);
             tr *= r2;
             ti *= r2;
         }
@@ -100,6 +103,17 @@ __device__ __forceinline__ void monomials(int P, T wx, T wy, F &&f)
         pr = nr;
     }
 }
+
+// Launch kern<T, P>(args...) for the runtime order p in [1, 16].
+#define IMQ_DISPATCH_P(p, LAUNCH)                                                        \
+    switch (p) {                                                                         \
+    case 1: LAUNCH(1); break;   case 2: LAUNCH(2); break;   case 3: LAUNCH(3); break;   \
+    case 4: LAUNCH(4); break;   case 5: LAUNCH(5); break;   case 6: LAUNCH(6); break;   \
+    case 7: LAUNCH(7); break;   case 8: LAUNCH(8); break;   case 9: LAUNCH(9); break;   \
+    case 10: LAUNCH(10); break; case 11: LAUNCH(11); break; case 12: LAUNCH(12); break; \
+    case 13: LAUNCH(13); break; case 14: LAUNCH(14); break; case 15: LAUNCH(15); break; \
+    default: LAUNCH(16); break;                                                          \
+    }
 
 // Column sums of an LDS matrix: sum_{j < n} a[j*ld + k] * w[j], unrolled so
 // that several reads are in flight.
@@ -122,24 +136,27 @@ __device__ __forceinline__ T lds_dot(const T *a, int ld, int k, const T *w, int 
 // One wave per leaf: each lane writes its point's monomials as one row of
 // an LDS matrix (odd row stride), then each lane sums one coefficient's
 // column against the weights of every right-hand side.
-template <typename T>
+constexpr int P2M_CHUNK = 32;      // points staged per round (LDS per wave halves vs 64)
+
+template <typename T, int P>
 __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restrict__ leaves,
                                             const T *__restrict__ us, int nrhs, T *__restrict__ M, int ld)
 {
     extern __shared__ unsigned char smem_raw[];
-    T *mono = reinterpret_cast<T *>(smem_raw);   // [64][ld]
-    T *su = mono + 64 * ld;                      // [64]
+    T *mono = reinterpret_cast<T *>(smem_raw);   // [P2M_CHUNK][ld]
+    T *su = mono + P2M_CHUNK * ld;               // [P2M_CHUNK]
     const int b = leaves[blockIdx.x];
     const int beg = t.begin[b], end = t.end[b];
     const T inv_s = pow2i<T>(t.level[b]);
-    const int P = t.P, K = t.K, lane = threadIdx.x;
-    for (int c0 = beg; c0 < end; c0 += 64) {
-        const int n = min(64, end - c0);
+    constexpr int K = (P + 1) * (P + 2) / 2;
+    const int lane = threadIdx.x;
+    for (int c0 = beg; c0 < end; c0 += P2M_CHUNK) {
+        const int n = min(P2M_CHUNK, end - c0);
         __syncthreads();
         if (lane < n) {
             T *row = mono + lane * ld;
-            monomials<T>(P, t.xl[c0 + lane] * inv_s, -t.yl[c0 + lane] * inv_s,
-                         [&](int k, T v) { row[k] = v; });
+            monomials<P>(t.xl[c0 + lane] * inv_s, -t.yl[c0 + lane] * inv_s,
+                         [&](int k, T v, bool) { row[k] = v; });
         }
         for (int r = 0; r < nrhs; ++r) {
             __syncthreads();
@@ -435,32 +452,25 @@ __global__ void k_fill(size_t n, T *__restrict__ p, T v)
 }
 
 // L2P: potential = sum Re(Lt[n,m] |w|^(n-m) w^m) at each point of a leaf.
-template <typename T>
+// The leaf's local expansion is staged in LDS; the order is a compile-time
+// constant so the evaluation loop is fully unrolled.
+template <typename T, int P>
 __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restrict__ leaves,
                                             const T *__restrict__ L, int nrhs, double *__restrict__ bs)
 {
+    constexpr int K = (P + 1) * (P + 2) / 2;
+    __shared__ T Ls[K];
     const int b = leaves[blockIdx.x];
     const T inv_s = pow2i<T>(t.level[b]);
-    const int P = t.P, K = t.K;
-    for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
-        const T wx = t.xl[i] * inv_s, wy = t.yl[i] * inv_s;
-        const T r2 = wx * wx + wy * wy;
-        for (int r = 0; r < nrhs; ++r) {
-            const T *Lb = L + (size_t(b) * nrhs + r) * K;
-            T acc = T(0), pr = T(1), pi = T(0);
-            for (int m = 0; m <= P; ++m) {
-                T tr = pr, ti = pi;
-                for (int n = m; n <= P; n += 2) {
-                    const int k = cidx(n, m);
-                    acc += Lb[k] * tr;
-                    if (m > 0) acc -= Lb[k + 1] * ti;
-                    tr *= r2;
-                    ti *= r2;
-                }
-                const T nr = pr * wx - pi * wy;
-                pi = pr * wy + pi * wx;
-                pr = nr;
-            }
+    for (int r = 0; r < nrhs; ++r) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += blockDim.x) Ls[k] = L[(size_t(b) * nrhs + r) * K + k];
+        __syncthreads();
+        for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+            T acc = T(0);
+            // real part of Lt * monomial: Re*Re - Im*Im
+            monomials<P>(t.xl[i] * inv_s, t.yl[i] * inv_s,
+                         [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
             bs[r * t.N + i] = double(acc);
         }
     }
@@ -735,11 +745,14 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s)
     const int nleaves = int(h.leaves.size());
     const int K = h.K;
     const int ld = K | 1;                                      // odd LDS row stride
-    const size_t lds = (size_t(64) * ld + 64) * sizeof(T);
     T *M = pd.M.as<T>();
     mark(t, 1, s);
-    hipLaunchKernelGGL(k_p2m<T>, dim3(nleaves), dim3(64), lds, s, v, t->leaves.as<int32_t>(),
-                       pd.us.as<T>(), nrhs, M, ld);
+    const size_t lds_p2m = (size_t(P2M_CHUNK) * ld + P2M_CHUNK) * sizeof(T);
+#define IMQ_P2M(PP)                                                                           \
+    hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, t->leaves.as<int32_t>(), \
+                       pd.us.as<T>(), nrhs, M, ld)
+    IMQ_DISPATCH_P(h.p, IMQ_P2M)
+#undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
     mark(t, 2, s);
     const imq_kernel_config &kc = t->kcfg;
@@ -812,7 +825,10 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     if ((st = fmm_upward<T>(t, nrhs, s)) != IMQ_OK) return st;
     if ((st = fmm_translate<T>(t, nrhs, s)) != IMQ_OK) return st;
     mark(t, 5, s);
-    hipLaunchKernelGGL(k_l2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs);
+#define IMQ_L2P(PP) \
+    hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs)
+    IMQ_DISPATCH_P(h.p, IMQ_L2P)
+#undef IMQ_L2P
     IMQ_HIP(hipGetLastError());
     mark(t, 6, s);
     hipLaunchKernelGGL(k_p2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, pd.us.as<T>(), nrhs, bs);

@@ -391,10 +391,20 @@ void build_gemm_lists(HostTree &t)
             if (t.pos[c] == s) return c;
         return -1;
     };
+    // Multipoles are read by V lists (as sources) and W lists; locals are
+    // written by V and X lists.  Shifts above the first level that needs them
+    // would only move zeros or unused coefficients, so they are not batched.
+    int need_m = L, need_l = L;
+    for (int b = 0; b < nbox; ++b) {
+        if (t.v_off[b + 1] > t.v_off[b] || t.x_off[b + 1] > t.x_off[b]) need_l = std::min(need_l, t.level[b]);
+        for (int v = t.v_off[b]; v < t.v_off[b + 1]; ++v) need_m = std::min(need_m, t.level[t.v_idx[v]]);
+        for (int w = t.w_off[b]; w < t.w_off[b + 1]; ++w) need_m = std::min(need_m, t.level[t.w_idx[w]]);
+    }
     // multipole shift: parents level by level, slots = child positions
     t.m2m.level_task_begin.assign(L + 1, 0);
     for (int l = 0; l < L; ++l) {
         t.m2m.level_task_begin[l] = int32_t(t.m2m.tasks.size());
+        if (l < need_m) continue;
         std::vector<int32_t> parents;
         for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
             if (t.nchild[b] > 0) parents.push_back(b);
@@ -405,7 +415,7 @@ void build_gemm_lists(HostTree &t)
     t.l2l.level_task_begin.assign(L + 1, 0);
     for (int l = 0; l < L; ++l) {
         t.l2l.level_task_begin[l] = int32_t(t.l2l.tasks.size());
-        if (l == 0) continue;
+        if (l == 0 || l - 1 < need_l) continue;     // the parent holds no local expansion
         for (int pos = 0; pos < 4; ++pos) {
             std::vector<int32_t> kids;
             for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
