@@ -39,20 +39,25 @@ def p2p_flops(info, nrhs=1):
 
 
 def time_products(tree, u, prec, steps, warmup):
+    """ms per product over `steps` timed products (no stage events inside the
+    timed region: each event record costs a few microseconds of idle GPU),
+    then a separate pass with stage events for the per-stage breakdown."""
     import torch
     for _ in range(warmup):
         tree.matvec(u, prec)
     torch.cuda.synchronize()
-    tree.set_stage_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     e0.record()
     for _ in range(steps):
         tree.matvec(u, prec)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    tree.set_stage_timing(True)
+    for _ in range(max(3, min(steps, 10))):
+        tree.matvec(u, prec)
+    torch.cuda.synchronize()
     stages = tree.stage_times()
     tree.set_stage_timing(False)
     return ms, stages

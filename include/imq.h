@@ -146,16 +146,17 @@ imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
                                const void *g, void *dv, double *dc, double *dxy,
                                imq_prec prec, hipStream_t stream);
 
-/* Launch shape of the batched translations (the M2L tile shape and that of
- * the shifts), chosen by the autotuner or by hand; 0 = default.
- *  *_kc    : coefficients staged per pipeline step (16, 32 or 64 in FP32;
- *            16 or 32 in FP64); for the shifts 0 means one step per source
- *            slot with at most two row blocks per workgroup (the default)
- *  *_split : the output rows of one tile are spread over this many
- *            workgroups (1 .. 10; ignored when shift_kc is 0)             */
+/* Launch shape of the batched translations, chosen by the autotuner or by
+ * hand; 0 = default.
+ *  m2l_kc     : coefficients staged per M2L pipeline step (16, 32 or 64 in
+ *               FP32; 16 or 32 in FP64)
+ *  m2l_split  : the output rows of one M2L tile are spread over this many
+ *               workgroups (1 .. 10)
+ *  shift_cols : columns (box, rhs) per workgroup of the level-by-level
+ *               shifts, 16 or 32 (32 only in FP32; 0 picks by level size) */
 typedef struct {
     int m2l_kc, m2l_split;
-    int shift_kc, shift_split;
+    int shift_cols;
 } imq_kernel_config;
 
 imq_status imq_set_kernel_config(imq_tree tree, const imq_kernel_config *cfg);

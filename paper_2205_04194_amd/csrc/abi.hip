@@ -145,10 +145,16 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     pad(m2m);
     pad(l2l);
     pad(m2l);
-    for (auto pr : {std::make_pair(&h.m2m, &t->g_m2m), std::make_pair(&h.m2l, &t->g_m2l),
-                    std::make_pair(&h.l2l, &t->g_l2l)}) {
-        const GemmList &g = *pr.first;
-        DevGemm &d = *pr.second;
+    {
+        std::vector<double> pk;
+        pack_shift_tables(m2m, KP, pk, t->cut_m2m);
+        m2m.swap(pk);
+        pack_shift_tables(l2l, KP, pk, t->cut_l2l);
+        l2l.swap(pk);
+    }
+    {
+        const GemmList &g = h.m2l;
+        DevGemm &d = t->g_m2l;
         if ((st = upload(d.tasks, g.tasks)) != IMQ_OK) return st;
         if ((st = upload(d.tbox, g.tbox)) != IMQ_OK) return st;
         if ((st = upload(d.tab, g.tab)) != IMQ_OK) return st;
@@ -156,6 +162,8 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
         d.level_task_begin = g.level_task_begin;
         d.ntasks = int(g.tasks.size());
     }
+    if ((st = upload(t->sh_par, h.sh_par)) != IMQ_OK) return st;
+    if ((st = upload(t->sh_kids, h.sh_kids)) != IMQ_OK) return st;
     if ((st = upload(t->f64.m2m, m2m)) != IMQ_OK) return st;
     if ((st = upload(t->f64.l2l, l2l)) != IMQ_OK) return st;
     if ((st = upload(t->f64.m2l, m2l)) != IMQ_OK) return st;
@@ -173,9 +181,10 @@ static void free_tree(imq_tree_s *t)
                       &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
                       &t->cn, &t->leaves, &t->xy_user, &t->set_off, &t->bs, &t->sol,
-                      &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw, &t->adj};
+                      &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw, &t->adj,
+                      &t->sh_par, &t->sh_kids};
     for (DevBuf *b : bufs) dev_free(*b);
-    for (DevGemm *g : {&t->g_m2m, &t->g_m2l, &t->g_l2l}) {
+    for (DevGemm *g : {&t->g_m2l}) {
         dev_free(g->tasks); dev_free(g->tbox); dev_free(g->tab); dev_free(g->src);
     }
     for (PrecData *pd : {&t->f64, &t->f32}) {
@@ -323,8 +332,8 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
 {
     if (!t || !cfg) { set_error("null argument"); return IMQ_EINVAL; }
     auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
-    if (!ok_kc(cfg->m2l_kc) || !ok_kc(cfg->shift_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
-        cfg->shift_split < 0 || cfg->shift_split > 10) {
+    if (!ok_kc(cfg->m2l_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
+        (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32)) {
         set_error("kernel config out of range");
         return IMQ_EINVAL;
     }
@@ -342,14 +351,9 @@ imq_status imq_set_level_orders(imq_tree t, int nlevels, const int *orders)
         if (orders[l] < 0 || orders[l] > h.p) { set_error("level order out of [0, order_p]"); return IMQ_EINVAL; }
     for (int l = 0; l < nlevels && l < h.nlev; ++l) h.Klev[l] = Kof(orders[l] > 0 ? orders[l] : h.p);
     for (GemmTask &k : h.m2l.tasks) k.kin = k.kout = h.Klev[k.level];
-    for (GemmTask &k : h.l2l.tasks) {
-        k.kin = h.Klev[k.level - 1];
-        k.kout = h.Klev[k.level];
-    }
     IMQ_HIP(hipDeviceSynchronize());
     if ((st = upload(t->Klev, h.Klev)) != IMQ_OK) return st;
     if ((st = upload(t->g_m2l.tasks, h.m2l.tasks)) != IMQ_OK) return st;
-    if ((st = upload(t->g_l2l.tasks, h.l2l.tasks)) != IMQ_OK) return st;
     return IMQ_OK;
 }
 
@@ -421,7 +425,8 @@ static const void *field(const HostTree &h, const char *w, int64_t &n, int &elem
 #define F(name) if (!std::strcmp(w, #name)) { n = int64_t(h.name.size()); elem = int(sizeof(h.name[0])); return h.name.data(); }
     F(perm) F(xl) F(yl) F(level) F(set) F(ix) F(iy) F(parent) F(child0) F(nchild) F(pos) F(begin)
     F(end) F(isleaf) F(cx) F(cy) F(level_begin) F(leaves) F(u_off) F(u_idx) F(v_off) F(v_idx)
-    F(v_cls) F(w_off) F(w_idx) F(x_off) F(x_idx) F(Klev) F(side) F(cn)
+    F(v_cls) F(w_off) F(w_idx) F(x_off) F(x_idx) F(Klev) F(side) F(cn) F(sh_par) F(sh_kids)
+    F(sh_level_begin)
 #undef F
     n = -1;
     elem = 0;

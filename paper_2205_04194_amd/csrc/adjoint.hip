@@ -193,6 +193,11 @@ imq_status ensure_odd_tables(imq_tree_s *t)
         make_l2l_odd_table(p, pos, tmp.data());
         pad_into(tmp, l2l.data() + pos * PP);
     }
+    {
+        std::vector<double> pk;
+        pack_shift_tables(l2l, KP, pk, t->cut_l2l_odd);
+        l2l.swap(pk);
+    }
     for (int s = 0; s < h.nsets; ++s)
         for (int l = 2; l < h.nlev; ++l)
             for (int cls = 0; cls < NCLASS; ++cls) {
@@ -249,12 +254,11 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
         launch_gemm<T>(s, 32, 1, t->g_m2l.ntasks, 2, t->g_m2l.tasks.as<GemmTask>(), 0, t->g_m2l.tbox.as<int32_t>(),
                        t->g_m2l.tab.as<int32_t>(), t->g_m2l.src.as<int32_t>(), pd.m2l_odd.as<T>(), KP, K,
                        pd.M.as<T>(), Lo, 0, 0, Ko);
-    for (int l = 1; l < h.nlev; ++l) {
-        const DevGemm &gl = t->g_l2l;
-        const int t0 = gl.level_task_begin[l], t1 = gl.level_task_begin[l + 1];
-        if (t1 <= t0) continue;
-        launch_gemm<T>(s, 0, 0, t1 - t0, 2, gl.tasks.as<GemmTask>(), t0, gl.tbox.as<int32_t>(),
-                       gl.tab.as<int32_t>(), gl.src.as<int32_t>(), pd.l2l_odd.as<T>(), KP, K, Lo, Lo, 1, Ko, Ko);
+    for (int l = std::max(h.need_l, 0); l + 1 < h.nlev; ++l) {
+        const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
+        launch_shift<T>(s, false, t->kcfg.shift_cols, np, 2, t->sh_par.as<int32_t>() + p0,
+                        t->sh_kids.as<int32_t>() + 4 * size_t(p0), pd.l2l_odd.as<T>(), KP, Ko, Ko,
+                        t->cut_l2l_odd, Lo, K, Lo, K);
     }
     IMQ_HIP(hipGetLastError());
     DTree<T> view = make_view<T>(t);

@@ -35,14 +35,36 @@ struct DTree {
 
 struct PrecData {              // everything that exists once per arithmetic type
     DevBuf xl, yl, wx;
-    DevBuf m2m, l2l, m2l;      // translation tables, zero-padded to KP x KP each
+    DevBuf m2m, l2l;           // shift tables, 4 quadrants, packed for k_shift
+    DevBuf m2l;                // translation tables, zero-padded to KP x KP each
     DevBuf us, M, L;           // workspace
     size_t ws_nrhs = 0;
     DevBuf Lx;                 // per-pair local expansions of the X lists
     size_t lx_nrhs = 0;
     DevBuf m2l_odd, l2l_odd;   // adjoint: tables to the n+m-odd local coefficients
+                               // (l2l_odd packed like l2l)
     DevBuf Lodd;               // adjoint: odd local coefficients
 };
+
+// Per row block of a packed shift table: the 16-coefficient input chunks
+// [lo, hi) that hold nonzero entries (the shifts are triangular in the degree).
+constexpr int SHIFT_MAXRB = 10;
+struct ShiftCuts {
+    int lo[SHIFT_MAXRB], hi[SHIFT_MAXRB];
+};
+
+// tabs: ntab tables of KP x KP (row-major, zero-padded); packed: same size in
+// the matrix-core lane order of k_shift.
+void pack_shift_tables(const std::vector<double> &tabs, int KP, std::vector<double> &packed, ShiftCuts &cuts);
+
+// One level of shifts.  up: out[par] = sum_q T_q in[kids_q]; else
+// out[kids_q] += T_q in[par].  par/kids: npar parents and their 4 children
+// (-1 = none); columns are (box, rhs) with box-major layout and leading
+// dimensions ldin/ldout; cols = 0 (automatic), 16 or 32 (tile width).
+template <typename T>
+void launch_shift(hipStream_t s, bool up, int cols, int npar, int nrhs, const int32_t *par,
+                  const int32_t *kids, const T *Apk, int KP, int kin, int kout, const ShiftCuts &cuts,
+                  const T *in, int ldin, T *out, int ldout);
 
 struct DevGemm {               // device copy of a GemmList
     DevBuf tasks, tbox, tab, src;
@@ -60,7 +82,9 @@ struct imq_tree_s {
     imq::DevBuf u_off, u_idx, v_off, v_idx, v_cls, w_off, w_idx, x_off, x_idx, Klev, cn, leaves;
     imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
     imq::PrecData f64, f32;
-    imq::DevGemm g_m2m, g_m2l, g_l2l;
+    imq::DevGemm g_m2l;
+    imq::DevBuf sh_par, sh_kids;           // shift lists (HostTree::sh_*)
+    imq::ShiftCuts cut_m2m = {}, cut_l2l = {}, cut_l2l_odd = {};
     imq_kernel_config kcfg = {};
     int KP = 0;                            // K rounded up to the MFMA tile (16)
     imq::DevBuf bs;                        // FP64 result accumulator, sorted order

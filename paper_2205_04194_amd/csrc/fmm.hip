@@ -12,9 +12,11 @@
 //   M2P      multipole of a finer box evaluated at points (W list)
 //   scatter  FP64 result -> caller order and type, times 1/side
 #include "device.h"
+#include "mfma.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 namespace imq {
@@ -233,30 +235,6 @@ __global__ void k_p2l_reduce(DTree<T> t, const int32_t *__restrict__ xboxes, int
 
 // ------------------------------------------------------------------ MFMA translations
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// 16x16x4 matrix-core step: lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// item v of lane l holds D[row(l/16, v)][l%16], where the FP32 form keeps four
-// consecutive rows per lane group and the FP64 form interleaves them.
-template <typename T> struct Mfma;
-template <> struct Mfma<float> {
-    using acc_t = f32x4;
-    static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
-};
-template <> struct Mfma<double> {
-    using acc_t = f64x4;
-    static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int q, int v) { return 4 * v + q; }
-};
-
 constexpr int GEMM_MAXRB = 10;        // row blocks of 16: KP <= 160 (p <= 16)
 constexpr int GEMM_MAXSLOT = 27;
 
@@ -412,11 +390,8 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     }
 }
 
-// Launch one batch of translation tasks.  kc > 0: that many coefficients
-// per pipeline step and the rows of a tile spread over `split` workgroups.
-// kc == 0 ("whole" mode, for the short level-by-level shifts): every slot
-// is staged in one step and each workgroup takes at most two row blocks, so
-// a task is one memory round trip per slot.
+// Launch one batch of translation tasks: kc coefficients per pipeline step
+// (0 = 32) and the rows of a tile spread over `split` workgroups.
 template <typename T>
 void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks,
                  int t0, const int32_t *tbox, const int32_t *tab, const int32_t *src,
@@ -425,13 +400,7 @@ void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const Ge
 #define IMQ_GEMM(KCV, RB)                                                                            \
     hipLaunchKernelGGL((k_gemm_tasks<T, KCV, RB>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,  \
                        tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr)
-    if (kc == 0) {
-        const int nrb = KP / 16;
-        const dim3 grid(ntask, nrhs, (nrb + 1) / 2);
-        if (KP <= 96) IMQ_GEMM(96, 2);
-        else IMQ_GEMM(160, 2);
-        return;
-    }
+    if (kc == 0) kc = 32;
     const dim3 grid(ntask, nrhs, split > 0 ? split : 1);
     if constexpr (sizeof(T) == 4) {
         if (kc >= 64) IMQ_GEMM(64, GEMM_MAXRB);
@@ -755,14 +724,11 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s)
 #undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
     mark(t, 2, s);
-    const imq_kernel_config &kc = t->kcfg;
-    for (int l = h.nlev - 2; l >= 0; --l) {
-        const DevGemm &g = t->g_m2m;
-        const int t0 = g.level_task_begin[l], t1 = g.level_task_begin[l + 1];
-        if (t1 <= t0) continue;
-        launch_gemm<T>(s, kc.shift_kc, kc.shift_split, t1 - t0, nrhs, g.tasks.as<GemmTask>(), t0,
-                       g.tbox.as<int32_t>(), g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.m2m.as<T>(),
-                       t->KP, K, M, M, 0, 0, 0);
+    for (int l = h.nlev - 2; l >= h.need_m; --l) {
+        const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
+        launch_shift<T>(s, true, t->kcfg.shift_cols, np, nrhs, t->sh_par.as<int32_t>() + p0,
+                        t->sh_kids.as<int32_t>() + 4 * size_t(p0), pd.m2m.as<T>(), t->KP, K, K, t->cut_m2m, M,
+                        K, M, K);
     }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
@@ -800,13 +766,11 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
         hipLaunchKernelGGL(k_p2l_reduce<T>, dim3(t->nxboxes), dim3(64), 0, s, v, t->x_boxes.as<int32_t>(),
                            nrhs, Lx, t->nxpairs, L);
     }
-    for (int l = 1; l < h.nlev; ++l) {
-        const DevGemm &g = t->g_l2l;
-        const int t0 = g.level_task_begin[l], t1 = g.level_task_begin[l + 1];
-        if (t1 <= t0) continue;
-        launch_gemm<T>(s, kc.shift_kc, kc.shift_split, t1 - t0, nrhs, g.tasks.as<GemmTask>(), t0,
-                       g.tbox.as<int32_t>(), g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.l2l.as<T>(), KP,
-                       K, L, L, 1, 0, 0);
+    for (int l = std::max(h.need_l, 0); l + 1 < h.nlev; ++l) {      // parents at level l
+        const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
+        launch_shift<T>(s, false, kc.shift_cols, np, nrhs, t->sh_par.as<int32_t>() + p0,
+                        t->sh_kids.as<int32_t>() + 4 * size_t(p0), pd.l2l.as<T>(), KP, h.Klev[l], h.Klev[l + 1],
+                        t->cut_l2l, L, K, L, K);
     }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;

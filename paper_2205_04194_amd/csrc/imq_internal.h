@@ -116,10 +116,17 @@ struct HostTree {
     std::vector<int32_t> w_off, w_idx;       // multipole -> target points (leaves)
     std::vector<int32_t> x_off, x_idx;       // source points -> local
 
-    // translation batches: multipole shift (targets = parents), expansion-to-
-    // local translation (targets = boxes with a V list), local shift
-    // (targets = children).  M2L tables are indexed (set*nlev + level)*NCLASS + class.
-    GemmList m2m, m2l, l2l;
+    // expansion-to-local batches (targets = boxes with a V list); tables are
+    // indexed (set*nlev + level)*NCLASS + class
+    GemmList m2l;
+
+    // level-by-level shifts: every box with children, level by level, and its
+    // child at each of the four positions (-1 if that quadrant is empty)
+    std::vector<int32_t> sh_par, sh_kids;    // kids: 4 per parent
+    std::vector<int32_t> sh_level_begin;     // nlev + 1, into sh_par
+    // shallowest level whose multipoles are read (V, W lists) and whose local
+    // expansions are written (V, X lists); shifts above them move nothing used
+    int need_m = 0, need_l = 0;
 
     int64_t p2p_pairs = 0, m2l_pairs = 0, m2p_evals = 0, p2l_evals = 0;
     int64_t m2m_pairs = 0, l2l_pairs = 0;

@@ -1,0 +1,262 @@
+// Level-by-level expansion shifts on the matrix cores.
+//
+//   M2M (upward):  M[parent] = sum over the four quadrants q of T_q M[child_q]
+//   L2L (downward): L[child_q] += T_q L[parent]
+//
+// T_q is the shift of the expansion centre from the parent's to the child's
+// (or back) for the child in quadrant q (Sec. 2.2: the addition theorem of the
+// solid harmonics; the lifted planes z = -c/2 and z = +c/2 stay fixed, so the
+// shift is horizontal and its table depends on the quadrant only).  One
+// launch per level: the tables are read from L2, the source expansions of a
+// tile are staged in LDS once, so a launch costs two dependent memory round
+// trips (the quadrant map, then the expansions) plus the matrix-core work.
+#include "device.h"
+#include "mfma.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+namespace imq {
+
+namespace {
+
+// Workgroup = 4 waves; wave w owns quadrant w.  A tile is TC = 16*NCB columns
+// (parent box, right-hand side).  Packed table layout: element j of lane l of
+// (quadrant, row block rb, chunk ch) is T[16 rb + l%16][16 ch + 4 j + l/16],
+// so one load of four values per lane feeds four 16x16x4 steps.
+template <typename T, int NRB, int NCB, bool UP>
+__global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
+                                               const int32_t *__restrict__ kids, int npar, int nrhs,
+                                               const T *__restrict__ Apk, int kin, int kout, ShiftCuts cuts,
+                                               const T *__restrict__ in, int ldin, T *__restrict__ out,
+                                               int ldout)
+{
+    constexpr int TC = 16 * NCB;
+    constexpr int KPC = NRB * 16;
+    constexpr int LD = KPC + (sizeof(T) == 4 ? 2 : 1);     // LDS row stride
+    constexpr int NROW = (UP ? 4 : 1) * TC;                 // staged source columns
+    constexpr int NBT = NROW * KPC / 256;                   // staged values per thread
+    constexpr int BATCH = sizeof(T) == 4 ? 32 : 16;
+    using acc_t = typename Mfma<T>::acc_t;
+    using Q = Quad<T>;
+    __shared__ T Bs[NROW * LD];
+    __shared__ int s_ci[4][TC];     // column of the child in quadrant q (-1: none)
+    __shared__ int s_pc[TC];        // column of the parent
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i16 = lane & 15, q = lane >> 4;
+    const int ncols = npar * nrhs;
+    const int col0 = blockIdx.x * TC;
+
+    if (tid < 4 * TC) {
+        const int sl = tid / TC, c = tid - sl * TC;
+        const int gc = col0 + c;
+        int ci = -1, pc = -1;
+        if (gc < ncols) {
+            const int pl = gc / nrhs, r = gc - pl * nrhs;
+            const int kid = kids[4 * pl + sl];
+            if (kid >= 0) ci = kid * nrhs + r;
+            pc = par[pl] * nrhs + r;
+        }
+        s_ci[sl][c] = ci;
+        if (sl == 0) s_pc[c] = pc;
+    }
+
+    // chunk range of this launch; the first table chunk is independent of the columns
+    const int nrb = (kout + 15) >> 4;
+    int chlo = NRB, chhi = 0;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+        if (rb < nrb && cuts.lo[rb] < cuts.hi[rb]) {
+            chlo = min(chlo, cuts.lo[rb]);
+            chhi = max(chhi, cuts.hi[rb]);
+        }
+    chhi = min(chhi, (kin + 15) >> 4);
+    const T *Aw = Apk + size_t(w) * NRB * NRB * 256 + lane * 4;
+    Q a[NRB];
+    auto load_a = [&](int ch, Q *dst) {
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb)
+            if (rb < nrb && ch >= cuts.lo[rb] && ch < cuts.hi[rb])
+                dst[rb] = *reinterpret_cast<const Q *>(Aw + (rb * NRB + ch) * 256);
+    };
+    if (chlo < chhi) load_a(chlo, a);
+    __syncthreads();
+
+    // stage the source expansions: row = (quadrant, column) or column, k fastest
+#pragma unroll
+    for (int j0 = 0; j0 < NBT; j0 += BATCH) {
+        T v[BATCH];
+#pragma unroll
+        for (int j = 0; j < BATCH; ++j)
+            if (j0 + j < NBT) {
+                const int e = tid + 256 * (j0 + j);
+                const int row = e / KPC, k = e - row * KPC;
+                const int col = UP ? s_ci[row / TC][row % TC] : s_pc[row];
+                v[j] = (col >= 0 && k < kin) ? in[size_t(col) * ldin + k] : T(0);
+            }
+#pragma unroll
+        for (int j = 0; j < BATCH; ++j)
+            if (j0 + j < NBT) {
+                const int e = tid + 256 * (j0 + j);
+                const int row = e / KPC, k = e - row * KPC;
+                Bs[row * LD + k] = v[j];
+            }
+    }
+
+    // wave-uniform: does quadrant w have a child in this tile?
+    const bool on = __ballot(lane < TC && s_ci[w][lane] >= 0) != 0;
+    acc_t acc[NRB][NCB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[rb][cb][v] = T(0);
+    if (!UP && on) {            // L2L adds to what the translations left in L
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int ci = s_ci[w][cb * 16 + i16];
+            if (ci < 0) continue;
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb)
+                if (rb < nrb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = rb * 16 + Mfma<T>::row(q, v);
+                        if (row < kout) acc[rb][cb][v] = out[size_t(ci) * ldout + row];
+                    }
+        }
+    }
+    __syncthreads();
+
+    if (on) {
+        const T *Bw = Bs + ((UP ? w * TC : 0) + i16) * LD + q;
+        for (int ch = chlo; ch < chhi; ++ch) {
+            Q an[NRB];
+            if (ch + 1 < chhi) load_a(ch + 1, an);
+            T b[NCB][4];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[cb][j] = Bw[cb * 16 * LD + ch * 16 + 4 * j];
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb)
+                if (rb < nrb && ch >= cuts.lo[rb] && ch < cuts.hi[rb])
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb)
+                            acc[rb][cb] = Mfma<T>::mac(a[rb].v[j], b[cb][j], acc[rb][cb]);
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) a[rb] = an[rb];
+        }
+    }
+
+    if (UP) {
+        // sum the four quadrants' partial results in LDS (fixed order)
+        __syncthreads();
+        T *red = Bs;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb)
+                if (rb < nrb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        red[(w * TC + cb * 16 + i16) * LD + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
+        __syncthreads();
+        for (int e = tid; e < TC * kout; e += 256) {
+            const int c = e / kout, k = e - c * kout;
+            const int pc = s_pc[c];
+            if (pc < 0) continue;
+            out[size_t(pc) * ldout + k] = ((red[c * LD + k] + red[(TC + c) * LD + k]) + red[(2 * TC + c) * LD + k]) +
+                                          red[(3 * TC + c) * LD + k];
+        }
+    } else if (on) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int ci = s_ci[w][cb * 16 + i16];
+            if (ci < 0) continue;
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb)
+                if (rb < nrb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = rb * 16 + Mfma<T>::row(q, v);
+                        if (row < kout) out[size_t(ci) * ldout + row] = acc[rb][cb][v];
+                    }
+        }
+    }
+}
+
+}  // namespace
+
+void pack_shift_tables(const std::vector<double> &tabs, int KP, std::vector<double> &packed, ShiftCuts &cuts)
+{
+    const int nrb = KP / 16;
+    const size_t PP = size_t(KP) * KP;
+    const size_t ntab = tabs.size() / PP;
+    packed.assign(tabs.size(), 0.0);
+    for (int rb = 0; rb < SHIFT_MAXRB; ++rb) { cuts.lo[rb] = 0; cuts.hi[rb] = 0; }
+    for (int rb = 0; rb < nrb; ++rb) {
+        int lo = nrb, hi = 0;
+        for (size_t tb = 0; tb < ntab; ++tb)
+            for (int ch = 0; ch < nrb; ++ch)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 4; ++j) {
+                        const double x = tabs[tb * PP + size_t(rb * 16 + l % 16) * KP + ch * 16 + 4 * j + l / 16];
+                        packed[tb * PP + ((size_t(rb) * nrb + ch) * 64 + l) * 4 + j] = x;
+                        if (x != 0.0) { lo = std::min(lo, ch); hi = std::max(hi, ch + 1); }
+                    }
+        if (lo < hi) { cuts.lo[rb] = lo; cuts.hi[rb] = hi; }
+    }
+}
+
+template <typename T>
+void launch_shift(hipStream_t s, bool up, int cols, int npar, int nrhs, const int32_t *par,
+                  const int32_t *kids, const T *Apk, int KP, int kin, int kout, const ShiftCuts &cuts,
+                  const T *in, int ldin, T *out, int ldout)
+{
+    const int ncols = npar * nrhs;
+    if (ncols <= 0) return;
+    // 32-column tiles halve the table traffic but need enough columns to fill the chip
+    bool wide = sizeof(T) == 4 && (cols == 32 || (cols == 0 && ncols >= 16 * 1024));
+#define IMQ_SHIFT(NRB, NCB)                                                                                \
+    do {                                                                                                   \
+        const dim3 grid(unsigned((ncols + 16 * NCB - 1) / (16 * NCB)));                                    \
+        if (up)                                                                                            \
+            hipLaunchKernelGGL((k_shift<T, NRB, NCB, true>), grid, dim3(256), 0, s, par, kids, npar, nrhs, \
+                               Apk, kin, kout, cuts, in, ldin, out, ldout);                                \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_shift<T, NRB, NCB, false>), grid, dim3(256), 0, s, par, kids, npar, nrhs,\
+                               Apk, kin, kout, cuts, in, ldin, out, ldout);                                \
+    } while (0)
+#define IMQ_SHIFT_NRB(NRB)                                       \
+    case NRB:                                                    \
+        if constexpr (sizeof(T) == 4) {                          \
+            if (wide) IMQ_SHIFT(NRB, 2); else IMQ_SHIFT(NRB, 1); \
+        } else {                                                 \
+            IMQ_SHIFT(NRB, 1);                                   \
+        }                                                        \
+        break;
+    switch (KP / 16) {
+        IMQ_SHIFT_NRB(1) IMQ_SHIFT_NRB(2) IMQ_SHIFT_NRB(3) IMQ_SHIFT_NRB(4) IMQ_SHIFT_NRB(5)
+        IMQ_SHIFT_NRB(6) IMQ_SHIFT_NRB(7) IMQ_SHIFT_NRB(8) IMQ_SHIFT_NRB(9) IMQ_SHIFT_NRB(10)
+        default: break;
+    }
+#undef IMQ_SHIFT_NRB
+#undef IMQ_SHIFT
+    (void)wide;
+}
+
+template void launch_shift<float>(hipStream_t, bool, int, int, int, const int32_t *, const int32_t *,
+                                  const float *, int, int, int, const ShiftCuts &, const float *, int, float *,
+                                  int);
+template void launch_shift<double>(hipStream_t, bool, int, int, int, const int32_t *, const int32_t *,
+                                   const double *, int, int, int, const ShiftCuts &, const double *, int,
+                                   double *, int);
+
+}  // namespace imq

@@ -382,49 +382,32 @@ void build_gemm_lists(HostTree &t)
 {
     const int nbox = int(t.level.size());
     const int L = t.nlev;
-    t.m2m = GemmList();
     t.m2l = GemmList();
-    t.l2l = GemmList();
-    // child of box b at position s, or -1
-    auto child_at = [&](int32_t b, int s) -> int32_t {
-        for (int c = t.child0[b]; c >= 0 && c < t.child0[b] + t.nchild[b]; ++c)
-            if (t.pos[c] == s) return c;
-        return -1;
-    };
     // Multipoles are read by V lists (as sources) and W lists; locals are
     // written by V and X lists.  Shifts above the first level that needs them
-    // would only move zeros or unused coefficients, so they are not batched.
-    int need_m = L, need_l = L;
+    // would only move zeros or unused coefficients, so they are skipped.
+    t.need_m = L;
+    t.need_l = L;
     for (int b = 0; b < nbox; ++b) {
-        if (t.v_off[b + 1] > t.v_off[b] || t.x_off[b + 1] > t.x_off[b]) need_l = std::min(need_l, t.level[b]);
-        for (int v = t.v_off[b]; v < t.v_off[b + 1]; ++v) need_m = std::min(need_m, t.level[t.v_idx[v]]);
-        for (int w = t.w_off[b]; w < t.w_off[b + 1]; ++w) need_m = std::min(need_m, t.level[t.w_idx[w]]);
+        if (t.v_off[b + 1] > t.v_off[b] || t.x_off[b + 1] > t.x_off[b]) t.need_l = std::min(t.need_l, t.level[b]);
+        for (int v = t.v_off[b]; v < t.v_off[b + 1]; ++v) t.need_m = std::min(t.need_m, t.level[t.v_idx[v]]);
+        for (int w = t.w_off[b]; w < t.w_off[b + 1]; ++w) t.need_m = std::min(t.need_m, t.level[t.w_idx[w]]);
     }
-    // multipole shift: parents level by level, slots = child positions
-    t.m2m.level_task_begin.assign(L + 1, 0);
+    // parents level by level with their children by quadrant
+    t.sh_par.clear();
+    t.sh_kids.clear();
+    t.sh_level_begin.assign(L + 1, 0);
     for (int l = 0; l < L; ++l) {
-        t.m2m.level_task_begin[l] = int32_t(t.m2m.tasks.size());
-        if (l < need_m) continue;
-        std::vector<int32_t> parents;
-        for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
-            if (t.nchild[b] > 0) parents.push_back(b);
-        add_tasks(t.m2m, parents, 4, t.K, t.K, l, {0, 1, 2, 3}, child_at);
-    }
-    t.m2m.level_task_begin[L] = int32_t(t.m2m.tasks.size());
-    // local shift: children grouped by position, one slot (the parent)
-    t.l2l.level_task_begin.assign(L + 1, 0);
-    for (int l = 0; l < L; ++l) {
-        t.l2l.level_task_begin[l] = int32_t(t.l2l.tasks.size());
-        if (l == 0 || l - 1 < need_l) continue;     // the parent holds no local expansion
-        for (int pos = 0; pos < 4; ++pos) {
-            std::vector<int32_t> kids;
-            for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
-                if (t.pos[b] == pos) kids.push_back(b);
-            add_tasks(t.l2l, kids, 1, t.Klev[l - 1], t.Klev[l], l, {pos},
-                      [&](int32_t b, int) { return t.parent[b]; });
+        t.sh_level_begin[l] = int32_t(t.sh_par.size());
+        for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b) {
+            if (t.nchild[b] == 0) continue;
+            t.sh_par.push_back(b);
+            int32_t k4[4] = {-1, -1, -1, -1};
+            for (int c = t.child0[b]; c < t.child0[b] + t.nchild[b]; ++c) k4[t.pos[c]] = c;
+            t.sh_kids.insert(t.sh_kids.end(), k4, k4 + 4);
         }
     }
-    t.l2l.level_task_begin[L] = int32_t(t.l2l.tasks.size());
+    t.sh_level_begin[L] = int32_t(t.sh_par.size());
     // expansion-to-local: (set, level, position) groups, 27 slots
     std::vector<int> cls;
     t.m2l.level_task_begin.assign(L + 1, 0);
@@ -448,7 +431,6 @@ void build_gemm_lists(HostTree &t)
             }
     }
     t.m2l.level_task_begin[L] = int32_t(t.m2l.tasks.size());
-    (void)nbox;
 }
 
 }  // namespace imq

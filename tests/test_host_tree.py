@@ -192,3 +192,26 @@ def test_level_orders_are_clamped_to_p():
     assert Klev[0] == K(8) and Klev[2] == K(8) and Klev[3] == K(6) and Klev[4] == K(4)
     assert all(k == K(8) for k in Klev[5:])
     H.free(h)
+
+
+def test_shift_lists_name_every_child_once_in_its_quadrant():
+    g = W.rng(77, 1)
+    xy = np.concatenate([W.mixture_points(3000, W.rng(77, 2), g), W.uniform_points(500, g)])
+    h, st = H.host_tree([xy], [0.02], leaf=16, p=6)
+    assert st == 0
+    try:
+        level, parent, pos, nchild = (H.get(h, k) for k in ("level", "parent", "pos", "nchild"))
+        par, kids, lb = H.get(h, "sh_par"), H.get(h, "sh_kids").reshape(-1, 4), H.get(h, "sh_level_begin")
+        assert len(kids) == len(par) and lb[0] == 0 and lb[-1] == len(par)
+        assert sorted(par.tolist()) == sorted(np.flatnonzero(nchild > 0).tolist())
+        for l in range(len(lb) - 1):
+            assert np.all(level[par[lb[l]:lb[l + 1]]] == l)
+        seen = np.zeros(len(level), dtype=int)
+        for b, k4 in zip(par, kids):
+            for q, c in enumerate(k4):
+                if c >= 0:
+                    assert parent[c] == b and pos[c] == q
+                    seen[c] += 1
+        assert np.all(seen[parent >= 0] == 1) and np.all(seen[parent < 0] == 0)
+    finally:
+        H.free(h)
