@@ -7,9 +7,10 @@
 // (or back) for the child in quadrant q (Sec. 2.2: the addition theorem of the
 // solid harmonics; the lifted planes z = -c/2 and z = +c/2 stay fixed, so the
 // shift is horizontal and its table depends on the quadrant only).  One
-// launch per level: the tables are read from L2, the source expansions of a
-// tile are staged in LDS once, so a launch costs two dependent memory round
-// trips (the quadrant map, then the expansions) plus the matrix-core work.
+// launch per level.  Each workgroup loads its slice of the tables into
+// registers at the start and stages the source expansions of its tile in LDS
+// once, so a launch costs two dependent memory round trips (the quadrant map,
+// then the expansions) plus the matrix-core work.
 #include "device.h"
 #include "mfma.h"
 
@@ -23,10 +24,11 @@ namespace imq {
 namespace {
 
 // Workgroup = 4 waves; wave w owns quadrant w.  A tile is TC = 16*NCB columns
-// (parent box, right-hand side).  Packed table layout: element j of lane l of
+// (parent box, right-hand side) times RBS row blocks of 16 output coefficients
+// (blockIdx.y picks the row blocks).  Packed table layout: element j of lane l of
 // (quadrant, row block rb, chunk ch) is T[16 rb + l%16][16 ch + 4 j + l/16],
 // so one load of four values per lane feeds four 16x16x4 steps.
-template <typename T, int NRB, int NCB, bool UP>
+template <typename T, int NRB, int NCB, int RBS, bool UP>
 __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
                                                const int32_t *__restrict__ kids, int npar, int nrhs,
                                                const T *__restrict__ Apk, int kin, int kout, ShiftCuts cuts,
@@ -64,25 +66,25 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
         if (sl == 0) s_pc[c] = pc;
     }
 
-    // chunk range of this launch; the first table chunk is independent of the columns
-    const int nrb = (kout + 15) >> 4;
-    int chlo = NRB, chhi = 0;
+    // This workgroup's row blocks rb0 + [0, RBS): their whole table slice is
+    // loaded into registers up front (it does not depend on the columns), so
+    // the matrix-core loop never waits on memory.
+    const int rb0 = blockIdx.y * RBS;
+    const int nrb = min((kout + 15) >> 4, rb0 + RBS) - rb0;
+    const int nchk = (kin + 15) >> 4;
+    int lo[RBS], hi[RBS];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb)
-        if (rb < nrb && cuts.lo[rb] < cuts.hi[rb]) {
-            chlo = min(chlo, cuts.lo[rb]);
-            chhi = max(chhi, cuts.hi[rb]);
-        }
-    chhi = min(chhi, (kin + 15) >> 4);
-    const T *Aw = Apk + size_t(w) * NRB * NRB * 256 + lane * 4;
-    Q a[NRB];
-    auto load_a = [&](int ch, Q *dst) {
+    for (int r = 0; r < RBS; ++r) {
+        lo[r] = r < nrb ? cuts.lo[rb0 + r] : 0;
+        hi[r] = r < nrb ? min(cuts.hi[rb0 + r], nchk) : 0;
+    }
+    const T *Aw = Apk + (size_t(w) * NRB + rb0) * NRB * 256 + lane * 4;
+    Q a[RBS][NRB];
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb)
-            if (rb < nrb && ch >= cuts.lo[rb] && ch < cuts.hi[rb])
-                dst[rb] = *reinterpret_cast<const Q *>(Aw + (rb * NRB + ch) * 256);
-    };
-    if (chlo < chhi) load_a(chlo, a);
+    for (int r = 0; r < RBS; ++r)
+#pragma unroll
+        for (int ch = 0; ch < NRB; ++ch)
+            if (ch >= lo[r] && ch < hi[r]) a[r][ch] = *reinterpret_cast<const Q *>(Aw + (r * NRB + ch) * 256);
     __syncthreads();
 
     // stage the source expansions: row = (quadrant, column) or column, k fastest
@@ -108,9 +110,9 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
 
     // wave-uniform: does quadrant w have a child in this tile?
     const bool on = __ballot(lane < TC && s_ci[w][lane] >= 0) != 0;
-    acc_t acc[NRB][NCB];
+    acc_t acc[RBS][NCB];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb)
+    for (int rb = 0; rb < RBS; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -121,11 +123,11 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
             const int ci = s_ci[w][cb * 16 + i16];
             if (ci < 0) continue;
 #pragma unroll
-            for (int rb = 0; rb < NRB; ++rb)
+            for (int rb = 0; rb < RBS; ++rb)
                 if (rb < nrb)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = rb * 16 + Mfma<T>::row(q, v);
+                        const int row = (rb0 + rb) * 16 + Mfma<T>::row(q, v);
                         if (row < kout) acc[rb][cb][v] = out[size_t(ci) * ldout + row];
                     }
         }
@@ -134,24 +136,25 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
 
     if (on) {
         const T *Bw = Bs + ((UP ? w * TC : 0) + i16) * LD + q;
-        for (int ch = chlo; ch < chhi; ++ch) {
-            Q an[NRB];
-            if (ch + 1 < chhi) load_a(ch + 1, an);
+#pragma unroll
+        for (int ch = 0; ch < NRB; ++ch) {
+            bool use = false;
+#pragma unroll
+            for (int r = 0; r < RBS; ++r) use |= ch >= lo[r] && ch < hi[r];
+            if (!use) continue;
             T b[NCB][4];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) b[cb][j] = Bw[cb * 16 * LD + ch * 16 + 4 * j];
 #pragma unroll
-            for (int rb = 0; rb < NRB; ++rb)
-                if (rb < nrb && ch >= cuts.lo[rb] && ch < cuts.hi[rb])
+            for (int r = 0; r < RBS; ++r)
+                if (ch >= lo[r] && ch < hi[r])
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
 #pragma unroll
                         for (int cb = 0; cb < NCB; ++cb)
-                            acc[rb][cb] = Mfma<T>::mac(a[rb].v[j], b[cb][j], acc[rb][cb]);
-#pragma unroll
-            for (int rb = 0; rb < NRB; ++rb) a[rb] = an[rb];
+                            acc[r][cb] = Mfma<T>::mac(a[r][ch].v[j], b[cb][j], acc[r][cb]);
         }
     }
 
@@ -162,18 +165,19 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-            for (int rb = 0; rb < NRB; ++rb)
+            for (int rb = 0; rb < RBS; ++rb)
                 if (rb < nrb)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
                         red[(w * TC + cb * 16 + i16) * LD + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
         __syncthreads();
-        for (int e = tid; e < TC * kout; e += 256) {
-            const int c = e / kout, k = e - c * kout;
+        const int row0 = rb0 * 16, nrow = min(kout - row0, nrb * 16);
+        for (int e = tid; e < TC * nrow; e += 256) {
+            const int c = e / nrow, k = e - c * nrow;
             const int pc = s_pc[c];
             if (pc < 0) continue;
-            out[size_t(pc) * ldout + k] = ((red[c * LD + k] + red[(TC + c) * LD + k]) + red[(2 * TC + c) * LD + k]) +
-                                          red[(3 * TC + c) * LD + k];
+            out[size_t(pc) * ldout + row0 + k] =
+                ((red[c * LD + k] + red[(TC + c) * LD + k]) + red[(2 * TC + c) * LD + k]) + red[(3 * TC + c) * LD + k];
         }
     } else if (on) {
 #pragma unroll
@@ -181,11 +185,11 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
             const int ci = s_ci[w][cb * 16 + i16];
             if (ci < 0) continue;
 #pragma unroll
-            for (int rb = 0; rb < NRB; ++rb)
+            for (int rb = 0; rb < RBS; ++rb)
                 if (rb < nrb)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = rb * 16 + Mfma<T>::row(q, v);
+                        const int row = (rb0 + rb) * 16 + Mfma<T>::row(q, v);
                         if (row < kout) out[size_t(ci) * ldout + row] = acc[rb][cb][v];
                     }
         }
@@ -221,18 +225,22 @@ void launch_shift(hipStream_t s, bool up, int cols, int npar, int nrhs, const in
                   const T *in, int ldin, T *out, int ldout)
 {
     const int ncols = npar * nrhs;
-    if (ncols <= 0) return;
+    const int nrb = (kout + 15) / 16;
+    if (ncols <= 0 || nrb <= 0) return;
     // 32-column tiles halve the table traffic but need enough columns to fill the chip
-    bool wide = sizeof(T) == 4 && (cols == 32 || (cols == 0 && ncols >= 16 * 1024));
-#define IMQ_SHIFT(NRB, NCB)                                                                                \
-    do {                                                                                                   \
-        const dim3 grid(unsigned((ncols + 16 * NCB - 1) / (16 * NCB)));                                    \
-        if (up)                                                                                            \
-            hipLaunchKernelGGL((k_shift<T, NRB, NCB, true>), grid, dim3(256), 0, s, par, kids, npar, nrhs, \
-                               Apk, kin, kout, cuts, in, ldin, out, ldout);                                \
-        else                                                                                               \
-            hipLaunchKernelGGL((k_shift<T, NRB, NCB, false>), grid, dim3(256), 0, s, par, kids, npar, nrhs,\
-                               Apk, kin, kout, cuts, in, ldin, out, ldout);                                \
+    const bool wide = sizeof(T) == 4 && (cols == 32 || (cols == 0 && ncols >= 16 * 1024));
+    // row blocks per workgroup: their table slice is held in registers
+    constexpr int RBS = sizeof(T) == 4 ? 2 : 1;
+    const unsigned gy = unsigned((nrb + RBS - 1) / RBS);
+#define IMQ_SHIFT(NRB, NCB)                                                                                  \
+    do {                                                                                                     \
+        const dim3 grid(unsigned((ncols + 16 * NCB - 1) / (16 * NCB)), gy);                                  \
+        if (up)                                                                                              \
+            hipLaunchKernelGGL((k_shift<T, NRB, NCB, RBS, true>), grid, dim3(256), 0, s, par, kids, npar,    \
+                               nrhs, Apk, kin, kout, cuts, in, ldin, out, ldout);                            \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_shift<T, NRB, NCB, RBS, false>), grid, dim3(256), 0, s, par, kids, npar,   \
+                               nrhs, Apk, kin, kout, cuts, in, ldin, out, ldout);                            \
     } while (0)
 #define IMQ_SHIFT_NRB(NRB)                                       \
     case NRB:                                                    \
