@@ -123,6 +123,11 @@ def main():
                     help="GMRES products per solve (0: skip the solve comparison)")
     ap.add_argument("--no-tune", action="store_true",
                     help="uniform order p and default launch shapes instead of the autotuner")
+    ap.add_argument("--orders", default="",
+                    help="comma-separated per-level orders to apply instead of tuning (with --prec)")
+    ap.add_argument("--m2l-kc", type=int, default=0)
+    ap.add_argument("--m2l-split", type=int, default=0)
+    ap.add_argument("--m2l-mode", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -162,7 +167,20 @@ def main():
         log(f"{prec} uniform p={args.p}: {ms:.3f} ms/product, rel err {err:.2e}, stages " +
             " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
     tuned = None
-    if not args.no_tune:
+    if args.orders:
+        prec = precs[0]
+        orders = [int(x) for x in args.orders.split(",")]
+        tree.set_level_orders(orders)
+        tree.set_kernel_config(m2l_kc=args.m2l_kc, m2l_split=args.m2l_split, m2l_mode=args.m2l_mode)
+        b = tree.matvec(u, prec)
+        err = float(torch.linalg.norm(b[rows] - exact) / torch.linalg.norm(exact))
+        ms, stages = time_products(tree, u, prec, args.steps, args.warmup)
+        tuned = {"ms": ms, "err": err, "stages": stages, "prec": prec, "level_orders": orders,
+                 "m2l_kc": args.m2l_kc, "m2l_split": args.m2l_split, "m2l_mode": args.m2l_mode,
+                 "tune_s": 0.0}
+        log(f"given {prec} orders {orders}: {ms:.3f} ms/product, rel err {err:.2e}, stages " +
+            " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
+    elif not args.no_tune:
         from paper_2205_04194_amd import autotune
         t0 = time.perf_counter()
         res = autotune.tune(tree, u, target=1e-6, precisions=precs, seed=1)
@@ -172,9 +190,10 @@ def main():
         ms, stages = time_products(tree, u, res.precision, args.steps, args.warmup)
         tuned = {"ms": ms, "err": err, "stages": stages, "prec": res.precision,
                  "level_orders": res.level_orders, "m2l_kc": res.m2l_kc, "m2l_split": res.m2l_split,
-                 "tune_s": t_tune}
+                 "m2l_mode": res.m2l_mode, "tune_s": t_tune}
         info = tree.info()
-        log(f"tuned {res.precision} orders {res.level_orders} kc {res.m2l_kc} split {res.m2l_split}: "
+        log(f"tuned {res.precision} orders {res.level_orders} mode {res.m2l_mode} kc {res.m2l_kc} "
+            f"split {res.m2l_split}: "
             f"{ms:.3f} ms/product, rel err {err:.2e}, stages " +
             " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
 
@@ -212,8 +231,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "c": d["c"], "leaf": args.leaf, "p": args.p,
                    "nrhs": 1, "precision": head,
-                   "level_orders": r.get("level_orders"), "m2l_kc": r.get("m2l_kc"),
-                   "m2l_split": r.get("m2l_split")},
+                   "level_orders": r.get("level_orders"), "m2l_mode": r.get("m2l_mode"),
+                   "m2l_kc": r.get("m2l_kc"), "m2l_split": r.get("m2l_split")},
         "rel_err_sampled_rows": r["err"],
         "tree_build_s": t_build,
         "stage_ms": st,

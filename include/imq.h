@@ -153,10 +153,15 @@ imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
  *  m2l_split  : the output rows of one M2L tile are spread over this many
  *               workgroups (1 .. 10)
  *  shift_cols : columns (box, rhs) per workgroup of the level-by-level
- *               shifts, 16 or 32 (32 only in FP32; 0 picks by level size) */
+ *               shifts, 16 or 32 (32 only in FP32; 0 picks by level size)
+ *  m2l_mode   : M2L kernel per level: 0 = operands streamed through
+ *               registers where a box has at most 80 coefficients (FP32) or
+ *               64 (FP64), the staged GEMM above; 1 = staged GEMM everywhere.
+ *               m2l_kc and m2l_split apply to the staged GEMM only. */
 typedef struct {
     int m2l_kc, m2l_split;
     int shift_cols;
+    int m2l_mode;
 } imq_kernel_config;
 
 imq_status imq_set_kernel_config(imq_tree tree, const imq_kernel_config *cfg);

@@ -160,9 +160,10 @@ class Tree:
             out[k] = list(v)[:inf.nlevels] if k.startswith("level_") else v
         return out
 
-    def set_kernel_config(self, m2l_kc: int = 0, m2l_split: int = 0, shift_cols: int = 0) -> None:
+    def set_kernel_config(self, m2l_kc: int = 0, m2l_split: int = 0, shift_cols: int = 0,
+                          m2l_mode: int = 0) -> None:
         """Launch shape of the batched translations (0 = default)."""
-        cfg = _lib.KernelConfig(m2l_kc, m2l_split, shift_cols)
+        cfg = _lib.KernelConfig(m2l_kc, m2l_split, shift_cols, m2l_mode)
         _lib.check(_lib.load().imq_set_kernel_config(self._h, ctypes.byref(cfg)),
                    "imq_set_kernel_config")
 

@@ -12,7 +12,8 @@ Search (all on one tree, no rebuild):
   2. per level, deepest first, the translation order is lowered while the
      error stays within the target (the lifted vertical offset c makes deep
      levels, whose boxes are small next to c, converge fastest);
-  3. the M2L pipeline depth and row split are timed and the fastest kept.
+  3. the M2L kernel choice (register streaming or staged GEMM) and the staged
+     GEMM's pipeline depth and row split are timed and the fastest kept.
 """
 from __future__ import annotations
 
@@ -32,6 +33,7 @@ class TuneResult:
     m2l_split: int
     error: float
     ms: float
+    m2l_mode: int = 0
     trials: List[dict] = field(default_factory=list)
 
 
@@ -55,7 +57,7 @@ def _time(tree, u, prec, reps=5):
 
 def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"),
          nrows: int = 1000, safety: float = 0.8, seed: int = 0,
-         kcs=(16, 32, 64), splits=(1, 2)) -> TuneResult:
+         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1)) -> TuneResult:
     """Fastest configuration of ``tree`` whose sampled-row relative 2-norm
     error is at most ``safety * target``; the tree is left configured."""
     n = tree.n
@@ -73,7 +75,7 @@ def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"
         orders = [pmax] * nlev
         tree.set_level_orders(orders)
         tree.set_kernel_config()
-        err = _error(tree, u, rows, exact, prec)
+        err = _error(tree, u, rows, exact, prec)      # default kernels while the orders are searched
         trials.append({"prec": prec, "orders": list(orders), "err": err})
         if err > budget:
             continue
@@ -99,24 +101,25 @@ def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"
                     break
                 orders, err = trial, e
         tree.set_level_orders(orders)
-        # 3. launch shape of the translations
-        shape, ms = (0, 0), float("inf")
-        for kc in kcs:
-            if prec == "fp64" and kc > 32:
-                continue
-            for sp in splits:
-                tree.set_kernel_config(m2l_kc=kc, m2l_split=sp)
-                t = _time(tree, u, prec)
-                trials.append({"prec": prec, "m2l_kc": kc, "m2l_split": sp, "ms": t})
-                if t < ms:
-                    shape, ms = (kc, sp), t
-        res = TuneResult(prec, list(orders), shape[0], shape[1], err, ms)
+        # 3. translation kernels and the launch shape of the staged GEMM
+        shape, ms = (0, 0, 0), float("inf")
+        for mode in modes:
+            for kc in kcs:
+                if prec == "fp64" and kc > 32:
+                    continue
+                for sp in splits:
+                    tree.set_kernel_config(m2l_kc=kc, m2l_split=sp, m2l_mode=mode)
+                    t = _time(tree, u, prec)
+                    trials.append({"prec": prec, "m2l_mode": mode, "m2l_kc": kc, "m2l_split": sp, "ms": t})
+                    if t < ms:
+                        shape, ms = (kc, sp, mode), t
+        res = TuneResult(prec, list(orders), shape[0], shape[1], err, ms, m2l_mode=shape[2])
         if best is None or res.ms < best.ms:
             best = res
     if best is None:
         raise RuntimeError(f"no precision reaches the target {target:g} at order {pmax}")
     tree.set_level_orders(best.level_orders)
-    tree.set_kernel_config(m2l_kc=best.m2l_kc, m2l_split=best.m2l_split)
+    tree.set_kernel_config(m2l_kc=best.m2l_kc, m2l_split=best.m2l_split, m2l_mode=best.m2l_mode)
     best.error = _error(tree, u, rows, exact, best.precision)
     best.trials = trials
     return best

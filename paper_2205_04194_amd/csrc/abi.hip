@@ -145,12 +145,14 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     pad(m2m);
     pad(l2l);
     pad(m2l);
+    std::vector<double> m2l_pk;
     {
         std::vector<double> pk;
         pack_shift_tables(m2m, KP, pk, t->cut_m2m);
         m2m.swap(pk);
         pack_shift_tables(l2l, KP, pk, t->cut_l2l);
         l2l.swap(pk);
+        pack_m2l_tables(m2l, KP, m2l_pk);
     }
     {
         const GemmList &g = h.m2l;
@@ -167,6 +169,8 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     if ((st = upload(t->f64.m2m, m2m)) != IMQ_OK) return st;
     if ((st = upload(t->f64.l2l, l2l)) != IMQ_OK) return st;
     if ((st = upload(t->f64.m2l, m2l)) != IMQ_OK) return st;
+    if ((st = upload(t->f64.m2l_pk, m2l_pk)) != IMQ_OK) return st;
+    if ((st = upload(t->f32.m2l_pk, to_f32(m2l_pk))) != IMQ_OK) return st;
     if ((st = upload(t->f64.wx, wx)) != IMQ_OK) return st;
     if ((st = upload(t->f32.m2m, to_f32(m2m))) != IMQ_OK) return st;
     if ((st = upload(t->f32.l2l, to_f32(l2l))) != IMQ_OK) return st;
@@ -188,7 +192,7 @@ static void free_tree(imq_tree_s *t)
         dev_free(g->tasks); dev_free(g->tbox); dev_free(g->tab); dev_free(g->src);
     }
     for (PrecData *pd : {&t->f64, &t->f32}) {
-        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->m2m, &pd->l2l, &pd->m2l, &pd->wx, &pd->us, &pd->M, &pd->L,
+        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->m2m, &pd->l2l, &pd->m2l, &pd->m2l_pk, &pd->wx, &pd->us, &pd->M, &pd->L,
                         &pd->Lx, &pd->m2l_odd, &pd->l2l_odd, &pd->Lodd};
         for (DevBuf *b : pb) dev_free(*b);
     }
@@ -333,7 +337,8 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
     if (!t || !cfg) { set_error("null argument"); return IMQ_EINVAL; }
     auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
     if (!ok_kc(cfg->m2l_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
-        (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32)) {
+        (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32) ||
+        cfg->m2l_mode < 0 || cfg->m2l_mode > 1) {
         set_error("kernel config out of range");
         return IMQ_EINVAL;
     }

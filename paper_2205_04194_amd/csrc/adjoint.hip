@@ -22,10 +22,6 @@
 
 namespace imq {
 
-template <typename T>
-void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks, int t0,
-                 const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *tables, int KP,
-                 int K, const T *in, T *out, int acc, int kin_ovr, int kout_ovr);
 template <typename T> imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s);
 template <typename T> imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s);
 
@@ -60,14 +56,14 @@ __global__ __launch_bounds__(64) void k_adjoint_eval(DTree<T> t, const int32_t *
                                                      const T *__restrict__ us, double *__restrict__ out)
 {
     const int b = leaves[blockIdx.x];
-    const int P = t.P, K = t.K;
+    const int P = t.P;
     const double inv_sd = ldexp(1.0, t.level[b]);
     const T inv_s = T(inv_sd);
     const double cnd = t.cn[t.set[b]];
     const T cc = T(cnd), c2 = T(cnd * cnd);
-    const T *Lv = L + (size_t(b) * 2 + 0) * K;
-    const T *Lg = L + (size_t(b) * 2 + 1) * K;
-    const T *Lov = Lo + (size_t(b) * 2 + 0) * K;
+    const T *Lv = L + (size_t(b) * 2 + 0) * t.KS;
+    const T *Lg = L + (size_t(b) * 2 + 1) * t.KS;
+    const T *Lov = Lo + (size_t(b) * 2 + 0) * t.KS;
     const int64_t N = t.N;
     for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
         const T xi = t.xl[i], yi = t.yl[i];
@@ -226,13 +222,13 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
 {
     const HostTree &h = t->h;
     const int64_t N = h.N;
-    const int K = h.K, KP = t->KP;
+    const int K = h.K, KP = t->KP, KS = coef_stride(K);
     const int nbox = int(h.level.size());
     imq_status st;
     if ((st = ensure_workspace<T>(t, 2)) != IMQ_OK) return st;
     if ((st = ensure_odd_tables(t)) != IMQ_OK) return st;
     PrecData &pd = prec_data<T>(t);
-    const size_t lo_bytes = sizeof(T) * size_t(nbox) * 2 * K;
+    const size_t lo_bytes = sizeof(T) * size_t(nbox) * 2 * KS;
     if (pd.Lodd.bytes < lo_bytes) IMQ_HIP(dev_alloc(pd.Lodd, lo_bytes));
     if (t->adj.bytes < sizeof(double) * 7 * size_t(N)) IMQ_HIP(dev_alloc(t->adj, sizeof(double) * 7 * size_t(N)));
     T *us = pd.us.as<T>();
@@ -247,18 +243,18 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
     T *Lo = pd.Lodd.as<T>();
     const int Ko = Kodd(h.p);
     {
-        const size_t n = size_t(nbox) * 2 * K;
+        const size_t n = size_t(nbox) * 2 * KS;
         hipLaunchKernelGGL(k_zero<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, Lo);
     }
     if (t->g_m2l.ntasks > 0)
         launch_gemm<T>(s, 32, 1, t->g_m2l.ntasks, 2, t->g_m2l.tasks.as<GemmTask>(), 0, t->g_m2l.tbox.as<int32_t>(),
-                       t->g_m2l.tab.as<int32_t>(), t->g_m2l.src.as<int32_t>(), pd.m2l_odd.as<T>(), KP, K,
+                       t->g_m2l.tab.as<int32_t>(), t->g_m2l.src.as<int32_t>(), pd.m2l_odd.as<T>(), KP, KS,
                        pd.M.as<T>(), Lo, 0, 0, Ko);
     for (int l = std::max(h.need_l, 0); l + 1 < h.nlev; ++l) {
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
         launch_shift<T>(s, false, t->kcfg.shift_cols, np, 2, t->sh_par.as<int32_t>() + p0,
                         t->sh_kids.as<int32_t>() + 4 * size_t(p0), pd.l2l_odd.as<T>(), KP, Ko, Ko,
-                        t->cut_l2l_odd, Lo, K, Lo, K);
+                        t->cut_l2l_odd, Lo, KS, Lo, KS);
     }
     IMQ_HIP(hipGetLastError());
     DTree<T> view = make_view<T>(t);

@@ -24,6 +24,7 @@ void dev_free(DevBuf &b);
 template <typename T>
 struct DTree {
     int nbox, nsets, nlev, K, P;
+    int KS;                    // stride of one expansion in M and L (K rounded up to 4)
     int64_t N;
     const int32_t *level, *set, *parent, *child0, *nchild, *pos, *begin, *end;
     const double *cx, *cy;
@@ -37,6 +38,7 @@ struct PrecData {              // everything that exists once per arithmetic typ
     DevBuf xl, yl, wx;
     DevBuf m2m, l2l;           // shift tables, 4 quadrants, packed for k_shift
     DevBuf m2l;                // translation tables, zero-padded to KP x KP each
+    DevBuf m2l_pk;             // the same, packed for k_m2l_stream
     DevBuf us, M, L;           // workspace
     size_t ws_nrhs = 0;
     DevBuf Lx;                 // per-pair local expansions of the X lists
@@ -65,6 +67,23 @@ template <typename T>
 void launch_shift(hipStream_t s, bool up, int cols, int npar, int nrhs, const int32_t *par,
                   const int32_t *kids, const T *Apk, int KP, int kin, int kout, const ShiftCuts &cuts,
                   const T *in, int ldin, T *out, int ldout);
+
+// M2L tables in the lane order of k_m2l_stream (same size as tabs).
+void pack_m2l_tables(const std::vector<double> &tabs, int KP, std::vector<double> &packed);
+
+// Expansion-to-local translations of tasks [task0, task0 + ntask), operands
+// streamed through registers class by class; for coefficient counts up to
+// kmax <= 80 (FP32) or 64 (FP64), else launches nothing and returns false.
+template <typename T>
+bool launch_m2l_stream(hipStream_t s, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
+                       const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk, int KP, int KS,
+                       const T *in, T *out);
+
+// Batched translation GEMM (fmm.hip); kc = staged coefficients per step.
+template <typename T>
+void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks, int t0,
+                 const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *tables, int KP, int KS,
+                 const T *in, T *out, int acc, int kin_ovr, int kout_ovr);
 
 struct DevGemm {               // device copy of a GemmList
     DevBuf tasks, tbox, tab, src;

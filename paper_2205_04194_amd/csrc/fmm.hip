@@ -166,7 +166,7 @@ __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restric
             __syncthreads();
             for (int k = lane; k < K; k += 64) {
                 const T v = lds_dot(mono, ld, k, su, n);
-                T &dst = M[(int64_t(b) * nrhs + r) * K + k];
+                T &dst = M[(int64_t(b) * nrhs + r) * t.KS + k];
                 dst = (c0 == beg) ? v : dst + v;
             }
         }
@@ -229,14 +229,13 @@ __global__ void k_p2l_reduce(DTree<T> t, const int32_t *__restrict__ xboxes, int
         for (int k = threadIdx.x; k < K; k += blockDim.x) {
             T s = T(0);
             for (int kp = t.x_off[b]; kp < t.x_off[b + 1]; ++kp) s += Lx[(size_t(r) * npairs + kp) * K + k];
-            L[(size_t(b) * nrhs + r) * K + k] += s;
+            L[(size_t(b) * nrhs + r) * t.KS + k] += s;
         }
 }
 
 // ------------------------------------------------------------------ MFMA translations
 
 constexpr int GEMM_MAXRB = 10;        // row blocks of 16: KP <= 160 (p <= 16)
-constexpr int GEMM_MAXSLOT = 27;
 
 // One task = one workgroup of 4 waves: out[:, col] (+)= sum_s T_s in[:, src(col, s)]
 // for the 64 columns (target box, rhs) of blockIdx.y and the row blocks of
@@ -258,7 +257,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
                                                     const int32_t *__restrict__ tbox,
                                                     const int32_t *__restrict__ tab,
                                                     const int32_t *__restrict__ src,
-                                                    const T *__restrict__ tables, int KP, int K, int nrhs,
+                                                    const T *__restrict__ tables, int KP, int KS, int nrhs,
                                                     const T *__restrict__ in, T *__restrict__ out,
                                                     int accumulate, int kin_ovr, int kout_ovr)
 {
@@ -334,7 +333,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
             const int c = e / KC, k = e % KC;
             const int ci = s_col[sl][c];
             const int kk = kc0 + k;
-            rb_[i] = (ci >= 0 && kk < tk.kin) ? in[size_t(ci) * K + kk] : T(0);
+            rb_[i] = (ci >= 0 && kk < tk.kin) ? in[size_t(ci) * KS + kk] : T(0);
         }
     };
 
@@ -375,7 +374,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
     const int gc = col0 + wave * 16 + r16;
     if (gc < ncols) {
         const int bl = gc / nrhs, r = gc - bl * nrhs;
-        T *o = out + (size_t(tbox[tk.box0 + bl]) * nrhs + r) * K;
+        T *o = out + (size_t(tbox[tk.box0 + bl]) * nrhs + r) * KS;
 #pragma unroll
         for (int rb = 0; rb < MAXRB; ++rb)
             if (rb < nrb)
@@ -395,11 +394,11 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
 template <typename T>
 void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks,
                  int t0, const int32_t *tbox, const int32_t *tab, const int32_t *src,
-                 const T *tables, int KP, int K, const T *in, T *out, int acc, int kin_ovr, int kout_ovr)
+                 const T *tables, int KP, int KS, const T *in, T *out, int acc, int kin_ovr, int kout_ovr)
 {
 #define IMQ_GEMM(KCV, RB)                                                                            \
     hipLaunchKernelGGL((k_gemm_tasks<T, KCV, RB>), grid, dim3(256), 0, s, tasks, t0, tbox, tab, src,  \
-                       tables, KP, K, nrhs, in, out, acc, kin_ovr, kout_ovr)
+                       tables, KP, KS, nrhs, in, out, acc, kin_ovr, kout_ovr)
     if (kc == 0) kc = 32;
     const dim3 grid(ntask, nrhs, split > 0 ? split : 1);
     if constexpr (sizeof(T) == 4) {
@@ -433,7 +432,7 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restric
     const T inv_s = pow2i<T>(t.level[b]);
     for (int r = 0; r < nrhs; ++r) {
         __syncthreads();
-        for (int k = threadIdx.x; k < K; k += blockDim.x) Ls[k] = L[(size_t(b) * nrhs + r) * K + k];
+        for (int k = threadIdx.x; k < K; k += blockDim.x) Ls[k] = L[(size_t(b) * nrhs + r) * t.KS + k];
         __syncthreads();
         for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
             T acc = T(0);
@@ -561,7 +560,7 @@ __global__ __launch_bounds__(64) void k_m2p_pairs(DTree<T> t, const int32_t *__r
     const T vz = T(cnd * inv_sd);
     for (int r = 0; r < nrhs; ++r) {
         __syncthreads();
-        for (int k = lane; k < K; k += 64) mw[k] = M[(size_t(a) * nrhs + r) * K + k] * wx[k];
+        for (int k = lane; k < K; k += 64) mw[k] = M[(size_t(a) * nrhs + r) * t.KS + k] * wx[k];
         __syncthreads();
         for (int i = t.begin[b] + lane; i < t.end[b]; i += 64) {
             T s = T(0);
@@ -656,6 +655,7 @@ DTree<T> make_view(const imq_tree_s *t)
     v.nsets = h.nsets;
     v.nlev = h.nlev;
     v.K = h.K;
+    v.KS = coef_stride(h.K);
     v.P = h.p;
     v.N = h.N;
     v.level = t->level.as<int32_t>(); v.set = t->set.as<int32_t>(); v.parent = t->parent.as<int32_t>();
@@ -681,8 +681,8 @@ imq_status ensure_workspace(imq_tree_s *t, int nrhs)
     const size_t nbox = t->h.level.size();
     if (pd.ws_nrhs < size_t(nrhs)) {
         IMQ_HIP(dev_alloc(pd.us, sizeof(T) * size_t(t->h.N) * nrhs));
-        IMQ_HIP(dev_alloc(pd.M, sizeof(T) * nbox * nrhs * t->h.K));
-        IMQ_HIP(dev_alloc(pd.L, sizeof(T) * nbox * nrhs * t->h.K));
+        IMQ_HIP(dev_alloc(pd.M, sizeof(T) * nbox * nrhs * coef_stride(t->h.K)));
+        IMQ_HIP(dev_alloc(pd.L, sizeof(T) * nbox * nrhs * coef_stride(t->h.K)));
         pd.ws_nrhs = nrhs;
     }
     if (pd.lx_nrhs < size_t(nrhs)) {
@@ -712,7 +712,7 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s)
     PrecData &pd = prec_data<T>(t);
     DTree<T> v = make_view<T>(t);
     const int nleaves = int(h.leaves.size());
-    const int K = h.K;
+    const int K = h.K, KS = coef_stride(K);
     const int ld = K | 1;                                      // odd LDS row stride
     T *M = pd.M.as<T>();
     mark(t, 1, s);
@@ -728,7 +728,7 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s)
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
         launch_shift<T>(s, true, t->kcfg.shift_cols, np, nrhs, t->sh_par.as<int32_t>() + p0,
                         t->sh_kids.as<int32_t>() + 4 * size_t(p0), pd.m2m.as<T>(), t->KP, K, K, t->cut_m2m, M,
-                        K, M, K);
+                        KS, M, KS);
     }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
@@ -742,21 +742,47 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
     PrecData &pd = prec_data<T>(t);
     DTree<T> v = make_view<T>(t);
     const int nbox = int(h.level.size());
-    const int K = h.K, KP = t->KP;
+    const int K = h.K, KP = t->KP, KS = coef_stride(K);
     const int ld = K | 1;
     const size_t lds = (size_t(64) * ld + 64) * sizeof(T);
     T *M = pd.M.as<T>(), *L = pd.L.as<T>();
     const imq_kernel_config &kc = t->kcfg;
     mark(t, 3, s);
     {
-        const size_t nL = size_t(nbox) * nrhs * K;
+        const size_t nL = size_t(nbox) * nrhs * KS;
         hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, L, T(0));
     }
-    if (t->g_m2l.ntasks > 0)
-        launch_gemm<T>(s, kc.m2l_kc > 0 ? kc.m2l_kc : 32, kc.m2l_split > 0 ? kc.m2l_split : 1,
-                       t->g_m2l.ntasks, nrhs, t->g_m2l.tasks.as<GemmTask>(), 0, t->g_m2l.tbox.as<int32_t>(),
-                       t->g_m2l.tab.as<int32_t>(), t->g_m2l.src.as<int32_t>(), pd.m2l.as<T>(), KP, K, M, L,
-                       0, 0, 0);
+    {
+        // Per level: the register-streaming kernel (mode 0, up to 80 coefficients
+        // in FP32 and 64 in FP64) or the staged GEMM; consecutive levels of one
+        // kind and row-block count share a launch.
+        const DevGemm &g = t->g_m2l;
+        const int smax = sizeof(T) == 4 ? 5 : 4;
+        const auto kind = [&](int l) {
+            const int nrb = (h.Klev[l] + 15) / 16;
+            return (kc.m2l_mode == 0 && nrb <= smax) ? nrb : 0;
+        };
+        for (int l = 0; l < h.nlev;) {
+            const int t0 = g.level_task_begin[l];
+            if (g.level_task_begin[l + 1] == t0) { ++l; continue; }
+            const int k = kind(l);
+            int l2 = l + 1, kmax = h.Klev[l];
+            while (l2 < h.nlev && (g.level_task_begin[l2 + 1] == g.level_task_begin[l2] || kind(l2) == k)) {
+                kmax = std::max(kmax, h.Klev[l2]);
+                ++l2;
+            }
+            const int nt = g.level_task_begin[l2] - t0;
+            bool done = false;
+            if (k > 0)
+                done = launch_m2l_stream<T>(s, kmax, nt, t0, nrhs, g.tasks.as<GemmTask>(), g.tbox.as<int32_t>(),
+                                            g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.m2l_pk.as<T>(), KP, KS, M, L);
+            if (!done)
+                launch_gemm<T>(s, kc.m2l_kc > 0 ? kc.m2l_kc : 32, kc.m2l_split > 0 ? kc.m2l_split : 1, nt, nrhs,
+                               g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
+                               g.src.as<int32_t>(), pd.m2l.as<T>(), KP, KS, M, L, 0, 0, 0);
+            l = l2;
+        }
+    }
     IMQ_HIP(hipGetLastError());
     mark(t, 4, s);
     if (t->nxpairs > 0) {
@@ -770,7 +796,7 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
         launch_shift<T>(s, false, kc.shift_cols, np, nrhs, t->sh_par.as<int32_t>() + p0,
                         t->sh_kids.as<int32_t>() + 4 * size_t(p0), pd.l2l.as<T>(), KP, h.Klev[l], h.Klev[l + 1],
-                        t->cut_l2l, L, K, L, K);
+                        t->cut_l2l, L, KS, L, KS);
     }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;

@@ -70,6 +70,7 @@ double legendre_at_zero(int n, int m);     // P_n^m(0), Condon-Shortley sign
 // (same set, level and child position).  Columns are (box, right-hand side)
 // pairs; one task is one workgroup's tile.
 constexpr int GEMM_TILE = 64;
+constexpr int GEMM_MAXSLOT = 27;  // V-list classes per child position
 struct GemmTask {
     int32_t box0;     // first target in GemmList::tbox
     int32_t nbox;     // targets in this task (<= GEMM_TILE)
@@ -86,6 +87,10 @@ struct GemmList {
     std::vector<int32_t> tbox, tab, src;
     std::vector<int32_t> level_task_begin;   // tasks of level l: [begin[l], begin[l+1])
 };
+
+// Stride of one expansion in the M and L arrays: K rounded up to 4, so that
+// every expansion starts on a 16-byte (FP32) or 32-byte (FP64) boundary.
+inline int coef_stride(int K) { return (K + 3) & ~3; }
 
 struct HostTree;
 void build_gemm_lists(HostTree &t);

@@ -1,0 +1,231 @@
+// Expansion-to-local translations (V lists) with every operand streamed
+// through registers.
+//
+// L[target] = sum over the (up to 27) occupied V-list classes s of
+// T_{level, set, class(s)} M[source_s]  (Sec. 2.2: the lifted translation from
+// the source plane z = -c/2 to the target plane z = +c/2).
+//
+// The batched GEMM of fmm.hip stages one class per step through LDS, so a
+// workgroup pays one memory round trip per class and coefficient chunk.
+// Here the 4 waves split the classes (wave w takes classes w, w+4, ...), each
+// wave loads its table slices and source expansions straight from memory in
+// the matrix-core lane order (16 bytes per lane and load), one class ahead of
+// the matrix cores, and the 4 partial results are summed in LDS in a fixed
+// order.
+#include "device.h"
+#include "mfma.h"
+
+#include <hip/hip_runtime.h>
+
+namespace imq {
+
+namespace {
+
+constexpr int SPW = (GEMM_MAXSLOT + 3) / 4;     // classes per wave
+
+// Task = GemmTask of the translation batches (<= 64 targets sharing level,
+// set and child position).  blockIdx.y picks TC = 16*NCB of its columns
+// (target, rhs).  Packed table layout (ntab x nrbT x nrbT chunks of 64 lanes x
+// 4): element j of lane l of (row block rb, input chunk ci) is
+// T[16 rb + l%16][16 ci + 4 (l/16) + j], so a lane's four values of a chunk
+// match four consecutive source coefficients.
+//
+// Wave w walks its classes w, w+4, ...
+// For class k the source expansions of class k+1 and, row block by row
+// block as soon as each is consumed, the table of class k+1 are requested
+// while the matrix cores work on class k; the source indices run one class
+// further ahead.  Register use: NRB*NRB + 2*NCB*NRB four-value quads.
+template <typename T, int NRB, int NCB>
+__global__ __launch_bounds__(256) void k_m2l_stream(const GemmTask *__restrict__ tasks, int task0,
+                                                    const int32_t *__restrict__ tbox,
+                                                    const int32_t *__restrict__ tab,
+                                                    const int32_t *__restrict__ src, const T *__restrict__ Apk,
+                                                    int nrbT, int nrhs, int KS, const T *__restrict__ in,
+                                                    T *__restrict__ out)
+{
+    constexpr int TC = 16 * NCB;
+    constexpr int LDR = NRB * 16 + 1;
+    using acc_t = typename Mfma<T>::acc_t;
+    using Q = Quad<T>;
+    __shared__ T red[4 * TC * LDR];
+    __shared__ int s_out[TC];
+
+    const GemmTask tk = tasks[task0 + blockIdx.x];
+    const int ncols = tk.nbox * nrhs;
+    const int col0 = blockIdx.y * TC;
+    if (col0 >= ncols) return;                       // uniform over the workgroup
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i16 = lane & 15, q = lane >> 4;
+    const int kin = tk.kin, kout = tk.kout;
+    const int nslot = tk.nslot;
+    if (tid < TC) {
+        const int gc = col0 + tid;
+        int o = -1;
+        if (gc < ncols) {
+            const int bl = gc / nrhs, r = gc - bl * nrhs;
+            o = tbox[tk.box0 + bl] * nrhs + r;
+        }
+        s_out[tid] = o;
+    }
+    int bl[NCB], rr[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        const int gc = col0 + cb * 16 + i16;
+        bl[cb] = gc < ncols ? gc / nrhs : -1;
+        rr[cb] = gc < ncols ? gc - bl[cb] * nrhs : 0;
+    }
+    auto source = [&](int k, int *sb) {
+        const int sl = w + 4 * k;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+            sb[cb] = (k < SPW && sl < nslot && bl[cb] >= 0) ? src[tk.src0 + bl[cb] * nslot + sl] : -1;
+    };
+    auto load_b = [&](const int *sb, Q (*dst)[NRB]) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int ci = 0; ci < NRB; ++ci) {
+                const int k0 = ci * 16 + 4 * q;
+                Q x;
+                if (sb[cb] >= 0 && k0 < kin) {
+                    // k0 + 3 < KS: KS is a multiple of 4 and kin <= KS
+                    x = *reinterpret_cast<const Q *>(in + (size_t(sb[cb]) * nrhs + rr[cb]) * KS + k0);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (k0 + j >= kin) x.v[j] = T(0);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) x.v[j] = T(0);
+                }
+                dst[cb][ci] = x;
+            }
+    };
+    auto table = [&](int k) -> const T * {
+        const int sl = w + 4 * k;
+        return (k < SPW && sl < nslot) ? Apk + size_t(tab[tk.tab0 + sl]) * nrbT * nrbT * 256 + lane * 4 : nullptr;
+    };
+
+    acc_t acc[NRB][NCB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[rb][cb][v] = T(0);
+
+    Q a[NRB][NRB];
+    Q bc[NCB][NRB], bn[NCB][NRB];
+    int sbc[NCB], sbn[NCB], sbnn[NCB];
+    source(0, sbc);
+    source(1, sbn);
+    const T *Ac = table(0);
+    if (Ac)
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+            for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = *reinterpret_cast<const Q *>(Ac + (rb * nrbT + ci) * 256);
+    load_b(sbc, bc);
+    for (int k = 0; k < SPW; ++k) {
+        const bool act = Ac != nullptr;               // wave-uniform
+        const T *An = table(k + 1);
+        load_b(sbn, bn);
+        source(k + 2, sbnn);
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) {
+            if (act)
+#pragma unroll
+                for (int ci = 0; ci < NRB; ++ci)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb)
+                            acc[rb][cb] = Mfma<T>::mac(a[rb][ci].v[j], bc[cb][ci].v[j], acc[rb][cb]);
+            if (An)
+#pragma unroll
+                for (int ci = 0; ci < NRB; ++ci)
+                    a[rb][ci] = *reinterpret_cast<const Q *>(An + (rb * nrbT + ci) * 256);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+            for (int ci = 0; ci < NRB; ++ci) bc[cb][ci] = bn[cb][ci];
+            sbn[cb] = sbnn[cb];
+        }
+        Ac = An;
+    }
+
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                red[(w * TC + cb * 16 + i16) * LDR + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
+    __syncthreads();
+    for (int e = tid; e < TC * kout; e += 256) {
+        const int c = e / kout, kk = e - c * kout;
+        const int o = s_out[c];
+        if (o < 0) continue;
+        out[size_t(o) * KS + kk] = ((red[c * LDR + kk] + red[(TC + c) * LDR + kk]) + red[(2 * TC + c) * LDR + kk]) +
+                                   red[(3 * TC + c) * LDR + kk];
+    }
+}
+
+}  // namespace
+
+void pack_m2l_tables(const std::vector<double> &tabs, int KP, std::vector<double> &packed)
+{
+    const int nrb = KP / 16;
+    const size_t PP = size_t(KP) * KP;
+    const size_t ntab = tabs.size() / PP;
+    packed.assign(tabs.size(), 0.0);
+    for (size_t tb = 0; tb < ntab; ++tb)
+        for (int rb = 0; rb < nrb; ++rb)
+            for (int ci = 0; ci < nrb; ++ci)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 4; ++j)
+                        packed[tb * PP + ((size_t(rb) * nrb + ci) * 64 + l) * 4 + j] =
+                            tabs[tb * PP + size_t(rb * 16 + l % 16) * KP + ci * 16 + 4 * (l / 16) + j];
+}
+
+
+template <typename T>
+bool launch_m2l_stream(hipStream_t s, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
+                       const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk, int KP, int KS,
+                       const T *in, T *out)
+{
+    const int nrb = (kmax + 15) / 16;
+    if (ntask <= 0) return true;
+#define IMQ_M2LS(NRB, NCB)                                                                                 \
+    hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB>),                                                        \
+                       dim3(ntask, unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB))), dim3(256), 0, s, \
+                       tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out)
+    if constexpr (sizeof(T) == 4) {
+        switch (nrb) {
+        case 1: IMQ_M2LS(1, 2); return true;
+        case 2: IMQ_M2LS(2, 2); return true;
+        case 3: IMQ_M2LS(3, 2); return true;
+        case 4: IMQ_M2LS(4, 1); return true;
+        case 5: IMQ_M2LS(5, 1); return true;
+        default: return false;
+        }
+    } else {
+        switch (nrb) {
+        case 1: IMQ_M2LS(1, 1); return true;
+        case 2: IMQ_M2LS(2, 1); return true;
+        case 3: IMQ_M2LS(3, 1); return true;
+        case 4: IMQ_M2LS(4, 1); return true;
+        default: return false;
+        }
+    }
+#undef IMQ_M2LS
+}
+
+template bool launch_m2l_stream<float>(hipStream_t, int, int, int, int, const GemmTask *, const int32_t *,
+                                       const int32_t *, const int32_t *, const float *, int, int, const float *,
+                                       float *);
+template bool launch_m2l_stream<double>(hipStream_t, int, int, int, int, const GemmTask *, const int32_t *,
+                                        const int32_t *, const int32_t *, const double *, int, int, const double *,
+                                        double *);
+
+}  // namespace imq

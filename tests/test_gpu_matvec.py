@@ -130,3 +130,47 @@ def test_invalid_arguments_raise(imq):
     tree = imq.build_tree(_dev(xy), 0.1, leaf=4, p=4)
     with pytest.raises(ValueError):
         tree.matvec(_dev(np.zeros(11)))
+
+
+@pytest.mark.parametrize("p", [3, 4, 6, 9, 12])
+def test_translation_kernels_agree_and_match_the_oracle(imq, p):
+    """The two M2L kernels (operands streamed through registers, staged GEMM)
+    compute the same truncated sums, so they differ by rounding only; both stay
+    within the truncation error of order p against the oracle."""
+    d = W.small(6000)
+    U = W.uniform_vector(6000, W.rng(67, p), nrhs=3)
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=16, p=p)
+    ref = oracle.matvec(d["xy"], d["c"], U)
+    out = {}
+    for mode in (0, 1):
+        tree.set_kernel_config(m2l_mode=mode)
+        out[mode, "fp64"] = tree.matvec(_dev(U), "fp64").cpu().numpy()
+        out[mode, "fp32"] = tree.matvec(_dev(U), "fp32").cpu().numpy()
+    for r in range(3):
+        assert _rel(out[0, "fp64"][r], out[1, "fp64"][r]) < 1e-12
+        for mode in (0, 1):
+            assert _rel(out[mode, "fp32"][r], out[1, "fp64"][r]) < 2e-6
+        err = _rel(out[0, "fp64"][r], ref[r])
+        print(f"p={p} rhs {r}: rel err vs oracle {err:.3e}")
+        assert err < {3: 1e-2, 4: 3e-3, 6: 3e-4, 9: 2e-5, 12: 1e-6}[p]
+
+
+def test_mixed_level_orders_use_both_kernels(imq):
+    d = W.small(20000)
+    u = _dev(d["u"])
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=16, p=12)
+    nlev = tree.info()["nlevels"]
+    orders = [12] * nlev
+    for l in range(nlev - 3, nlev):
+        orders[l] = {nlev - 3: 6, nlev - 2: 4, nlev - 1: 3}[l]
+    tree.set_level_orders(orders)
+    res = {}
+    for mode in (0, 1):
+        tree.set_kernel_config(m2l_mode=mode)
+        res[mode] = tree.matvec(u, "fp64").cpu().numpy()
+    assert _rel(res[0], res[1]) < 1e-12
+    rows = np.arange(0, 20000, 37)
+    exact = oracle.matvec(d["xy"], d["c"], d["u"], xy_targets=d["xy"][rows])
+    err = _rel(res[0][rows], exact)
+    print(f"mixed orders {orders}: rel err {err:.3e}")
+    assert err < 1e-3
