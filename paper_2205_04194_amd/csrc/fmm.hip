@@ -467,24 +467,33 @@ constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 p
 // P2P: b_i += sum over U-list leaves a of sum_j u_j / sqrt(|x_i - x_j|^2 + c^2).
 // One wave per target leaf.  Lane l takes target l % TP (TP = the leaf's
 // point count rounded up to a power of two, at least 4) in lane group
-// l / TP of G = 64 / TP groups.  The U-list sources are staged, relative to
-// the target leaf's centre, in LDS chunks of up to 256 (padded with zero
-// weights to a multiple of 4 G); each group sums a contiguous quarter-aligned
-// run of the chunk, 4 sources per step, and the G partial sums of a target
-// are combined with shuffles.  Partial sums over one chunk are kept in T,
-// the running sum in FP64.
+// l / TP of G = 64 / TP groups.
+// Staging: the U list is read 64 entries at a time, one entry per lane (box,
+// first point, count, offset of its centre); a wave prefix sum of the counts
+// numbers the sources of the batch consecutively.  Chunks of up to 256 of
+// them are then gathered with every load of the chunk in flight at once
+// (each lane finds the entry of its slot by binary search over the prefix
+// sums in LDS), relative to the target leaf's centre and padded with zero
+// weights to a multiple of 4 G.  Each group sums a contiguous quarter-aligned
+// run of the chunk, 4 sources per step, and the G partial sums of a target are
+// combined with shuffles.  Partial sums over one chunk are kept in T, the
+// running sum in FP64.
 template <typename T>
 __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restrict__ leaves,
                                             const T *__restrict__ us, int nrhs, double *__restrict__ bs)
 {
     using V4 = typename Vec4<T>::type;
     __shared__ V4 sx4[P2P_LDS / 4], sy4[P2P_LDS / 4], su4[P2P_LDS / 4];
+    __shared__ int s_beg[64], s_off[65];
+    __shared__ T s_ox[64], s_oy[64];
     T *sx = reinterpret_cast<T *>(sx4), *sy = reinterpret_cast<T *>(sy4), *su = reinterpret_cast<T *>(su4);
+    constexpr int SPL = P2P_CHUNK / 64;          // chunk slots per lane
     const int b = leaves[blockIdx.x];
     const int lane = threadIdx.x;
     const double cnd = t.cn[t.set[b]];
     const T c2 = T(cnd * cnd);
     const int u0 = t.u_off[b], u1 = t.u_off[b + 1];
+    const double bcx = t.cx[b], bcy = t.cy[b];
     for (int t0 = t.begin[b]; t0 < t.end[b]; t0 += 64) {
         const int ntc = min(64, t.end[b] - t0);
         int TP = 4;
@@ -495,43 +504,78 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
         const T xi = t.xl[i], yi = t.yl[i];
         for (int r = 0; r < nrhs; ++r) {
             double acc = 0.0;
-            int pos = 0;
-            auto flush = [&]() {
-                const int per = ((pos + G - 1) / G + 3) & ~3;   // sources per group, multiple of 4
-                for (int j = pos + lane; j < per * G; j += 64) {
-                    sx[j] = T(0); sy[j] = T(0); su[j] = T(0);
+            for (int ub = u0; ub < u1; ub += 64) {
+                const int nb = min(64, u1 - ub);
+                int cnt = 0, beg = 0;
+                T ox = T(0), oy = T(0);
+                if (lane < nb) {
+                    const int a = t.u_idx[ub + lane];
+                    beg = t.begin[a];
+                    cnt = t.end[a] - beg;
+                    ox = T(t.cx[a] - bcx);
+                    oy = T(t.cy[a] - bcy);
                 }
-                __syncthreads();
-                T part = T(0);
-                const int q0 = grp * per / 4, q1 = q0 + per / 4;
-                for (int qv = q0; qv < q1; ++qv) {
-                    const V4 X = sx4[qv], Y = sy4[qv], U = su4[qv];
+                int incl = cnt;                  // inclusive prefix sum over the wave
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const T dx = xi - X[k], dy = yi - Y[k];
-                        part += U[k] * rsqrt_fast(fma(dx, dx, fma(dy, dy, c2)));
-                    }
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int v = __shfl_up(incl, d);
+                    if (lane >= d) incl += v;
                 }
-                acc += double(part);
+                const int total = __shfl(incl, 63);
+                __syncthreads();                 // previous batch's entries no longer read
+                s_beg[lane] = beg;
+                s_off[lane] = incl - cnt;
+                s_ox[lane] = ox;
+                s_oy[lane] = oy;
+                if (lane == 0) s_off[64] = total;
                 __syncthreads();
-                pos = 0;
-            };
-            for (int uu = u0; uu < u1; ++uu) {
-                const int a = t.u_idx[uu];
-                const T ox = T(t.cx[a] - t.cx[b]), oy = T(t.cy[a] - t.cy[b]);
-                for (int j0 = t.begin[a]; j0 < t.end[a]; j0 += 64) {
-                    const int ns = min(64, t.end[a] - j0);
-                    if (pos + ns > P2P_CHUNK) flush();
-                    if (lane < ns) {
-                        const int j = j0 + lane;
-                        sx[pos + lane] = t.xl[j] + ox;
-                        sy[pos + lane] = t.yl[j] + oy;
-                        su[pos + lane] = us[r * t.N + j];
+                for (int c0 = 0; c0 < total; c0 += P2P_CHUNK) {
+                    const int n = min(P2P_CHUNK, total - c0);
+                    T vx[SPL], vy[SPL], vu[SPL];
+#pragma unroll
+                    for (int k = 0; k < SPL; ++k) {
+                        const int slot = c0 + lane + 64 * k;
+                        vx[k] = vy[k] = vu[k] = T(0);
+                        if (slot < total) {
+                            int lo = 0, hi = nb - 1;           // last entry with s_off <= slot
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (s_off[mid] <= slot) lo = mid; else hi = mid - 1;
+                            }
+                            const int j = s_beg[lo] + (slot - s_off[lo]);
+                            vx[k] = t.xl[j] + s_ox[lo];
+                            vy[k] = t.yl[j] + s_oy[lo];
+                            vu[k] = us[r * t.N + j];
+                        }
                     }
-                    pos += ns;
+                    const int per = ((n + G - 1) / G + 3) & ~3;   // sources per group, multiple of 4
+#pragma unroll
+                    for (int k = 0; k < SPL; ++k) {
+                        const int e = lane + 64 * k;
+                        if (e < per * G) {
+                            sx[e] = vx[k];
+                            sy[e] = vy[k];
+                            su[e] = vu[k];
+                        }
+                    }
+                    for (int e = P2P_CHUNK + lane; e < per * G; e += 64) {
+                        sx[e] = T(0); sy[e] = T(0); su[e] = T(0);
+                    }
+                    __syncthreads();
+                    T part = T(0);
+                    const int q0 = grp * per / 4, q1 = q0 + per / 4;
+                    for (int qv = q0; qv < q1; ++qv) {
+                        const V4 X = sx4[qv], Y = sy4[qv], U = su4[qv];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const T dx = xi - X[k], dy = yi - Y[k];
+                            part += U[k] * rsqrt_fast(fma(dx, dx, fma(dy, dy, c2)));
+                        }
+                    }
+                    acc += double(part);
+                    __syncthreads();
                 }
             }
-            if (pos > 0) flush();
             for (int off = TP; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
             if (grp == 0 && valid) bs[r * t.N + i] += acc;
         }
