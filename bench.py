@@ -128,6 +128,7 @@ def main():
     ap.add_argument("--m2l-kc", type=int, default=0)
     ap.add_argument("--m2l-split", type=int, default=0)
     ap.add_argument("--m2l-mode", type=int, default=0)
+    ap.add_argument("--p2p-wg", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -171,7 +172,8 @@ def main():
         prec = precs[0]
         orders = [int(x) for x in args.orders.split(",")]
         tree.set_level_orders(orders)
-        tree.set_kernel_config(m2l_kc=args.m2l_kc, m2l_split=args.m2l_split, m2l_mode=args.m2l_mode)
+        tree.set_kernel_config(m2l_kc=args.m2l_kc, m2l_split=args.m2l_split, m2l_mode=args.m2l_mode,
+                              p2p_wg=args.p2p_wg)
         b = tree.matvec(u, prec)
         err = float(torch.linalg.norm(b[rows] - exact) / torch.linalg.norm(exact))
         ms, stages = time_products(tree, u, prec, args.steps, args.warmup)

@@ -157,11 +157,14 @@ imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
  *  m2l_mode   : M2L kernel per level: 0 = operands streamed through
  *               registers where a box has at most 80 coefficients (FP32) or
  *               64 (FP64), the staged GEMM above; 1 = staged GEMM everywhere.
- *               m2l_kc and m2l_split apply to the staged GEMM only. */
+ *               m2l_kc and m2l_split apply to the staged GEMM only.
+ *  p2p_wg     : workgroups of the near-field kernel while it runs alongside
+ *               the tree passes (each takes every p2p_wg-th leaf); 0 = 2048 */
 typedef struct {
     int m2l_kc, m2l_split;
     int shift_cols;
     int m2l_mode;
+    int p2p_wg;
 } imq_kernel_config;
 
 imq_status imq_set_kernel_config(imq_tree tree, const imq_kernel_config *cfg);
@@ -196,7 +199,10 @@ imq_status imq_get_tree_info(imq_tree tree, imq_tree_info *info);
  * recorded on the product's stream around every stage (no synchronisation
  * inside the product), and imq_get_stage_times synchronises on them and
  * returns the mean per stage in ms (host array of IMQ_NSTAGES entries, stage
- * order as in imq_stage_name).  At most 256 products are recorded. */
+ * order as in imq_stage_name).  At most 256 products are recorded.  While
+ * timing is on, the near field runs on the product's stream between the
+ * translations and L2P instead of concurrently with the tree passes, so the
+ * stage times add up to a longer product than an untimed one. */
 #define IMQ_NSTAGES 9
 imq_status imq_set_stage_timing(imq_tree tree, int on);
 imq_status imq_get_stage_times(imq_tree tree, double *ms);

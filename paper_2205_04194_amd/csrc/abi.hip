@@ -198,6 +198,15 @@ static void free_tree(imq_tree_s *t)
     }
     for (auto &e : t->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipStream_t &x : t->side)
+        if (x) {
+            (void)hipStreamSynchronize(x);
+            (void)hipStreamDestroy(x);
+        }
+    for (hipEvent_t e : {t->ev_fork, t->ev_join, t->ev_tfork})
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : t->ev_tjoin)
+        if (e) (void)hipEventDestroy(e);
     delete t;
 }
 
@@ -241,7 +250,7 @@ const char *imq_status_string(imq_status s)
 const char *imq_stage_name(int k)
 {
     static const char *names[IMQ_NSTAGES] = {"gather", "p2m", "m2m", "m2l", "p2l+l2l",
-                                             "l2p", "p2p", "m2p", "scatter"};
+                                             "p2p", "l2p", "m2p", "scatter"};
     return (k >= 0 && k < IMQ_NSTAGES) ? names[k] : "?";
 }
 
@@ -338,7 +347,7 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
     auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
     if (!ok_kc(cfg->m2l_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
         (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32) ||
-        cfg->m2l_mode < 0 || cfg->m2l_mode > 1) {
+        cfg->m2l_mode < 0 || cfg->m2l_mode > 1 || cfg->p2p_wg < 0) {
         set_error("kernel config out of range");
         return IMQ_EINVAL;
     }

@@ -112,6 +112,14 @@ struct imq_tree_s {
     // and the boxes that own at least one pair
     imq::DevBuf w_tgt, w_scr, w_leaves, x_tgt, x_boxes, Pw;
     int nwpairs = 0, nwleaves = 0, nwscr = 0, nxpairs = 0, nxboxes = 0;
+    // extra streams: side[0] runs the near field alongside the tree passes,
+    // side[1..] run translation levels concurrently (with the caller's stream
+    // that makes 4 streams, the hardware queues a process gets by default)
+    static constexpr int NSIDE = 3;
+    hipStream_t side[NSIDE] = {};
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;          // near field
+    hipEvent_t ev_tfork = nullptr, ev_tjoin[NSIDE] = {};      // translations
+    imq_status ensure_side();
     // solver workspace
     imq::DevBuf sol;
     size_t sol_bytes = 0;

@@ -424,7 +424,7 @@ __global__ void k_fill(size_t n, T *__restrict__ p, T v)
 // constant so the evaluation loop is fully unrolled.
 template <typename T, int P>
 __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ L, int nrhs, double *__restrict__ bs)
+                                            const T *__restrict__ L, int nrhs, double *__restrict__ bs, int add)
 {
     constexpr int K = (P + 1) * (P + 2) / 2;
     __shared__ T Ls[K];
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restric
             // real part of Lt * monomial: Re*Re - Im*Im
             monomials<P>(t.xl[i] * inv_s, t.yl[i] * inv_s,
                          [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
-            bs[r * t.N + i] = double(acc);
+            bs[r * t.N + i] = add ? bs[r * t.N + i] + double(acc) : double(acc);
         }
     }
 }
@@ -465,7 +465,8 @@ constexpr int P2P_CHUNK = 256;                 // sources staged per round
 constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 per lane group
 
 // P2P: b_i += sum over U-list leaves a of sum_j u_j / sqrt(|x_i - x_j|^2 + c^2).
-// One wave per target leaf.  Lane l takes target l % TP (TP = the leaf's
+// One wave per target leaf at a time; workgroup g takes leaves g, g + grid, ...
+// (a smaller grid leaves wave slots free for kernels running alongside).  Lane l takes target l % TP (TP = the leaf's
 // point count rounded up to a power of two, at least 4) in lane group
 // l / TP of G = 64 / TP groups.
 // Staging: the U list is read 64 entries at a time, one entry per lane (box,
@@ -479,8 +480,8 @@ constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 p
 // combined with shuffles.  Partial sums over one chunk are kept in T, the
 // running sum in FP64.
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ us, int nrhs, double *__restrict__ bs)
+__global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restrict__ leaves, int nleaves,
+                                            const T *__restrict__ us, int nrhs, double *__restrict__ bs, int add)
 {
     using V4 = typename Vec4<T>::type;
     __shared__ V4 sx4[P2P_LDS / 4], sy4[P2P_LDS / 4], su4[P2P_LDS / 4];
@@ -488,8 +489,9 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
     __shared__ T s_ox[64], s_oy[64];
     T *sx = reinterpret_cast<T *>(sx4), *sy = reinterpret_cast<T *>(sy4), *su = reinterpret_cast<T *>(su4);
     constexpr int SPL = P2P_CHUNK / 64;          // chunk slots per lane
-    const int b = leaves[blockIdx.x];
     const int lane = threadIdx.x;
+    for (int lf = blockIdx.x; lf < nleaves; lf += gridDim.x) {
+    const int b = leaves[lf];
     const double cnd = t.cn[t.set[b]];
     const T c2 = T(cnd * cnd);
     const int u0 = t.u_off[b], u1 = t.u_off[b + 1];
@@ -577,8 +579,10 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
                 }
             }
             for (int off = TP; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
-            if (grp == 0 && valid) bs[r * t.N + i] += acc;
+            if (grp == 0 && valid) bs[r * t.N + i] = add ? bs[r * t.N + i] + acc : acc;
         }
+    }
+    __syncthreads();                             // LDS of this leaf no longer read
     }
 }
 
@@ -749,8 +753,40 @@ static inline void mark(imq_tree_s *, int stage, hipStream_t s)
 }
 
 // Upward pass: leaf expansions and multipole shifts (stages P2M, M2M).
+}  // namespace imq
+
+imq_status imq_tree_s::ensure_side()
+{
+    if (side[0]) return IMQ_OK;
+    for (hipStream_t &x : side) IMQ_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&ev_fork, &ev_join, &ev_tfork}) IMQ_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    for (hipEvent_t &e : ev_tjoin) IMQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return IMQ_OK;
+}
+
+namespace imq {
+
+// Launch the near field on the tree's second stream once everything queued
+// on s so far (the gathered charges) is done; ev_join marks its completion.
 template <typename T>
-imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s)
+imq_status fork_p2p(imq_tree_s *t, int nrhs, hipStream_t s)
+{
+    imq_status st = t->ensure_side();
+    if (st != IMQ_OK) return st;
+    PrecData &pd = prec_data<T>(t);
+    IMQ_HIP(hipEventRecord(t->ev_fork, s));
+    IMQ_HIP(hipStreamWaitEvent(t->side[0], t->ev_fork, 0));
+    const int nleaves = int(t->h.leaves.size());
+    const int wg = t->kcfg.p2p_wg > 0 ? t->kcfg.p2p_wg : 2048;
+    hipLaunchKernelGGL(k_p2p<T>, dim3(unsigned(std::min(nleaves, wg))), dim3(64), 0, t->side[0], make_view<T>(t),
+                       t->leaves.as<int32_t>(), nleaves, pd.us.as<T>(), nrhs, t->bs.as<double>(), 0);
+    IMQ_HIP(hipGetLastError());
+    IMQ_HIP(hipEventRecord(t->ev_join, t->side[0]));
+    return IMQ_OK;
+}
+
+template <typename T>
+imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork)
 {
     const HostTree &h = t->h;
     PrecData &pd = prec_data<T>(t);
@@ -768,6 +804,10 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s)
 #undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
     mark(t, 2, s);
+    if (fork) {      // the near field shares the GPU with the latency-bound shifts and translations
+        imq_status st = fork_p2p<T>(t, nrhs, s);
+        if (st != IMQ_OK) return st;
+    }
     for (int l = h.nlev - 2; l >= h.need_m; --l) {
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
         launch_shift<T>(s, true, t->kcfg.shift_cols, np, nrhs, t->sh_par.as<int32_t>() + p0,
@@ -806,9 +846,21 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
             const int nrb = (h.Klev[l] + 15) / 16;
             return (kc.m2l_mode == 0 && nrb <= smax) ? nrb : 0;
         };
+        // level groups are independent: with the product untimed they run on
+        // the caller's stream and side[1..] in turn
+        const bool conc = g_cur_events == nullptr;
+        int ngroup = 0;
+        if (conc) {
+            imq_status st = t->ensure_side();
+            if (st != IMQ_OK) return st;
+            IMQ_HIP(hipEventRecord(t->ev_tfork, s));
+            for (int i = 1; i < imq_tree_s::NSIDE; ++i) IMQ_HIP(hipStreamWaitEvent(t->side[i], t->ev_tfork, 0));
+        }
         for (int l = 0; l < h.nlev;) {
             const int t0 = g.level_task_begin[l];
             if (g.level_task_begin[l + 1] == t0) { ++l; continue; }
+            const int si = conc ? ngroup++ % imq_tree_s::NSIDE : 0;     // 0: the caller's stream
+            hipStream_t gs = si == 0 ? s : t->side[si];
             const int k = kind(l);
             int l2 = l + 1, kmax = h.Klev[l];
             while (l2 < h.nlev && (g.level_task_begin[l2 + 1] == g.level_task_begin[l2] || kind(l2) == k)) {
@@ -818,14 +870,19 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
             const int nt = g.level_task_begin[l2] - t0;
             bool done = false;
             if (k > 0)
-                done = launch_m2l_stream<T>(s, kmax, nt, t0, nrhs, g.tasks.as<GemmTask>(), g.tbox.as<int32_t>(),
+                done = launch_m2l_stream<T>(gs, kmax, nt, t0, nrhs, g.tasks.as<GemmTask>(), g.tbox.as<int32_t>(),
                                             g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.m2l_pk.as<T>(), KP, KS, M, L);
             if (!done)
-                launch_gemm<T>(s, kc.m2l_kc > 0 ? kc.m2l_kc : 32, kc.m2l_split > 0 ? kc.m2l_split : 1, nt, nrhs,
+                launch_gemm<T>(gs, kc.m2l_kc > 0 ? kc.m2l_kc : 32, kc.m2l_split > 0 ? kc.m2l_split : 1, nt, nrhs,
                                g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
                                g.src.as<int32_t>(), pd.m2l.as<T>(), KP, KS, M, L, 0, 0, 0);
             l = l2;
         }
+        if (conc)
+            for (int i = 1; i < imq_tree_s::NSIDE; ++i) {
+                IMQ_HIP(hipEventRecord(t->ev_tjoin[i], t->side[i]));
+                IMQ_HIP(hipStreamWaitEvent(s, t->ev_tjoin[i], 0));
+            }
     }
     IMQ_HIP(hipGetLastError());
     mark(t, 4, s);
@@ -846,6 +903,11 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
     return IMQ_OK;
 }
 
+// The near field (P2P) depends only on the gathered charges, so it runs on a
+// second stream of the tree, concurrently with the latency-bound shifts and
+// translations (it is forked after P2M, which competes with it for the
+// vector ALUs), and initialises bs; L2P and M2P then add to it.  With stage
+// timing on, every stage runs on the caller's stream in order.
 template <typename T>
 imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
 {
@@ -856,16 +918,21 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     const int32_t *leaves = t->leaves.as<int32_t>();
     double *bs = t->bs.as<double>();
     imq_status st;
-    if ((st = fmm_upward<T>(t, nrhs, s)) != IMQ_OK) return st;
+    const bool overlap = g_cur_events == nullptr;
+    if ((st = fmm_upward<T>(t, nrhs, s, overlap)) != IMQ_OK) return st;
     if ((st = fmm_translate<T>(t, nrhs, s)) != IMQ_OK) return st;
     mark(t, 5, s);
+    if (overlap) {
+        IMQ_HIP(hipStreamWaitEvent(s, t->ev_join, 0));
+    } else {
+        hipLaunchKernelGGL(k_p2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, nleaves, pd.us.as<T>(), nrhs, bs, 0);
+        IMQ_HIP(hipGetLastError());
+    }
+    mark(t, 6, s);
 #define IMQ_L2P(PP) \
-    hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs)
+    hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs, 1)
     IMQ_DISPATCH_P(h.p, IMQ_L2P)
 #undef IMQ_L2P
-    IMQ_HIP(hipGetLastError());
-    mark(t, 6, s);
-    hipLaunchKernelGGL(k_p2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, pd.us.as<T>(), nrhs, bs);
     IMQ_HIP(hipGetLastError());
     mark(t, 7, s);
     if (t->nwpairs > 0) {
@@ -886,8 +953,8 @@ template void launch_gemm<double>(hipStream_t, int, int, int, int, const GemmTas
 template void launch_gemm<float>(hipStream_t, int, int, int, int, const GemmTask *, int, const int32_t *,
                                  const int32_t *, const int32_t *, const float *, int, int, const float *,
                                  float *, int, int, int);
-template imq_status fmm_upward<double>(imq_tree_s *, int, hipStream_t);
-template imq_status fmm_upward<float>(imq_tree_s *, int, hipStream_t);
+template imq_status fmm_upward<double>(imq_tree_s *, int, hipStream_t, bool);
+template imq_status fmm_upward<float>(imq_tree_s *, int, hipStream_t, bool);
 template imq_status fmm_translate<double>(imq_tree_s *, int, hipStream_t);
 template imq_status fmm_translate<float>(imq_tree_s *, int, hipStream_t);
 template imq_status fmm_sorted<double>(imq_tree_s *, int, hipStream_t);
