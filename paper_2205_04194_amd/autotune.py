@@ -39,7 +39,7 @@ class TuneResult:
 
 def _error(tree, u, rows, exact, prec):
     b = tree.matvec(u, prec)
-    return float(torch.linalg.norm(b[rows] - exact) / torch.linalg.norm(exact))
+    return float(torch.linalg.norm(b[..., rows] - exact) / torch.linalg.norm(exact))
 
 
 def _time(tree, u, prec, reps=5):

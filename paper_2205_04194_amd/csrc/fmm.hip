@@ -444,6 +444,179 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restric
     }
 }
 
+// Many right-hand sides: the leaf expansions and their evaluation as
+// matrix-core products over a leaf,
+//   P2M  M[k][r]  = sum_j mono_k(conj w_j) u_r[j]       (K x points) x (points x rhs)
+//   L2P  b_r[j]  += sum_k s_k mono_k(w_j) L[k][r]       (points x K) x (K x rhs)
+// with s_k = -1 on imaginary parts (the real part of Lt * monomial).  One wave
+// per (leaf, block of RB right-hand sides); the monomials of up to 64 points
+// are the rows of an LDS matrix (row stride = 17 mod 32 words: conflict-free
+// row writes, nearly conflict-free reads) and the right-hand-side block is
+// staged rhs-major (stride = 2 mod 32).
+constexpr int BATCH_RHS_MIN = 8;   // from this many right-hand sides on
+
+template <int K> constexpr int mono_ld() { return ((K + 15) / 16) * 16 + (((K + 15) / 16) & 1 ? 1 : 17); }
+
+template <typename T, int P, int RB>
+__global__ __launch_bounds__(64) void k_p2m_mfma(DTree<T> t, const int32_t *__restrict__ leaves,
+                                                 const T *__restrict__ us, int nrhs, T *__restrict__ M)
+{
+    constexpr int K = (P + 1) * (P + 2) / 2, NRB = (K + 15) / 16, LDM = mono_ld<K>();
+    constexpr int NCB = RB / 16, LDU = 64 + 2;
+    using acc_t = typename Mfma<T>::acc_t;
+    __shared__ T mono[64 * LDM];
+    __shared__ T su[RB * LDU];
+    const int b = leaves[blockIdx.x];
+    const int r0 = blockIdx.y * RB;
+    const int lane = threadIdx.x, i16 = lane & 15, q = lane >> 4;
+    const int beg = t.begin[b], end = t.end[b];
+    const T inv_s = pow2i<T>(t.level[b]);
+    const int64_t N = t.N;
+    acc_t acc[NRB][NCB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[rb][cb][v] = T(0);
+    for (int c0 = beg; c0 < end; c0 += 64) {
+        const int n = min(64, end - c0);
+        __syncthreads();
+        {
+            T *row = mono + lane * LDM;
+            if (lane < n)
+                monomials<P>(t.xl[c0 + lane] * inv_s, -t.yl[c0 + lane] * inv_s,
+                             [&](int k, T v, bool) { row[k] = v; });
+            else
+#pragma unroll
+                for (int k = 0; k < K; ++k) row[k] = T(0);
+#pragma unroll
+            for (int k = K; k < NRB * 16; ++k) row[k] = T(0);
+        }
+#pragma unroll
+        for (int rr = 0; rr < RB; rr += 16) {            // 16 loads in flight per lane
+            T v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const bool ok = lane < n && r0 + rr + j < nrhs;
+                v[j] = ok ? us[(r0 + rr + j) * N + c0 + lane] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) su[(rr + j) * LDU + lane] = v[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            T bv[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) bv[cb] = su[(cb * 16 + i16) * LDU + 4 * ks + q];
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) {
+                const T av = mono[(4 * ks + q) * LDM + rb * 16 + i16];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = Mfma<T>::mac(av, bv[cb], acc[rb][cb]);
+            }
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        const int r = r0 + cb * 16 + i16;
+        if (r >= nrhs) continue;
+        T *o = M + (size_t(b) * nrhs + r) * t.KS;
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = rb * 16 + Mfma<T>::row(q, v);
+                if (k < K) o[k] = acc[rb][cb][v];
+            }
+    }
+}
+
+template <typename T, int P, int RB>
+__global__ __launch_bounds__(64) void k_l2p_mfma(DTree<T> t, const int32_t *__restrict__ leaves,
+                                                 const T *__restrict__ L, int nrhs, double *__restrict__ bs)
+{
+    constexpr int K = (P + 1) * (P + 2) / 2, NRB = (K + 15) / 16, LDM = mono_ld<K>();
+    constexpr int NCB = RB / 16, LDL = NRB * 16 + 2;
+    using acc_t = typename Mfma<T>::acc_t;
+    __shared__ T mono[64 * LDM];
+    __shared__ T sl[RB * LDL];
+    const int b = leaves[blockIdx.x];
+    const int r0 = blockIdx.y * RB;
+    const int lane = threadIdx.x, i16 = lane & 15, q = lane >> 4;
+    const int beg = t.begin[b], end = t.end[b];
+    const T inv_s = pow2i<T>(t.level[b]);
+    const int64_t N = t.N;
+    constexpr int NSL = RB * NRB * 16 / 64;            // staged values per lane
+#pragma unroll
+    for (int e0 = 0; e0 < NSL; e0 += 16) {               // 16 loads in flight per lane
+        T v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = lane + 64 * (e0 + j);
+            const int r = e / (NRB * 16), k = e - r * (NRB * 16);
+            v[j] = (e0 + j < NSL && r0 + r < nrhs && k < K) ? L[(size_t(b) * nrhs + r0 + r) * t.KS + k] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int e = lane + 64 * (e0 + j);
+            const int r = e / (NRB * 16), k = e - r * (NRB * 16);
+            if (e0 + j < NSL) sl[r * LDL + k] = v[j];
+        }
+    }
+    for (int c0 = beg; c0 < end; c0 += 64) {
+        const int n = min(64, end - c0);
+        __syncthreads();
+        {
+            T *row = mono + lane * LDM;
+            if (lane < n)
+                monomials<P>(t.xl[c0 + lane] * inv_s, t.yl[c0 + lane] * inv_s,
+                             [&](int k, T v, bool im) { row[k] = im ? -v : v; });
+            else
+#pragma unroll
+                for (int k = 0; k < K; ++k) row[k] = T(0);
+#pragma unroll
+            for (int k = K; k < NRB * 16; ++k) row[k] = T(0);
+        }
+        __syncthreads();
+        // transposed product (rhs x points) = L^T (rhs x K) . mono^T (K x points):
+        // a lane's outputs are one point of four right-hand sides, so each store
+        // instruction writes 16 consecutive points of a right-hand side
+        acc_t acc[NCB][4];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[cb][pb][v] = T(0);
+#pragma unroll
+        for (int ks = 0; ks < NRB * 4; ++ks) {
+            T bv[4];
+#pragma unroll
+            for (int pb = 0; pb < 4; ++pb) bv[pb] = mono[(pb * 16 + i16) * LDM + 4 * ks + q];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const T av = sl[(cb * 16 + i16) * LDL + 4 * ks + q];
+#pragma unroll
+                for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = Mfma<T>::mac(av, bv[pb], acc[cb][pb]);
+            }
+        }
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+            const int j = pb * 16 + i16;
+            if (j >= n) continue;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = r0 + cb * 16 + Mfma<T>::row(q, v);
+                    if (r < nrhs) bs[r * N + c0 + j] += double(acc[cb][pb][v]);
+                }
+        }
+    }
+}
+
 // Reciprocal square root for the direct sums: the hardware estimate in
 // FP32; in FP64 the estimate refined by two Newton steps
 // y <- y (3 - x y^2) / 2, each roughly doubling the number of correct bits.
@@ -466,7 +639,9 @@ constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 p
 
 // P2P: b_i += sum over U-list leaves a of sum_j u_j / sqrt(|x_i - x_j|^2 + c^2).
 // One wave per target leaf at a time; workgroup g takes leaves g, g + grid, ...
-// (a smaller grid leaves wave slots free for kernels running alongside).  Lane l takes target l % TP (TP = the leaf's
+// (a smaller grid leaves wave slots free for kernels running alongside).
+// SIDE only tells the two launch forms apart in profiles: alongside the tree
+// passes (true) or alone on the caller's stream (false).  Lane l takes target l % TP (TP = the leaf's
 // point count rounded up to a power of two, at least 4) in lane group
 // l / TP of G = 64 / TP groups.
 // Staging: the U list is read 64 entries at a time, one entry per lane (box,
@@ -479,17 +654,18 @@ constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 p
 // run of the chunk, 4 sources per step, and the G partial sums of a target are
 // combined with shuffles.  Partial sums over one chunk are kept in T, the
 // running sum in FP64.
-template <typename T>
+template <typename T, bool SIDE, int NR>
 __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restrict__ leaves, int nleaves,
                                             const T *__restrict__ us, int nrhs, double *__restrict__ bs, int add)
 {
     using V4 = typename Vec4<T>::type;
-    __shared__ V4 sx4[P2P_LDS / 4], sy4[P2P_LDS / 4], su4[P2P_LDS / 4];
+    __shared__ V4 sx4[P2P_LDS / 4], sy4[P2P_LDS / 4], su4[NR][P2P_LDS / 4];
     __shared__ int s_beg[64], s_off[65];
     __shared__ T s_ox[64], s_oy[64];
-    T *sx = reinterpret_cast<T *>(sx4), *sy = reinterpret_cast<T *>(sy4), *su = reinterpret_cast<T *>(su4);
+    T *sx = reinterpret_cast<T *>(sx4), *sy = reinterpret_cast<T *>(sy4);
     constexpr int SPL = P2P_CHUNK / 64;          // chunk slots per lane
     const int lane = threadIdx.x;
+    const int64_t N = t.N;
     for (int lf = blockIdx.x; lf < nleaves; lf += gridDim.x) {
     const int b = leaves[lf];
     const double cnd = t.cn[t.set[b]];
@@ -504,8 +680,11 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
         const bool valid = ti < ntc;
         const int i = t0 + (valid ? ti : 0);
         const T xi = t.xl[i], yi = t.yl[i];
-        for (int r = 0; r < nrhs; ++r) {
-            double acc = 0.0;
+        for (int r0 = 0; r0 < nrhs; r0 += NR) {          // NR right-hand sides per pass
+            const int nr = min(NR, nrhs - r0);
+            double acc[NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[q] = 0.0;
             for (int ub = u0; ub < u1; ub += 64) {
                 const int nb = min(64, u1 - ub);
                 int cnt = 0, beg = 0;
@@ -533,11 +712,13 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
                 __syncthreads();
                 for (int c0 = 0; c0 < total; c0 += P2P_CHUNK) {
                     const int n = min(P2P_CHUNK, total - c0);
-                    T vx[SPL], vy[SPL], vu[SPL];
+                    T vx[SPL], vy[SPL], vu[SPL][NR];
 #pragma unroll
                     for (int k = 0; k < SPL; ++k) {
                         const int slot = c0 + lane + 64 * k;
-                        vx[k] = vy[k] = vu[k] = T(0);
+                        vx[k] = vy[k] = T(0);
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) vu[k][q] = T(0);
                         if (slot < total) {
                             int lo = 0, hi = nb - 1;           // last entry with s_off <= slot
                             while (lo < hi) {
@@ -547,7 +728,9 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
                             const int j = s_beg[lo] + (slot - s_off[lo]);
                             vx[k] = t.xl[j] + s_ox[lo];
                             vy[k] = t.yl[j] + s_oy[lo];
-                            vu[k] = us[r * t.N + j];
+#pragma unroll
+                            for (int q = 0; q < NR; ++q)
+                                if (q < nr) vu[k][q] = us[(r0 + q) * N + j];
                         }
                     }
                     const int per = ((n + G - 1) / G + 3) & ~3;   // sources per group, multiple of 4
@@ -557,33 +740,66 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
                         if (e < per * G) {
                             sx[e] = vx[k];
                             sy[e] = vy[k];
-                            su[e] = vu[k];
+#pragma unroll
+                            for (int q = 0; q < NR; ++q) reinterpret_cast<T *>(su4[q])[e] = vu[k][q];
                         }
                     }
                     for (int e = P2P_CHUNK + lane; e < per * G; e += 64) {
-                        sx[e] = T(0); sy[e] = T(0); su[e] = T(0);
+                        sx[e] = T(0); sy[e] = T(0);
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) reinterpret_cast<T *>(su4[q])[e] = T(0);
                     }
                     __syncthreads();
-                    T part = T(0);
+                    T part[NR];
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) part[q] = T(0);
                     const int q0 = grp * per / 4, q1 = q0 + per / 4;
                     for (int qv = q0; qv < q1; ++qv) {
-                        const V4 X = sx4[qv], Y = sy4[qv], U = su4[qv];
+                        const V4 X = sx4[qv], Y = sy4[qv];
+                        T kv[4];
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
                             const T dx = xi - X[k], dy = yi - Y[k];
-                            part += U[k] * rsqrt_fast(fma(dx, dx, fma(dy, dy, c2)));
+                            kv[k] = rsqrt_fast(fma(dx, dx, fma(dy, dy, c2)));
+                        }
+#pragma unroll
+                        for (int q = 0; q < NR; ++q) {
+                            const V4 U = su4[q][qv];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) part[q] += U[k] * kv[k];
                         }
                     }
-                    acc += double(part);
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) acc[q] += double(part[q]);
                     __syncthreads();
                 }
             }
-            for (int off = TP; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
-            if (grp == 0 && valid) bs[r * t.N + i] = add ? bs[r * t.N + i] + acc : acc;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                double aq = acc[q];
+                for (int off = TP; off < 64; off <<= 1) aq += __shfl_xor(aq, off);
+                if (q < nr && grp == 0 && valid) {
+                    double &dst = bs[(r0 + q) * N + i];
+                    dst = add ? dst + aq : aq;
+                }
+            }
         }
     }
     __syncthreads();                             // LDS of this leaf no longer read
     }
+}
+
+// Near-field launch: NR right-hand sides share each kernel value.
+template <typename T, bool SIDE>
+void launch_p2p(hipStream_t s, unsigned grid, const DTree<T> &v, const int32_t *leaves, int nleaves,
+                const T *us, int nrhs, double *bs)
+{
+    if (nrhs == 1)
+        hipLaunchKernelGGL((k_p2p<T, SIDE, 1>), dim3(grid), dim3(64), 0, s, v, leaves, nleaves, us, nrhs, bs, 0);
+    else if (nrhs <= 4)
+        hipLaunchKernelGGL((k_p2p<T, SIDE, 4>), dim3(grid), dim3(64), 0, s, v, leaves, nleaves, us, nrhs, bs, 0);
+    else
+        hipLaunchKernelGGL((k_p2p<T, SIDE, 16>), dim3(grid), dim3(64), 0, s, v, leaves, nleaves, us, nrhs, bs, 0);
 }
 
 // M2P, one wave per (target leaf b, W-list box a) pair k: the multipole of
@@ -778,8 +994,8 @@ imq_status fork_p2p(imq_tree_s *t, int nrhs, hipStream_t s)
     IMQ_HIP(hipStreamWaitEvent(t->side[0], t->ev_fork, 0));
     const int nleaves = int(t->h.leaves.size());
     const int wg = t->kcfg.p2p_wg > 0 ? t->kcfg.p2p_wg : 2048;
-    hipLaunchKernelGGL(k_p2p<T>, dim3(unsigned(std::min(nleaves, wg))), dim3(64), 0, t->side[0], make_view<T>(t),
-                       t->leaves.as<int32_t>(), nleaves, pd.us.as<T>(), nrhs, t->bs.as<double>(), 0);
+    launch_p2p<T, true>(t->side[0], unsigned(std::min(nleaves, wg)), make_view<T>(t), t->leaves.as<int32_t>(),
+                        nleaves, pd.us.as<T>(), nrhs, t->bs.as<double>());
     IMQ_HIP(hipGetLastError());
     IMQ_HIP(hipEventRecord(t->ev_join, t->side[0]));
     return IMQ_OK;
@@ -797,9 +1013,15 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork)
     T *M = pd.M.as<T>();
     mark(t, 1, s);
     const size_t lds_p2m = (size_t(P2M_CHUNK) * ld + P2M_CHUNK) * sizeof(T);
-#define IMQ_P2M(PP)                                                                           \
-    hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, t->leaves.as<int32_t>(), \
-                       pd.us.as<T>(), nrhs, M, ld)
+    constexpr int RB = sizeof(T) == 4 ? 64 : 32;
+    const dim3 gb(unsigned(nleaves), unsigned((nrhs + RB - 1) / RB));
+#define IMQ_P2M(PP)                                                                                    \
+    if (nrhs >= BATCH_RHS_MIN)                                                                         \
+        hipLaunchKernelGGL((k_p2m_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, t->leaves.as<int32_t>(),     \
+                           pd.us.as<T>(), nrhs, M);                                                    \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, t->leaves.as<int32_t>(), \
+                           pd.us.as<T>(), nrhs, M, ld)
     IMQ_DISPATCH_P(h.p, IMQ_P2M)
 #undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
@@ -925,12 +1147,17 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     if (overlap) {
         IMQ_HIP(hipStreamWaitEvent(s, t->ev_join, 0));
     } else {
-        hipLaunchKernelGGL(k_p2p<T>, dim3(nleaves), dim3(64), 0, s, v, leaves, nleaves, pd.us.as<T>(), nrhs, bs, 0);
+        launch_p2p<T, false>(s, unsigned(nleaves), v, leaves, nleaves, pd.us.as<T>(), nrhs, bs);
         IMQ_HIP(hipGetLastError());
     }
     mark(t, 6, s);
-#define IMQ_L2P(PP) \
-    hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs, 1)
+    constexpr int RB = sizeof(T) == 4 ? 64 : 32;
+    const dim3 gb(unsigned(nleaves), unsigned((nrhs + RB - 1) / RB));
+#define IMQ_L2P(PP)                                                                                    \
+    if (nrhs >= BATCH_RHS_MIN)                                                                         \
+        hipLaunchKernelGGL((k_l2p_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs); \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs, 1)
     IMQ_DISPATCH_P(h.p, IMQ_L2P)
 #undef IMQ_L2P
     IMQ_HIP(hipGetLastError());

@@ -174,3 +174,23 @@ def test_mixed_level_orders_use_both_kernels(imq):
     err = _rel(res[0][rows], exact)
     print(f"mixed orders {orders}: rel err {err:.3e}")
     assert err < 1e-3
+
+
+@pytest.mark.parametrize("nrhs", [8, 70])
+def test_batched_right_hand_sides_match_single_products(imq, nrhs):
+    """From 8 right-hand sides on, P2M and L2P run as matrix-core products
+    over (points x coefficients x rhs) and the near field shares each kernel
+    value across the block; every column must equal its own single-RHS
+    product up to rounding and the oracle within the FP64/FP32 targets."""
+    d = W.small(3000)
+    U = W.uniform_vector(3000, W.rng(68, nrhs), nrhs=nrhs)
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=32, p=12)
+    B64 = tree.matvec(_dev(U), "fp64").cpu().numpy()
+    B32 = tree.matvec(_dev(U), "fp32").cpu().numpy()
+    cols = sorted({0, 1, nrhs // 2, nrhs - 1})
+    ref = oracle.matvec(d["xy"], d["c"], U[cols])
+    for k, r in enumerate(cols):
+        single = tree.matvec(_dev(U[r]), "fp64").cpu().numpy()
+        assert _rel(B64[r], single) < 1e-12
+        assert _rel(B64[r], ref[k]) < 1e-6
+        assert _rel(B32[r], ref[k]) < 1e-5
