@@ -3,9 +3,13 @@
 One step = one fast product b = A u (every stage of the hot path: gather,
 P2M, M2M, M2L, P2L, L2L, L2P, P2P, M2P, scatter) on the 1,000,000-point
 8-component Gaussian-mixture workload (c = 0.02, leaf <= 64), inputs
-resident in HBM.  The headline precision is the cheapest one whose relative
-2-norm error on sampled rows (exact FP64 rows computed on the GPU) is at
-most 1e-6.
+resident in HBM.  The configuration (precision, per-level orders, kernels)
+is the autotuner's fastest whose relative 2-norm error on sampled rows
+(exact FP64 rows computed on the GPU) is at most 1e-6.
+
+Also reported: the uniform-order products, a GMRES / mixed-precision solve
+comparison, batching (64 right-hand sides at N = 2e5; 256 point sets in one
+forest), the adjoint at N = 1e5, and the FP64 CPU oracle on a row sample.
 
 Prints one JSON line (see the end of main()).
 """
@@ -20,7 +24,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}          # dense MFMA
+# Vector ALU without packed FP32 (the build disables it): 256 CU x 64 lanes x
+# 2 flop (FMA) x 2.4 GHz, the same for FP32 and FP64.
+PEAK_TFLOPS_VALU = {"fp64": 78.6, "fp32": 78.6}
+# HBM bytes of one FP32 near-field launch on mixture1m, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a plain 256 MiB copy
+# (profiles/p2p_mixture1m_fp32.md); to be re-measured whenever k_p2p changes.
+P2P_TRAFFIC_BYTES = (59398 * 2.0 + 8628 * 1.0) * 1024
 HBM_GBS = 8000.0
 
 
@@ -29,7 +40,7 @@ def log(*a):
 
 
 def m2l_flops(info, nrhs=1):
-    """Algorithmic flops of one M2L launch: 2 K_l^2 per translation and RHS."""
+    """Algorithmic flops of the M2L stage: 2 K_l^2 per translation and RHS."""
     return sum(2.0 * k * k * n for k, n in zip(info["level_K"], info["level_m2l_pairs"])) * nrhs
 
 
@@ -107,6 +118,86 @@ def solve_compare(tree, f, iters):
     return res
 
 
+def _tuned_run(tree, U, steps, nrows=300):
+    """Autotune, then time `steps` products; error over sampled rows of every column."""
+    import torch
+    from paper_2205_04194_amd import autotune
+    t0 = time.perf_counter()
+    res = autotune.tune(tree, U, target=1e-6, nrows=nrows, seed=2)
+    t_tune = time.perf_counter() - t0
+    n = U.shape[-1]
+    rows = torch.tensor(np.sort(np.random.default_rng(9).choice(n, min(nrows, n), replace=False)),
+                        device=U.device)
+    exact = tree.rows_exact(U, rows)
+    b = tree.matvec(U, res.precision)
+    err = float(torch.linalg.norm(b[..., rows] - exact) / torch.linalg.norm(exact))
+    ms, stages = time_products(tree, U, res.precision, steps, 2)
+    return {"ms_per_step": ms, "rel_err_sampled_rows": err, "precision": res.precision,
+            "level_orders": res.level_orders, "m2l_mode": res.m2l_mode, "tune_s": t_tune,
+            "stage_ms": stages}
+
+
+def batched_extras(dev, steps):
+    """Batching: 64 right-hand sides on one tree, and 256 point sets in one forest."""
+    import torch
+    import workloads as W
+    import paper_2205_04194_amd as imq
+    out = {}
+    d = W.batched_rhs()
+    U = torch.tensor(d["u"], device=dev)
+    t0 = time.perf_counter()
+    tree = imq.build_tree(torch.tensor(d["xy"], device=dev), d["c"], leaf=d["leaf"], p=d["p"])
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    r = _tuned_run(tree, U, steps)
+    r.update({"workload": "batched_rhs", "N": len(d["xy"]), "nrhs": int(U.shape[0]), "c": d["c"],
+              "tree_build_s": tb, "rhs_columns_per_s": U.shape[0] * 1e3 / r["ms_per_step"]})
+    tree.close()
+    out["rhs64"] = r
+    log(f"batched 64 RHS: {r['ms_per_step']:.3f} ms, {r['rhs_columns_per_s']:.0f} columns/s, err {r['rel_err_sampled_rows']:.2e}")
+    d = W.batched_sets()
+    u = torch.tensor(d["u"], device=dev)
+    t0 = time.perf_counter()
+    tree = imq.build_tree(torch.tensor(d["xy"], device=dev), list(d["c"]), leaf=d["leaf"], p=d["p"],
+                          set_offsets=list(d["offsets"]))
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    r = _tuned_run(tree, u, steps)
+    r.update({"workload": "batched_sets", "nsets": len(d["c"]), "N_total": len(d["xy"]),
+              "tree_build_s": tb, "products_per_s": 1e3 / r["ms_per_step"]})
+    tree.close()
+    out["sets256"] = r
+    log(f"batched 256 sets: {r['ms_per_step']:.3f} ms, err {r['rel_err_sampled_rows']:.2e}")
+    return out
+
+
+def adjoint_extra(dev, steps):
+    """Gradients of ||A(c, X) v - f||^2 (dv, dc, dX) at N = 1e5, FP64 expansions, p = 16."""
+    import torch
+    import workloads as W
+    import paper_2205_04194_amd as imq
+    d = W.grad(100_000)
+    v = torch.tensor(d["v"], device=dev)
+    f = torch.tensor(d["f"], device=dev)
+    tree = imq.build_tree(torch.tensor(d["xy"], device=dev), d["c"], leaf=64, p=16, direct_max=1 << 30)
+    g = 2.0 * (tree.matvec(v, "fp64") - f)
+    out = {"workload": "grad100k", "N": len(d["xy"]), "p": 16}
+    for prec in ("fp64", "fp32"):
+        tree.backward(v, g, prec=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            tree.backward(v, g, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{prec}_ms"] = e0.elapsed_time(e1) / steps
+    tree.close()
+    log(f"adjoint N=1e5: fp64 {out['fp64_ms']:.3f} ms, fp32 {out['fp32_ms']:.3f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +210,8 @@ def main():
     ap.add_argument("--rows", type=int, default=2000, help="sampled rows for the error check")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batching (64 RHS, 256 sets) and adjoint measurements")
     ap.add_argument("--solve-iters", type=int, default=150,
                     help="GMRES products per solve (0: skip the solve comparison)")
     ap.add_argument("--no-tune", action="store_true",
@@ -206,17 +299,19 @@ def main():
         head = min(ok, key=lambda p: results[p]["ms"]) if ok else "fp64"
         r = results[head]
     st = r["stages"]
-    dom = max(st, key=st.get)
-    flops = {"m2l": m2l_flops(info), "p2p": p2p_flops(info)}
-    if dom in flops:
-        achieved = flops[dom] / (st[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma" if dom == "m2l" else "alu", "achieved": achieved,
-                "peak": PEAK_TFLOPS[head],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[head], "traffic": None,
-                "algorithmic_flops_per_launch": flops[dom], "launch_ms": st[dom]}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "launch_ms": st[dom]}
+    # Roofline of the largest single kernel of the product: the near field
+    # (one launch; in the stage pass it runs alone on the timed stream).
+    peak = PEAK_TFLOPS_VALU[head]
+    p2p_ms = st["p2p"]
+    achieved = p2p_flops(info) / (p2p_ms * 1e-3) / 1e12
+    roof = {"kernel": "k_p2p (near field, P2P)", "bound": "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": P2P_TRAFFIC_BYTES if (head == "fp32" and args.workload == "mixture1m") else None,
+            "algorithmic_flops_per_launch": p2p_flops(info), "pairs": info["p2p_pairs"],
+            "launch_ms": p2p_ms,
+            "m2l_stage": {"flops": m2l_flops(info), "ms": st["m2l"],
+                          "tflops": m2l_flops(info) / (st["m2l"] * 1e-3) / 1e12,
+                          "mfma_peak": PEAK_TFLOPS[head]}}
 
     out = {
         "metric": "IMQ matvecs/sec at N=1M (rel err 1e-6)",
@@ -244,6 +339,10 @@ def main():
     }
     if args.solve_iters > 0:
         out["solve"] = solve_compare(tree, torch.tensor(d["f"], device=dev), args.solve_iters)
+    tree.close()
+    if not args.no_extras:
+        out["batched"] = batched_extras(dev, args.steps)
+        out["adjoint"] = adjoint_extra(dev, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d["xy"], d["c"], d["u"], args.cpu_budget)
     print(json.dumps(out), flush=True)

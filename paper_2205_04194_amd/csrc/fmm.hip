@@ -638,8 +638,9 @@ constexpr int P2P_CHUNK = 256;                 // sources staged per round
 constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 per lane group
 
 // P2P: b_i += sum over U-list leaves a of sum_j u_j / sqrt(|x_i - x_j|^2 + c^2).
-// One wave per target leaf at a time; workgroup g takes leaves g, g + grid, ...
-// (a smaller grid leaves wave slots free for kernels running alongside).
+// One wave per target leaf at a time; with a grid smaller than the leaf count
+// a workgroup walks several leaves (leaving wave slots free for kernels
+// running alongside).
 // SIDE only tells the two launch forms apart in profiles: alongside the tree
 // passes (true) or alone on the caller's stream (false).  Lane l takes target l % TP (TP = the leaf's
 // point count rounded up to a power of two, at least 4) in lane group
@@ -666,6 +667,10 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, const int32_t *__restric
     constexpr int SPL = P2P_CHUNK / 64;          // chunk slots per lane
     const int lane = threadIdx.x;
     const int64_t N = t.N;
+    // Leaves are dealt round robin (as the hardware deals workgroups to the
+    // XCDs): the kernel is ALU-bound, and giving each XCD a contiguous eighth of
+    // the Morton order for L2 locality unbalances clustered inputs (measured
+    // slower on the mixture workload).
     for (int lf = blockIdx.x; lf < nleaves; lf += gridDim.x) {
     const int b = leaves[lf];
     const double cnd = t.cn[t.set[b]];
