@@ -203,7 +203,7 @@ static void free_tree(imq_tree_s *t)
             (void)hipStreamSynchronize(x);
             (void)hipStreamDestroy(x);
         }
-    for (hipEvent_t e : {t->ev_fork, t->ev_join, t->ev_tfork})
+    for (hipEvent_t e : {t->ev_fork, t->ev_join, t->ev_tfork, t->ev_start, t->ev_prep})
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : t->ev_tjoin)
         if (e) (void)hipEventDestroy(e);

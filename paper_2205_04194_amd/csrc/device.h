@@ -119,6 +119,7 @@ struct imq_tree_s {
     hipStream_t side[NSIDE] = {};
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;          // near field
     hipEvent_t ev_tfork = nullptr, ev_tjoin[NSIDE] = {};      // translations
+    hipEvent_t ev_start = nullptr, ev_prep = nullptr;         // gathered weights; L cleared + X pairs
     imq_status ensure_side();
     // solver workspace
     imq::DevBuf sol;

@@ -980,12 +980,16 @@ imq_status imq_tree_s::ensure_side()
 {
     if (side[0]) return IMQ_OK;
     for (hipStream_t &x : side) IMQ_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    for (hipEvent_t *e : {&ev_fork, &ev_join, &ev_tfork}) IMQ_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    for (hipEvent_t *e : {&ev_fork, &ev_join, &ev_tfork, &ev_start, &ev_prep})
+        IMQ_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     for (hipEvent_t &e : ev_tjoin) IMQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return IMQ_OK;
 }
 
 namespace imq {
+
+template <typename T>
+imq_status prep_locals(imq_tree_s *t, int nrhs, hipStream_t s);
 
 // Launch the near field on the tree's second stream once everything queued
 // on s so far (the gathered charges) is done; ev_join marks its completion.
@@ -1017,6 +1021,11 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork)
     const int ld = K | 1;                                      // odd LDS row stride
     T *M = pd.M.as<T>();
     mark(t, 1, s);
+    if (fork) {
+        imq_status st = t->ensure_side();
+        if (st != IMQ_OK) return st;
+        IMQ_HIP(hipEventRecord(t->ev_start, s));          // gathered weights ready
+    }
     const size_t lds_p2m = (size_t(P2M_CHUNK) * ld + P2M_CHUNK) * sizeof(T);
     constexpr int RB = sizeof(T) == 4 ? 64 : 32;
     const dim3 gb(unsigned(nleaves), unsigned((nrhs + RB - 1) / RB));
@@ -1031,9 +1040,16 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork)
 #undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
     mark(t, 2, s);
-    if (fork) {      // the near field shares the GPU with the latency-bound shifts and translations
-        imq_status st = fork_p2p<T>(t, nrhs, s);
+    if (fork) {
+        // Queued after P2M so that P2M's workgroups are dispatched first: clear L
+        // and form the X pairs on side[1] (they need only the gathered weights),
+        // then the near field, which shares the GPU with the latency-bound
+        // shifts and translations.
+        IMQ_HIP(hipStreamWaitEvent(t->side[1], t->ev_start, 0));
+        imq_status st = prep_locals<T>(t, nrhs, t->side[1]);
         if (st != IMQ_OK) return st;
+        IMQ_HIP(hipEventRecord(t->ev_prep, t->side[1]));
+        if ((st = fork_p2p<T>(t, nrhs, s)) != IMQ_OK) return st;
     }
     for (int l = h.nlev - 2; l >= h.need_m; --l) {
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
@@ -1046,22 +1062,50 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork)
 }
 
 // Translations and downward pass into L (stages M2L, P2L, L2L).
+// Clear L and form the X-list pair expansions (they need only the gathered
+// weights); on side[1] when the product overlaps its stages.
 template <typename T>
-imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
+imq_status prep_locals(imq_tree_s *t, int nrhs, hipStream_t s)
+{
+    const HostTree &h = t->h;
+    PrecData &pd = prec_data<T>(t);
+    const int K = h.K, KS = coef_stride(K), ld = K | 1;
+    const size_t nL = size_t(h.level.size()) * nrhs * KS;
+    hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, pd.L.as<T>(), T(0));
+    if (t->nxpairs > 0)
+        hipLaunchKernelGGL(k_p2l_pairs<T>, dim3(t->nxpairs), dim3(64), (size_t(64) * ld + 64) * sizeof(T), s,
+                           make_view<T>(t), t->x_tgt.as<int32_t>(), pd.us.as<T>(), nrhs, pd.wx.as<T>(),
+                           pd.Lx.as<T>(), ld, t->nxpairs);
+    IMQ_HIP(hipGetLastError());
+    return IMQ_OK;
+}
+
+// Translations and downward pass into L (stages M2L, P2L, L2L).  overlap: L
+// was cleared and the X pairs formed on side[1] (ev_prep); the M2L level
+// groups run on the caller's stream and side[1..], the W-list pair
+// evaluations (M2P, which need only M) on side[2] ahead of its M2L group.
+template <typename T>
+imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
 {
     const HostTree &h = t->h;
     PrecData &pd = prec_data<T>(t);
     DTree<T> v = make_view<T>(t);
-    const int nbox = int(h.level.size());
     const int K = h.K, KP = t->KP, KS = coef_stride(K);
-    const int ld = K | 1;
-    const size_t lds = (size_t(64) * ld + 64) * sizeof(T);
     T *M = pd.M.as<T>(), *L = pd.L.as<T>();
     const imq_kernel_config &kc = t->kcfg;
     mark(t, 3, s);
-    {
-        const size_t nL = size_t(nbox) * nrhs * KS;
-        hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, L, T(0));
+    imq_status st;
+    if (!overlap) {
+        if ((st = prep_locals<T>(t, nrhs, s)) != IMQ_OK) return st;
+    } else {
+        if ((st = t->ensure_side()) != IMQ_OK) return st;
+        IMQ_HIP(hipEventRecord(t->ev_tfork, s));                  // multipoles complete
+        for (int i = 1; i < imq_tree_s::NSIDE; ++i) IMQ_HIP(hipStreamWaitEvent(t->side[i], t->ev_tfork, 0));
+        if (t->nwpairs > 0)
+            hipLaunchKernelGGL(k_m2p_pairs<T>, dim3(t->nwpairs), dim3(64), 0, t->side[2], v, t->w_tgt.as<int32_t>(),
+                               t->w_scr.as<int32_t>(), M, pd.wx.as<T>(), nrhs, t->Pw.as<double>(), t->nwscr);
+        IMQ_HIP(hipStreamWaitEvent(s, t->ev_prep, 0));              // L cleared
+        IMQ_HIP(hipStreamWaitEvent(t->side[2], t->ev_prep, 0));
     }
     {
         // Per level: the register-streaming kernel (mode 0, up to 80 coefficients
@@ -1073,20 +1117,11 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
             const int nrb = (h.Klev[l] + 15) / 16;
             return (kc.m2l_mode == 0 && nrb <= smax) ? nrb : 0;
         };
-        // level groups are independent: with the product untimed they run on
-        // the caller's stream and side[1..] in turn
-        const bool conc = g_cur_events == nullptr;
         int ngroup = 0;
-        if (conc) {
-            imq_status st = t->ensure_side();
-            if (st != IMQ_OK) return st;
-            IMQ_HIP(hipEventRecord(t->ev_tfork, s));
-            for (int i = 1; i < imq_tree_s::NSIDE; ++i) IMQ_HIP(hipStreamWaitEvent(t->side[i], t->ev_tfork, 0));
-        }
         for (int l = 0; l < h.nlev;) {
             const int t0 = g.level_task_begin[l];
             if (g.level_task_begin[l + 1] == t0) { ++l; continue; }
-            const int si = conc ? ngroup++ % imq_tree_s::NSIDE : 0;     // 0: the caller's stream
+            const int si = overlap ? ngroup++ % imq_tree_s::NSIDE : 0;     // 0: the caller's stream
             hipStream_t gs = si == 0 ? s : t->side[si];
             const int k = kind(l);
             int l2 = l + 1, kmax = h.Klev[l];
@@ -1105,7 +1140,7 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
                                g.src.as<int32_t>(), pd.m2l.as<T>(), KP, KS, M, L, 0, 0, 0);
             l = l2;
         }
-        if (conc)
+        if (overlap)
             for (int i = 1; i < imq_tree_s::NSIDE; ++i) {
                 IMQ_HIP(hipEventRecord(t->ev_tjoin[i], t->side[i]));
                 IMQ_HIP(hipStreamWaitEvent(s, t->ev_tjoin[i], 0));
@@ -1113,13 +1148,9 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s)
     }
     IMQ_HIP(hipGetLastError());
     mark(t, 4, s);
-    if (t->nxpairs > 0) {
-        T *Lx = pd.Lx.as<T>();
-        hipLaunchKernelGGL(k_p2l_pairs<T>, dim3(t->nxpairs), dim3(64), lds, s, v, t->x_tgt.as<int32_t>(),
-                           pd.us.as<T>(), nrhs, pd.wx.as<T>(), Lx, ld, t->nxpairs);
+    if (t->nxpairs > 0)
         hipLaunchKernelGGL(k_p2l_reduce<T>, dim3(t->nxboxes), dim3(64), 0, s, v, t->x_boxes.as<int32_t>(),
-                           nrhs, Lx, t->nxpairs, L);
-    }
+                           nrhs, pd.Lx.as<T>(), t->nxpairs, L);
     for (int l = std::max(h.need_l, 0); l + 1 < h.nlev; ++l) {      // parents at level l
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
         launch_shift<T>(s, false, kc.shift_cols, np, nrhs, t->sh_par.as<int32_t>() + p0,
@@ -1147,7 +1178,7 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     imq_status st;
     const bool overlap = g_cur_events == nullptr;
     if ((st = fmm_upward<T>(t, nrhs, s, overlap)) != IMQ_OK) return st;
-    if ((st = fmm_translate<T>(t, nrhs, s)) != IMQ_OK) return st;
+    if ((st = fmm_translate<T>(t, nrhs, s, overlap)) != IMQ_OK) return st;
     mark(t, 5, s);
     if (overlap) {
         IMQ_HIP(hipStreamWaitEvent(s, t->ev_join, 0));
@@ -1169,8 +1200,9 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     mark(t, 7, s);
     if (t->nwpairs > 0) {
         double *Pw = t->Pw.as<double>();
-        hipLaunchKernelGGL(k_m2p_pairs<T>, dim3(t->nwpairs), dim3(64), 0, s, v, t->w_tgt.as<int32_t>(),
-                           t->w_scr.as<int32_t>(), pd.M.as<T>(), pd.wx.as<T>(), nrhs, Pw, t->nwscr);
+        if (!overlap)            // else already run on side[2], joined after the translations
+            hipLaunchKernelGGL(k_m2p_pairs<T>, dim3(t->nwpairs), dim3(64), 0, s, v, t->w_tgt.as<int32_t>(),
+                               t->w_scr.as<int32_t>(), pd.M.as<T>(), pd.wx.as<T>(), nrhs, Pw, t->nwscr);
         hipLaunchKernelGGL(k_m2p_reduce<T>, dim3(t->nwleaves), dim3(64), 0, s, v, t->w_leaves.as<int32_t>(),
                            t->w_scr.as<int32_t>(), nrhs, Pw, t->nwscr, bs);
     }
@@ -1187,8 +1219,8 @@ template void launch_gemm<float>(hipStream_t, int, int, int, int, const GemmTask
                                  float *, int, int, int);
 template imq_status fmm_upward<double>(imq_tree_s *, int, hipStream_t, bool);
 template imq_status fmm_upward<float>(imq_tree_s *, int, hipStream_t, bool);
-template imq_status fmm_translate<double>(imq_tree_s *, int, hipStream_t);
-template imq_status fmm_translate<float>(imq_tree_s *, int, hipStream_t);
+template imq_status fmm_translate<double>(imq_tree_s *, int, hipStream_t, bool);
+template imq_status fmm_translate<float>(imq_tree_s *, int, hipStream_t, bool);
 template imq_status fmm_sorted<double>(imq_tree_s *, int, hipStream_t);
 template imq_status fmm_sorted<float>(imq_tree_s *, int, hipStream_t);
 template imq_status ensure_workspace<double>(imq_tree_s *, int);
