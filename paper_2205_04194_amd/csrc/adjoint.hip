@@ -22,7 +22,7 @@
 
 namespace imq {
 
-template <typename T> imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork);
+template <typename T> imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const UserVec *io);
 template <typename T> imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap);
 
 namespace {
@@ -237,7 +237,7 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
 
     hipLaunchKernelGGL((k_gather2<Tio, T>), grid1(N), dim3(256), 0, s, N, t->perm.as<int32_t>(), v, g, us);
     IMQ_HIP(hipGetLastError());
-    if ((st = fmm_upward<T>(t, 2, s, false)) != IMQ_OK) return st;
+    if ((st = fmm_upward<T>(t, 2, s, false, nullptr)) != IMQ_OK) return st;
     if ((st = fmm_translate<T>(t, 2, s, false)) != IMQ_OK) return st;
     // odd (vertical-derivative) coefficients: same batches, other tables
     T *Lo = pd.Lodd.as<T>();

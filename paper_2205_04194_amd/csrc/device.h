@@ -85,6 +85,31 @@ void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const Ge
                  const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *tables, int KP, int KS,
                  const T *in, T *out, int acc, int kin_ovr, int kout_ovr);
 
+// Caller-order vectors for the kernels that read the weights or write the
+// result directly (the overlapped product skips the separate gather into
+// Morton order on its critical path, and the scatter): element (r, i) of the
+// sorted order is v[r * ld + perm[i]], FP32 or FP64.
+struct UserVec {
+    const void *in = nullptr;    // weights u (null: read the gathered copy)
+    void *out = nullptr;         // result b (null: leave it in bs)
+    int64_t ldu = 0, ldb = 0;
+    int f32 = 0;
+    const int32_t *perm = nullptr;
+    const double *scale = nullptr;   // 1/side per sorted point
+    __device__ __forceinline__ double get(int r, int i) const
+    {
+        const int64_t j = r * ldu + perm[i];
+        return f32 ? double(static_cast<const float *>(in)[j]) : static_cast<const double *>(in)[j];
+    }
+    __device__ __forceinline__ void put(int r, int i, double v) const
+    {
+        const int64_t j = r * ldb + perm[i];
+        v *= scale[i];
+        if (f32) static_cast<float *>(out)[j] = float(v);
+        else static_cast<double *>(out)[j] = v;
+    }
+};
+
 struct DevGemm {               // device copy of a GemmList
     DevBuf tasks, tbox, tab, src;
     std::vector<int32_t> level_task_begin;
@@ -143,7 +168,7 @@ template <typename T> PrecData &prec_data(imq_tree_s *t);
 // FP64 or FP32 fast product on sorted, already-gathered vectors:
 // us (T, nrhs x N) -> bs (FP64, nrhs x N) in normalised units.
 template <typename T>
-imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s);
+imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io = nullptr);
 
 template <typename T>
 imq_status ensure_workspace(imq_tree_s *t, int nrhs);

@@ -62,6 +62,7 @@ __device__ __forceinline__ void irregular_even(int P, T vx, T vy, T vz, F &&f)
 
 // ------------------------------------------------------------------ kernels
 
+
 template <typename Tin, typename T>
 __global__ void k_gather(int64_t N, const int32_t *__restrict__ perm, const Tin *__restrict__ u,
                          int64_t ldu, T *__restrict__ us)
@@ -142,7 +143,8 @@ constexpr int P2M_CHUNK = 32;      // points staged per round (LDS per wave halv
 
 template <typename T, int P>
 __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ us, int nrhs, T *__restrict__ M, int ld)
+                                            const T *__restrict__ us, int nrhs, T *__restrict__ M, int ld,
+                                            UserVec io)
 {
     extern __shared__ unsigned char smem_raw[];
     T *mono = reinterpret_cast<T *>(smem_raw);   // [P2M_CHUNK][ld]
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restric
         }
         for (int r = 0; r < nrhs; ++r) {
             __syncthreads();
-            if (lane < n) su[lane] = us[r * t.N + c0 + lane];
+            if (lane < n) su[lane] = io.in ? T(io.get(r, c0 + lane)) : us[r * t.N + c0 + lane];
             __syncthreads();
             for (int k = lane; k < K; k += 64) {
                 const T v = lds_dot(mono, ld, k, su, n);
@@ -424,7 +426,8 @@ __global__ void k_fill(size_t n, T *__restrict__ p, T v)
 // constant so the evaluation loop is fully unrolled.
 template <typename T, int P>
 __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ L, int nrhs, double *__restrict__ bs, int add)
+                                            const T *__restrict__ L, int nrhs, double *__restrict__ bs, int add,
+                                            UserVec io)
 {
     constexpr int K = (P + 1) * (P + 2) / 2;
     __shared__ T Ls[K];
@@ -439,7 +442,9 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restric
             // real part of Lt * monomial: Re*Re - Im*Im
             monomials<P>(t.xl[i] * inv_s, t.yl[i] * inv_s,
                          [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
-            bs[r * t.N + i] = add ? bs[r * t.N + i] + double(acc) : double(acc);
+            const double val = add ? bs[r * t.N + i] + double(acc) : double(acc);
+            if (io.out) io.put(r, i, val);
+            else bs[r * t.N + i] = val;
         }
     }
 }
@@ -1011,7 +1016,7 @@ imq_status fork_p2p(imq_tree_s *t, int nrhs, hipStream_t s)
 }
 
 template <typename T>
-imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork)
+imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const UserVec *io)
 {
     const HostTree &h = t->h;
     PrecData &pd = prec_data<T>(t);
@@ -1021,10 +1026,24 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork)
     const int ld = K | 1;                                      // odd LDS row stride
     T *M = pd.M.as<T>();
     mark(t, 1, s);
+    const UserVec uv = io ? *io : UserVec();
     if (fork) {
         imq_status st = t->ensure_side();
         if (st != IMQ_OK) return st;
-        IMQ_HIP(hipEventRecord(t->ev_start, s));          // gathered weights ready
+        IMQ_HIP(hipEventRecord(t->ev_start, s));
+        if (uv.in) {       // P2M reads the caller's weights; the Morton-order copy is for P2P and P2L
+            IMQ_HIP(hipStreamWaitEvent(t->side[0], t->ev_start, 0));
+            const int64_t N = h.N;
+            const dim3 gg(unsigned((N + 255) / 256), nrhs);
+            if (uv.f32)
+                hipLaunchKernelGGL((k_gather<float, T>), gg, dim3(256), 0, t->side[0], N, t->perm.as<int32_t>(),
+                                   static_cast<const float *>(uv.in), uv.ldu, pd.us.template as<T>());
+            else
+                hipLaunchKernelGGL((k_gather<double, T>), gg, dim3(256), 0, t->side[0], N, t->perm.as<int32_t>(),
+                                   static_cast<const double *>(uv.in), uv.ldu, pd.us.template as<T>());
+            IMQ_HIP(hipGetLastError());
+            IMQ_HIP(hipEventRecord(t->ev_start, t->side[0]));   // now: the copy is ready
+        }
     }
     const size_t lds_p2m = (size_t(P2M_CHUNK) * ld + P2M_CHUNK) * sizeof(T);
     constexpr int RB = sizeof(T) == 4 ? 64 : 32;
@@ -1035,7 +1054,7 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork)
                            pd.us.as<T>(), nrhs, M);                                                    \
     else                                                                                               \
         hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, t->leaves.as<int32_t>(), \
-                           pd.us.as<T>(), nrhs, M, ld)
+                           pd.us.as<T>(), nrhs, M, ld, uv)
     IMQ_DISPATCH_P(h.p, IMQ_P2M)
 #undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
@@ -1167,7 +1186,7 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
 // vector ALUs), and initialises bs; L2P and M2P then add to it.  With stage
 // timing on, every stage runs on the caller's stream in order.
 template <typename T>
-imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
+imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
 {
     const HostTree &h = t->h;
     PrecData &pd = prec_data<T>(t);
@@ -1177,7 +1196,8 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     double *bs = t->bs.as<double>();
     imq_status st;
     const bool overlap = g_cur_events == nullptr;
-    if ((st = fmm_upward<T>(t, nrhs, s, overlap)) != IMQ_OK) return st;
+    if (io && !overlap) { set_error("internal: caller-order I/O needs the overlapped product"); return IMQ_EINVAL; }
+    if ((st = fmm_upward<T>(t, nrhs, s, overlap, io)) != IMQ_OK) return st;
     if ((st = fmm_translate<T>(t, nrhs, s, overlap)) != IMQ_OK) return st;
     mark(t, 5, s);
     if (overlap) {
@@ -1187,26 +1207,32 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
         IMQ_HIP(hipGetLastError());
     }
     mark(t, 6, s);
+    const UserVec uv = io ? *io : UserVec();
+    const auto m2p = [&]() -> imq_status {
+        if (t->nwpairs > 0) {
+            double *Pw = t->Pw.as<double>();
+            if (!overlap)        // else already run on side[2], joined after the translations
+                hipLaunchKernelGGL(k_m2p_pairs<T>, dim3(t->nwpairs), dim3(64), 0, s, v, t->w_tgt.as<int32_t>(),
+                                   t->w_scr.as<int32_t>(), pd.M.as<T>(), pd.wx.as<T>(), nrhs, Pw, t->nwscr);
+            hipLaunchKernelGGL(k_m2p_reduce<T>, dim3(t->nwleaves), dim3(64), 0, s, v, t->w_leaves.as<int32_t>(),
+                               t->w_scr.as<int32_t>(), nrhs, Pw, t->nwscr, bs);
+        }
+        IMQ_HIP(hipGetLastError());
+        return IMQ_OK;
+    };
+    if (uv.out && (st = m2p()) != IMQ_OK) return st;      // L2P then writes the caller's vector last
     constexpr int RB = sizeof(T) == 4 ? 64 : 32;
     const dim3 gb(unsigned(nleaves), unsigned((nrhs + RB - 1) / RB));
 #define IMQ_L2P(PP)                                                                                    \
     if (nrhs >= BATCH_RHS_MIN)                                                                         \
         hipLaunchKernelGGL((k_l2p_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs); \
     else                                                                                               \
-        hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs, 1)
+        hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs, 1, uv)
     IMQ_DISPATCH_P(h.p, IMQ_L2P)
 #undef IMQ_L2P
     IMQ_HIP(hipGetLastError());
     mark(t, 7, s);
-    if (t->nwpairs > 0) {
-        double *Pw = t->Pw.as<double>();
-        if (!overlap)            // else already run on side[2], joined after the translations
-            hipLaunchKernelGGL(k_m2p_pairs<T>, dim3(t->nwpairs), dim3(64), 0, s, v, t->w_tgt.as<int32_t>(),
-                               t->w_scr.as<int32_t>(), pd.M.as<T>(), pd.wx.as<T>(), nrhs, Pw, t->nwscr);
-        hipLaunchKernelGGL(k_m2p_reduce<T>, dim3(t->nwleaves), dim3(64), 0, s, v, t->w_leaves.as<int32_t>(),
-                           t->w_scr.as<int32_t>(), nrhs, Pw, t->nwscr, bs);
-    }
-    IMQ_HIP(hipGetLastError());
+    if (!uv.out && (st = m2p()) != IMQ_OK) return st;
     mark(t, 8, s);
     return IMQ_OK;
 }
@@ -1217,12 +1243,12 @@ template void launch_gemm<double>(hipStream_t, int, int, int, int, const GemmTas
 template void launch_gemm<float>(hipStream_t, int, int, int, int, const GemmTask *, int, const int32_t *,
                                  const int32_t *, const int32_t *, const float *, int, int, const float *,
                                  float *, int, int, int);
-template imq_status fmm_upward<double>(imq_tree_s *, int, hipStream_t, bool);
-template imq_status fmm_upward<float>(imq_tree_s *, int, hipStream_t, bool);
+template imq_status fmm_upward<double>(imq_tree_s *, int, hipStream_t, bool, const UserVec *);
+template imq_status fmm_upward<float>(imq_tree_s *, int, hipStream_t, bool, const UserVec *);
 template imq_status fmm_translate<double>(imq_tree_s *, int, hipStream_t, bool);
 template imq_status fmm_translate<float>(imq_tree_s *, int, hipStream_t, bool);
-template imq_status fmm_sorted<double>(imq_tree_s *, int, hipStream_t);
-template imq_status fmm_sorted<float>(imq_tree_s *, int, hipStream_t);
+template imq_status fmm_sorted<double>(imq_tree_s *, int, hipStream_t, const UserVec *);
+template imq_status fmm_sorted<float>(imq_tree_s *, int, hipStream_t, const UserVec *);
 template imq_status ensure_workspace<double>(imq_tree_s *, int);
 template imq_status ensure_workspace<float>(imq_tree_s *, int);
 template DTree<double> make_view<double>(const imq_tree_s *);
@@ -1256,9 +1282,21 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
     if (st != IMQ_OK) return st;
     g_cur_events = t->stage_events();
     mark(t, 0, s);
-    if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) == IMQ_OK &&
-        (st = fmm_sorted<T>(t, nrhs, s)) == IMQ_OK &&
-        (st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) == IMQ_OK)
+    if (!g_cur_events && nrhs < BATCH_RHS_MIN) {
+        // overlapped product: L2P, the last stage, writes b in caller order (no
+        // separate scatter).  Reading u through the permutation inside P2M
+        // instead of gathering it first was measured slower: it puts a second
+        // dependent load in P2M, which is on the critical path.
+        UserVec io;
+        io.out = b;
+        io.ldb = ldb;
+        io.f32 = sizeof(Tio) == 4;
+        io.perm = t->perm.as<int32_t>();
+        io.scale = t->pt_scale.as<double>();
+        if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) == IMQ_OK) st = fmm_sorted<T>(t, nrhs, s, &io);
+    } else if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) == IMQ_OK &&
+               (st = fmm_sorted<T>(t, nrhs, s, nullptr)) == IMQ_OK &&
+               (st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) == IMQ_OK)
         mark(t, 9, s);
     g_cur_events = nullptr;
     return st;

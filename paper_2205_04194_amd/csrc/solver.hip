@@ -19,7 +19,7 @@
 namespace imq {
 
 template <typename T>
-imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s);
+imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io);
 template <typename T>
 imq_status ensure_workspace(imq_tree_s *t, int nrhs);
 
@@ -156,7 +156,7 @@ struct Solver {
             hipLaunchKernelGGL(k_to_type_f, grid1(N), dim3(256), 0, s, N, xin, us);
         else
             hipLaunchKernelGGL(k_to_type_d, grid1(N), dim3(256), 0, s, N, xin, us);
-        if ((st = fmm_sorted<T>(t, 1, s)) != IMQ_OK) return st;
+        if ((st = fmm_sorted<T>(t, 1, s, nullptr)) != IMQ_OK) return st;
         hipLaunchKernelGGL(k_scale, grid1(N), dim3(256), 0, s, N, t->bs.as<double>(),
                            t->pt_scale.as<double>(), yout);
         IMQ_HIP(hipGetLastError());
