@@ -264,29 +264,41 @@ def main():
     if args.orders:
         prec = precs[0]
         orders = [int(x) for x in args.orders.split(",")]
+        if max(orders) < args.p:            # as after tuning: the tree at the highest order
+            tree.close()
+            tree = imq.build_tree(xy, d["c"], leaf=args.leaf, p=max(orders))
         tree.set_level_orders(orders)
         tree.set_kernel_config(m2l_kc=args.m2l_kc, m2l_split=args.m2l_split, m2l_mode=args.m2l_mode,
                               p2p_wg=args.p2p_wg)
         b = tree.matvec(u, prec)
         err = float(torch.linalg.norm(b[rows] - exact) / torch.linalg.norm(exact))
         ms, stages = time_products(tree, u, prec, args.steps, args.warmup)
+        info = tree.info()
         tuned = {"ms": ms, "err": err, "stages": stages, "prec": prec, "level_orders": orders,
                  "m2l_kc": args.m2l_kc, "m2l_split": args.m2l_split, "m2l_mode": args.m2l_mode,
-                 "tune_s": 0.0}
+                 "tune_s": 0.0, "p": info["order_p"]}
         log(f"given {prec} orders {orders}: {ms:.3f} ms/product, rel err {err:.2e}, stages " +
             " ".join(f"{k}={v:.3f}" for k, v in stages.items()))
     elif not args.no_tune:
         from paper_2205_04194_amd import autotune
         t0 = time.perf_counter()
         res = autotune.tune(tree, u, target=1e-6, precisions=precs, seed=1)
+        pmax = max(res.level_orders)
+        if pmax < args.p:
+            # multipoles need no more than the highest translation order: rebuild
+            # the tree at that order (P2M, M2M and M2P do less work)
+            tree.close()
+            tree = imq.build_tree(xy, d["c"], leaf=args.leaf, p=pmax)
+            tree.set_level_orders(res.level_orders)
+            tree.set_kernel_config(m2l_kc=res.m2l_kc, m2l_split=res.m2l_split, m2l_mode=res.m2l_mode)
+            info = tree.info()
         t_tune = time.perf_counter() - t0
         b = tree.matvec(u, res.precision)
         err = float(torch.linalg.norm(b[rows] - exact) / torch.linalg.norm(exact))
         ms, stages = time_products(tree, u, res.precision, args.steps, args.warmup)
         tuned = {"ms": ms, "err": err, "stages": stages, "prec": res.precision,
                  "level_orders": res.level_orders, "m2l_kc": res.m2l_kc, "m2l_split": res.m2l_split,
-                 "m2l_mode": res.m2l_mode, "tune_s": t_tune}
-        info = tree.info()
+                 "m2l_mode": res.m2l_mode, "tune_s": t_tune, "p": info["order_p"]}
         log(f"tuned {res.precision} orders {res.level_orders} mode {res.m2l_mode} kc {res.m2l_kc} "
             f"split {res.m2l_split}: "
             f"{ms:.3f} ms/product, rel err {err:.2e}, stages " +
@@ -326,7 +338,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32"}[head],
         "data": "synthetic",
-        "config": {"workload": args.workload, "N": n, "c": d["c"], "leaf": args.leaf, "p": args.p,
+        "config": {"workload": args.workload, "N": n, "c": d["c"], "leaf": args.leaf, "p": r.get("p", args.p),
                    "nrhs": 1, "precision": head,
                    "level_orders": r.get("level_orders"), "m2l_mode": r.get("m2l_mode"),
                    "m2l_kc": r.get("m2l_kc"), "m2l_split": r.get("m2l_split")},

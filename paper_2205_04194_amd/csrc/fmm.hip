@@ -422,16 +422,15 @@ __global__ void k_fill(size_t n, T *__restrict__ p, T v)
 }
 
 // L2P: potential = sum Re(Lt[n,m] |w|^(n-m) w^m) at each point of a leaf.
-// The leaf's local expansion is staged in LDS; the order is a compile-time
-// constant so the evaluation loop is fully unrolled.
-template <typename T, int P>
-__global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ L, int nrhs, double *__restrict__ bs, int add,
-                                            UserVec io)
+// The leaf's local expansion carries only the coefficients of its level's
+// translation order Q <= P (the rest are zero), so the evaluation runs at Q:
+// the kernel is instantiated for the tree's order P and switches, per leaf,
+// to the fully unrolled evaluation of order Q.  The expansion is staged in LDS.
+template <typename T, int Q>
+__device__ __forceinline__ void l2p_leaf(const DTree<T> &t, int b, T *Ls, const T *__restrict__ L, int nrhs,
+                                         double *__restrict__ bs, int add, const UserVec &io)
 {
-    constexpr int K = (P + 1) * (P + 2) / 2;
-    __shared__ T Ls[K];
-    const int b = leaves[blockIdx.x];
+    constexpr int K = (Q + 1) * (Q + 2) / 2;
     const T inv_s = pow2i<T>(t.level[b]);
     for (int r = 0; r < nrhs; ++r) {
         __syncthreads();
@@ -440,13 +439,35 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restric
         for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
             T acc = T(0);
             // real part of Lt * monomial: Re*Re - Im*Im
-            monomials<P>(t.xl[i] * inv_s, t.yl[i] * inv_s,
+            monomials<Q>(t.xl[i] * inv_s, t.yl[i] * inv_s,
                          [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
             const double val = add ? bs[r * t.N + i] + double(acc) : double(acc);
             if (io.out) io.put(r, i, val);
             else bs[r * t.N + i] = val;
         }
     }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restrict__ leaves,
+                                            const T *__restrict__ L, int nrhs, double *__restrict__ bs, int add,
+                                            UserVec io)
+{
+    __shared__ T Ls[(P + 1) * (P + 2) / 2];
+    const int b = leaves[blockIdx.x];
+    const int Kl = t.Klev[t.level[b]];
+    int q = 0;                                   // order with (q+1)(q+2)/2 = Kl
+    while ((q + 2) * (q + 3) / 2 <= Kl) ++q;
+#define IMQ_L2P_Q(Q) \
+    case Q: if constexpr (Q <= P) { l2p_leaf<T, Q>(t, b, Ls, L, nrhs, bs, add, io); return; } break;
+    switch (q) {
+        IMQ_L2P_Q(1) IMQ_L2P_Q(2) IMQ_L2P_Q(3) IMQ_L2P_Q(4) IMQ_L2P_Q(5) IMQ_L2P_Q(6) IMQ_L2P_Q(7)
+        IMQ_L2P_Q(8) IMQ_L2P_Q(9) IMQ_L2P_Q(10) IMQ_L2P_Q(11) IMQ_L2P_Q(12) IMQ_L2P_Q(13) IMQ_L2P_Q(14)
+        IMQ_L2P_Q(15) IMQ_L2P_Q(16)
+        default: break;
+    }
+#undef IMQ_L2P_Q
+    l2p_leaf<T, P>(t, b, Ls, L, nrhs, bs, add, io);
 }
 
 // Many right-hand sides: the leaf expansions and their evaluation as
