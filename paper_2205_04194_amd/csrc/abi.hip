@@ -91,6 +91,14 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     UP(begin); UP(end); UP(cx); UP(cy); UP(u_off); UP(u_idx); UP(v_off); UP(v_idx); UP(v_cls);
     UP(w_off); UP(w_idx); UP(x_off); UP(x_idx); UP(Klev); UP(leaves);
 #undef UP
+    {   // leaf records
+        std::vector<LeafRec> lr(h.leaves.size());
+        for (size_t i = 0; i < lr.size(); ++i) {
+            const int b = h.leaves[i];
+            lr[i] = LeafRec{b, h.begin[b], h.end[b], h.level[b]};
+        }
+        if ((st = upload(t->leafrec, lr)) != IMQ_OK) return st;
+    }
     {   // W and X lists as flat pairs
         std::vector<int32_t> w_tgt, w_scr, w_leaves, x_tgt, x_boxes;
         int32_t scr = 0;
@@ -184,7 +192,7 @@ static void free_tree(imq_tree_s *t)
     DevBuf *bufs[] = {&t->perm, &t->pt_scale, &t->level, &t->set, &t->parent, &t->child0, &t->nchild,
                       &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
-                      &t->cn, &t->leaves, &t->xy_user, &t->set_off, &t->bs, &t->sol,
+                      &t->cn, &t->leaves, &t->leafrec, &t->xy_user, &t->set_off, &t->bs, &t->sol,
                       &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw, &t->adj,
                       &t->sh_par, &t->sh_kids};
     for (DevBuf *b : bufs) dev_free(*b);

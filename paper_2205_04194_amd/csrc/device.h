@@ -20,6 +20,16 @@ struct DevBuf {
 hipError_t dev_alloc(DevBuf &b, size_t bytes);
 void dev_free(DevBuf &b);
 
+// One leaf: its box, first and past-the-end point, level (one 16-byte load).
+struct alignas(16) LeafRec {
+    int box, begin, end, level;
+};
+
+// Coefficient count of the translations at every level, by value.
+struct LevelK {
+    int K[32];
+};
+
 // Read-only view of the forest for kernels, in arithmetic type T.
 template <typename T>
 struct DTree {
@@ -30,6 +40,7 @@ struct DTree {
     const double *cx, *cy;
     const int32_t *u_off, *u_idx, *v_off, *v_idx, *v_cls, *w_off, *w_idx, *x_off, *x_idx;
     const int32_t *Klev;
+    const LeafRec *leafrec;    // per leaf, in the order of the leaf list
     const double *cn;          // per set: c / side
     const T *xl, *yl;          // leaf-local coordinates, sorted order
 };
@@ -125,6 +136,7 @@ struct imq_tree_s {
     imq::DevBuf perm, pt_scale, level, set, parent, child0, nchild, pos, begin, end, cx, cy;
     imq::DevBuf u_off, u_idx, v_off, v_idx, v_cls, w_off, w_idx, x_off, x_idx, Klev, cn, leaves;
     imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
+    imq::DevBuf leafrec;                   // LeafRec per leaf
     imq::PrecData f64, f32;
     imq::DevGemm g_m2l;
     imq::DevBuf sh_par, sh_kids;           // shift lists (HostTree::sh_*)

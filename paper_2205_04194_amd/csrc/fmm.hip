@@ -142,29 +142,37 @@ __device__ __forceinline__ T lds_dot(const T *a, int ld, int k, const T *w, int 
 constexpr int P2M_CHUNK = 32;      // points staged per round (LDS per wave halves vs 64)
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ us, int nrhs, T *__restrict__ M, int ld,
-                                            UserVec io)
+__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const T *__restrict__ us, int nrhs, T *__restrict__ M,
+                                            int ld, UserVec io)
 {
     extern __shared__ unsigned char smem_raw[];
     T *mono = reinterpret_cast<T *>(smem_raw);   // [P2M_CHUNK][ld]
     T *su = mono + P2M_CHUNK * ld;               // [P2M_CHUNK]
-    const int b = leaves[blockIdx.x];
-    const int beg = t.begin[b], end = t.end[b];
-    const T inv_s = pow2i<T>(t.level[b]);
+    const LeafRec lr = t.leafrec[blockIdx.x];
+    const int b = lr.box, beg = lr.begin, end = lr.end;
+    const T inv_s = pow2i<T>(lr.level);
     constexpr int K = (P + 1) * (P + 2) / 2;
     const int lane = threadIdx.x;
     for (int c0 = beg; c0 < end; c0 += P2M_CHUNK) {
         const int n = min(P2M_CHUNK, end - c0);
+        // the point and its first weight are requested together
+        T x = T(0), y = T(0), u0 = T(0);
+        if (lane < n) {
+            x = t.xl[c0 + lane];
+            y = t.yl[c0 + lane];
+            u0 = io.in ? T(io.get(0, c0 + lane)) : us[c0 + lane];
+        }
         __syncthreads();
         if (lane < n) {
             T *row = mono + lane * ld;
-            monomials<P>(t.xl[c0 + lane] * inv_s, -t.yl[c0 + lane] * inv_s,
-                         [&](int k, T v, bool) { row[k] = v; });
+            monomials<P>(x * inv_s, -y * inv_s, [&](int k, T v, bool) { row[k] = v; });
+            su[lane] = u0;
         }
         for (int r = 0; r < nrhs; ++r) {
-            __syncthreads();
-            if (lane < n) su[lane] = io.in ? T(io.get(r, c0 + lane)) : us[r * t.N + c0 + lane];
+            if (r > 0) {
+                __syncthreads();
+                if (lane < n) su[lane] = io.in ? T(io.get(r, c0 + lane)) : us[r * t.N + c0 + lane];
+            }
             __syncthreads();
             for (int k = lane; k < K; k += 64) {
                 const T v = lds_dot(mono, ld, k, su, n);
@@ -427,21 +435,26 @@ __global__ void k_fill(size_t n, T *__restrict__ p, T v)
 // the kernel is instantiated for the tree's order P and switches, per leaf,
 // to the fully unrolled evaluation of order Q.  The expansion is staged in LDS.
 template <typename T, int Q>
-__device__ __forceinline__ void l2p_leaf(const DTree<T> &t, int b, T *Ls, const T *__restrict__ L, int nrhs,
-                                         double *__restrict__ bs, int add, const UserVec &io)
+__device__ __forceinline__ void l2p_leaf(const DTree<T> &t, const LeafRec &lr, T *Ls, const T *__restrict__ L,
+                                         int nrhs, double *__restrict__ bs, int add, const UserVec &io)
 {
     constexpr int K = (Q + 1) * (Q + 2) / 2;
-    const T inv_s = pow2i<T>(t.level[b]);
-    for (int r = 0; r < nrhs; ++r) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < K; k += blockDim.x) Ls[k] = L[(size_t(b) * nrhs + r) * t.KS + k];
-        __syncthreads();
-        for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
+    const T inv_s = pow2i<T>(lr.level);
+    for (int i0 = lr.begin; i0 < lr.end; i0 += blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        const bool ok = i < lr.end;
+        for (int r = 0; r < nrhs; ++r) {
+            __syncthreads();                     // the previous expansion is no longer read
+            // the point, the partial result and the expansion are requested together
+            const T x = ok ? t.xl[i] * inv_s : T(0), y = ok ? t.yl[i] * inv_s : T(0);
+            const double prev = (ok && add) ? bs[r * t.N + i] : 0.0;
+            for (int k = threadIdx.x; k < K; k += blockDim.x) Ls[k] = L[(size_t(lr.box) * nrhs + r) * t.KS + k];
+            __syncthreads();
+            if (!ok) continue;
             T acc = T(0);
             // real part of Lt * monomial: Re*Re - Im*Im
-            monomials<Q>(t.xl[i] * inv_s, t.yl[i] * inv_s,
-                         [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
-            const double val = add ? bs[r * t.N + i] + double(acc) : double(acc);
+            monomials<Q>(x, y, [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
+            const double val = prev + double(acc);
             if (io.out) io.put(r, i, val);
             else bs[r * t.N + i] = val;
         }
@@ -449,17 +462,16 @@ __device__ __forceinline__ void l2p_leaf(const DTree<T> &t, int b, T *Ls, const 
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restrict__ leaves,
-                                            const T *__restrict__ L, int nrhs, double *__restrict__ bs, int add,
-                                            UserVec io)
+__global__ __launch_bounds__(64) void k_l2p(DTree<T> t, LevelK lk, const T *__restrict__ L, int nrhs,
+                                            double *__restrict__ bs, int add, UserVec io)
 {
     __shared__ T Ls[(P + 1) * (P + 2) / 2];
-    const int b = leaves[blockIdx.x];
-    const int Kl = t.Klev[t.level[b]];
+    const LeafRec lr = t.leafrec[blockIdx.x];
+    const int Kl = lk.K[lr.level];
     int q = 0;                                   // order with (q+1)(q+2)/2 = Kl
     while ((q + 2) * (q + 3) / 2 <= Kl) ++q;
 #define IMQ_L2P_Q(Q) \
-    case Q: if constexpr (Q <= P) { l2p_leaf<T, Q>(t, b, Ls, L, nrhs, bs, add, io); return; } break;
+    case Q: if constexpr (Q <= P) { l2p_leaf<T, Q>(t, lr, Ls, L, nrhs, bs, add, io); return; } break;
     switch (q) {
         IMQ_L2P_Q(1) IMQ_L2P_Q(2) IMQ_L2P_Q(3) IMQ_L2P_Q(4) IMQ_L2P_Q(5) IMQ_L2P_Q(6) IMQ_L2P_Q(7)
         IMQ_L2P_Q(8) IMQ_L2P_Q(9) IMQ_L2P_Q(10) IMQ_L2P_Q(11) IMQ_L2P_Q(12) IMQ_L2P_Q(13) IMQ_L2P_Q(14)
@@ -467,7 +479,7 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, const int32_t *__restric
         default: break;
     }
 #undef IMQ_L2P_Q
-    l2p_leaf<T, P>(t, b, Ls, L, nrhs, bs, add, io);
+    l2p_leaf<T, P>(t, lr, Ls, L, nrhs, bs, add, io);
 }
 
 // Many right-hand sides: the leaf expansions and their evaluation as
@@ -962,6 +974,7 @@ DTree<T> make_view(const imq_tree_s *t)
     v.w_off = t->w_off.as<int32_t>(); v.w_idx = t->w_idx.as<int32_t>();
     v.x_off = t->x_off.as<int32_t>(); v.x_idx = t->x_idx.as<int32_t>();
     v.Klev = t->Klev.as<int32_t>();
+    v.leafrec = t->leafrec.as<LeafRec>();
     v.cn = t->cn.as<double>();
     const PrecData &pd = prec_data<T>(const_cast<imq_tree_s *>(t));
     v.xl = pd.xl.as<T>();
@@ -1074,8 +1087,7 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
         hipLaunchKernelGGL((k_p2m_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, t->leaves.as<int32_t>(),     \
                            pd.us.as<T>(), nrhs, M);                                                    \
     else                                                                                               \
-        hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, t->leaves.as<int32_t>(), \
-                           pd.us.as<T>(), nrhs, M, ld, uv)
+        hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, pd.us.as<T>(), nrhs, M, ld, uv)
     IMQ_DISPATCH_P(h.p, IMQ_P2M)
 #undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
@@ -1242,13 +1254,15 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
         return IMQ_OK;
     };
     if (uv.out && (st = m2p()) != IMQ_OK) return st;      // L2P then writes the caller's vector last
+    LevelK lk = {};
+    for (int l = 0; l < h.nlev && l < 32; ++l) lk.K[l] = h.Klev[l];
     constexpr int RB = sizeof(T) == 4 ? 64 : 32;
     const dim3 gb(unsigned(nleaves), unsigned((nrhs + RB - 1) / RB));
 #define IMQ_L2P(PP)                                                                                    \
     if (nrhs >= BATCH_RHS_MIN)                                                                         \
         hipLaunchKernelGGL((k_l2p_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs); \
     else                                                                                               \
-        hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs, 1, uv)
+        hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, lk, pd.L.as<T>(), nrhs, bs, 1, uv)
     IMQ_DISPATCH_P(h.p, IMQ_L2P)
 #undef IMQ_L2P
     IMQ_HIP(hipGetLastError());
