@@ -7,11 +7,11 @@
 //
 // The batched GEMM of fmm.hip stages one class per step through LDS, so a
 // workgroup pays one memory round trip per class and coefficient chunk.
-// Here the 4 waves split the classes (wave w takes classes w, w+4, ...), each
-// wave loads its table slices and source expansions straight from memory in
-// the matrix-core lane order (16 bytes per lane and load), one class ahead of
-// the matrix cores, and the 4 partial results are summed in LDS in a fixed
-// order.
+// Here the NW waves of a workgroup (4 or 8) split the classes (wave w takes
+// classes w, w + NW, ...); each wave loads its table slices and source
+// expansions straight from memory in the matrix-core lane order (16 bytes per
+// lane and load), one class ahead of the matrix cores, and the partial results
+// of the waves are summed in LDS in a fixed order.
 #include "device.h"
 #include "mfma.h"
 
@@ -21,7 +21,6 @@ namespace imq {
 
 namespace {
 
-constexpr int SPW = (GEMM_MAXSLOT + 3) / 4;     // classes per wave
 
 // Task = GemmTask of the translation batches (<= 64 targets sharing level,
 // set and child position).  blockIdx.y picks TC = 16*NCB of its columns
@@ -30,13 +29,13 @@ constexpr int SPW = (GEMM_MAXSLOT + 3) / 4;     // classes per wave
 // T[16 rb + l%16][16 ci + 4 (l/16) + j], so a lane's four values of a chunk
 // match four consecutive source coefficients.
 //
-// Wave w walks its classes w, w+4, ...
+// Wave w walks its classes w, w+NW, ...
 // For class k the source expansions of class k+1 and, row block by row
 // block as soon as each is consumed, the table of class k+1 are requested
 // while the matrix cores work on class k; the source indices run one class
 // further ahead.  Register use: NRB*NRB + 2*NCB*NRB four-value quads.
-template <typename T, int NRB, int NCB>
-__global__ __launch_bounds__(256) void k_m2l_stream(const GemmTask *__restrict__ tasks, int task0,
+template <typename T, int NRB, int NCB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restrict__ tasks, int task0,
                                                     const int32_t *__restrict__ tbox,
                                                     const int32_t *__restrict__ tab,
                                                     const int32_t *__restrict__ src, const T *__restrict__ Apk,
@@ -47,7 +46,8 @@ __global__ __launch_bounds__(256) void k_m2l_stream(const GemmTask *__restrict__
     constexpr int LDR = NRB * 16 + 1;
     using acc_t = typename Mfma<T>::acc_t;
     using Q = Quad<T>;
-    __shared__ T red[4 * TC * LDR];
+    constexpr int SPW = (GEMM_MAXSLOT + NW - 1) / NW;  // classes per wave
+    __shared__ T red[NW * TC * LDR];
     __shared__ int s_out[TC];
 
     const GemmTask tk = tasks[task0 + blockIdx.x];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_m2l_stream(const GemmTask *__restrict__
         rr[cb] = gc < ncols ? gc - bl[cb] * nrhs : 0;
     }
     auto source = [&](int k, int *sb) {
-        const int sl = w + 4 * k;
+        const int sl = w + NW * k;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
             sb[cb] = (k < SPW && sl < nslot && bl[cb] >= 0) ? src[tk.src0 + bl[cb] * nslot + sl] : -1;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_m2l_stream(const GemmTask *__restrict__
             }
     };
     auto table = [&](int k) -> const T * {
-        const int sl = w + 4 * k;
+        const int sl = w + NW * k;
         return (k < SPW && sl < nslot) ? Apk + size_t(tab[tk.tab0 + sl]) * nrbT * nrbT * 256 + lane * 4 : nullptr;
     };
 
@@ -162,12 +162,14 @@ __global__ __launch_bounds__(256) void k_m2l_stream(const GemmTask *__restrict__
             for (int v = 0; v < 4; ++v)
                 red[(w * TC + cb * 16 + i16) * LDR + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
     __syncthreads();
-    for (int e = tid; e < TC * kout; e += 256) {
+    for (int e = tid; e < TC * kout; e += 64 * NW) {
         const int c = e / kout, kk = e - c * kout;
         const int o = s_out[c];
         if (o < 0) continue;
-        out[size_t(o) * KS + kk] = ((red[c * LDR + kk] + red[(TC + c) * LDR + kk]) + red[(2 * TC + c) * LDR + kk]) +
-                                   red[(3 * TC + c) * LDR + kk];
+        T sum = red[c * LDR + kk];
+#pragma unroll
+        for (int ww = 1; ww < NW; ++ww) sum += red[(ww * TC + c) * LDR + kk];
+        out[size_t(o) * KS + kk] = sum;
     }
 }
 
@@ -196,25 +198,28 @@ bool launch_m2l_stream(hipStream_t s, int kmax, int ntask, int task0, int nrhs, 
 {
     const int nrb = (kmax + 15) / 16;
     if (ntask <= 0) return true;
-#define IMQ_M2LS(NRB, NCB)                                                                                 \
-    hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB>),                                                        \
-                       dim3(ntask, unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB))), dim3(256), 0, s, \
+    // 4 waves per workgroup everywhere: 8 (a class chain half as long) was
+    // measured slower on the mixture workload, in particular beside the near
+    // field, whose small workgroups leave few CUs with 8 wave slots free
+#define IMQ_M2LS(NRB, NCB, NW)                                                                             \
+    hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW>),                                                    \
+                       dim3(ntask, unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB))), dim3(64 * NW), 0, s, \
                        tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out)
     if constexpr (sizeof(T) == 4) {
         switch (nrb) {
-        case 1: IMQ_M2LS(1, 2); return true;
-        case 2: IMQ_M2LS(2, 2); return true;
-        case 3: IMQ_M2LS(3, 2); return true;
-        case 4: IMQ_M2LS(4, 1); return true;
-        case 5: IMQ_M2LS(5, 1); return true;
+        case 1: IMQ_M2LS(1, 2, 4); return true;
+        case 2: IMQ_M2LS(2, 2, 4); return true;
+        case 3: IMQ_M2LS(3, 2, 4); return true;
+        case 4: IMQ_M2LS(4, 1, 4); return true;
+        case 5: IMQ_M2LS(5, 1, 4); return true;
         default: return false;
         }
     } else {
         switch (nrb) {
-        case 1: IMQ_M2LS(1, 1); return true;
-        case 2: IMQ_M2LS(2, 1); return true;
-        case 3: IMQ_M2LS(3, 1); return true;
-        case 4: IMQ_M2LS(4, 1); return true;
+        case 1: IMQ_M2LS(1, 1, 4); return true;
+        case 2: IMQ_M2LS(2, 1, 4); return true;
+        case 3: IMQ_M2LS(3, 1, 4); return true;
+        case 4: IMQ_M2LS(4, 1, 4); return true;
         default: return false;
         }
     }
