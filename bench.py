@@ -30,8 +30,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}          # dense MFMA
 PEAK_TFLOPS_VALU = {"fp64": 78.6, "fp32": 78.6}
 # HBM bytes of one FP32 near-field launch on mixture1m, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a plain 256 MiB copy
-# (profiles/p2p_mixture1m_fp32.md); None until re-measured after k_p2p changes.
-P2P_TRAFFIC_BYTES = None
+# (profiles/p2p_mixture1m_fp32.md); to be re-measured whenever k_p2p changes.
+P2P_TRAFFIC_BYTES = (60454 * 2.0 + 8628 * 1.0) * 1024
 HBM_GBS = 8000.0
 
 
@@ -101,20 +101,30 @@ def cpu_baseline(xy, c, u, budget_s):
 
 def solve_compare(tree, f, iters):
     """GMRES(50) on the FP64 product vs FP32-product GMRES inside FP64
-    refinement, both capped at the same number of products, tolerance 1e-10.
-    Reports the explicit FP64-product residual reached and the wall time."""
+    refinement, as time to a common tolerance.  Unpreconditioned GMRES cannot
+    reach 1e-10 on these ill-conditioned systems, so the tolerance is
+    max(1e-10, the explicit FP64 residual that FP64 GMRES reaches in `iters`
+    products); both solvers then run to it (cap 2 x iters products)."""
     import torch
-    res = {}
-    for name, mixed in (("fp64", False), ("mixed", True)):
+
+    def run(mixed, tol, cap):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, st = tree.solve(f, tol=1e-10, restart=50, max_iters=iters, mixed_ir=mixed)
+        _, st = tree.solve(f, tol=tol, restart=50, max_iters=cap, mixed_ir=mixed)
         torch.cuda.synchronize()
-        res[name] = {"seconds": time.perf_counter() - t0, "relres": st["relres"],
-                     "iters": st["iters"], "outer": st["outer_iters"], "converged": st["converged"]}
-        log(f"solve {name}: {res[name]}")
-    res["note"] = ("unpreconditioned GMRES does not reach 1e-10 on this ill-conditioned system; "
-                   "relres is the explicit residual after the product budget")
+        return {"seconds": time.perf_counter() - t0, "relres": st["relres"], "iters": st["iters"],
+                "outer": st["outer_iters"], "converged": bool(st["converged"])}
+
+    probe = run(False, 1e-10, iters)
+    tol = max(1e-10, probe["relres"] * 1.0001)
+    res = {"budget_fp64": probe, "tolerance": tol}
+    for name, mixed in (("fp64", False), ("mixed", True)):
+        res[name] = run(mixed, tol, 2 * iters)
+        log(f"solve {name} to {tol:.3e}: {res[name]}")
+    if res["fp64"]["converged"] and res["mixed"]["converged"]:
+        res["mixed_speedup"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
+    res["note"] = ("unpreconditioned GMRES(50) does not reach 1e-10 on this system; the tolerance is the "
+                   "explicit FP64-product residual FP64 GMRES reaches in the product budget")
     return res
 
 
