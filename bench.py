@@ -147,6 +147,30 @@ def _tuned_run(tree, U, steps, nrows=300):
             "stage_ms": stages}
 
 
+def _graph_ms(tree, u, prec, steps):
+    """ms per replay of the product captured in one HIP graph (torch.cuda.graph)."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        tree.matvec(u, prec)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tree.matvec(u, prec)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def batched_extras(dev, steps):
     """Batching: 64 right-hand sides on one tree, and 256 point sets in one forest."""
     import torch
@@ -175,6 +199,8 @@ def batched_extras(dev, steps):
     r = _tuned_run(tree, u, steps)
     r.update({"workload": "batched_sets", "nsets": len(d["c"]), "N_total": len(d["xy"]),
               "tree_build_s": tb, "products_per_s": 1e3 / r["ms_per_step"]})
+    r["graph_ms_per_step"] = _graph_ms(tree, u, r["precision"], steps)
+    log(f"batched 256 sets, captured in one HIP graph: {r['graph_ms_per_step']:.3f} ms per replay")
     tree.close()
     out["sets256"] = r
     log(f"batched 256 sets: {r['ms_per_step']:.3f} ms, err {r['rel_err_sampled_rows']:.2e}")
