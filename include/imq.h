@@ -159,12 +159,17 @@ imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
  *               64 (FP64), the staged GEMM above; 1 = staged GEMM everywhere.
  *               m2l_kc and m2l_split apply to the staged GEMM only.
  *  p2p_wg     : workgroups of the near-field kernel while it runs alongside
- *               the tree passes (each takes every p2p_wg-th leaf); 0 = 2048 */
+ *               the tree passes (each takes every p2p_wg-th leaf); 0 = 2048
+ *  p2p_mode   : near field in FP32 with one right-hand side: 0 = vector form
+ *               everywhere; 1 = matrix-core form (squared distances as a
+ *               rank-4 product) for the leaves whose neighbourhood is small
+ *               against c, vector form for the rest */
 typedef struct {
     int m2l_kc, m2l_split;
     int shift_cols;
     int m2l_mode;
     int p2p_wg;
+    int p2p_mode;
 } imq_kernel_config;
 
 imq_status imq_set_kernel_config(imq_tree tree, const imq_kernel_config *cfg);

@@ -161,9 +161,9 @@ class Tree:
         return out
 
     def set_kernel_config(self, m2l_kc: int = 0, m2l_split: int = 0, shift_cols: int = 0,
-                          m2l_mode: int = 0, p2p_wg: int = 0) -> None:
+                          m2l_mode: int = 0, p2p_wg: int = 0, p2p_mode: int = 0) -> None:
         """Launch shape of the batched translations and the near field (0 = default)."""
-        cfg = _lib.KernelConfig(m2l_kc, m2l_split, shift_cols, m2l_mode, p2p_wg)
+        cfg = _lib.KernelConfig(m2l_kc, m2l_split, shift_cols, m2l_mode, p2p_wg, p2p_mode)
         _lib.check(_lib.load().imq_set_kernel_config(self._h, ctypes.byref(cfg)),
                    "imq_set_kernel_config")
 

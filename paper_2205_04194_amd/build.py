@@ -22,6 +22,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # no packed FP32 instructions anywhere in the device code
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# per source: the near field's matrix-core results go straight to VGPRs (no
+# copies out of the accumulation registers in its inner loop)
+FILE_FLAGS = {"p2p.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def sources():
@@ -33,7 +36,7 @@ def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
     if src.endswith(".hip"):
-        cmd[1:1] = ["-x", "hip", *DEVICE]
+        cmd[1:1] = ["-x", "hip", *DEVICE, *FILE_FLAGS.get(os.path.basename(src), [])]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

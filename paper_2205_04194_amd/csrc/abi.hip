@@ -82,6 +82,52 @@ static void make_tables(const HostTree &h, std::vector<double> &m2m, std::vector
     for (auto &x : th) x.join();
 }
 
+// The near field's view of the U lists: per entry (target leaf b, source
+// leaf a) the points of a and the offset of its centre from b's.
+template <typename T>
+static std::vector<URec<T>> u_records(const HostTree &h)
+{
+    std::vector<URec<T>> r(h.u_idx.size());
+    const int nbox = int(h.level.size());
+    for (int b = 0; b < nbox; ++b)
+        for (int k = h.u_off[b]; k < h.u_off[b + 1]; ++k) {
+            const int a = h.u_idx[k];
+            r[k] = URec<T>{h.begin[a], h.end[a] - h.begin[a], T(h.cx[a] - h.cx[b]), T(h.cy[a] - h.cy[b])};
+        }
+    return r;
+}
+
+// Per leaf, whether its FP32 near field may take the matrix-core form, whose
+// squared distances come from the expansion
+// |x_i - x_j|^2 = |x_i|^2 + |x_j|^2 - 2 x_i . x_j about the leaf's centre and
+// so carry about (1 + (|x_i|^2 + |x_j|^2) / c^2) units of rounding, against
+// about 2 for the direct differences.  A leaf qualifies when that ratio,
+// bounded with the largest point radius of each leaf of its U list, is at
+// most NEAR_MF_RATIO (so at most about 3 units).
+constexpr double NEAR_MF_RATIO = 2.0;
+
+static std::vector<NearLeaf> near_leaves(const HostTree &h)
+{
+    const int nbox = int(h.level.size());
+    std::vector<double> rad(nbox, 0.0);           // largest distance of a point from its leaf's centre
+    for (int b : h.leaves)
+        for (int i = h.begin[b]; i < h.end[b]; ++i)
+            rad[b] = std::max(rad[b], std::sqrt(h.xl[i] * h.xl[i] + h.yl[i] * h.yl[i]));
+    std::vector<NearLeaf> nl(h.leaves.size());
+    for (size_t l = 0; l < h.leaves.size(); ++l) {
+        const int b = h.leaves[l];
+        double far = 0.0;
+        for (int k = h.u_off[b]; k < h.u_off[b + 1]; ++k) {
+            const int a = h.u_idx[k];
+            far = std::max(far, std::hypot(h.cx[a] - h.cx[b], h.cy[a] - h.cy[b]) + rad[a]);
+        }
+        const double cn = h.cn[h.set[b]];
+        const int mf = (rad[b] * rad[b] + far * far) <= NEAR_MF_RATIO * cn * cn ? 1 : 0;
+        nl[l] = NearLeaf{h.begin[b], h.end[b], h.u_off[b], h.u_off[b + 1], cn * cn, mf, 0};
+    }
+    return nl;
+}
+
 static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
 {
     const HostTree &h = t->h;
@@ -98,6 +144,7 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
             lr[i] = LeafRec{b, h.begin[b], h.end[b], h.level[b]};
         }
         if ((st = upload(t->leafrec, lr)) != IMQ_OK) return st;
+        if ((st = upload(t->nleaf, near_leaves(h))) != IMQ_OK) return st;
     }
     {   // W and X lists as flat pairs
         std::vector<int32_t> w_tgt, w_scr, w_leaves, x_tgt, x_boxes;
@@ -135,6 +182,8 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     if ((st = upload(t->f64.yl, h.yl)) != IMQ_OK) return st;
     if ((st = upload(t->f32.xl, to_f32(h.xl))) != IMQ_OK) return st;
     if ((st = upload(t->f32.yl, to_f32(h.yl))) != IMQ_OK) return st;
+    if ((st = upload(t->f64.urec, u_records<double>(h))) != IMQ_OK) return st;
+    if ((st = upload(t->f32.urec, u_records<float>(h))) != IMQ_OK) return st;
 
     std::vector<double> m2m, l2l, m2l, wx;
     make_tables(h, m2m, l2l, m2l, wx);
@@ -192,7 +241,7 @@ static void free_tree(imq_tree_s *t)
     DevBuf *bufs[] = {&t->perm, &t->pt_scale, &t->level, &t->set, &t->parent, &t->child0, &t->nchild,
                       &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
-                      &t->cn, &t->leaves, &t->leafrec, &t->xy_user, &t->set_off, &t->bs, &t->sol,
+                      &t->cn, &t->leaves, &t->leafrec, &t->nleaf, &t->xy_user, &t->set_off, &t->bs, &t->sol,
                       &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw, &t->adj,
                       &t->sh_par, &t->sh_kids};
     for (DevBuf *b : bufs) dev_free(*b);
@@ -200,7 +249,7 @@ static void free_tree(imq_tree_s *t)
         dev_free(g->tasks); dev_free(g->tbox); dev_free(g->tab); dev_free(g->src);
     }
     for (PrecData *pd : {&t->f64, &t->f32}) {
-        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->m2m, &pd->l2l, &pd->m2l, &pd->m2l_pk, &pd->wx, &pd->us, &pd->M, &pd->L,
+        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->urec, &pd->m2m, &pd->l2l, &pd->m2l, &pd->m2l_pk, &pd->wx, &pd->us, &pd->M, &pd->L,
                         &pd->Lx, &pd->m2l_odd, &pd->l2l_odd, &pd->Lodd};
         for (DevBuf *b : pb) dev_free(*b);
     }
@@ -355,7 +404,7 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
     auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
     if (!ok_kc(cfg->m2l_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
         (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32) ||
-        cfg->m2l_mode < 0 || cfg->m2l_mode > 1 || cfg->p2p_wg < 0) {
+        cfg->m2l_mode < 0 || cfg->m2l_mode > 1 || cfg->p2p_wg < 0 || cfg->p2p_mode < 0 || cfg->p2p_mode > 1) {
         set_error("kernel config out of range");
         return IMQ_EINVAL;
     }

@@ -25,6 +25,24 @@ struct alignas(16) LeafRec {
     int box, begin, end, level;
 };
 
+// One U-list entry of a target leaf, as the near field reads it (one 16- or
+// 32-byte load): the source leaf's points [beg, beg + cnt) in sorted order and
+// its centre minus the target leaf's centre, rounded to T.
+template <typename T>
+struct alignas(16) URec {
+    int beg, cnt;
+    T ox, oy;
+};
+
+// One leaf as the near field reads it (one 32-byte load): its points
+// [begin, end), its U-list entries [u0, u1), c^2 of its set in the scaled
+// coordinates, and whether its FP32 sums may take the matrix-core form.
+struct alignas(16) NearLeaf {
+    int begin, end, u0, u1;
+    double c2;
+    int mf, pad;
+};
+
 // Coefficient count of the translations at every level, by value.
 struct LevelK {
     int K[32];
@@ -41,12 +59,15 @@ struct DTree {
     const int32_t *u_off, *u_idx, *v_off, *v_idx, *v_cls, *w_off, *w_idx, *x_off, *x_idx;
     const int32_t *Klev;
     const LeafRec *leafrec;    // per leaf, in the order of the leaf list
+    const NearLeaf *nleaf;     // per leaf, in the order of the leaf list
     const double *cn;          // per set: c / side
     const T *xl, *yl;          // leaf-local coordinates, sorted order
+    const URec<T> *urec;       // per U-list entry (aligned with u_idx)
 };
 
 struct PrecData {              // everything that exists once per arithmetic type
     DevBuf xl, yl, wx;
+    DevBuf urec;               // URec<T> per U-list entry
     DevBuf m2m, l2l;           // shift tables, 4 quadrants, packed for k_shift
     DevBuf m2l;                // translation tables, zero-padded to KP x KP each
     DevBuf m2l_pk;             // the same, packed for k_m2l_stream
@@ -78,6 +99,16 @@ template <typename T>
 void launch_shift(hipStream_t s, bool up, int cols, int npar, int nrhs, const int32_t *par,
                   const int32_t *kids, const T *Apk, int KP, int kin, int kout, const ShiftCuts &cuts,
                   const T *in, int ldin, T *out, int ldout);
+
+// Near field of every leaf (grid-stride over the nleaves leaves with `grid`
+// workgroups): bs[r N + i] = sum over the U list of the kernel times us, in
+// sorted order, for nrhs right-hand sides.  SIDE tells apart in profiles the
+// launch beside the tree passes (true) from the one on the caller's stream.
+// mf: FP32 leaves flagged in v.nleaf take the matrix-core form (one
+// right-hand side only).
+template <typename T, bool SIDE>
+void launch_p2p(hipStream_t s, unsigned grid, const DTree<T> &v, int nleaves, const T *us, int nrhs, double *bs,
+                bool mf);
 
 // M2L tables in the lane order of k_m2l_stream (same size as tabs).
 void pack_m2l_tables(const std::vector<double> &tabs, int KP, std::vector<double> &packed);
@@ -137,6 +168,7 @@ struct imq_tree_s {
     imq::DevBuf u_off, u_idx, v_off, v_idx, v_cls, w_off, w_idx, x_off, x_idx, Klev, cn, leaves;
     imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
     imq::DevBuf leafrec;                   // LeafRec per leaf
+    imq::DevBuf nleaf;                     // NearLeaf per leaf
     imq::PrecData f64, f32;
     imq::DevGemm g_m2l;
     imq::DevBuf sh_par, sh_kids;           // shift lists (HostTree::sh_*)

@@ -655,253 +655,6 @@ __global__ __launch_bounds__(64) void k_l2p_mfma(DTree<T> t, const int32_t *__re
     }
 }
 
-// Reciprocal square root for the direct sums: the hardware estimate in
-// FP32; in FP64 the estimate refined by two Newton steps
-// y <- y (3 - x y^2) / 2, each roughly doubling the number of correct bits.
-__device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_fast(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
-}
-
-template <typename T> struct Vec4;
-template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
-template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
-
-constexpr int P2P_CHUNK = 256;                 // sources staged per round
-constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 per lane group
-
-// P2P: b_i += sum over U-list leaves a of sum_j u_j / sqrt(|x_i - x_j|^2 + c^2).
-// One wave per target leaf at a time; with a grid smaller than the leaf count
-// a workgroup walks several leaves (leaving wave slots free for kernels
-// running alongside).
-// SIDE only tells the two launch forms apart in profiles: alongside the tree
-// passes (true) or alone on the caller's stream (false).  Lane l takes target l % TP (TP = the leaf's
-// point count rounded up to a power of two, at least 4) in lane group
-// l / TP of G = 64 / TP groups.
-// Staging: the U list is read 64 entries at a time, one entry per lane (box,
-// first point, count, offset of its centre); a wave prefix sum of the counts
-// numbers the sources of the batch consecutively.  Chunks of up to 256 of
-// them are then gathered with every load of the chunk in flight at once
-// (each lane finds the entry of its slot by binary search over the prefix
-// sums in LDS), relative to the target leaf's centre and padded with zero
-// weights to a multiple of 4 G.  Each group sums a contiguous quarter-aligned
-// run of the chunk, 4 sources per step, and the G partial sums of a target are
-// combined with shuffles.  Partial sums over one chunk are kept in T, the
-// running sum in FP64.
-// One block of up to 128 targets of a leaf (R per lane): lane l takes targets
-// ti and ti + TP of group g (l = g TP + ti, TP = ceil(ntc / R) rounded up to 4
-// at least, G = 64 / TP groups; lanes past G TP idle).  R is chosen per leaf
-// to keep the most lanes busy (e.g. 40 points: R = 2, 60 of 64 lanes instead
-// of 40).  The U list is read 64 entries at a time, one per lane (first
-// point, count, centre offset); a wave prefix sum numbers the batch's sources,
-// and chunks of up to 256 are gathered with every load of the chunk in flight
-// (each lane finds its slot's entry by binary search over the prefix sums in
-// LDS), relative to the target leaf's centre and padded with zero weights to
-// a multiple of 4 G.  Each group sums a contiguous quarter-aligned run of the
-// chunk, 4 sources per step; partial sums over one chunk are kept in T, the
-// running sums in FP64, and the G group sums of a target are added with lane
-// shuffles in group order.
-template <typename T, int NR, int R>
-__device__ __forceinline__ void p2p_block(const DTree<T> &t, int b, int t0, int ntc, T c2, double bcx,
-                                          double bcy, const T *__restrict__ us, int nrhs,
-                                          double *__restrict__ bs, int add, typename Vec4<T>::type *sx4,
-                                          typename Vec4<T>::type *sy4, typename Vec4<T>::type (*su4)[P2P_LDS / 4],
-                                          int *s_beg, int *s_off, T *s_ox, T *s_oy)
-{
-    using V4 = typename Vec4<T>::type;
-    T *sx = reinterpret_cast<T *>(sx4), *sy = reinterpret_cast<T *>(sy4);
-    constexpr int SPL = P2P_CHUNK / 64;          // chunk slots per lane
-    const int lane = threadIdx.x;
-    const int64_t N = t.N;
-    const int u0 = t.u_off[b], u1 = t.u_off[b + 1];
-    const int TP = max(4, (ntc + R - 1) / R);
-    const int G = 64 / TP, grp = lane / TP, ti = lane % TP;
-    bool valid[R];
-    T xi[R], yi[R];
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-        valid[rr] = grp < G && ti + rr * TP < ntc;
-        const int i = t0 + (valid[rr] ? ti + rr * TP : 0);
-        xi[rr] = t.xl[i];
-        yi[rr] = t.yl[i];
-    }
-    for (int r0 = 0; r0 < nrhs; r0 += NR) {          // NR right-hand sides per pass
-        const int nr = min(NR, nrhs - r0);
-        double acc[R][NR];
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-            for (int q = 0; q < NR; ++q) acc[rr][q] = 0.0;
-        for (int ub = u0; ub < u1; ub += 64) {
-            const int nb = min(64, u1 - ub);
-            int cnt = 0, beg = 0;
-            T ox = T(0), oy = T(0);
-            if (lane < nb) {
-                const int a = t.u_idx[ub + lane];
-                beg = t.begin[a];
-                cnt = t.end[a] - beg;
-                ox = T(t.cx[a] - bcx);
-                oy = T(t.cy[a] - bcy);
-            }
-            int incl = cnt;                  // inclusive prefix sum over the wave
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int v = __shfl_up(incl, d);
-                if (lane >= d) incl += v;
-            }
-            const int total = __shfl(incl, 63);
-            __syncthreads();                 // previous batch's entries no longer read
-            s_beg[lane] = beg;
-            s_off[lane] = incl - cnt;
-            s_ox[lane] = ox;
-            s_oy[lane] = oy;
-            if (lane == 0) s_off[64] = total;
-            __syncthreads();
-            for (int c0 = 0; c0 < total; c0 += P2P_CHUNK) {
-                const int n = min(P2P_CHUNK, total - c0);
-                T vx[SPL], vy[SPL], vu[SPL][NR];
-#pragma unroll
-                for (int k = 0; k < SPL; ++k) {
-                    const int slot = c0 + lane + 64 * k;
-                    vx[k] = vy[k] = T(0);
-#pragma unroll
-                    for (int q = 0; q < NR; ++q) vu[k][q] = T(0);
-                    if (slot < total) {
-                        int lo = 0, hi = nb - 1;           // last entry with s_off <= slot
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (s_off[mid] <= slot) lo = mid; else hi = mid - 1;
-                        }
-                        const int j = s_beg[lo] + (slot - s_off[lo]);
-                        vx[k] = t.xl[j] + s_ox[lo];
-                        vy[k] = t.yl[j] + s_oy[lo];
-#pragma unroll
-                        for (int q = 0; q < NR; ++q)
-                            if (q < nr) vu[k][q] = us[(r0 + q) * N + j];
-                    }
-                }
-                const int per = ((n + G - 1) / G + 3) & ~3;   // sources per group, multiple of 4
-#pragma unroll
-                for (int k = 0; k < SPL; ++k) {
-                    const int e = lane + 64 * k;
-                    if (e < per * G) {
-                        sx[e] = vx[k];
-                        sy[e] = vy[k];
-#pragma unroll
-                        for (int q = 0; q < NR; ++q) reinterpret_cast<T *>(su4[q])[e] = vu[k][q];
-                    }
-                }
-                for (int e = P2P_CHUNK + lane; e < per * G; e += 64) {
-                    sx[e] = T(0); sy[e] = T(0);
-#pragma unroll
-                    for (int q = 0; q < NR; ++q) reinterpret_cast<T *>(su4[q])[e] = T(0);
-                }
-                __syncthreads();
-                if (grp < G) {
-                    T part[R][NR];
-#pragma unroll
-                    for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-                        for (int q = 0; q < NR; ++q) part[rr][q] = T(0);
-                    const int q0 = grp * per / 4, q1 = q0 + per / 4;
-                    for (int qv = q0; qv < q1; ++qv) {
-                        const V4 X = sx4[qv], Y = sy4[qv];
-#pragma unroll
-                        for (int rr = 0; rr < R; ++rr) {
-                            T kv[4];
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) {
-                                const T dx = xi[rr] - X[k], dy = yi[rr] - Y[k];
-                                kv[k] = rsqrt_fast(fma(dx, dx, fma(dy, dy, c2)));
-                            }
-#pragma unroll
-                            for (int q = 0; q < NR; ++q) {
-                                const V4 U = su4[q][qv];
-#pragma unroll
-                                for (int k = 0; k < 4; ++k) part[rr][q] += U[k] * kv[k];
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-                        for (int q = 0; q < NR; ++q) acc[rr][q] += double(part[rr][q]);
-                }
-                __syncthreads();
-            }
-        }
-        // group sums in group order; group 0 writes
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                double aq = acc[rr][q];
-                for (int g = 1; g < G; ++g) aq += __shfl(acc[rr][q], ti + g * TP);
-                if (q < nr && grp == 0 && valid[rr]) {
-                    double &dst = bs[(r0 + q) * N + t0 + ti + rr * TP];
-                    dst = add ? dst + aq : aq;
-                }
-            }
-    }
-}
-
-template <typename T, bool SIDE, int NR>
-__global__ __launch_bounds__(64) void k_p2p(DTree<T> t, int nleaves, const T *__restrict__ us, int nrhs,
-                                            double *__restrict__ bs, int add)
-{
-    using V4 = typename Vec4<T>::type;
-    __shared__ V4 sx4[P2P_LDS / 4], sy4[P2P_LDS / 4], su4[NR][P2P_LDS / 4];
-    __shared__ int s_beg[64], s_off[65];
-    __shared__ T s_ox[64], s_oy[64];
-    // Leaves are dealt round robin (as the hardware deals workgroups to the
-    // XCDs): the kernel is ALU-bound, and giving each XCD a contiguous eighth of
-    // the Morton order for L2 locality unbalances clustered inputs (measured
-    // slower on the mixture workload).
-    for (int lf = blockIdx.x; lf < nleaves; lf += gridDim.x) {
-        const LeafRec lr = t.leafrec[lf];
-        const int b = lr.box;
-        const double cnd = t.cn[t.set[b]];
-        const T c2 = T(cnd * cnd);
-        const double bcx = t.cx[b], bcy = t.cy[b];
-        for (int t0 = lr.begin; t0 < lr.end; t0 += 128) {
-            const int ntc = min(128, lr.end - t0);
-            // targets per lane: the choice that keeps the most lanes busy
-            const int g1 = ntc <= 64 ? 64 / max(4, ntc) : 0;
-            const int g2 = 64 / max(4, (ntc + 1) / 2);
-            if (NR <= 4 && g2 * ntc > 2 * g1 * ntc)
-                p2p_block<T, NR, (NR <= 4 ? 2 : 1)>(t, b, t0, ntc, c2, bcx, bcy, us, nrhs, bs, add, sx4, sy4, su4,
-                                                      s_beg, s_off, s_ox, s_oy);
-            else if (ntc <= 64)
-                p2p_block<T, NR, 1>(t, b, t0, ntc, c2, bcx, bcy, us, nrhs, bs, add, sx4, sy4, su4, s_beg, s_off,
-                                    s_ox, s_oy);
-            else {           // 65..128 targets with 16 right-hand sides: two blocks of one per lane
-                p2p_block<T, NR, 1>(t, b, t0, 64, c2, bcx, bcy, us, nrhs, bs, add, sx4, sy4, su4, s_beg, s_off,
-                                    s_ox, s_oy);
-                p2p_block<T, NR, 1>(t, b, t0 + 64, ntc - 64, c2, bcx, bcy, us, nrhs, bs, add, sx4, sy4, su4,
-                                    s_beg, s_off, s_ox, s_oy);
-            }
-        }
-        __syncthreads();                         // LDS of this leaf no longer read
-    }
-}
-
-// Near-field launch: NR right-hand sides share each kernel value.
-template <typename T, bool SIDE>
-void launch_p2p(hipStream_t s, unsigned grid, const DTree<T> &v, int nleaves, const T *us, int nrhs, double *bs)
-{
-    if (nrhs == 1)
-        hipLaunchKernelGGL((k_p2p<T, SIDE, 1>), dim3(grid), dim3(64), 0, s, v, nleaves, us, nrhs, bs, 0);
-    else if (nrhs <= 4)
-        hipLaunchKernelGGL((k_p2p<T, SIDE, 4>), dim3(grid), dim3(64), 0, s, v, nleaves, us, nrhs, bs, 0);
-    else
-        hipLaunchKernelGGL((k_p2p<T, SIDE, 16>), dim3(grid), dim3(64), 0, s, v, nleaves, us, nrhs, bs, 0);
-}
-
 // M2P, one wave per (target leaf b, W-list box a) pair k: the multipole of
 // a evaluated at b's points,
 //     potential = (1/s_a) sum Re(Mt[n,m] eps_m c_{nm} I_n^m((x - z_a)/s_a)),
@@ -1032,10 +785,12 @@ DTree<T> make_view(const imq_tree_s *t)
     v.x_off = t->x_off.as<int32_t>(); v.x_idx = t->x_idx.as<int32_t>();
     v.Klev = t->Klev.as<int32_t>();
     v.leafrec = t->leafrec.as<LeafRec>();
+    v.nleaf = t->nleaf.as<NearLeaf>();
     v.cn = t->cn.as<double>();
     const PrecData &pd = prec_data<T>(const_cast<imq_tree_s *>(t));
     v.xl = pd.xl.as<T>();
     v.yl = pd.yl.as<T>();
+    v.urec = pd.urec.as<URec<T>>();
     return v;
 }
 
@@ -1100,7 +855,7 @@ imq_status fork_p2p(imq_tree_s *t, int nrhs, hipStream_t s)
     const int nleaves = int(t->h.leaves.size());
     const int wg = t->kcfg.p2p_wg > 0 ? t->kcfg.p2p_wg : 2048;
     launch_p2p<T, true>(t->side[0], unsigned(std::min(nleaves, wg)), make_view<T>(t), nleaves, pd.us.as<T>(),
-                        nrhs, t->bs.as<double>());
+                        nrhs, t->bs.as<double>(), t->kcfg.p2p_mode == 1);
     IMQ_HIP(hipGetLastError());
     IMQ_HIP(hipEventRecord(t->ev_join, t->side[0]));
     return IMQ_OK;
@@ -1293,7 +1048,7 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
     if (overlap) {
         IMQ_HIP(hipStreamWaitEvent(s, t->ev_join, 0));
     } else {
-        launch_p2p<T, false>(s, unsigned(nleaves), v, nleaves, pd.us.as<T>(), nrhs, bs);
+        launch_p2p<T, false>(s, unsigned(nleaves), v, nleaves, pd.us.as<T>(), nrhs, bs, t->kcfg.p2p_mode == 1);
         IMQ_HIP(hipGetLastError());
     }
     mark(t, 6, s);
