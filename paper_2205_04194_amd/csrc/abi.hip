@@ -97,14 +97,15 @@ static std::vector<URec<T>> u_records(const HostTree &h)
     return r;
 }
 
-// Per leaf, whether its FP32 near field may take the matrix-core form, whose
-// squared distances come from the expansion
-// |x_i - x_j|^2 = |x_i|^2 + |x_j|^2 - 2 x_i . x_j about the leaf's centre and
-// so carry about (1 + (|x_i|^2 + |x_j|^2) / c^2) units of rounding, against
-// about 2 for the direct differences.  A leaf qualifies when that ratio,
+// Per leaf, whether its near field may take the squared distances from the
+// expansion |x_i - x_j|^2 = |x_i|^2 + |x_j|^2 - 2 x_i . x_j about the leaf's
+// centre (one operation fewer per pair than the differences, and a rank-4
+// product for the matrix cores), which carries about
+// (1 + (|x_i|^2 + |x_j|^2) / c^2) units of rounding in |x_i - x_j|^2 + c^2,
+// against about 2 for the differences.  A leaf qualifies when that ratio,
 // bounded with the largest point radius of each leaf of its U list, is at
-// most NEAR_MF_RATIO (so at most about 3 units).
-constexpr double NEAR_MF_RATIO = 2.0;
+// most NEAR_EXPAND_RATIO (so at most about 3 units).
+constexpr double NEAR_EXPAND_RATIO = 2.0;
 
 static std::vector<NearLeaf> near_leaves(const HostTree &h)
 {
@@ -122,8 +123,8 @@ static std::vector<NearLeaf> near_leaves(const HostTree &h)
             far = std::max(far, std::hypot(h.cx[a] - h.cx[b], h.cy[a] - h.cy[b]) + rad[a]);
         }
         const double cn = h.cn[h.set[b]];
-        const int mf = (rad[b] * rad[b] + far * far) <= NEAR_MF_RATIO * cn * cn ? 1 : 0;
-        nl[l] = NearLeaf{h.begin[b], h.end[b], h.u_off[b], h.u_off[b + 1], cn * cn, mf, 0};
+        const int expand = (rad[b] * rad[b] + far * far) <= NEAR_EXPAND_RATIO * cn * cn ? 1 : 0;
+        nl[l] = NearLeaf{h.begin[b], h.end[b], h.u_off[b], h.u_off[b + 1], cn * cn, expand, 0};
     }
     return nl;
 }

@@ -36,11 +36,12 @@ struct alignas(16) URec {
 
 // One leaf as the near field reads it (one 32-byte load): its points
 // [begin, end), its U-list entries [u0, u1), c^2 of its set in the scaled
-// coordinates, and whether its FP32 sums may take the matrix-core form.
+// coordinates, and whether its squared distances may be taken from the
+// expansion about the leaf's centre (expand = 1).
 struct alignas(16) NearLeaf {
     int begin, end, u0, u1;
     double c2;
-    int mf, pad;
+    int expand, pad;
 };
 
 // Coefficient count of the translations at every level, by value.

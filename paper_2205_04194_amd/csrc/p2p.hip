@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace imq {
 
@@ -47,8 +48,9 @@ struct alignas(16) SRec {
 // keeps its small footprint and its occupancy).
 template <typename T, int NR, bool MF>
 struct alignas(32) P2PStage {                  // every array starts on a 32-byte boundary
-    // vector form: the chunk's sources, read back four at a time
-    T x[P2P_LDS], y[P2P_LDS], u[NR][P2P_LDS];
+    // vector form: the chunk's sources (and |x|^2 for the expanded
+    // distances), read back four at a time
+    T x[P2P_LDS], y[P2P_LDS], w[P2P_LDS], u[NR][P2P_LDS];
     // matrix-core form (FP32, one right-hand side): per source |x|^2, x, y and
     // a row of zeros (written once), and the weights
     float B[MF ? 4 : 1][MF ? P2P_MF_LD : 4];
@@ -139,7 +141,10 @@ __device__ __forceinline__ void p2p_sources(const DTree<T> &t, int u0, int u1, c
 // step, in a loop whose trip count is the same for every lane.  Partial sums
 // over one chunk are kept in T, the running sums in FP64, and the G group sums
 // of a target are added with lane shuffles in group order.
-template <typename T, int NR, int R, bool MF>
+// EXP: the squared distance plus c^2 as (|x_i|^2 + c^2 + |x_j|^2) - 2 x_i . x_j
+// (one add and two fused multiply-adds instead of two subtractions and two
+// fused multiply-adds), for leaves whose neighbourhood is small against c.
+template <typename T, int NR, int R, bool MF, bool EXP>
 __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl, int t0, int ntc,
                                           const T *__restrict__ us, int nrhs, double *__restrict__ bs, int add,
                                           P2PStage<T, NR, MF> &sh)
@@ -151,13 +156,18 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
     const int TP = max(4, (ntc + R - 1) / R);
     const int G = 64 / TP, grp = lane / TP, ti = lane % TP;
     bool valid[R];
-    T xi[R], yi[R];
+    T xi[R], yi[R], ai[R];
 #pragma unroll
     for (int rr = 0; rr < R; ++rr) {
         valid[rr] = grp < G && ti + rr * TP < ntc;
         const int i = t0 + (valid[rr] ? ti + rr * TP : 0);
         xi[rr] = t.xl[i];
         yi[rr] = t.yl[i];
+        if constexpr (EXP) {
+            ai[rr] = fma(xi[rr], xi[rr], fma(yi[rr], yi[rr], c2));
+            xi[rr] *= T(-2);
+            yi[rr] *= T(-2);
+        }
     }
     for (int r0 = 0; r0 < nrhs; r0 += NR) {          // NR right-hand sides per pass
         const int nr = min(NR, nrhs - r0);
@@ -169,6 +179,7 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
         auto store = [&](int e, T x, T y, const T (&u)[NR]) {
             sh.x[e] = x;
             sh.y[e] = y;
+            if constexpr (EXP) sh.w[e] = fma(x, x, y * y);
 #pragma unroll
             for (int q = 0; q < NR; ++q) sh.u[q][e] = u[q];
         };
@@ -177,6 +188,7 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
             for (int e = P2P_CHUNK / 4 + lane; e < per * G / 4; e += 64) {
                 reinterpret_cast<V4 *>(sh.x)[e] = V4{T(0), T(0), T(0), T(0)};
                 reinterpret_cast<V4 *>(sh.y)[e] = V4{T(0), T(0), T(0), T(0)};
+                if constexpr (EXP) reinterpret_cast<V4 *>(sh.w)[e] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
                 for (int q = 0; q < NR; ++q) reinterpret_cast<V4 *>(sh.u[q])[e] = V4{T(0), T(0), T(0), T(0)};
             }
@@ -190,15 +202,22 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
                 const int nq = __builtin_amdgcn_readfirstlane(per >> 2);   // the same in every lane
                 const V4 *px = reinterpret_cast<const V4 *>(sh.x) + grp * nq;
                 const V4 *py = reinterpret_cast<const V4 *>(sh.y) + grp * nq;
+                const V4 *pw = reinterpret_cast<const V4 *>(sh.w) + grp * nq;
                 for (int it = 0; it < nq; ++it) {
                     const V4 X = px[it], Y = py[it];
+                    V4 W;
+                    if constexpr (EXP) W = pw[it];
 #pragma unroll
                     for (int rr = 0; rr < R; ++rr) {
                         T kv[4];
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            const T dx = xi[rr] - X[k], dy = yi[rr] - Y[k];
-                            kv[k] = rsqrt_fast(fma(dx, dx, fma(dy, dy, c2)));
+                            if constexpr (EXP) {
+                                kv[k] = rsqrt_fast(fma(xi[rr], X[k], fma(yi[rr], Y[k], ai[rr] + W[k])));
+                            } else {
+                                const T dx = xi[rr] - X[k], dy = yi[rr] - Y[k];
+                                kv[k] = rsqrt_fast(fma(dx, dx, fma(dy, dy, c2)));
+                            }
                         }
 #pragma unroll
                         for (int q = 0; q < NR; ++q) {
@@ -355,7 +374,7 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, int nleaves, const T *__
     for (int lf = blockIdx.x; lf < nleaves; lf += gridDim.x) {
         const NearLeaf nl = t.nleaf[lf];
         if constexpr (MF) {
-            if (nl.mf) {
+            if (nl.expand) {
                 for (int t0 = nl.begin; t0 < nl.end; t0 += 64) {
                     const int ntc = min(64, nl.end - t0);
                     switch ((ntc + 15) >> 4) {
@@ -368,20 +387,27 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, int nleaves, const T *__
                 continue;
             }
         }
-        for (int t0 = nl.begin; t0 < nl.end; t0 += 128) {
-            const int ntc = min(128, nl.end - t0);
-            // targets per lane: the choice that keeps the most lanes busy
-            const int g1 = ntc <= 64 ? 64 / max(4, ntc) : 0;
-            const int g2 = 64 / max(4, (ntc + 1) / 2);
-            if (NR <= 4 && g2 * ntc > 2 * g1 * ntc)
-                p2p_block<T, NR, (NR <= 4 ? 2 : 1), MF>(t, nl, t0, ntc, us, nrhs, bs, add, sh);
-            else if (ntc <= 64)
-                p2p_block<T, NR, 1, MF>(t, nl, t0, ntc, us, nrhs, bs, add, sh);
-            else {           // 65..128 targets with 16 right-hand sides: two blocks of one per lane
-                p2p_block<T, NR, 1, MF>(t, nl, t0, 64, us, nrhs, bs, add, sh);
-                p2p_block<T, NR, 1, MF>(t, nl, t0 + 64, ntc - 64, us, nrhs, bs, add, sh);
+        auto blocks = [&](auto exp) {
+            constexpr bool E = decltype(exp)::value;
+            for (int t0 = nl.begin; t0 < nl.end; t0 += 128) {
+                const int ntc = min(128, nl.end - t0);
+                // targets per lane: the choice that keeps the most lanes busy
+                const int g1 = ntc <= 64 ? 64 / max(4, ntc) : 0;
+                const int g2 = 64 / max(4, (ntc + 1) / 2);
+                if (NR <= 4 && g2 * ntc > 2 * g1 * ntc)
+                    p2p_block<T, NR, (NR <= 4 ? 2 : 1), MF, E>(t, nl, t0, ntc, us, nrhs, bs, add, sh);
+                else if (ntc <= 64)
+                    p2p_block<T, NR, 1, MF, E>(t, nl, t0, ntc, us, nrhs, bs, add, sh);
+                else {       // 65..128 targets with 16 right-hand sides: two blocks of one per lane
+                    p2p_block<T, NR, 1, MF, E>(t, nl, t0, 64, us, nrhs, bs, add, sh);
+                    p2p_block<T, NR, 1, MF, E>(t, nl, t0 + 64, ntc - 64, us, nrhs, bs, add, sh);
+                }
             }
-        }
+        };
+        if (nl.expand)
+            blocks(std::true_type{});
+        else
+            blocks(std::false_type{});
     }
 }
 
