@@ -55,20 +55,36 @@ struct alignas(32) P2PStage {                  // every array starts on a 32-byt
     // a row of zeros (written once), and the weights
     float B[MF ? 4 : 1][MF ? P2P_MF_LD : 4];
     float U[MF ? P2P_CHUNK : 4];
-    // staging: per entry of the batch its first slot (and the total after
-    // the last), the offset from slot number to point index and the centre
-    // offset
-    int off[65];
+    // staging: 1 + the entry that starts at each slot of the chunk (else 0),
+    // and per entry of the batch the offset from slot number to point index
+    // and the centre offset
+    int mk[P2P_CHUNK];
     SRec<T> rec[64];
 };
+
+// Inclusive running maximum over the 64 lanes of a wave (values >= 0): a
+// Hillis-Steele scan inside each row of 16 lanes (row shifts by 1, 2, 4, 8),
+// then the last lane of rows 0 and 2 into rows 1 and 3, then lane 31 into
+// rows 2 and 3 (row broadcasts).  Lanes with no source lane keep 0.
+__device__ __forceinline__ int wave_max_scan(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return v;
+}
 
 // The sources of a target leaf (U-list entries [u0, u1)), staged a chunk of
 // up to 256 at a time.  The entry records are read 64 at a time, one per
 // lane, and a wave prefix sum numbers the batch's sources consecutively.
 // Lane l gathers slots l, l + 64, l + 128, l + 192 of a chunk (each load of
-// the wave covers consecutive points), finding a slot's entry by binary
-// search over the entries' first slots in LDS, with every load of the chunk
-// in flight at once.  store(e, x, y, u) puts the source of chunk slot e into
+// the wave covers consecutive points), with every load of the chunk in flight
+// at once.  A slot's entry comes from marking each entry's first slot in LDS
+// and a running maximum over the slots (across the wave for each group of
+// 64 slots, carried from group to group).  store(e, x, y, u) puts the source of chunk slot e into
 // the stage (coordinates relative to the target leaf's centre, zero past the
 // chunk's n sources); consume(n) then runs once per chunk, in source order.
 template <typename T, int NR, bool MF, typename S, typename F>
@@ -91,12 +107,21 @@ __device__ __forceinline__ void p2p_sources(const DTree<T> &t, int u0, int u1, c
         const int total = __shfl(incl, 63);
         const int off = incl - ur.cnt;               // first slot of this lane's entry
         __syncthreads();                             // previous batch's records no longer read
-        sh.off[lane] = off;
         sh.rec[lane] = SRec<T>{ur.beg - off, ur.ox, ur.oy};
-        if (lane == 0) sh.off[64] = total;
-        __syncthreads();
+        int carry = 0;                               // 1 + entry of the slot before the group
         for (int c0 = 0; c0 < total; c0 += P2P_CHUNK) {
             const int n = min(P2P_CHUNK, total - c0);
+            *reinterpret_cast<int4 *>(&sh.mk[4 * lane]) = make_int4(0, 0, 0, 0);
+            __syncthreads();
+            if (ur.cnt > 0 && off >= c0 && off < c0 + P2P_CHUNK) sh.mk[off - c0] = lane + 1;
+            __syncthreads();
+            int ent[SPL];
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) {
+                const int m = max(wave_max_scan(sh.mk[lane + 64 * k]), carry);
+                carry = __builtin_amdgcn_readlane(m, 63);
+                ent[k] = max(m - 1, 0);
+            }
             T vx[SPL], vy[SPL], vu[SPL][NR];
 #pragma unroll
             for (int k = 0; k < SPL; ++k) {
@@ -105,12 +130,7 @@ __device__ __forceinline__ void p2p_sources(const DTree<T> &t, int u0, int u1, c
 #pragma unroll
                 for (int q = 0; q < NR; ++q) vu[k][q] = T(0);
                 if (sl < total) {
-                    int lo = 0, hi = nb - 1;         // last entry with off <= sl
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (sh.off[mid] <= sl) lo = mid; else hi = mid - 1;
-                    }
-                    const SRec<T> rc = sh.rec[lo];
+                    const SRec<T> rc = sh.rec[ent[k]];
                     const int j = sl + rc.jo;
                     vx[k] = t.xl[j] + rc.ox;
                     vy[k] = t.yl[j] + rc.oy;
