@@ -33,8 +33,11 @@ namespace {
 // For class k the source expansions of class k+1 and, row block by row
 // block as soon as each is consumed, the table of class k+1 are requested
 // while the matrix cores work on class k; the source indices run one class
-// further ahead.  Register use: NRB*NRB + 2*NCB*NRB four-value quads.
-template <typename T, int NRB, int NCB, int NW>
+// further ahead.  blockIdx.z picks the RBW output row blocks (of NRB) that the
+// workgroup computes: small levels spread over NRB / RBW times more
+// workgroups, each reading only its rows of every table.  Register use:
+// RBW*NRB + 2*NCB*NRB four-value quads.
+template <typename T, int NRB, int NCB, int NW, int RBW>
 __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restrict__ tasks, int task0,
                                                     const int32_t *__restrict__ tbox,
                                                     const int32_t *__restrict__ tab,
@@ -42,8 +45,9 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
                                                     int nrbT, int nrhs, int KS, const T *__restrict__ in,
                                                     T *__restrict__ out)
 {
+    static_assert(NRB % RBW == 0, "whole row-block groups");
     constexpr int TC = 16 * NCB;
-    constexpr int LDR = NRB * 16 + 1;
+    constexpr int LDR = RBW * 16 + 1;
     using acc_t = typename Mfma<T>::acc_t;
     using Q = Quad<T>;
     constexpr int SPW = (GEMM_MAXSLOT + NW - 1) / NW;  // classes per wave
@@ -57,6 +61,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int i16 = lane & 15, q = lane >> 4;
     const int kin = tk.kin, kout = tk.kout;
+    const int rb0 = blockIdx.z * RBW;                // first output row block of the workgroup
+    if (rb0 * 16 >= kout) return;                    // uniform over the workgroup
     const int nslot = tk.nslot;
     if (tid < TC) {
         const int gc = col0 + tid;
@@ -102,18 +108,19 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
     };
     auto table = [&](int k) -> const T * {
         const int sl = w + NW * k;
-        return (k < SPW && sl < nslot) ? Apk + size_t(tab[tk.tab0 + sl]) * nrbT * nrbT * 256 + lane * 4 : nullptr;
+        return (k < SPW && sl < nslot) ? Apk + (size_t(tab[tk.tab0 + sl]) * nrbT + rb0) * nrbT * 256 + lane * 4
+                                       : nullptr;
     };
 
-    acc_t acc[NRB][NCB];
+    acc_t acc[RBW][NCB];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb)
+    for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[rb][cb][v] = T(0);
 
-    Q a[NRB][NRB];
+    Q a[RBW][NRB];
     Q bc[NCB][NRB], bn[NCB][NRB];
     int sbc[NCB], sbn[NCB], sbnn[NCB];
     source(0, sbc);
@@ -121,7 +128,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
     const T *Ac = table(0);
     if (Ac)
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb)
+        for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
             for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = *reinterpret_cast<const Q *>(Ac + (rb * nrbT + ci) * 256);
     load_b(sbc, bc);
@@ -131,7 +138,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
         load_b(sbn, bn);
         source(k + 2, sbnn);
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) {
+        for (int rb = 0; rb < RBW; ++rb) {
             if (act)
 #pragma unroll
                 for (int ci = 0; ci < NRB; ++ci)
@@ -157,19 +164,20 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb)
+        for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 red[(w * TC + cb * 16 + i16) * LDR + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
     __syncthreads();
-    for (int e = tid; e < TC * kout; e += 64 * NW) {
-        const int c = e / kout, kk = e - c * kout;
+    const int nk = min(kout - rb0 * 16, RBW * 16);   // output rows of the workgroup
+    for (int e = tid; e < TC * nk; e += 64 * NW) {
+        const int c = e / nk, kk = e - c * nk;
         const int o = s_out[c];
         if (o < 0) continue;
         T sum = red[c * LDR + kk];
 #pragma unroll
         for (int ww = 1; ww < NW; ++ww) sum += red[(ww * TC + c) * LDR + kk];
-        out[size_t(o) * KS + kk] = sum;
+        out[size_t(o) * KS + rb0 * 16 + kk] = sum;
     }
 }
 
@@ -201,10 +209,18 @@ bool launch_m2l_stream(hipStream_t s, int kmax, int ntask, int task0, int nrhs, 
     // 4 waves per workgroup everywhere: 8 (a class chain half as long) was
     // measured slower on the mixture workload, in particular beside the near
     // field, whose small workgroups leave few CUs with 8 wave slots free
+    // Levels too small to give every CU a few workgroups split the output rows
+    // (one row block per workgroup).
 #define IMQ_M2LS(NRB, NCB, NW)                                                                             \
-    hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW>),                                                    \
-                       dim3(ntask, unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB))), dim3(64 * NW), 0, s, \
-                       tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out)
+    do {                                                                                                   \
+        const unsigned ny = unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB));                      \
+        if (NRB > 1 && size_t(ntask) * ny < 512)                                                           \
+            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, 1>), dim3(ntask, ny, NRB), dim3(64 * NW), 0, s, \
+                               tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out);             \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, NRB>), dim3(ntask, ny, 1), dim3(64 * NW), 0, s, \
+                               tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out);             \
+    } while (0)
     if constexpr (sizeof(T) == 4) {
         switch (nrb) {
         case 1: IMQ_M2LS(1, 2, 4); return true;
