@@ -265,6 +265,8 @@ static void free_tree(imq_tree_s *t)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : t->ev_tjoin)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : t->ev_grp)
+        if (e) (void)hipEventDestroy(e);
     delete t;
 }
 

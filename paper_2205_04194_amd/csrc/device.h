@@ -115,10 +115,11 @@ void launch_p2p(hipStream_t s, unsigned grid, const DTree<T> &v, int nleaves, co
 void pack_m2l_tables(const std::vector<double> &tabs, int KP, std::vector<double> &packed);
 
 // Expansion-to-local translations of tasks [task0, task0 + ntask), operands
-// streamed through registers class by class; for coefficient counts up to
-// kmax <= 80 (FP32) or 64 (FP64), else launches nothing and returns false.
+// streamed through registers class by class (acc: added to out, else stored);
+// for coefficient counts up to kmax <= 80 (FP32) or 64 (FP64), else launches
+// nothing and returns false.
 template <typename T>
-bool launch_m2l_stream(hipStream_t s, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
+bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
                        const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk, int KP, int KS,
                        const T *in, T *out);
 
@@ -189,7 +190,9 @@ struct imq_tree_s {
     hipStream_t side[NSIDE] = {};
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;          // near field
     hipEvent_t ev_tfork = nullptr, ev_tjoin[NSIDE] = {};      // translations
-    hipEvent_t ev_start = nullptr, ev_prep = nullptr;         // gathered weights; L cleared + X pairs
+    hipEvent_t ev_start = nullptr, ev_prep = nullptr;         // gathered weights; L cleared + X lists added
+    static constexpr int NGROUP_EV = 32;                      // M2L level groups done (the L2L chain waits)
+    hipEvent_t ev_grp[NGROUP_EV] = {};
     imq_status ensure_side();
     // solver workspace
     imq::DevBuf sol;

@@ -834,6 +834,7 @@ imq_status imq_tree_s::ensure_side()
     for (hipEvent_t *e : {&ev_fork, &ev_join, &ev_tfork, &ev_start, &ev_prep})
         IMQ_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     for (hipEvent_t &e : ev_tjoin) IMQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (hipEvent_t &e : ev_grp) IMQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return IMQ_OK;
 }
 
@@ -936,18 +937,24 @@ imq_status prep_locals(imq_tree_s *t, int nrhs, hipStream_t s)
     const int K = h.K, KS = coef_stride(K), ld = K | 1;
     const size_t nL = size_t(h.level.size()) * nrhs * KS;
     hipLaunchKernelGGL(k_fill<T>, dim3(unsigned((nL + 255) / 256)), dim3(256), 0, s, nL, pd.L.as<T>(), T(0));
-    if (t->nxpairs > 0)
+    if (t->nxpairs > 0) {
         hipLaunchKernelGGL(k_p2l_pairs<T>, dim3(t->nxpairs), dim3(64), (size_t(64) * ld + 64) * sizeof(T), s,
                            make_view<T>(t), t->x_tgt.as<int32_t>(), pd.us.as<T>(), nrhs, pd.wx.as<T>(),
                            pd.Lx.as<T>(), ld, t->nxpairs);
+        hipLaunchKernelGGL(k_p2l_reduce<T>, dim3(t->nxboxes), dim3(64), 0, s, make_view<T>(t),
+                           t->x_boxes.as<int32_t>(), nrhs, pd.Lx.as<T>(), t->nxpairs, pd.L.as<T>());
+    }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
 }
 
-// Translations and downward pass into L (stages M2L, P2L, L2L).  overlap: L
-// was cleared and the X pairs formed on side[1] (ev_prep); the M2L level
-// groups run on the caller's stream and side[1..], the W-list pair
-// evaluations (M2P, which need only M) on side[2] ahead of its M2L group.
+// Translations and downward pass into L (stages M2L, L2L; the X lists were
+// added into the cleared L by prep_locals, so every M2L launch adds).
+// overlap: the prep ran on side[1] (ev_prep); the M2L level groups run on
+// side[1] and side[2], the W-list pair evaluations (M2P, which need only M)
+// on side[2] ahead of its groups, and the L2L chain on the caller's stream
+// starts as soon as the groups of the levels it reaches are done, beside the
+// (larger) groups of the deeper levels.
 template <typename T>
 imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
 {
@@ -968,13 +975,14 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
         if (t->nwpairs > 0)
             hipLaunchKernelGGL(k_m2p_pairs<T>, dim3(t->nwpairs), dim3(64), 0, t->side[2], v, t->w_tgt.as<int32_t>(),
                                t->w_scr.as<int32_t>(), M, pd.wx.as<T>(), nrhs, t->Pw.as<double>(), t->nwscr);
-        IMQ_HIP(hipStreamWaitEvent(s, t->ev_prep, 0));              // L cleared
+        IMQ_HIP(hipStreamWaitEvent(s, t->ev_prep, 0));              // L cleared, X lists added
         IMQ_HIP(hipStreamWaitEvent(t->side[2], t->ev_prep, 0));
     }
+    // Per level: the register-streaming kernel (mode 0, up to 80 coefficients
+    // in FP32 and 64 in FP64) or the staged GEMM; consecutive levels of one
+    // kind and row-block count share a launch (a group).
+    std::vector<int> group_of(h.nlev, -1);
     {
-        // Per level: the register-streaming kernel (mode 0, up to 80 coefficients
-        // in FP32 and 64 in FP64) or the staged GEMM; consecutive levels of one
-        // kind and row-block count share a launch.
         const DevGemm &g = t->g_m2l;
         const int smax = sizeof(T) == 4 ? 5 : 4;
         const auto kind = [&](int l) {
@@ -985,8 +993,8 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
         for (int l = 0; l < h.nlev;) {
             const int t0 = g.level_task_begin[l];
             if (g.level_task_begin[l + 1] == t0) { ++l; continue; }
-            const int si = overlap ? ngroup++ % imq_tree_s::NSIDE : 0;     // 0: the caller's stream
-            hipStream_t gs = si == 0 ? s : t->side[si];
+            const bool own_ev = overlap && ngroup < imq_tree_s::NGROUP_EV;
+            hipStream_t gs = own_ev ? t->side[1 + ngroup % (imq_tree_s::NSIDE - 1)] : s;
             const int k = kind(l);
             int l2 = l + 1, kmax = h.Klev[l];
             while (l2 < h.nlev && (g.level_task_begin[l2 + 1] == g.level_task_begin[l2] || kind(l2) == k)) {
@@ -996,31 +1004,42 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
             const int nt = g.level_task_begin[l2] - t0;
             bool done = false;
             if (k > 0)
-                done = launch_m2l_stream<T>(gs, kmax, nt, t0, nrhs, g.tasks.as<GemmTask>(), g.tbox.as<int32_t>(),
+                done = launch_m2l_stream<T>(gs, 1, kmax, nt, t0, nrhs, g.tasks.as<GemmTask>(), g.tbox.as<int32_t>(),
                                             g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.m2l_pk.as<T>(), KP, KS, M, L);
             if (!done)
                 launch_gemm<T>(gs, kc.m2l_kc > 0 ? kc.m2l_kc : 32, kc.m2l_split > 0 ? kc.m2l_split : 1, nt, nrhs,
                                g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),
-                               g.src.as<int32_t>(), pd.m2l.as<T>(), KP, KS, M, L, 0, 0, 0);
+                               g.src.as<int32_t>(), pd.m2l.as<T>(), KP, KS, M, L, 1, 0, 0);
+            if (own_ev) {
+                IMQ_HIP(hipEventRecord(t->ev_grp[ngroup], gs));
+                for (int ll = l; ll < l2; ++ll) group_of[ll] = ngroup;
+            }
+            ++ngroup;
             l = l2;
         }
-        if (overlap)
-            for (int i = 1; i < imq_tree_s::NSIDE; ++i) {
-                IMQ_HIP(hipEventRecord(t->ev_tjoin[i], t->side[i]));
-                IMQ_HIP(hipStreamWaitEvent(s, t->ev_tjoin[i], 0));
-            }
     }
     IMQ_HIP(hipGetLastError());
     mark(t, 4, s);
-    if (t->nxpairs > 0)
-        hipLaunchKernelGGL(k_p2l_reduce<T>, dim3(t->nxboxes), dim3(64), 0, s, v, t->x_boxes.as<int32_t>(),
-                           nrhs, pd.Lx.as<T>(), t->nxpairs, L);
+    int waited = -1;                                               // groups are waited for in order
+    auto wait_level = [&](int l) -> imq_status {
+        if (l < h.nlev && group_of[l] > waited) {
+            for (int gi = waited + 1; gi <= group_of[l]; ++gi) IMQ_HIP(hipStreamWaitEvent(s, t->ev_grp[gi], 0));
+            waited = group_of[l];
+        }
+        return IMQ_OK;
+    };
     for (int l = std::max(h.need_l, 0); l + 1 < h.nlev; ++l) {      // parents at level l
+        if ((st = wait_level(l)) != IMQ_OK || (st = wait_level(l + 1)) != IMQ_OK) return st;
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
         launch_shift<T>(s, false, kc.shift_cols, np, nrhs, t->sh_par.as<int32_t>() + p0,
                         t->sh_kids.as<int32_t>() + 4 * size_t(p0), pd.l2l.as<T>(), KP, h.Klev[l], h.Klev[l + 1],
                         t->cut_l2l, L, KS, L, KS);
     }
+    if (overlap)
+        for (int i = 1; i < imq_tree_s::NSIDE; ++i) {
+            IMQ_HIP(hipEventRecord(t->ev_tjoin[i], t->side[i]));
+            IMQ_HIP(hipStreamWaitEvent(s, t->ev_tjoin[i], 0));
+        }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
 }

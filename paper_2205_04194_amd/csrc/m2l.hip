@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
                                                     const int32_t *__restrict__ tab,
                                                     const int32_t *__restrict__ src, const T *__restrict__ Apk,
                                                     int nrbT, int nrhs, int KS, const T *__restrict__ in,
-                                                    T *__restrict__ out)
+                                                    T *__restrict__ out, int add)
 {
     static_assert(NRB % RBW == 0, "whole row-block groups");
     constexpr int TC = 16 * NCB;
@@ -177,7 +177,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
         T sum = red[c * LDR + kk];
 #pragma unroll
         for (int ww = 1; ww < NW; ++ww) sum += red[(ww * TC + c) * LDR + kk];
-        out[size_t(o) * KS + rb0 * 16 + kk] = sum;
+        T &dst = out[size_t(o) * KS + rb0 * 16 + kk];
+        dst = add ? dst + sum : sum;
     }
 }
 
@@ -200,7 +201,7 @@ void pack_m2l_tables(const std::vector<double> &tabs, int KP, std::vector<double
 
 
 template <typename T>
-bool launch_m2l_stream(hipStream_t s, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
+bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
                        const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk, int KP, int KS,
                        const T *in, T *out)
 {
@@ -216,10 +217,10 @@ bool launch_m2l_stream(hipStream_t s, int kmax, int ntask, int task0, int nrhs, 
         const unsigned ny = unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB));                      \
         if (NRB > 1 && size_t(ntask) * ny < 512)                                                           \
             hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, 1>), dim3(ntask, ny, NRB), dim3(64 * NW), 0, s, \
-                               tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out);             \
+                               tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out, acc);             \
         else                                                                                               \
             hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, NRB>), dim3(ntask, ny, 1), dim3(64 * NW), 0, s, \
-                               tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out);             \
+                               tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out, acc);             \
     } while (0)
     if constexpr (sizeof(T) == 4) {
         switch (nrb) {
@@ -242,10 +243,10 @@ bool launch_m2l_stream(hipStream_t s, int kmax, int ntask, int task0, int nrhs, 
 #undef IMQ_M2LS
 }
 
-template bool launch_m2l_stream<float>(hipStream_t, int, int, int, int, const GemmTask *, const int32_t *,
+template bool launch_m2l_stream<float>(hipStream_t, int, int, int, int, int, const GemmTask *, const int32_t *,
                                        const int32_t *, const int32_t *, const float *, int, int, const float *,
                                        float *);
-template bool launch_m2l_stream<double>(hipStream_t, int, int, int, int, const GemmTask *, const int32_t *,
+template bool launch_m2l_stream<double>(hipStream_t, int, int, int, int, int, const GemmTask *, const int32_t *,
                                         const int32_t *, const int32_t *, const double *, int, int, const double *,
                                         double *);
 
