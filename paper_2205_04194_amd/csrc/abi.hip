@@ -97,34 +97,14 @@ static std::vector<URec<T>> u_records(const HostTree &h)
     return r;
 }
 
-// Per leaf, whether its near field may take the squared distances from the
-// expansion |x_i - x_j|^2 = |x_i|^2 + |x_j|^2 - 2 x_i . x_j about the leaf's
-// centre (one operation fewer per pair than the differences, and a rank-4
-// product for the matrix cores), which carries about
-// (1 + (|x_i|^2 + |x_j|^2) / c^2) units of rounding in |x_i - x_j|^2 + c^2,
-// against about 2 for the differences.  A leaf qualifies when that ratio,
-// bounded with the largest point radius of each leaf of its U list, is at
-// most NEAR_EXPAND_RATIO (so at most about 3 units).
-constexpr double NEAR_EXPAND_RATIO = 2.0;
-
+// The near field's per-leaf records (the expansion flag comes from the host tree).
 static std::vector<NearLeaf> near_leaves(const HostTree &h)
 {
-    const int nbox = int(h.level.size());
-    std::vector<double> rad(nbox, 0.0);           // largest distance of a point from its leaf's centre
-    for (int b : h.leaves)
-        for (int i = h.begin[b]; i < h.end[b]; ++i)
-            rad[b] = std::max(rad[b], std::sqrt(h.xl[i] * h.xl[i] + h.yl[i] * h.yl[i]));
     std::vector<NearLeaf> nl(h.leaves.size());
     for (size_t l = 0; l < h.leaves.size(); ++l) {
         const int b = h.leaves[l];
-        double far = 0.0;
-        for (int k = h.u_off[b]; k < h.u_off[b + 1]; ++k) {
-            const int a = h.u_idx[k];
-            far = std::max(far, std::hypot(h.cx[a] - h.cx[b], h.cy[a] - h.cy[b]) + rad[a]);
-        }
         const double cn = h.cn[h.set[b]];
-        const int expand = (rad[b] * rad[b] + far * far) <= NEAR_EXPAND_RATIO * cn * cn ? 1 : 0;
-        nl[l] = NearLeaf{h.begin[b], h.end[b], h.u_off[b], h.u_off[b + 1], cn * cn, expand, 0};
+        nl[l] = NearLeaf{h.begin[b], h.end[b], h.u_off[b], h.u_off[b + 1], cn * cn, h.near_expand[l], 0};
     }
     return nl;
 }
@@ -500,7 +480,7 @@ static const void *field(const HostTree &h, const char *w, int64_t &n, int &elem
     F(perm) F(xl) F(yl) F(level) F(set) F(ix) F(iy) F(parent) F(child0) F(nchild) F(pos) F(begin)
     F(end) F(isleaf) F(cx) F(cy) F(level_begin) F(leaves) F(u_off) F(u_idx) F(v_off) F(v_idx)
     F(v_cls) F(w_off) F(w_idx) F(x_off) F(x_idx) F(Klev) F(side) F(cn) F(sh_par) F(sh_kids)
-    F(sh_level_begin)
+    F(sh_level_begin) F(near_expand)
 #undef F
     n = -1;
     elem = 0;

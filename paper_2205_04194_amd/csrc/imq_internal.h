@@ -120,6 +120,9 @@ struct HostTree {
     std::vector<int32_t> v_off, v_idx, v_cls; // same-level translations
     std::vector<int32_t> w_off, w_idx;       // multipole -> target points (leaves)
     std::vector<int32_t> x_off, x_idx;       // source points -> local
+    // per leaf (leaf-list order): 1 if its near field may form the squared
+    // distances from the expansion about the leaf's centre (see tree.cpp)
+    std::vector<int32_t> near_expand;
 
     // expansion-to-local batches (targets = boxes with a V list); tables are
     // indexed (set*nlev + level)*NCLASS + class

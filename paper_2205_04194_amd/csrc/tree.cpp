@@ -84,6 +84,37 @@ struct Builder {
 };
 }  // namespace
 
+// Per leaf, whether its near field may take the squared distances from the
+// expansion |x_i - x_j|^2 = |x_i|^2 + |x_j|^2 - 2 x_i . x_j about the leaf's
+// centre (one operation fewer per pair than the differences, and a rank-4
+// product for the matrix cores).  In |x_i - x_j|^2 + c^2 the expansion
+// carries about (1 + (|x_i|^2 + |x_j|^2) / c^2) units of rounding against
+// about 2 for the differences.  A leaf qualifies when that ratio, bounded with
+// the largest point radius r of each leaf of its U list
+// (r_b^2 + max_a (|c_a - c_b| + r_a)^2 <= NEAR_EXPAND_RATIO c^2), is at most
+// NEAR_EXPAND_RATIO, so at most about 3 units.
+static constexpr double NEAR_EXPAND_RATIO = 2.0;
+
+static void near_expansion_flags(HostTree &h)
+{
+    const int nbox = int(h.level.size());
+    std::vector<double> rad(nbox, 0.0);
+    for (int b : h.leaves)
+        for (int i = h.begin[b]; i < h.end[b]; ++i)
+            rad[b] = std::max(rad[b], std::sqrt(h.xl[i] * h.xl[i] + h.yl[i] * h.yl[i]));
+    h.near_expand.assign(h.leaves.size(), 0);
+    for (size_t l = 0; l < h.leaves.size(); ++l) {
+        const int b = h.leaves[l];
+        double far = 0.0;
+        for (int k = h.u_off[b]; k < h.u_off[b + 1]; ++k) {
+            const int a = h.u_idx[k];
+            far = std::max(far, std::hypot(h.cx[a] - h.cx[b], h.cy[a] - h.cy[b]) + rad[a]);
+        }
+        const double cn = h.cn[h.set[b]];
+        h.near_expand[l] = (rad[b] * rad[b] + far * far) <= NEAR_EXPAND_RATIO * cn * cn ? 1 : 0;
+    }
+}
+
 imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const double *y,
                            const double *c, const imq_tree_params &prm, HostTree &t)
 {
@@ -326,6 +357,7 @@ imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const
     flatten(X, t.x_off, t.x_idx);
 
     build_gemm_lists(t);
+    near_expansion_flags(t);
 
     auto npts = [&](int b) { return int64_t(t.end[b] - t.begin[b]); };
     for (int b = 0; b < nbox; ++b) {

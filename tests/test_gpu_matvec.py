@@ -194,3 +194,29 @@ def test_batched_right_hand_sides_match_single_products(imq, nrhs):
         assert _rel(B64[r], single) < 1e-12
         assert _rel(B64[r], ref[k]) < 1e-6
         assert _rel(B32[r], ref[k]) < 1e-5
+
+
+@pytest.mark.parametrize("c", [0.03, 0.3])
+def test_near_field_forms_match_the_oracle(imq, c):
+    """The near field takes, per leaf, direct differences or the expansion of
+    the squared distance about the leaf's centre (where its rounding bound
+    allows), on the vector unit (default) or, with p2p_mode = 1 in FP32 and one
+    right-hand side, as a rank-4 matrix-core product.  Both kernels must give
+    the product to the FP32 target and agree with each other to rounding; the
+    mixture at c = 0.03 has leaves of both kinds, at c = 0.3 nearly all expand."""
+    n = 20000
+    g = W.rng(92, 3)
+    xy = W.mixture_points(n, W.rng(92, 1), g)
+    u = W.uniform_vector(n, W.rng(92, 2))
+    tree = imq.build_tree(_dev(xy), c, leaf=32, p=12)
+    rows = np.arange(0, n, 41)
+    exact = oracle.matvec(xy, c, u, xy_targets=xy[rows])
+    out = {}
+    for mode in (0, 1):
+        tree.set_kernel_config(p2p_mode=mode)
+        out[mode] = tree.matvec(_dev(u), "fp32").cpu().numpy()
+        err = _rel(out[mode][rows], exact)
+        print(f"c={c} p2p_mode={mode}: rel err vs oracle {err:.3e}")
+        assert err < 1e-5
+    assert _rel(out[1], out[0]) < 1e-6
+    tree.set_kernel_config()

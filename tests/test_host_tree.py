@@ -215,3 +215,44 @@ def test_shift_lists_name_every_child_once_in_its_quadrant():
         assert np.all(seen[parent >= 0] == 1) and np.all(seen[parent < 0] == 0)
     finally:
         H.free(h)
+
+
+@pytest.mark.parametrize("kind,c", [("uniform", 0.12), ("uniform", 0.004), ("mixture", 0.03), ("mixture", 0.3)])
+def test_near_expansion_flags_hold_their_rounding_bound(kind, c):
+    """A leaf may form |x_i - x_j|^2 + c^2 from the expansion about its centre
+    only where (|x_i|^2 + |x_j|^2) <= 2 c^2 over all its near pairs (coordinates
+    from the leaf's centre, scaled units).  The host flags a leaf by an upper
+    bound of that ratio (largest point radius per leaf), so the flags must be
+    exactly that bound's, and every flagged leaf must satisfy the ratio over its
+    actual pairs."""
+    g = W.rng(91, 3)
+    xy = W.uniform_points(3000, g) if kind == "uniform" else W.mixture_points(3000, W.rng(91, 1), g)
+    h, st = H.host_tree([xy], [c], 16, p=4)
+    assert st == 0
+    try:
+        leaves, begin, end = H.get(h, "leaves"), H.get(h, "begin"), H.get(h, "end")
+        u_off, u_idx = H.get(h, "u_off"), H.get(h, "u_idx")
+        cx, cy, xl, yl = H.get(h, "cx"), H.get(h, "cy"), H.get(h, "xl"), H.get(h, "yl")
+        cn2 = H.get(h, "cn")[0] ** 2
+        flags = H.get(h, "near_expand")
+        assert flags.size == leaves.size and set(np.unique(flags)) <= {0, 1}
+        rad = {b: float(np.sqrt(xl[begin[b]:end[b]] ** 2 + yl[begin[b]:end[b]] ** 2).max(initial=0.0))
+               for b in leaves}
+        for f, b in zip(flags, leaves):
+            srcs = u_idx[u_off[b]:u_off[b + 1]]
+            far = max(np.hypot(cx[a] - cx[b], cy[a] - cy[b]) + rad[a] for a in srcs)
+            assert f == int(rad[b] ** 2 + far ** 2 <= 2.0 * cn2)
+            if f:
+                ti2 = rad[b] ** 2
+                sj2 = max(float(((xl[begin[a]:end[a]] + cx[a] - cx[b]) ** 2 +
+                                 (yl[begin[a]:end[a]] + cy[a] - cy[b]) ** 2).max(initial=0.0)) for a in srcs)
+                assert ti2 + sj2 <= 2.0 * cn2 * (1 + 1e-12)
+        frac = flags.mean()
+        if kind == "uniform":                    # one leaf geometry: all or none
+            assert frac == (1.0 if c == 0.12 else 0.0)
+        elif c == 0.3:
+            assert frac > 0.9                    # all but the few coarse leaves of the sparse region
+        else:
+            assert 0.0 < frac < 1.0              # both forms occur
+    finally:
+        H.free(h)
