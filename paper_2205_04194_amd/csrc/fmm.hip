@@ -429,6 +429,14 @@ __global__ void k_fill(size_t n, T *__restrict__ p, T v)
     if (i < n) p[i] = v;
 }
 
+// The per-pair W-list (M2P) evaluations that L2P adds for its leaf's points
+// (Pw null: none; they are then added by k_m2p_reduce).
+struct M2PParts {
+    const int32_t *w_scr = nullptr;
+    const double *Pw = nullptr;
+    int nscr = 0;
+};
+
 // L2P: potential = sum Re(Lt[n,m] |w|^(n-m) w^m) at each point of a leaf.
 // The leaf's local expansion carries only the coefficients of its level's
 // translation order Q <= P (the rest are zero), so the evaluation runs at Q:
@@ -436,7 +444,8 @@ __global__ void k_fill(size_t n, T *__restrict__ p, T v)
 // to the fully unrolled evaluation of order Q.  The expansion is staged in LDS.
 template <typename T, int Q>
 __device__ __forceinline__ void l2p_leaf(const DTree<T> &t, const LeafRec &lr, T *Ls, const T *__restrict__ L,
-                                         int nrhs, double *__restrict__ bs, int add, const UserVec &io)
+                                         int nrhs, double *__restrict__ bs, int add, const UserVec &io,
+                                         const M2PParts &wp)
 {
     constexpr int K = (Q + 1) * (Q + 2) / 2;
     const T inv_s = pow2i<T>(lr.level);
@@ -454,7 +463,10 @@ __device__ __forceinline__ void l2p_leaf(const DTree<T> &t, const LeafRec &lr, T
             T acc = T(0);
             // real part of Lt * monomial: Re*Re - Im*Im
             monomials<Q>(x, y, [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
-            const double val = prev + double(acc);
+            double val = prev + double(acc);
+            if (wp.Pw)                            // the leaf's W-list evaluations, in list order
+                for (int kp = t.w_off[lr.box]; kp < t.w_off[lr.box + 1]; ++kp)
+                    val += wp.Pw[size_t(r) * wp.nscr + wp.w_scr[kp] + (i - lr.begin)];
             if (io.out) io.put(r, i, val);
             else bs[r * t.N + i] = val;
         }
@@ -463,7 +475,7 @@ __device__ __forceinline__ void l2p_leaf(const DTree<T> &t, const LeafRec &lr, T
 
 template <typename T, int P>
 __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, LevelK lk, const T *__restrict__ L, int nrhs,
-                                            double *__restrict__ bs, int add, UserVec io)
+                                            double *__restrict__ bs, int add, UserVec io, M2PParts wp)
 {
     __shared__ T Ls[(P + 1) * (P + 2) / 2];
     const LeafRec lr = t.leafrec[blockIdx.x];
@@ -471,7 +483,7 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, LevelK lk, const T *__re
     int q = 0;                                   // order with (q+1)(q+2)/2 = Kl
     while ((q + 2) * (q + 3) / 2 <= Kl) ++q;
 #define IMQ_L2P_Q(Q) \
-    case Q: if constexpr (Q <= P) { l2p_leaf<T, Q>(t, lr, Ls, L, nrhs, bs, add, io); return; } break;
+    case Q: if constexpr (Q <= P) { l2p_leaf<T, Q>(t, lr, Ls, L, nrhs, bs, add, io, wp); return; } break;
     switch (q) {
         IMQ_L2P_Q(1) IMQ_L2P_Q(2) IMQ_L2P_Q(3) IMQ_L2P_Q(4) IMQ_L2P_Q(5) IMQ_L2P_Q(6) IMQ_L2P_Q(7)
         IMQ_L2P_Q(8) IMQ_L2P_Q(9) IMQ_L2P_Q(10) IMQ_L2P_Q(11) IMQ_L2P_Q(12) IMQ_L2P_Q(13) IMQ_L2P_Q(14)
@@ -479,7 +491,7 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, LevelK lk, const T *__re
         default: break;
     }
 #undef IMQ_L2P_Q
-    l2p_leaf<T, P>(t, lr, Ls, L, nrhs, bs, add, io);
+    l2p_leaf<T, P>(t, lr, Ls, L, nrhs, bs, add, io, wp);
 }
 
 // Many right-hand sides: the leaf expansions and their evaluation as
@@ -1084,7 +1096,18 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
         IMQ_HIP(hipGetLastError());
         return IMQ_OK;
     };
-    if (uv.out && (st = m2p()) != IMQ_OK) return st;      // L2P then writes the caller's vector last
+    // Overlapped product with the result in caller order: L2P writes it last
+    // and adds the W-list evaluations itself (one launch fewer on the chain).
+    M2PParts wp;
+    if (uv.out && t->nwpairs > 0) {
+        if (!overlap) {
+            set_error("internal: caller-order output needs the overlapped product");
+            return IMQ_EINVAL;
+        }
+        wp.w_scr = t->w_scr.as<int32_t>();
+        wp.Pw = t->Pw.as<double>();
+        wp.nscr = t->nwscr;
+    }
     LevelK lk = {};
     for (int l = 0; l < h.nlev && l < 32; ++l) lk.K[l] = h.Klev[l];
     constexpr int RB = sizeof(T) == 4 ? 64 : 32;
@@ -1093,7 +1116,7 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
     if (nrhs >= BATCH_RHS_MIN)                                                                         \
         hipLaunchKernelGGL((k_l2p_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs); \
     else                                                                                               \
-        hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, lk, pd.L.as<T>(), nrhs, bs, 1, uv)
+        hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, lk, pd.L.as<T>(), nrhs, bs, 1, uv, wp)
     IMQ_DISPATCH_P(h.p, IMQ_L2P)
 #undef IMQ_L2P
     IMQ_HIP(hipGetLastError());
