@@ -211,7 +211,9 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
     // measured slower on the mixture workload, in particular beside the near
     // field, whose small workgroups leave few CUs with 8 wave slots free
     // Levels too small to give every CU a few workgroups split the output rows
-    // (one row block per workgroup).
+    // (one row block per workgroup).  16 target columns per workgroup
+    // everywhere: at the fine levels (up to 48 coefficients) 32 columns gave
+    // half the workgroups and a 7% slower M2L stage.
 #define IMQ_M2LS(NRB, NCB, NW)                                                                             \
     do {                                                                                                   \
         const unsigned ny = unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB));                      \
@@ -224,9 +226,9 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
     } while (0)
     if constexpr (sizeof(T) == 4) {
         switch (nrb) {
-        case 1: IMQ_M2LS(1, 2, 4); return true;
-        case 2: IMQ_M2LS(2, 2, 4); return true;
-        case 3: IMQ_M2LS(3, 2, 4); return true;
+        case 1: IMQ_M2LS(1, 1, 4); return true;
+        case 2: IMQ_M2LS(2, 1, 4); return true;
+        case 3: IMQ_M2LS(3, 1, 4); return true;
         case 4: IMQ_M2LS(4, 1, 4); return true;
         case 5: IMQ_M2LS(5, 1, 4); return true;
         default: return false;
