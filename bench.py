@@ -207,6 +207,49 @@ def batched_extras(dev, steps):
     return out
 
 
+def evaluate_extra(dev, steps, m=250_000):
+    """Interpolant evaluation: the 1M-point mixture's sites with coefficients
+    u ~ U(-1, 1), evaluated at m uniform points of the unit square."""
+    import torch
+    import workloads as W
+    import paper_2205_04194_amd as imq
+    d = W.mixture1m()
+    n = len(d["xy"])
+    yt = W.uniform_points(m, W.rng("mixture1m", 5))
+    lam = torch.tensor(d["u"], device=dev)
+    t0 = time.perf_counter()
+    tree = imq.build_eval_tree(torch.tensor(d["xy"], device=dev), d["c"], torch.tensor(yt, device=dev),
+                               leaf=64, p=12)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    if tree.n != n + m:
+        raise RuntimeError("an evaluation point coincides with a data site")
+    ufull = torch.cat([lam, torch.zeros(m, dtype=lam.dtype, device=dev)])
+    r = _tuned_run(tree, ufull, steps)         # orders and precision for the tree's product
+    prec = r["precision"]
+    k = torch.tensor(np.sort(np.random.default_rng(11).choice(m, 300, replace=False)), device=dev)
+    exact = tree.rows_exact(ufull, n + k)      # fresh evaluation points follow the sites
+    s = tree.evaluate(lam, prec)
+    err = float(torch.linalg.norm(s[k] - exact) / torch.linalg.norm(exact))
+    for _ in range(2):
+        tree.evaluate(lam, prec)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        tree.evaluate(lam, prec)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tree.close()
+    out = {"workload": "mixture1m sites, uniform evaluation points", "N": n, "M": m, "c": d["c"],
+           "tree_build_s": tb, "precision": prec, "level_orders": r["level_orders"], "ms_per_eval": ms,
+           "rel_err_sampled_points": err, "points_per_s": m * 1e3 / ms}
+    log(f"evaluate {m} points from {n} sites: {ms:.3f} ms ({prec}), err {err:.2e}, build {tb:.2f} s")
+    return out
+
+
 def adjoint_extra(dev, steps):
     """Gradients of ||A(c, X) v - f||^2 (dv, dc, dX) at N = 1e5, FP64 expansions, p = 16."""
     import torch
@@ -391,6 +434,7 @@ def main():
     if not args.no_extras:
         out["batched"] = batched_extras(dev, args.steps)
         out["adjoint"] = adjoint_extra(dev, args.steps)
+        out["evaluate"] = evaluate_extra(dev, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d["xy"], d["c"], d["u"], args.cpu_budget)
     print(json.dumps(out), flush=True)

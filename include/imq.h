@@ -105,6 +105,33 @@ imq_status imq_rows_exact(imq_tree tree, int nrhs, const double *u, int64_t ldu,
                           int64_t nrows, const int64_t *rows, double *b,
                           int64_t ldb, hipStream_t stream);
 
+/* Evaluation of the interpolant (Sec. 2, eq. interp_eq)
+ *     P(y) = sum_j lambda_j / sqrt(|y - x_j|^2 + c^2)
+ * at points y that need not be data sites, for one set of n data sites x_j.
+ * imq_build_eval_tree builds a tree over the data sites and the m evaluation
+ * points together; the evaluation points are targets only (weight zero in
+ * every product of this tree).  An evaluation point that coincides with a
+ * data site or with an earlier evaluation point is not inserted and takes
+ * the value of that point.
+ *  xy_src : device FP64 SoA x[0..n), y[0..n): the data sites (IMQ_EDUPLICATE
+ *           if two coincide)
+ *  xy_tgt : device FP64 SoA x[0..m), y[0..m): the evaluation points (m >= 0)
+ *  c      : shape parameter (> 0)
+ * The tree answers imq_matvec and imq_rows_exact over its own points (the
+ * data sites first, then the inserted evaluation points, Ntot in all) and
+ * imq_evaluate.  Synchronises `stream`. */
+imq_status imq_build_eval_tree(const double *xy_src, int64_t n, const double *xy_tgt, int64_t m, double c,
+                               const imq_tree_params *params, hipStream_t stream, imq_tree *out);
+
+/* s[r*lds + k] = P_r(y_k), k < m, for the coefficients lambda (nrhs columns
+ * of length n, leading dimension ldl >= n, element type `dtype`; s the same
+ * with lds >= m) on a tree from imq_build_eval_tree (else IMQ_EINVAL): one
+ * fast product over the tree's points with the evaluation points' weights
+ * zero, read at the evaluation points.  Keeps a workspace of 2 * nrhs * Ntot
+ * elements in the tree (allocated on first use, grown when nrhs grows). */
+imq_status imq_evaluate(imq_tree tree, int nrhs, imq_dtype dtype, const void *lambda, int64_t ldl, void *s,
+                        int64_t lds, imq_prec prec, hipStream_t stream);
+
 typedef struct {
     double tol;        /* stop when ||f - A a|| <= tol ||f|| (FP64 product)  */
     int restart;       /* GMRES restart length m (1 .. 256)                 */

@@ -45,6 +45,14 @@ int imq_debug_host_tree_get(void *h, const char *what, void *out);
 
 void imq_debug_host_tree_free(void *h);
 
+/* The point list of an evaluation tree (host arrays): data sites xs, ys (n)
+ * and evaluation points xt, yt (m); writes map[k] for k < m (the index, in
+ * the tree's point list, of the point evaluation point k takes its value
+ * from) and returns the number of points in the tree, or a negative
+ * imq_status (IMQ_EINVAL, IMQ_EDUPLICATE). */
+int64_t imq_debug_eval_points(int64_t n, const double *xs, const double *ys, int64_t m, const double *xt,
+                              const double *yt, int64_t *map);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,7 @@ import torch
 from . import _lib
 from ._lib import IMQError, PREC
 
-__all__ = ["Tree", "build_tree", "matvec", "solve", "IMQMatvec", "IMQError"]
+__all__ = ["Tree", "build_tree", "build_eval_tree", "matvec", "solve", "IMQMatvec", "IMQError"]
 
 
 def _stream_ptr(stream=None) -> ctypes.c_void_p:
@@ -79,6 +79,55 @@ class Tree:
                                     _stream_ptr(stream), ctypes.byref(h))
         _lib.check(st, "imq_build_tree")
         self._h = h
+
+    # ------------------------------------------------------------ evaluation
+    @classmethod
+    def for_evaluation(cls, xy_src: torch.Tensor, c: float, xy_tgt: torch.Tensor, leaf: int = 64,
+                       p: int = 12, level_order=None, max_level: int = 0, direct_max: int = 0,
+                       stream=None) -> "Tree":
+        """Tree over data sites and evaluation points together (imq_build_eval_tree)."""
+        lib = _lib.load()
+        for a in (xy_src, xy_tgt):
+            if a.dim() != 2 or a.shape[1] != 2 or not a.is_cuda:
+                raise ValueError("xy_src and xy_tgt must be cuda tensors of shape (n, 2)")
+        self = cls.__new__(cls)
+        # SoA copies held in locals for the duration of the call (a temporary
+        # passed by pointer could be freed and its memory reused before the
+        # library reads it)
+        src = xy_src.detach().to(torch.float64).t().contiguous()
+        tgt = xy_tgt.detach().to(torch.float64).t().contiguous()
+        self.n_src, self.m_eval = xy_src.shape[0], xy_tgt.shape[0]
+        self.nsets, self.c, self.leaf, self.p = 1, [float(c)], leaf, p
+        self.device = xy_src.device
+        prm = _lib.params(leaf, p, max_level, level_order, direct_max)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.imq_build_eval_tree(_dptr(src), self.n_src, _dptr(tgt),
+                                         self.m_eval, float(c), ctypes.byref(prm), _stream_ptr(stream),
+                                         ctypes.byref(h))
+        _lib.check(st, "imq_build_eval_tree")
+        self._h = h
+        self.n = int(self.info()["npoints"])
+        self.offsets = [0, self.n]
+        self._xy = None
+        return self
+
+    def evaluate(self, lam: torch.Tensor, prec: str = "fp64", stream=None) -> torch.Tensor:
+        """Interpolant sum_j lam_j phi(|y_k - x_j|) at the evaluation points: (m,) or (nrhs, m)."""
+        lib = _lib.load()
+        one = lam.dim() == 1
+        l2 = (lam.unsqueeze(0) if one else lam).contiguous()
+        if l2.shape[1] != self.n_src:
+            raise ValueError("lam has the wrong length")
+        if l2.dtype not in (torch.float64, torch.float32):
+            raise ValueError("lam must be float64 or float32")
+        s = torch.empty((l2.shape[0], self.m_eval), dtype=l2.dtype, device=self.device)
+        dt = _lib.F64 if l2.dtype == torch.float64 else _lib.F32
+        with torch.cuda.device(self.device):
+            st = lib.imq_evaluate(self._h, l2.shape[0], dt, _dptr(l2), self.n_src, _dptr(s),
+                                  max(self.m_eval, 1), PREC[prec], _stream_ptr(stream))
+        _lib.check(st, "imq_evaluate")
+        return s[0] if one else s
 
     # ----------------------------------------------------------------- product
     def matvec(self, u: torch.Tensor, prec: str = "fp64", stream=None) -> torch.Tensor:
@@ -195,6 +244,11 @@ class Tree:
 
 def build_tree(xy, c, leaf: int = 64, p: int = 12, **kw) -> Tree:
     return Tree(xy, c, leaf=leaf, p=p, **kw)
+
+
+def build_eval_tree(xy_src, c, xy_tgt, leaf: int = 64, p: int = 12, **kw) -> Tree:
+    """Tree for evaluating the interpolant of the data sites xy_src at xy_tgt."""
+    return Tree.for_evaluation(xy_src, c, xy_tgt, leaf=leaf, p=p, **kw)
 
 
 def matvec(tree: Tree, u: torch.Tensor, prec: str = "fp64") -> torch.Tensor:

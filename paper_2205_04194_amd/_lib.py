@@ -64,6 +64,8 @@ _p = ctypes.POINTER
 SIGNATURES = {
     "imq_build_tree": (_int, [_int, _p(_i64), _vp, _p(_dbl), _p(TreeParams), _vp, _p(_vp)]),
     "imq_matvec": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _int, _vp]),
+    "imq_build_eval_tree": (_int, [_vp, _i64, _vp, _i64, _dbl, _p(TreeParams), _vp, _p(_vp)]),
+    "imq_evaluate": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _int, _vp]),
     "imq_rows_exact": (_int, [_vp, _int, _vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "imq_solve": (_int, [_vp, _int, _vp, _i64, _vp, _i64, _p(SolveOpts), _p(SolveStats), _vp]),
     "imq_matvec_backward": (_int, [_vp, _int, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
@@ -81,6 +83,7 @@ SIGNATURES = {
     "imq_debug_host_tree_size": (_i64, [_vp, ctypes.c_char_p]),
     "imq_debug_host_tree_get": (_int, [_vp, ctypes.c_char_p, _vp]),
     "imq_debug_host_tree_free": (None, [_vp]),
+    "imq_debug_eval_points": (_i64, [_i64, _p(_dbl), _p(_dbl), _i64, _p(_dbl), _p(_dbl), _p(_i64)]),
 }
 
 

@@ -224,7 +224,7 @@ static void free_tree(imq_tree_s *t)
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
                       &t->cn, &t->leaves, &t->leafrec, &t->nleaf, &t->xy_user, &t->set_off, &t->bs, &t->sol,
                       &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw, &t->adj,
-                      &t->sh_par, &t->sh_kids};
+                      &t->sh_par, &t->sh_kids, &t->eval_map, &t->eval_u, &t->eval_b};
     for (DevBuf *b : bufs) dev_free(*b);
     for (DevGemm *g : {&t->g_m2l}) {
         dev_free(g->tasks); dev_free(g->tbox); dev_free(g->tab); dev_free(g->src);
@@ -258,6 +258,50 @@ static imq_status check_tree(imq_tree t)
     if (dev != t->device) IMQ_HIP(hipSetDevice(t->device));
     return IMQ_OK;
 }
+
+namespace {
+// the product's input: the coefficients at the data sites, zero at the
+// evaluation points
+template <typename V>
+__global__ void k_eval_in(int64_t n, int64_t N, const V *__restrict__ lam, int64_t ldl, V *__restrict__ u)
+{
+    const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < N) u[r * N + i] = i < n ? lam[r * ldl + i] : V(0);
+}
+
+template <typename V>
+__global__ void k_eval_out(int64_t m, int64_t N, const int64_t *__restrict__ map, const V *__restrict__ b,
+                           V *__restrict__ s, int64_t lds)
+{
+    const int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int r = blockIdx.y;
+    if (k < m) s[r * lds + k] = b[r * N + map[k]];
+}
+
+template <typename V>
+imq_status evaluate_typed(imq_tree_s *t, int nrhs, const V *lam, int64_t ldl, V *s, int64_t lds, imq_prec prec,
+                          hipStream_t stream)
+{
+    const int64_t N = t->h.N, n = t->eval_n, m = t->eval_m;
+    const size_t bytes = sizeof(V) * size_t(nrhs) * size_t(N);
+    if (t->eval_u.bytes < bytes) {
+        dev_free(t->eval_u);
+        dev_free(t->eval_b);
+        IMQ_HIP(dev_alloc(t->eval_u, bytes));
+        IMQ_HIP(dev_alloc(t->eval_b, bytes));
+    }
+    V *u = t->eval_u.as<V>(), *b = t->eval_b.as<V>();
+    hipLaunchKernelGGL(k_eval_in<V>, dim3(unsigned((N + 255) / 256), nrhs), dim3(256), 0, stream, n, N, lam, ldl, u);
+    IMQ_HIP(hipGetLastError());
+    const imq_status st = imq_matvec(t, nrhs, sizeof(V) == 8 ? IMQ_F64 : IMQ_F32, u, N, b, N, prec, stream);
+    if (st != IMQ_OK) return st;
+    hipLaunchKernelGGL(k_eval_out<V>, dim3(unsigned((m + 255) / 256), nrhs), dim3(256), 0, stream, m, N,
+                       t->eval_map.as<int64_t>(), b, s, lds);
+    IMQ_HIP(hipGetLastError());
+    return IMQ_OK;
+}
+}  // namespace
 
 }  // namespace imq
 
@@ -313,6 +357,63 @@ imq_status imq_build_tree(int nsets, const int64_t *set_offsets, const double *x
     if (st != IMQ_OK) { free_tree(t); return st; }
     *out = t;
     return IMQ_OK;
+}
+
+imq_status imq_build_eval_tree(const double *xy_src, int64_t n, const double *xy_tgt, int64_t m, double c,
+                               const imq_tree_params *params, hipStream_t stream, imq_tree *out)
+{
+    if (!out) { set_error("out is null"); return IMQ_EINVAL; }
+    *out = nullptr;
+    if (!xy_src || n < 1 || m < 0 || (m > 0 && !xy_tgt) || !params) {
+        set_error("null argument, n < 1 or m < 0");
+        return IMQ_EINVAL;
+    }
+    if (n + m > 0x7fffffff) { set_error("too many points"); return IMQ_EINVAL; }
+    std::vector<double> hs(2 * size_t(n)), ht(2 * size_t(m));
+    IMQ_HIP(hipMemcpyAsync(hs.data(), xy_src, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, stream));
+    if (m > 0) IMQ_HIP(hipMemcpyAsync(ht.data(), xy_tgt, sizeof(double) * ht.size(), hipMemcpyDeviceToHost, stream));
+    IMQ_HIP(hipStreamSynchronize(stream));
+    std::vector<double> x, y;
+    std::vector<int64_t> map;
+    imq_status st = eval_points(n, hs.data(), hs.data() + n, m, ht.data(), ht.data() + m, x, y, map);
+    if (st != IMQ_OK) return st;
+    const int64_t N = int64_t(x.size());
+    std::vector<double> soa(x);
+    soa.insert(soa.end(), y.begin(), y.end());
+    DevBuf dxy;
+    if ((st = upload(dxy, soa)) != IMQ_OK) return st;   // the tree copies what it keeps
+    const int64_t offs[2] = {0, N};
+    st = imq_build_tree(1, offs, dxy.as<double>(), &c, params, stream, out);
+    dev_free(dxy);
+    if (st != IMQ_OK) return st;
+    imq_tree t = *out;
+    t->eval_n = n;
+    t->eval_m = m;
+    if ((st = upload(t->eval_map, map)) != IMQ_OK) {
+        imq_tree_free(t);
+        *out = nullptr;
+        return st;
+    }
+    return IMQ_OK;
+}
+
+
+imq_status imq_evaluate(imq_tree t, int nrhs, imq_dtype dtype, const void *lambda, int64_t ldl, void *s,
+                        int64_t lds, imq_prec prec, hipStream_t stream)
+{
+    imq_status st = check_tree(t);
+    if (st != IMQ_OK) return st;
+    if (t->eval_n < 0) { set_error("not an evaluation tree (imq_build_eval_tree)"); return IMQ_EINVAL; }
+    if (nrhs < 1 || nrhs > 65535 || !lambda || ldl < t->eval_n || (t->eval_m > 0 && (!s || lds < t->eval_m))) {
+        set_error("bad nrhs, pointer or leading dimension");
+        return IMQ_EINVAL;
+    }
+    if (dtype != IMQ_F64 && dtype != IMQ_F32) { set_error("unknown dtype"); return IMQ_EINVAL; }
+    if (prec != IMQ_PREC_FP64 && prec != IMQ_PREC_FP32) { set_error("unknown precision"); return IMQ_EINVAL; }
+    if (t->eval_m == 0) return IMQ_OK;
+    if (dtype == IMQ_F64)
+        return evaluate_typed<double>(t, nrhs, (const double *)lambda, ldl, (double *)s, lds, prec, stream);
+    return evaluate_typed<float>(t, nrhs, (const float *)lambda, ldl, (float *)s, lds, prec, stream);
 }
 
 imq_status imq_matvec(imq_tree t, int nrhs, imq_dtype dtype, const void *u, int64_t ldu, void *b,
@@ -504,6 +605,18 @@ int imq_debug_host_tree_get(void *hp, const char *what, void *out)
 }
 
 void imq_debug_host_tree_free(void *hp) { delete static_cast<HostTree *>(hp); }
+
+int64_t imq_debug_eval_points(int64_t n, const double *xs, const double *ys, int64_t m, const double *xt,
+                              const double *yt, int64_t *map)
+{
+    if (n < 1 || m < 0 || !xs || !ys || (m > 0 && (!xt || !yt || !map))) return IMQ_EINVAL;
+    std::vector<double> x, y;
+    std::vector<int64_t> mp;
+    const imq_status st = eval_points(n, xs, ys, m, xt, yt, x, y, mp);
+    if (st != IMQ_OK) return st;
+    std::copy(mp.begin(), mp.end(), map);
+    return int64_t(x.size());
+}
 
 imq_status imq_solve(imq_tree t, int nrhs, const double *f, int64_t ldf, double *a, int64_t lda,
                      const imq_solve_opts *opts, imq_solve_stats *stats, hipStream_t stream)

@@ -194,6 +194,10 @@ struct imq_tree_s {
     static constexpr int NGROUP_EV = 32;                      // M2L level groups done (the L2L chain waits)
     hipEvent_t ev_grp[NGROUP_EV] = {};
     imq_status ensure_side();
+    // evaluation tree (imq_build_eval_tree): data sites, evaluation points,
+    // per evaluation point the tree point it reads, and the product's workspace
+    int64_t eval_n = -1, eval_m = 0;
+    imq::DevBuf eval_map, eval_u, eval_b;
     // solver workspace
     imq::DevBuf sol;
     size_t sol_bytes = 0;

@@ -140,6 +140,16 @@ struct HostTree {
     int64_t m2m_pairs = 0, l2l_pairs = 0;
 };
 
+// Points of an evaluation tree: the n data sites (xs, ys), then each of the m
+// evaluation points (xt, yt) that coincides with no earlier point, data site
+// or evaluation point (-0 and +0 coincide); map[k] is the index, in that
+// list, of the point whose value evaluation point k takes.  Returns IMQ_OK,
+// IMQ_EINVAL (a coordinate not finite) or IMQ_EDUPLICATE (two data sites
+// coincide).
+imq_status eval_points(int64_t n, const double *xs, const double *ys, int64_t m, const double *xt,
+                       const double *yt, std::vector<double> &x, std::vector<double> &y,
+                       std::vector<int64_t> &map);
+
 // Returns IMQ_OK, IMQ_EINVAL or IMQ_EDUPLICATE.
 imq_status build_host_tree(int nsets, const int64_t *set_offsets, const double *x,
                            const double *y, const double *c, const imq_tree_params &prm,

@@ -22,7 +22,9 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <cstring>
 #include <numeric>
+#include <unordered_map>
 
 namespace imq {
 
@@ -463,6 +465,49 @@ void build_gemm_lists(HostTree &t)
             }
     }
     t.m2l.level_task_begin[L] = int32_t(t.m2l.tasks.size());
+}
+
+imq_status eval_points(int64_t n, const double *xs, const double *ys, int64_t m, const double *xt,
+                       const double *yt, std::vector<double> &x, std::vector<double> &y,
+                       std::vector<int64_t> &map)
+{
+    struct KeyHash {
+        size_t operator()(const std::pair<uint64_t, uint64_t> &k) const
+        {
+            return size_t(k.first * 0x9E3779B97F4A7C15ull ^ (k.second + 0x632BE59BD9B4E019ull + (k.first << 6)));
+        }
+    };
+    auto key = [](double a, double b) {
+        a += 0.0;                                // -0 -> +0: the same point
+        b += 0.0;
+        uint64_t ka, kb;
+        std::memcpy(&ka, &a, 8);
+        std::memcpy(&kb, &b, 8);
+        return std::make_pair(ka, kb);
+    };
+    std::unordered_map<std::pair<uint64_t, uint64_t>, int64_t, KeyHash> seen;
+    seen.reserve(size_t(n + m));
+    x.assign(xs, xs + n);
+    y.assign(ys, ys + n);
+    map.assign(size_t(m), -1);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(xs[i]) || !std::isfinite(ys[i])) { set_error("non-finite data site"); return IMQ_EINVAL; }
+        if (!seen.emplace(key(xs[i], ys[i]), i).second) {
+            set_error("duplicate data sites: points " + std::to_string(seen[key(xs[i], ys[i])]) + " and " +
+                      std::to_string(i));
+            return IMQ_EDUPLICATE;
+        }
+    }
+    for (int64_t k = 0; k < m; ++k) {
+        if (!std::isfinite(xt[k]) || !std::isfinite(yt[k])) { set_error("non-finite evaluation point"); return IMQ_EINVAL; }
+        const auto r = seen.emplace(key(xt[k], yt[k]), int64_t(x.size()));
+        if (r.second) {
+            x.push_back(xt[k]);
+            y.push_back(yt[k]);
+        }
+        map[size_t(k)] = r.first->second;
+    }
+    return IMQ_OK;
 }
 
 }  // namespace imq

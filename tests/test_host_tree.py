@@ -256,3 +256,42 @@ def test_near_expansion_flags_hold_their_rounding_bound(kind, c):
             assert 0.0 < frac < 1.0              # both forms occur
     finally:
         H.free(h)
+
+
+def test_eval_points_alias_coincident_points():
+    """An evaluation tree inserts the data sites, then every evaluation point
+    that coincides with no earlier point; the others read the point they
+    coincide with (-0 and +0 are the same coordinate).  Coincident data sites
+    are an error, as for any tree."""
+    import ctypes
+    from paper_2205_04194_amd import _lib as L
+    lib = L.load()
+    g = W.rng(95, 1)
+    xs = W.uniform_points(50, g)
+    xt = np.concatenate([W.uniform_points(20, g), xs[[3, 7, 3]], [[0.0, 0.5], [-0.0, 0.5]]])
+    xt = np.concatenate([xt, xt[[0, 5]]])                 # evaluation points repeated
+    xs = np.concatenate([xs, [[0.0, 0.5]]])               # a data site at (+0, 0.5)
+    n, m = len(xs), len(xt)
+    P = ctypes.POINTER(ctypes.c_double)
+    cols = [np.ascontiguousarray(a) for a in (xs[:, 0], xs[:, 1], xt[:, 0], xt[:, 1])]
+    mp = np.zeros(m, dtype=np.int64)
+    kept = lib.imq_debug_eval_points(n, cols[0].ctypes.data_as(P), cols[1].ctypes.data_as(P), m,
+                                     cols[2].ctypes.data_as(P), cols[3].ctypes.data_as(P),
+                                     mp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    assert kept == n + 20                                 # only the 20 fresh points are inserted
+    assert np.array_equal(mp[:20], np.arange(n, n + 20))
+    assert mp[20] == 3 and mp[21] == 7 and mp[22] == 3
+    assert mp[23] == n - 1 and mp[24] == n - 1            # (+0, 0.5) and (-0, 0.5) read the data site
+    assert mp[25] == mp[0] and mp[26] == mp[5]
+    # the point each evaluation point reads is that point
+    pts = np.concatenate([xs, xt[:20]])
+    assert np.array_equal(pts[mp] + 0.0, xt + 0.0)
+    dup = np.ascontiguousarray(np.concatenate([xs[:, 0], xs[:1, 0]]))
+    dupy = np.ascontiguousarray(np.concatenate([xs[:, 1], xs[:1, 1]]))
+    assert lib.imq_debug_eval_points(n + 1, dup.ctypes.data_as(P), dupy.ctypes.data_as(P), 0,
+                                     None, None, None) == -2
+    bad = cols[2].copy()
+    bad[4] = np.nan
+    assert lib.imq_debug_eval_points(n, cols[0].ctypes.data_as(P), cols[1].ctypes.data_as(P), m,
+                                     bad.ctypes.data_as(P), cols[3].ctypes.data_as(P),
+                                     mp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))) == -1
