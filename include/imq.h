@@ -190,13 +190,23 @@ imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
  *  p2p_mode   : near field in FP32 with one right-hand side: 0 = vector form
  *               everywhere; 1 = matrix-core form (squared distances as a
  *               rank-4 product) for the leaves whose neighbourhood is small
- *               against c, vector form for the rest */
+ *               against c, vector form for the rest
+ *  far_field  : 0 = the tree passes above (multipole shifts, translations to
+ *               local expansions, local evaluation); 1 = the paper's
+ *               Algorithm 1 (Sec. 2.2): the multipole of every box from its
+ *               own points, evaluated directly at the points of every box of
+ *               its same-level interaction (V) list, at every level, plus
+ *               the direct near field.  Uniform order p on every level.  The
+ *               adaptive W/X interactions must be summed directly (a tree
+ *               built with a large direct_max; a uniform tree has none), else
+ *               the product returns IMQ_EUNSUPPORTED. */
 typedef struct {
     int m2l_kc, m2l_split;
     int shift_cols;
     int m2l_mode;
     int p2p_wg;
     int p2p_mode;
+    int far_field;
 } imq_kernel_config;
 
 imq_status imq_set_kernel_config(imq_tree tree, const imq_kernel_config *cfg);

@@ -210,9 +210,11 @@ class Tree:
         return out
 
     def set_kernel_config(self, m2l_kc: int = 0, m2l_split: int = 0, shift_cols: int = 0,
-                          m2l_mode: int = 0, p2p_wg: int = 0, p2p_mode: int = 0) -> None:
-        """Launch shape of the batched translations and the near field (0 = default)."""
-        cfg = _lib.KernelConfig(m2l_kc, m2l_split, shift_cols, m2l_mode, p2p_wg, p2p_mode)
+                          m2l_mode: int = 0, p2p_wg: int = 0, p2p_mode: int = 0,
+                          far_field: int = 0) -> None:
+        """Launch shape of the batched translations and the near field (0 = default);
+        far_field = 1 selects the paper's Algorithm 1 for the far field."""
+        cfg = _lib.KernelConfig(m2l_kc, m2l_split, shift_cols, m2l_mode, p2p_wg, p2p_mode, far_field)
         _lib.check(_lib.load().imq_set_kernel_config(self._h, ctypes.byref(cfg)),
                    "imq_set_kernel_config")
 

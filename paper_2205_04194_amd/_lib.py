@@ -38,7 +38,8 @@ class SolveStats(ctypes.Structure):
 class KernelConfig(ctypes.Structure):
     _fields_ = [("m2l_kc", ctypes.c_int), ("m2l_split", ctypes.c_int),
                 ("shift_cols", ctypes.c_int), ("m2l_mode", ctypes.c_int),
-                ("p2p_wg", ctypes.c_int), ("p2p_mode", ctypes.c_int)]
+                ("p2p_wg", ctypes.c_int), ("p2p_mode", ctypes.c_int),
+                ("far_field", ctypes.c_int)]
 
 
 class TreeInfo(ctypes.Structure):

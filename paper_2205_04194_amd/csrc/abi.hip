@@ -125,6 +125,22 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
             lr[i] = LeafRec{b, h.begin[b], h.end[b], h.level[b]};
         }
         if ((st = upload(t->leafrec, lr)) != IMQ_OK) return st;
+        // every box that can be a V-list source, with the leaves under it: a
+        // contiguous range of the leaves in point order
+        std::vector<int32_t> lord(lr.size()), lbeg(lr.size());
+        for (size_t i = 0; i < lr.size(); ++i) lord[i] = int32_t(i);
+        std::sort(lord.begin(), lord.end(), [&](int32_t a, int32_t b) { return lr[a].begin < lr[b].begin; });
+        for (size_t i = 0; i < lr.size(); ++i) lbeg[i] = lr[lord[i]].begin;
+        if ((st = upload(t->boxleaf, lord)) != IMQ_OK) return st;
+        std::vector<BoxRec> br;
+        for (int b = 0; b < int(h.level.size()); ++b) {
+            if (h.level[b] < h.need_m) continue;
+            const int l0 = int(std::lower_bound(lbeg.begin(), lbeg.end(), h.begin[b]) - lbeg.begin());
+            const int l1 = int(std::lower_bound(lbeg.begin(), lbeg.end(), h.end[b]) - lbeg.begin());
+            br.push_back(BoxRec{b, l0, l1, h.level[b]});
+        }
+        if ((st = upload(t->boxrec, br)) != IMQ_OK) return st;
+        t->nboxrec = int(br.size());
         if ((st = upload(t->nleaf, near_leaves(h))) != IMQ_OK) return st;
     }
     {   // W and X lists as flat pairs
@@ -222,7 +238,7 @@ static void free_tree(imq_tree_s *t)
     DevBuf *bufs[] = {&t->perm, &t->pt_scale, &t->level, &t->set, &t->parent, &t->child0, &t->nchild,
                       &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
-                      &t->cn, &t->leaves, &t->leafrec, &t->nleaf, &t->xy_user, &t->set_off, &t->bs, &t->sol,
+                      &t->cn, &t->leaves, &t->leafrec, &t->boxrec, &t->boxleaf, &t->nleaf, &t->xy_user, &t->set_off, &t->bs, &t->sol,
                       &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw, &t->adj,
                       &t->sh_par, &t->sh_kids, &t->eval_map, &t->eval_u, &t->eval_b};
     for (DevBuf *b : bufs) dev_free(*b);
@@ -488,7 +504,8 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
     auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
     if (!ok_kc(cfg->m2l_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
         (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32) ||
-        cfg->m2l_mode < 0 || cfg->m2l_mode > 1 || cfg->p2p_wg < 0 || cfg->p2p_mode < 0 || cfg->p2p_mode > 1) {
+        cfg->m2l_mode < 0 || cfg->m2l_mode > 1 || cfg->p2p_wg < 0 || cfg->p2p_mode < 0 || cfg->p2p_mode > 1 ||
+        cfg->far_field < 0 || cfg->far_field > 1) {
         set_error("kernel config out of range");
         return IMQ_EINVAL;
     }

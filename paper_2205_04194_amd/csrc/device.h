@@ -25,6 +25,13 @@ struct alignas(16) LeafRec {
     int box, begin, end, level;
 };
 
+// A box whose multipole is formed from its own points (Algorithm 1 mode):
+// the leaves under it are entries [leaf0, leaf1) of the point-ordered leaf
+// index list (one 16-byte load).
+struct alignas(16) BoxRec {
+    int box, leaf0, leaf1, level;
+};
+
 // One U-list entry of a target leaf, as the near field reads it (one 16- or
 // 32-byte load): the source leaf's points [beg, beg + cnt) in sorted order and
 // its centre minus the target leaf's centre, rounded to T.
@@ -170,6 +177,9 @@ struct imq_tree_s {
     imq::DevBuf u_off, u_idx, v_off, v_idx, v_cls, w_off, w_idx, x_off, x_idx, Klev, cn, leaves;
     imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
     imq::DevBuf leafrec;                   // LeafRec per leaf
+    imq::DevBuf boxrec;                    // BoxRec per box at levels >= need_m (Algorithm 1 mode)
+    imq::DevBuf boxleaf;                   // leaf-list indices in point order (BoxRec ranges)
+    int nboxrec = 0;
     imq::DevBuf nleaf;                     // NearLeaf per leaf
     imq::PrecData f64, f32;
     imq::DevGemm g_m2l;

@@ -142,13 +142,13 @@ __device__ __forceinline__ T lds_dot(const T *a, int ld, int k, const T *w, int 
 constexpr int P2M_CHUNK = 32;      // points staged per round (LDS per wave halves vs 64)
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const T *__restrict__ us, int nrhs, T *__restrict__ M,
-                                            int ld, UserVec io)
+__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const LeafRec *__restrict__ recs, const T *__restrict__ us,
+                                            int nrhs, T *__restrict__ M, int ld, UserVec io)
 {
     extern __shared__ unsigned char smem_raw[];
     T *mono = reinterpret_cast<T *>(smem_raw);   // [P2M_CHUNK][ld]
     T *su = mono + P2M_CHUNK * ld;               // [P2M_CHUNK]
-    const LeafRec lr = t.leafrec[blockIdx.x];
+    const LeafRec lr = recs[blockIdx.x];
     const int b = lr.box, beg = lr.begin, end = lr.end;
     const T inv_s = pow2i<T>(lr.level);
     constexpr int K = (P + 1) * (P + 2) / 2;
@@ -179,6 +179,60 @@ __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const T *__restrict__ us
                 T &dst = M[(int64_t(b) * nrhs + r) * t.KS + k];
                 dst = (c0 == beg) ? v : dst + v;
             }
+        }
+    }
+}
+
+// P2M of any box from its own points (Algorithm 1 mode): the leaves under
+// the box (lord: leaf-list indices in point order), chunk by chunk, with each leaf's points moved from its centre to
+// the box's; the column sums are kept in registers and stored once.  For a
+// leaf this is k_p2m's arithmetic.
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_p2m_box(DTree<T> t, const BoxRec *__restrict__ recs,
+                                                const int32_t *__restrict__ lord, const T *__restrict__ us,
+                                                int nrhs, T *__restrict__ M, int ld)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T *mono = reinterpret_cast<T *>(smem_raw);   // [P2M_CHUNK][ld]
+    T *su = mono + P2M_CHUNK * ld;               // [P2M_CHUNK]
+    constexpr int K = (P + 1) * (P + 2) / 2, KPL = (K + 63) / 64;
+    const BoxRec rc = recs[blockIdx.x];
+    const int b = rc.box, lane = threadIdx.x;
+    const double inv_sd = ldexp(1.0, rc.level);
+    const T inv_s = T(inv_sd);
+    for (int r = 0; r < nrhs; ++r) {
+        T acc[KPL];
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) acc[j] = T(0);
+        for (int li = rc.leaf0; li < rc.leaf1; ++li) {
+            const LeafRec lr = t.leafrec[lord[li]];
+            const T ox = T((t.cx[lr.box] - t.cx[b]) * inv_sd), oy = T((t.cy[lr.box] - t.cy[b]) * inv_sd);
+            for (int c0 = lr.begin; c0 < lr.end; c0 += P2M_CHUNK) {
+                const int n = min(P2M_CHUNK, lr.end - c0);
+                T x = T(0), y = T(0), u = T(0);
+                if (lane < n) {
+                    x = t.xl[c0 + lane] * inv_s + ox;
+                    y = t.yl[c0 + lane] * inv_s + oy;
+                    u = us[r * t.N + c0 + lane];
+                }
+                __syncthreads();                 // the previous chunk is no longer read
+                if (lane < n) {
+                    T *row = mono + lane * ld;
+                    monomials<P>(x, -y, [&](int k, T v, bool) { row[k] = v; });
+                    su[lane] = u;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) {
+                    const int k = lane + 64 * j;
+                    if (k < K) acc[j] += lds_dot(mono, ld, k, su, n);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            const int k = lane + 64 * j;
+            if (k < K) M[(size_t(b) * nrhs + r) * t.KS + k] = acc[j];
         }
     }
 }
@@ -721,6 +775,52 @@ __global__ __launch_bounds__(64) void k_m2p_reduce(DTree<T> t, const int32_t *__
         }
 }
 
+// The far field of the paper's Algorithm 1 (Sec. 2.2, eq. MatxVec): every
+// box's multipole is formed from its own points, and evaluated directly at
+// the points of each box of its V list (the well-separated boxes of the same
+// partition not already treated at a coarser one).  One workgroup per leaf:
+// for the leaf and each of its ancestors b, for each box a in b's V list, the
+// multipole of a at the leaf's points (the V-list relation is symmetric, so
+// this visits every pair of Algorithm 1 once), summed per point in FP64 and
+// added to bs.  The multipole, premultiplied by the constants, is staged in LDS.
+template <typename T>
+__global__ __launch_bounds__(64) void k_alg1_far(DTree<T> t, const T *__restrict__ M, const T *__restrict__ wx,
+                                                 int nrhs, double *__restrict__ bs)
+{
+    __shared__ T mw[KMAX + 1];
+    const LeafRec lr = t.leafrec[blockIdx.x];
+    const int P = t.P, K = t.K, lane = threadIdx.x;
+    const double cnd = t.cn[t.set[lr.box]];
+    for (int r = 0; r < nrhs; ++r)
+        for (int i0 = lr.begin; i0 < lr.end; i0 += 64) {
+            const int i = i0 + lane;
+            const bool ok = i < lr.end;
+            const T xi = ok ? t.xl[i] : T(0), yi = ok ? t.yl[i] : T(0);
+            double acc = 0.0;
+            for (int b = lr.box; b >= 0; b = t.parent[b])
+                for (int v = t.v_off[b]; v < t.v_off[b + 1]; ++v) {
+                    const int a = t.v_idx[v];
+                    const double inv_sd = ldexp(1.0, t.level[a]);
+                    const T inv_s = T(inv_sd);
+                    const T ox = T((t.cx[lr.box] - t.cx[a]) * inv_sd), oy = T((t.cy[lr.box] - t.cy[a]) * inv_sd);
+                    const T vz = T(cnd * inv_sd);
+                    __syncthreads();                 // the previous multipole is no longer read
+                    for (int k = lane; k < K; k += 64) mw[k] = M[(size_t(a) * nrhs + r) * t.KS + k] * wx[k];
+                    __syncthreads();
+                    if (ok) {
+                        T sv = T(0);
+                        irregular_even<T>(P, xi * inv_s + ox, yi * inv_s + oy, vz, [&](int n, int m, T re, T im) {
+                            const int k = cidx(n, m);
+                            sv += mw[k] * re;
+                            if (m > 0) sv -= mw[k + 1] * im;
+                        });
+                        acc += double(sv * inv_s);
+                    }
+                }
+            if (ok) bs[r * t.N + i] += acc;
+        }
+}
+
 // Exact rows: b[r*ldb + k] = sum_j A_{rows[k], j} u_j in FP64 over the row's set.
 __global__ __launch_bounds__(256) void k_rows_exact(int nsets, const int64_t *__restrict__ set_off,
                                                     const double *__restrict__ c, const double *__restrict__ xy,
@@ -912,7 +1012,8 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
         hipLaunchKernelGGL((k_p2m_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, t->leaves.as<int32_t>(),     \
                            pd.us.as<T>(), nrhs, M);                                                    \
     else                                                                                               \
-        hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, pd.us.as<T>(), nrhs, M, ld, uv)
+        hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, t->leafrec.as<LeafRec>(),   \
+                           pd.us.as<T>(), nrhs, M, ld, uv)
     IMQ_DISPATCH_P(h.p, IMQ_P2M)
 #undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
@@ -1126,6 +1227,47 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
     return IMQ_OK;
 }
 
+// Algorithm 1 (Sec. 2.2) on sorted, gathered vectors: P2M for every box at
+// the levels that have V lists, the direct near field (which writes bs), then
+// the direct multipole evaluations of k_alg1_far.  In order on s.
+template <typename T>
+imq_status alg1_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
+{
+    const HostTree &h = t->h;
+    if (t->nwpairs > 0 || t->nxpairs > 0) {
+        set_error("Algorithm 1 mode needs the adaptive W/X interactions summed directly (build with a larger direct_max)");
+        return IMQ_EUNSUPPORTED;
+    }
+    PrecData &pd = prec_data<T>(t);
+    DTree<T> v = make_view<T>(t);
+    const int nleaves = int(h.leaves.size());
+    const int K = h.K, ld = K | 1;
+    double *bs = t->bs.as<double>();
+    mark(t, 1, s);
+    const size_t lds_p2m = (size_t(P2M_CHUNK) * ld + P2M_CHUNK) * sizeof(T);
+    if (t->nboxrec > 0) {
+#define IMQ_P2M_ALL(PP)                                                                                  \
+        hipLaunchKernelGGL((k_p2m_box<T, PP>), dim3(unsigned(t->nboxrec)), dim3(64), lds_p2m, s, v,       \
+                           t->boxrec.as<BoxRec>(), t->boxleaf.as<int32_t>(), pd.us.as<T>(), nrhs, pd.M.as<T>(), ld)
+        IMQ_DISPATCH_P(h.p, IMQ_P2M_ALL)
+#undef IMQ_P2M_ALL
+        IMQ_HIP(hipGetLastError());
+    }
+    mark(t, 2, s);
+    mark(t, 3, s);
+    mark(t, 4, s);
+    mark(t, 5, s);
+    launch_p2p<T, false>(s, unsigned(nleaves), v, nleaves, pd.us.as<T>(), nrhs, bs, false);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 6, s);
+    hipLaunchKernelGGL(k_alg1_far<T>, dim3(unsigned(nleaves)), dim3(64), 0, s, v, pd.M.as<T>(), pd.wx.as<T>(),
+                       nrhs, bs);
+    IMQ_HIP(hipGetLastError());
+    mark(t, 7, s);
+    mark(t, 8, s);
+    return IMQ_OK;
+}
+
 template void launch_gemm<double>(hipStream_t, int, int, int, int, const GemmTask *, int, const int32_t *,
                                   const int32_t *, const int32_t *, const double *, int, int,
                                   const double *, double *, int, int, int);
@@ -1171,7 +1313,11 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
     if (st != IMQ_OK) return st;
     g_cur_events = t->stage_events();
     mark(t, 0, s);
-    if (!g_cur_events && nrhs < BATCH_RHS_MIN) {
+    if (t->kcfg.far_field == 1) {
+        if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) == IMQ_OK && (st = alg1_sorted<T>(t, nrhs, s)) == IMQ_OK &&
+            (st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) == IMQ_OK)
+            mark(t, 9, s);
+    } else if (!g_cur_events && nrhs < BATCH_RHS_MIN) {
         // overlapped product: L2P, the last stage, writes b in caller order (no
         // separate scatter).  Reading u through the permutation inside P2M
         // instead of gathering it first was measured slower: it puts a second
