@@ -956,7 +956,8 @@ template <typename T>
 imq_status prep_locals(imq_tree_s *t, int nrhs, hipStream_t s);
 
 // Launch the near field on the tree's second stream once everything queued
-// on s so far (the gathered charges) is done; ev_join marks its completion.
+// on s so far (the gathered charges, P2M and the first shift levels) is done;
+// ev_join marks its completion.
 template <typename T>
 imq_status fork_p2p(imq_tree_s *t, int nrhs, hipStream_t s)
 {
@@ -1020,20 +1021,37 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
     mark(t, 2, s);
     if (fork) {
         // Queued after P2M so that P2M's workgroups are dispatched first: clear L
-        // and form the X pairs on side[1] (they need only the gathered weights),
-        // then the near field, which shares the GPU with the latency-bound
-        // shifts and translations.
+        // and form the X pairs on side[1] (they need only the gathered weights).
+        // The near field, which shares the GPU with the latency-bound shifts
+        // and translations, is forked below.
         IMQ_HIP(hipStreamWaitEvent(t->side[1], t->ev_start, 0));
         imq_status st = prep_locals<T>(t, nrhs, t->side[1]);
         if (st != IMQ_OK) return st;
         IMQ_HIP(hipEventRecord(t->ev_prep, t->side[1]));
-        if ((st = fork_p2p<T>(t, nrhs, s)) != IMQ_OK) return st;
     }
+    // The near field is forked once the two finest upward shift levels are
+    // queued: it slows every latency-bound shift launch it runs beside, and
+    // the first two levels are the widest.  Measured on the 1M mixture
+    // (product ms) by the number of shift levels queued before the fork:
+    // 0: 0.335, 1: 0.337, 2: 0.329, 3: 0.336, 4: 0.345, all 8: 0.374.
+    constexpr int P2P_FORK_AFTER = 2;
+    int nshift = 0;
+    bool forked = !fork;
     for (int l = h.nlev - 2; l >= h.need_m; --l) {
+        if (!forked && nshift == P2P_FORK_AFTER) {
+            imq_status st = fork_p2p<T>(t, nrhs, s);
+            if (st != IMQ_OK) return st;
+            forked = true;
+        }
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
         launch_shift<T>(s, true, t->kcfg.shift_cols, np, nrhs, t->sh_par.as<int32_t>() + p0,
                         t->sh_kids.as<int32_t>() + 4 * size_t(p0), pd.m2m.as<T>(), t->KP, K, K, t->cut_m2m, M,
                         KS, M, KS);
+        ++nshift;
+    }
+    if (!forked) {
+        imq_status st = fork_p2p<T>(t, nrhs, s);
+        if (st != IMQ_OK) return st;
     }
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
@@ -1160,7 +1178,8 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
 // The near field (P2P) depends only on the gathered charges, so it runs on a
 // second stream of the tree, concurrently with the latency-bound shifts and
 // translations (it is forked after P2M, which competes with it for the
-// vector ALUs), and initialises bs; L2P and M2P then add to it.  With stage
+// vector ALUs, and the two finest upward shift levels), and initialises bs;
+// L2P and M2P then add to it.  With stage
 // timing on, every stage runs on the caller's stream in order.
 template <typename T>
 imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
