@@ -67,7 +67,7 @@ struct DTree {
     const int32_t *u_off, *u_idx, *v_off, *v_idx, *v_cls, *w_off, *w_idx, *x_off, *x_idx;
     const int32_t *Klev;
     const LeafRec *leafrec;    // per leaf, in the order of the leaf list
-    const NearLeaf *nleaf;     // per leaf, in the order of the leaf list
+    const NearLeaf *nleaf;     // per leaf, costliest first (not the leaf-list order)
     const double *cn;          // per set: c / side
     const T *xl, *yl;          // leaf-local coordinates, sorted order
     const URec<T> *urec;       // per U-list entry (aligned with u_idx)
@@ -180,7 +180,7 @@ struct imq_tree_s {
     imq::DevBuf boxrec;                    // BoxRec per box at levels >= need_m (Algorithm 1 mode)
     imq::DevBuf boxleaf;                   // leaf-list indices in point order (BoxRec ranges)
     int nboxrec = 0;
-    imq::DevBuf nleaf;                     // NearLeaf per leaf
+    imq::DevBuf nleaf;                     // NearLeaf per leaf, costliest first
     imq::PrecData f64, f32;
     imq::DevGemm g_m2l;
     imq::DevBuf sh_par, sh_kids;           // shift lists (HostTree::sh_*)
