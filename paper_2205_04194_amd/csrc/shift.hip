@@ -88,6 +88,33 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
     __syncthreads();
 
     // stage the source expansions: row = (quadrant, column) or column, k fastest
+    constexpr int TPR = 256 / NROW;                         // threads per staged row
+    constexpr int FPT = KPC / TPR;                          // values per thread
+    if constexpr (sizeof(T) == 4 && 256 % NROW == 0 && FPT % 4 == 0) {
+        // one row per TPR threads, FPT/4 four-value loads each (one column
+        // lookup per thread instead of one per value)
+        const int row = tid / TPR, k0 = (tid % TPR) * FPT;
+        const int col = UP ? s_ci[row / TC][row % TC] : s_pc[row];
+        Q v[FPT / 4];
+#pragma unroll
+        for (int j = 0; j < FPT / 4; ++j) {
+            const int k = k0 + 4 * j;
+            // k + 3 < ldin: the stride is a multiple of 4 and covers kin
+            if (col >= 0 && k < kin) {
+                v[j] = *reinterpret_cast<const Q *>(in + size_t(col) * ldin + k);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (k + e >= kin) v[j].v[e] = T(0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[j].v[e] = T(0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < FPT / 4; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[row * LD + k0 + 4 * j + e] = v[j].v[e];
+    } else
 #pragma unroll
     for (int j0 = 0; j0 < NBT; j0 += BATCH) {
         T v[BATCH];
