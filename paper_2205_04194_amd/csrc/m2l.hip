@@ -170,10 +170,11 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
                 red[(w * TC + cb * 16 + i16) * LDR + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
     __syncthreads();
     const int nk = min(kout - rb0 * 16, RBW * 16);   // output rows of the workgroup
-    for (int e = tid; e < TC * nk; e += 64 * NW) {
-        const int c = e / nk, kk = e - c * nk;
+    constexpr int NKM = RBW * 16;                     // at most: the index math is by a constant
+    for (int e = tid; e < TC * NKM; e += 64 * NW) {
+        const int c = e / NKM, kk = e - c * NKM;
         const int o = s_out[c];
-        if (o < 0) continue;
+        if (o < 0 || kk >= nk) continue;
         T sum = red[c * LDR + kk];
 #pragma unroll
         for (int ww = 1; ww < NW; ++ww) sum += red[(ww * TC + c) * LDR + kk];

@@ -199,10 +199,11 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
                         red[(w * TC + cb * 16 + i16) * LD + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
         __syncthreads();
         const int row0 = rb0 * 16, nrow = min(kout - row0, nrb * 16);
-        for (int e = tid; e < TC * nrow; e += 256) {
-            const int c = e / nrow, k = e - c * nrow;
+        constexpr int NR = RBS * 16;                         // rows of a tile: the index math is by a constant
+        for (int e = tid; e < TC * NR; e += 256) {
+            const int c = e / NR, k = e - c * NR;
             const int pc = s_pc[c];
-            if (pc < 0) continue;
+            if (pc < 0 || k >= nrow) continue;
             out[size_t(pc) * ldout + row0 + k] =
                 ((red[c * LD + k] + red[(TC + c) * LD + k]) + red[(2 * TC + c) * LD + k]) + red[(3 * TC + c) * LD + k];
         }
