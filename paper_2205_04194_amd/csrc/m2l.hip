@@ -86,25 +86,25 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
         for (int cb = 0; cb < NCB; ++cb)
             sb[cb] = (k < SPW && sl < nslot && bl[cb] >= 0) ? src[tk.src0 + bl[cb] * nslot + sl] : -1;
     };
+    // Every lane loads every quad (a missing source or a coefficient past kin
+    // reads box 0 or coefficient 0 and is zeroed after the load): no branch
+    // around the loads, which matters where the vector units are shared.
     auto load_b = [&](const int *sb, Q (*dst)[NRB]) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
+        for (int cb = 0; cb < NCB; ++cb) {
+            const bool okc = sb[cb] >= 0;
+            const T *base = in + (size_t(okc ? sb[cb] : 0) * nrhs + rr[cb]) * KS;
 #pragma unroll
             for (int ci = 0; ci < NRB; ++ci) {
                 const int k0 = ci * 16 + 4 * q;
-                Q x;
-                if (sb[cb] >= 0 && k0 < kin) {
-                    // k0 + 3 < KS: KS is a multiple of 4 and kin <= KS
-                    x = *reinterpret_cast<const Q *>(in + (size_t(sb[cb]) * nrhs + rr[cb]) * KS + k0);
+                // k0 + 3 < KS when k0 < kin: KS is a multiple of 4 and kin <= KS
+                Q x = *reinterpret_cast<const Q *>(base + (k0 < kin ? k0 : 0));
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (k0 + j >= kin) x.v[j] = T(0);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) x.v[j] = T(0);
-                }
+                for (int j = 0; j < 4; ++j)
+                    if (!okc || k0 + j >= kin) x.v[j] = T(0);
                 dst[cb][ci] = x;
             }
+        }
     };
     auto table = [&](int k) -> const T * {
         const int sl = w + NW * k;
