@@ -106,10 +106,12 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
             }
         }
     };
+    // class k of this wave exists (wave-uniform); its table slice, or table
+    // 0 when it does not (loaded all the same, and not used)
+    auto has = [&](int k) { return k < SPW && w + NW * k < nslot; };
     auto table = [&](int k) -> const T * {
-        const int sl = w + NW * k;
-        return (k < SPW && sl < nslot) ? Apk + (size_t(tab[tk.tab0 + sl]) * nrbT + rb0) * nrbT * 256 + lane * 4
-                                       : nullptr;
+        const int tb = has(k) ? tab[tk.tab0 + w + NW * k] : 0;
+        return Apk + (size_t(tb) * nrbT + rb0) * nrbT * 256 + lane * 4;
     };
 
     acc_t acc[RBW][NCB];
@@ -126,14 +128,13 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
     source(0, sbc);
     source(1, sbn);
     const T *Ac = table(0);
-    if (Ac)
 #pragma unroll
-        for (int rb = 0; rb < RBW; ++rb)
+    for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
-            for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = *reinterpret_cast<const Q *>(Ac + (rb * nrbT + ci) * 256);
+        for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = *reinterpret_cast<const Q *>(Ac + (rb * nrbT + ci) * 256);
     load_b(sbc, bc);
     for (int k = 0; k < SPW; ++k) {
-        const bool act = Ac != nullptr;               // wave-uniform
+        const bool act = has(k);                      // wave-uniform
         const T *An = table(k + 1);
         load_b(sbn, bn);
         source(k + 2, sbnn);
@@ -147,10 +148,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
 #pragma unroll
                         for (int cb = 0; cb < NCB; ++cb)
                             acc[rb][cb] = Mfma<T>::mac(a[rb][ci].v[j], bc[cb][ci].v[j], acc[rb][cb]);
-            if (An)
 #pragma unroll
-                for (int ci = 0; ci < NRB; ++ci)
-                    a[rb][ci] = *reinterpret_cast<const Q *>(An + (rb * nrbT + ci) * 256);
+            for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = *reinterpret_cast<const Q *>(An + (rb * nrbT + ci) * 256);
         }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
@@ -158,7 +157,6 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
             for (int ci = 0; ci < NRB; ++ci) bc[cb][ci] = bn[cb][ci];
             sbn[cb] = sbnn[cb];
         }
-        Ac = An;
     }
 
 #pragma unroll
