@@ -95,20 +95,19 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
         // lookup per thread instead of one per value)
         const int row = tid / TPR, k0 = (tid % TPR) * FPT;
         const int col = UP ? s_ci[row / TC][row % TC] : s_pc[row];
+        // every thread loads (a missing child reads column 0, coefficients
+        // past kin read coefficient 0; both are zeroed): no branch around the
+        // loads
+        const T *base = in + size_t(col >= 0 ? col : 0) * ldin;
         Q v[FPT / 4];
 #pragma unroll
         for (int j = 0; j < FPT / 4; ++j) {
             const int k = k0 + 4 * j;
-            // k + 3 < ldin: the stride is a multiple of 4 and covers kin
-            if (col >= 0 && k < kin) {
-                v[j] = *reinterpret_cast<const Q *>(in + size_t(col) * ldin + k);
+            // k + 3 < ldin when k < kin: the stride is a multiple of 4 and covers kin
+            v[j] = *reinterpret_cast<const Q *>(base + (k < kin ? k : 0));
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (k + e >= kin) v[j].v[e] = T(0);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[j].v[e] = T(0);
-            }
+            for (int e = 0; e < 4; ++e)
+                if (col < 0 || k + e >= kin) v[j].v[e] = T(0);
         }
 #pragma unroll
         for (int j = 0; j < FPT / 4; ++j)
