@@ -155,13 +155,12 @@ __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const LeafRec *__restric
     const int lane = threadIdx.x;
     for (int c0 = beg; c0 < end; c0 += P2M_CHUNK) {
         const int n = min(P2M_CHUNK, end - c0);
-        // the point and its first weight are requested together
-        T x = T(0), y = T(0), u0 = T(0);
-        if (lane < n) {
-            x = t.xl[c0 + lane];
-            y = t.yl[c0 + lane];
-            u0 = io.in ? T(io.get(0, c0 + lane)) : us[c0 + lane];
-        }
+        // the point and its first weight are requested together, by every
+        // lane (lanes past the chunk read its first point): no branch around
+        // the loads
+        const int ip = c0 + (lane < n ? lane : 0);
+        const T x = t.xl[ip], y = t.yl[ip];
+        const T u0 = io.in ? T(io.get(0, ip)) : us[ip];
         __syncthreads();
         if (lane < n) {
             T *row = mono + lane * ld;
