@@ -31,7 +31,7 @@ PEAK_TFLOPS_VALU = {"fp64": 78.6, "fp32": 78.6}
 # HBM bytes of one FP32 near-field launch on mixture1m, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a plain 256 MiB copy
 # (profiles/p2p_mixture1m_fp32.md); to be re-measured whenever k_p2p changes.
-P2P_TRAFFIC_BYTES = (60894 * 2.0 + 8636 * 1.0) * 1024
+P2P_TRAFFIC_BYTES = (60919 * 2.0 + 8636 * 1.0) * 1024
 HBM_GBS = 8000.0
 
 
