@@ -88,6 +88,25 @@ imq_status imq_build_tree(int nsets, const int64_t *set_offsets, const double *x
                           const double *c, const imq_tree_params *params,
                           hipStream_t stream, imq_tree *out);
 
+/* Device memory of a tree (its lists, tables and workspaces) from the
+ * caller's allocator instead of hipMalloc/hipFree, e.g. a framework's caching
+ * allocator.  alloc returns at least `bytes` of device memory on the current
+ * device, 256-byte aligned, or NULL on failure (the call then returns
+ * IMQ_ENOMEM); free releases a pointer alloc returned.  Both are called on
+ * the host, from the thread of the imq_ call that needs them (every call on
+ * the tree may allocate; imq_tree_free frees), with `ctx` passed through;
+ * the allocator and ctx must stay valid until imq_tree_free returns. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} imq_allocator;
+
+/* imq_build_tree with the tree's device memory from `alloc` (NULL: hipMalloc). */
+imq_status imq_build_tree_alloc(int nsets, const int64_t *set_offsets, const double *xy,
+                                const double *c, const imq_tree_params *params,
+                                const imq_allocator *alloc, hipStream_t stream, imq_tree *out);
+
 /* b = A u for every set and right-hand side, in the caller's point order.
  *  u : nrhs columns of length Ntot, column r at u + r*ldu (ldu >= Ntot),
  *      element type `dtype`.

@@ -33,6 +33,23 @@ def _dptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _torch_allocator(device) -> "_lib.Allocator":
+    """imq_allocator over PyTorch's caching allocator (the callbacks are kept
+    alive by the returned structure's owner, the Tree)."""
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device)
+        except Exception:          # out of memory: the library reports IMQ_ENOMEM
+            return None
+
+    def free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = _lib.Allocator(_lib.ALLOC_FN(alloc), _lib.FREE_FN(free), None)
+    a._keep = (alloc, free)
+    return a
+
+
 class Tree:
     """A quadtree forest over one or more point sets, resident on the GPU.
 
@@ -44,11 +61,13 @@ class Tree:
     level_order optional per-level truncation of the translations
     direct_max  W/X interactions with at most this many points in the finer
                 box are summed directly (0: 2*leaf, negative: never)
+    allocator   None (the library's hipMalloc) or "torch": the tree's device
+                memory comes from PyTorch's caching allocator
     """
 
     def __init__(self, xy: torch.Tensor, c, leaf: int = 64, p: int = 12,
                  set_offsets: Optional[Sequence[int]] = None, level_order=None,
-                 max_level: int = 0, direct_max: int = 0, stream=None):
+                 max_level: int = 0, direct_max: int = 0, stream=None, allocator=None):
         lib = _lib.load()
         if xy.dim() != 2 or xy.shape[1] != 2:
             raise ValueError("xy must have shape (N, 2)")
@@ -74,9 +93,17 @@ class Tree:
         c_arr = (ctypes.c_double * nsets)(*cs)
         prm = _lib.params(leaf, p, max_level, level_order, direct_max)
         h = ctypes.c_void_p()
+        self._alloc = None
+        if allocator not in (None, "torch"):
+            raise ValueError('allocator must be None or "torch"')
         with torch.cuda.device(self.device):
-            st = lib.imq_build_tree(nsets, off_arr, _dptr(soa), c_arr, ctypes.byref(prm),
-                                    _stream_ptr(stream), ctypes.byref(h))
+            if allocator == "torch":
+                self._alloc = _torch_allocator(self.device)
+                st = lib.imq_build_tree_alloc(nsets, off_arr, _dptr(soa), c_arr, ctypes.byref(prm),
+                                              ctypes.byref(self._alloc), _stream_ptr(stream), ctypes.byref(h))
+            else:
+                st = lib.imq_build_tree(nsets, off_arr, _dptr(soa), c_arr, ctypes.byref(prm),
+                                        _stream_ptr(stream), ctypes.byref(h))
         _lib.check(st, "imq_build_tree")
         self._h = h
 

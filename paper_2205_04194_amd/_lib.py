@@ -42,6 +42,14 @@ class KernelConfig(ctypes.Structure):
                 ("far_field", ctypes.c_int)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 class TreeInfo(ctypes.Structure):
     _fields_ = [("npoints", ctypes.c_int64), ("nboxes", ctypes.c_int64), ("nleaves", ctypes.c_int64),
                 ("depth", ctypes.c_int), ("order_p", ctypes.c_int), ("K", ctypes.c_int),
@@ -64,6 +72,7 @@ _p = ctypes.POINTER
 
 SIGNATURES = {
     "imq_build_tree": (_int, [_int, _p(_i64), _vp, _p(_dbl), _p(TreeParams), _vp, _p(_vp)]),
+    "imq_build_tree_alloc": (_int, [_int, _p(_i64), _vp, _p(_dbl), _p(TreeParams), _p(Allocator), _vp, _p(_vp)]),
     "imq_matvec": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _int, _vp]),
     "imq_build_eval_tree": (_int, [_vp, _i64, _vp, _i64, _dbl, _p(TreeParams), _vp, _p(_vp)]),
     "imq_evaluate": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _int, _vp]),

@@ -284,6 +284,7 @@ static void free_tree(imq_tree_s *t)
 static imq_status check_tree(imq_tree t)
 {
     if (!t) { set_error("null tree handle"); return IMQ_EINVAL; }
+    g_alloc = t->allocator();                 // the tree's buffers come from its allocator
     int dev = -1;
     IMQ_HIP(hipGetDevice(&dev));
     if (dev != t->device) IMQ_HIP(hipSetDevice(t->device));
@@ -372,6 +373,14 @@ const char *imq_stage_name(int k)
 imq_status imq_build_tree(int nsets, const int64_t *set_offsets, const double *xy, const double *c,
                           const imq_tree_params *params, hipStream_t stream, imq_tree *out)
 {
+    return imq_build_tree_alloc(nsets, set_offsets, xy, c, params, nullptr, stream, out);
+}
+
+imq_status imq_build_tree_alloc(int nsets, const int64_t *set_offsets, const double *xy, const double *c,
+                                const imq_tree_params *params, const imq_allocator *alloc, hipStream_t stream,
+                                imq_tree *out)
+{
+    if (alloc && (!alloc->alloc || !alloc->free)) { set_error("allocator without alloc or free"); return IMQ_EINVAL; }
     if (!out) { set_error("out is null"); return IMQ_EINVAL; }
     *out = nullptr;
     if (nsets < 1 || !set_offsets || !xy || !c || !params) { set_error("null argument or nsets < 1"); return IMQ_EINVAL; }
@@ -382,6 +391,8 @@ imq_status imq_build_tree(int nsets, const int64_t *set_offsets, const double *x
     IMQ_HIP(hipStreamSynchronize(stream));
     auto *t = new imq_tree_s();
     IMQ_HIP(hipGetDevice(&t->device));
+    if (alloc) t->alloc = *alloc;
+    g_alloc = t->allocator();
     imq_status st = build_host_tree(nsets, set_offsets, hxy.data(), hxy.data() + N, c, *params, t->h);
     if (st != IMQ_OK) { delete t; return st; }
     st = upload_tree(t, xy);

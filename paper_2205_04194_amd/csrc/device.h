@@ -14,9 +14,13 @@ namespace imq {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    const imq_allocator *al = nullptr;   // the allocator p came from (null: hipMalloc)
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Allocations use the allocator of the tree whose imq_ call is running on this
+// thread (set on entry by every such call; null: hipMalloc).
+extern thread_local const imq_allocator *g_alloc;
 hipError_t dev_alloc(DevBuf &b, size_t bytes);
 void dev_free(DevBuf &b);
 
@@ -186,6 +190,8 @@ struct imq_tree_s {
     imq::DevBuf sh_par, sh_kids;           // shift lists (HostTree::sh_*)
     imq::ShiftCuts cut_m2m = {}, cut_l2l = {}, cut_l2l_odd = {};
     imq_kernel_config kcfg = {};
+    imq_allocator alloc = {};              // the caller's allocator, if alloc.alloc is set
+    const imq_allocator *allocator() const { return alloc.alloc ? &alloc : nullptr; }
     int KP = 0;                            // K rounded up to the MFMA tile (16)
     imq::DevBuf bs;                        // FP64 result accumulator, sorted order
     size_t bs_nrhs = 0;

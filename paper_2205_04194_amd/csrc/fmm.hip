@@ -853,21 +853,37 @@ __global__ __launch_bounds__(256) void k_rows_exact(int nsets, const int64_t *__
 
 // ------------------------------------------------------------------ host side
 
+thread_local const imq_allocator *g_alloc = nullptr;
+
 hipError_t dev_alloc(DevBuf &b, size_t bytes)
 {
     dev_free(b);
     if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(&b.p, bytes);
-    if (e == hipSuccess) b.bytes = bytes;
-    else b.p = nullptr;
+    hipError_t e;
+    if (g_alloc) {
+        b.p = g_alloc->alloc(bytes, g_alloc->ctx);
+        e = b.p ? hipSuccess : hipErrorOutOfMemory;
+    } else {
+        e = hipMalloc(&b.p, bytes);
+    }
+    if (e == hipSuccess) {
+        b.bytes = bytes;
+        b.al = g_alloc;
+    } else {
+        b.p = nullptr;
+    }
     return e;
 }
 
 void dev_free(DevBuf &b)
 {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) {
+        if (b.al) b.al->free(b.p, b.al->ctx);
+        else (void)hipFree(b.p);
+    }
     b.p = nullptr;
     b.bytes = 0;
+    b.al = nullptr;
 }
 
 template <typename T> PrecData &prec_data(imq_tree_s *t);

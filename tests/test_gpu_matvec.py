@@ -220,3 +220,31 @@ def test_near_field_forms_match_the_oracle(imq, c):
         assert err < 1e-5
     assert _rel(out[1], out[0]) < 1e-6
     tree.set_kernel_config()
+
+
+def test_caller_allocator_gives_the_same_products(imq):
+    """A tree whose device memory comes from PyTorch's caching allocator
+    (imq_build_tree_alloc) computes exactly what the default tree computes;
+    its buffers are visible to PyTorch's memory accounting and are returned
+    when the tree is freed."""
+    d = W.small(6000)
+    U = W.uniform_vector(6000, W.rng(69, 1), nrhs=2)
+    base = imq.build_tree(_dev(d["xy"]), d["c"], leaf=32, p=10)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=32, p=10, allocator="torch")
+    held = torch.cuda.memory_allocated() - before
+    for prec in ("fp64", "fp32"):
+        b0 = base.matvec(_dev(U), prec).cpu().numpy()
+        b1 = tree.matvec(_dev(U), prec).cpu().numpy()
+        assert np.array_equal(b0, b1), prec
+    a0, _ = base.solve(_dev(d["u"]), tol=1e-6, max_iters=60)
+    a1, _ = tree.solve(_dev(d["u"]), tol=1e-6, max_iters=60)
+    assert torch.equal(a0, a1)
+    grown = torch.cuda.memory_allocated() - before
+    print(f"caller allocator: {held} bytes after the build, {grown} with workspaces")
+    assert held > 0 and grown >= held
+    tree.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= before + (1 << 20)   # tensors of this test aside
+    base.close()
