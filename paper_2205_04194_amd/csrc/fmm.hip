@@ -138,7 +138,8 @@ __device__ __forceinline__ T lds_dot(const T *a, int ld, int k, const T *w, int 
 // P2M: Mt[n,m] = sum_j u_j |w_j|^(n-m) conj(w_j)^m over a leaf's points.
 // One wave per leaf: each lane writes its point's monomials as one row of
 // an LDS matrix (odd row stride), then each lane sums one coefficient's
-// column against the weights of every right-hand side.
+// column against the weights of every right-hand side.  recs: the leaves,
+// one per workgroup.
 constexpr int P2M_CHUNK = 32;      // points staged per round (LDS per wave halves vs 64)
 
 template <typename T, int P>
