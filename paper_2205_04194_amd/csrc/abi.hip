@@ -250,6 +250,7 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
 
 static void free_tree(imq_tree_s *t)
 {
+    if (g_alloc == &t->alloc) g_alloc = nullptr;   // never left pointing into a freed tree
     DevBuf *bufs[] = {&t->perm, &t->pt_scale, &t->level, &t->set, &t->parent, &t->child0, &t->nchild,
                       &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
@@ -423,6 +424,7 @@ imq_status imq_build_eval_tree(const double *xy_src, int64_t n, const double *xy
     std::vector<double> soa(x);
     soa.insert(soa.end(), y.begin(), y.end());
     DevBuf dxy;
+    g_alloc = nullptr;                                    // a temporary of this call: hipMalloc
     if ((st = upload(dxy, soa)) != IMQ_OK) return st;   // the tree copies what it keeps
     const int64_t offs[2] = {0, N};
     st = imq_build_tree(1, offs, dxy.as<double>(), &c, params, stream, out);

@@ -854,6 +854,10 @@ __global__ __launch_bounds__(256) void k_rows_exact(int nsets, const int64_t *__
 
 // ------------------------------------------------------------------ host side
 
+// The allocator of the tree an entry point is working on (null: hipMalloc).
+// Every entry point that allocates sets it first: the tree builders to the
+// new tree's, the calls on a tree through their argument check; a freed
+// tree's is cleared.  Each buffer remembers the allocator that made it.
 thread_local const imq_allocator *g_alloc = nullptr;
 
 hipError_t dev_alloc(DevBuf &b, size_t bytes)

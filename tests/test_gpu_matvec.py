@@ -247,4 +247,14 @@ def test_caller_allocator_gives_the_same_products(imq):
     tree.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() <= before + (1 << 20)   # tensors of this test aside
+    # the last call before the free was on the caller-allocated tree: a build
+    # after it allocates with hipMalloc again, never through the freed tree
+    src, tgt = d["xy"][:3000], d["xy"][3000:3400]
+    ev = imq.build_eval_tree(_dev(src), d["c"], _dev(tgt), leaf=32, p=10)
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= before + (1 << 20)
+    s = ev.evaluate(_dev(d["u"][:3000])).cpu().numpy()
+    exact = oracle.matvec(src, d["c"], d["u"][:3000], xy_targets=tgt)
+    assert _rel(s, exact) < 1e-6
+    ev.close()
     base.close()
