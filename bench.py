@@ -357,7 +357,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the product runs on one GPU only (no multi-GPU sharding); --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -44,7 +44,7 @@ typedef enum {
     IMQ_EDUPLICATE = -2,    /* two data sites coincide: A would be singular   */
     IMQ_ENOMEM = -3,        /* device or host allocation failed               */
     IMQ_EHIP = -4,          /* a HIP runtime call failed                      */
-    IMQ_EUNSUPPORTED = -5   /* valid request this build does not support      */
+    IMQ_EUNSUPPORTED = -5   /* valid request the library does not support     */
 } imq_status;
 
 /* Element type of the vectors handed across the boundary. */
