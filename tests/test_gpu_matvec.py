@@ -258,3 +258,21 @@ def test_caller_allocator_gives_the_same_products(imq):
     assert _rel(s, exact) < 1e-6
     ev.close()
     base.close()
+
+
+def test_shift_column_tiles_give_the_same_products(imq):
+    """The FP32 shift kernels take parents in 16- or 32-column tiles
+    (shift_cols); the tile width only regroups parents among workgroups, so
+    both give the product to the FP32 target and agree to rounding."""
+    d = W.small(6000)
+    U = W.uniform_vector(6000, W.rng(70, 1), nrhs=3)
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=16, p=10)
+    rows = np.arange(0, 6000, 37)
+    exact = oracle.matvec(d["xy"], d["c"], U, xy_targets=d["xy"][rows])
+    out = {}
+    for cols in (16, 32):
+        tree.set_kernel_config(shift_cols=cols)
+        out[cols] = tree.matvec(_dev(U), "fp32").cpu().numpy()
+        assert _rel(out[cols][:, rows], exact) < 1e-5, cols
+    assert _rel(out[32], out[16]) < 1e-6
+    tree.set_kernel_config()
