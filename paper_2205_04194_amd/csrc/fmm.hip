@@ -1049,12 +1049,13 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
         if (st != IMQ_OK) return st;
         IMQ_HIP(hipEventRecord(t->ev_prep, t->side[1]));
     }
-    // The near field is forked once the two finest upward shift levels are
-    // queued: it slows every latency-bound shift launch it runs beside, and
-    // the first two levels are the widest.  Measured on the 1M mixture
-    // (product ms) by the number of shift levels queued before the fork:
-    // 0: 0.335, 1: 0.337, 2: 0.329, 3: 0.336, 4: 0.345, all 8: 0.374.
-    constexpr int P2P_FORK_AFTER = 2;
+    // The near field is forked once the finest upward shift level is queued:
+    // it slows every latency-bound shift launch it runs beside, and the finest
+    // level is the widest.  Measured on the 1M mixture (product ms, alternating
+    // runs on one GPU) by the number of shift levels queued before the fork:
+    // 0: 0.289-0.296, 1: 0.292-0.295, 2: 0.297-0.298, 3: 0.304; with all
+    // eight queued first the product took 0.374 (an earlier kernel set).
+    constexpr int P2P_FORK_AFTER = 1;
     int nshift = 0;
     bool forked = !fork;
     for (int l = h.nlev - 2; l >= h.need_m; --l) {
@@ -1198,7 +1199,7 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
 // The near field (P2P) depends only on the gathered charges, so it runs on a
 // second stream of the tree, concurrently with the latency-bound shifts and
 // translations (it is forked after P2M, which competes with it for the
-// vector ALUs, and the two finest upward shift levels), and initialises bs;
+// vector ALUs, and the finest upward shift level), and initialises bs;
 // L2P and M2P then add to it.  With stage
 // timing on, every stage runs on the caller's stream in order.
 template <typename T>
