@@ -23,7 +23,10 @@
  *    stream-ordered; only the calls that say so synchronise.
  *  - Errors are returned as a status, never thrown; imq_last_error() gives a
  *    thread-local detail string for the last failing call.
- *  - A tree handle may be used by one stream at a time.
+ *  - A tree handle may be used by one stream at a time.  A call on a handle
+ *    that imq_tree_free has freed returns IMQ_EINVAL.
+ *  - Calls on a tree run on the device the tree was built on; the caller's
+ *    current device is the same after the call as before it.
  */
 #ifndef IMQ_H
 #define IMQ_H
@@ -152,18 +155,31 @@ imq_status imq_evaluate(imq_tree tree, int nrhs, imq_dtype dtype, const void *la
                         int64_t lds, imq_prec prec, hipStream_t stream);
 
 typedef struct {
-    double tol;        /* stop when ||f - A a|| <= tol ||f|| (FP64 product)  */
-    int restart;       /* GMRES restart length m (1 .. 256)                 */
+    double tol;        /* stop when ||f - A~ a|| <= tol ||f||, A~ the FP64
+                          fast product (below)                              */
+    int restart;       /* GMRES restart length m (1 .. 4096)                */
     int max_iters;     /* cap on inner iterations summed over everything     */
     int mixed_ir;      /* 1: FP32 inner GMRES inside FP64 refinement         */
     int max_outer;     /* cap on refinement steps (mixed_ir only; 0 = 10)    */
+    double *history;   /* host, optional (NULL: none): nrhs x max_iters
+                          entries; entry r*max_iters + k is column r's GMRES
+                          residual estimate |g_(k+1)| / ||f_r|| after its
+                          inner iteration k (entries from stats[r].iters on
+                          are not written)                                   */
 } imq_solve_opts;
 
 typedef struct {        /* host */
     int iters;          /* inner GMRES iterations (matrix products)          */
     int outer_iters;    /* refinement steps (1 without mixed_ir)             */
-    int converged;      /* 1 if relres <= tol                                */
-    double relres;      /* final explicit ||f - A a|| / ||f||, FP64 product  */
+    int converged;      /* 1 if relres_fast64 <= tol                         */
+    double relres_fast64; /* final explicit ||f - A~ a|| / ||f||: the residual
+                           of the system the solver solves, whose operator A~
+                           is the FP64 fast product of the tree as configured
+                           (order, per-level orders).  It is not the residual
+                           with the exact A: that differs by (A - A~) a,
+                           which grows with ||a|| and can be far above tol on
+                           ill-conditioned systems; imq_rows_exact gives
+                           exact rows to measure it.                        */
 } imq_solve_stats;
 
 /* Solve A a = f (eq. interp_system) by restarted GMRES on the fast product.
@@ -176,21 +192,28 @@ imq_status imq_solve(imq_tree tree, int nrhs, const double *f, int64_t ldf,
                      double *a, int64_t lda, const imq_solve_opts *opts,
                      imq_solve_stats *stats, hipStream_t stream);
 
-/* Adjoint of b = A(c, X) v for a scalar loss L with upstream g = dL/db.
- * Derivatives of the entries of eq. IMQ_def:
- *   dv   = A g                                   (A is symmetric)
- *   dc[s]= sum_ij g_i v_j dA_ij/dc,  dA_ij/dc = -c (r_ij^2 + c^2)^(-3/2)
- *   dxy  = d/dx_k of sum_ij g_i A_ij v_j
- *        = -sum_j (g_k v_j + v_k g_j)(x_k - x_j)(r_kj^2 + c^2)^(-3/2)
- * for every set s.  v, g, dv: FP64 or FP32 per `dtype` (one column each);
- * dc: device FP64, nsets entries; dxy: device FP64 SoA 2 x Ntot.  The
- * interaction lists are those of `tree`, which must sum its adaptive W/X
+/* Adjoint of B = A(c, X) V (nrhs columns b_r = A v_r) for a scalar loss L
+ * with upstream gradients g_r = dL/db_r.  Derivatives of the entries of
+ * eq. IMQ_def:
+ *   dv_r  = A g_r                                (A is symmetric)
+ *   dc[s] = sum_r sum_ij g_ri v_rj dA_ij/dc,  dA_ij/dc = -c (r_ij^2 + c^2)^(-3/2)
+ *   dxy   = sum_r d/dx_k of sum_ij g_ri A_ij v_rj
+ *         = -sum_r sum_j (g_rk v_rj + v_rk g_rj)(x_k - x_j)(r_kj^2 + c^2)^(-3/2)
+ * for every set s.
+ *  v, g : nrhs columns of length Ntot (leading dimensions ldv, ldg >= Ntot),
+ *         FP64 or FP32 per `dtype`
+ *  dv   : same layout with lddv, same dtype (written)
+ *  dc   : device FP64, nsets entries (written, summed over the columns)
+ *  dxy  : device FP64 SoA 2 x Ntot: d/dx then d/dy (written, summed over the
+ *         columns)
+ * The interaction lists are those of `tree`, which must sum its adaptive W/X
  * interactions directly (built with direct_max >= Ntot), else
  * IMQ_EUNSUPPORTED.  The vertical derivative uses translation tables to the
- * n+m-odd local coefficients, generated on the first call. */
-imq_status imq_matvec_backward(imq_tree tree, imq_dtype dtype, const void *v,
-                               const void *g, void *dv, double *dc, double *dxy,
-                               imq_prec prec, hipStream_t stream);
+ * n+m-odd local coefficients, generated on the first call.  IMQ_EINVAL for
+ * nrhs < 1, a null pointer or a leading dimension below Ntot. */
+imq_status imq_matvec_backward(imq_tree tree, int nrhs, imq_dtype dtype, const void *v, int64_t ldv,
+                               const void *g, int64_t ldg, void *dv, int64_t lddv, double *dc,
+                               double *dxy, imq_prec prec, hipStream_t stream);
 
 /* Launch shape of the batched translations, chosen by the autotuner or by
  * hand; 0 = default.
@@ -264,7 +287,7 @@ imq_status imq_get_tree_info(imq_tree tree, imq_tree_info *info);
  * timing is on, the near field runs on the product's stream between the
  * translations and L2P instead of concurrently with the tree passes, so the
  * stage times add up to a longer product than an untimed one. */
-#define IMQ_NSTAGES 9
+#define IMQ_NSTAGES 10
 imq_status imq_set_stage_timing(imq_tree tree, int on);
 imq_status imq_get_stage_times(imq_tree tree, double *ms);
 const char *imq_stage_name(int stage);

@@ -51,6 +51,8 @@ def _load():
         lib.imq_oracle_grad.restype = None
         lib.imq_oracle_threads.argtypes = []
         lib.imq_oracle_threads.restype = ctypes.c_int
+        lib.imq_oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.imq_oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -66,6 +68,11 @@ def _f64(a) -> np.ndarray:
 def threads() -> int:
     """Number of OpenMP threads the C oracle runs with."""
     return int(_load().imq_oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the C oracle's loops on n threads (results do not depend on n)."""
+    _load().imq_oracle_set_threads(int(n))
 
 
 # ----------------------------------------------------------------------------

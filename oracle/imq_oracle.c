@@ -64,6 +64,17 @@ int imq_oracle_threads(void)
 #endif
 }
 
+/* Threads of the following parallel loops (n >= 1); the arithmetic of every
+ * row is the same whatever the count. */
+void imq_oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * b[r*ldb + i] = sum_j A(t_i, s_j) u[r*ldu + j]  for i < nt, r < nrhs.
  * Targets (xt, yt) and sources (xs, ys) may be the same arrays.

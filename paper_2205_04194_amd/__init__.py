@@ -33,6 +33,21 @@ def _dptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _check_vec(t: torch.Tensor, name: str, n: int, device, allow_2d: bool = True) -> None:
+    """Reject a tensor that the library would read out of bounds or from host
+    memory: it must be a float64/float32 tensor on the tree's device, of
+    shape (n,) or (nrhs, n)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda or t.device != device:
+        raise ValueError(f"{name} must be on the tree's device {device} (got {t.device})")
+    if t.dtype not in (torch.float64, torch.float32):
+        raise ValueError(f"{name} must be float64 or float32 (got {t.dtype})")
+    if t.dim() not in ((1, 2) if allow_2d else (1,)) or t.shape[-1] != n or (t.dim() == 2 and t.shape[0] < 1):
+        want = f"({n},) or (nrhs, {n})" if allow_2d else f"({n},)"
+        raise ValueError(f"{name} must have shape {want} (got {tuple(t.shape)})")
+
+
 def _torch_allocator(device) -> "_lib.Allocator":
     """imq_allocator over PyTorch's caching allocator (the callbacks are kept
     alive by the returned structure's owner, the Tree)."""
@@ -142,12 +157,9 @@ class Tree:
     def evaluate(self, lam: torch.Tensor, prec: str = "fp64", stream=None) -> torch.Tensor:
         """Interpolant sum_j lam_j phi(|y_k - x_j|) at the evaluation points: (m,) or (nrhs, m)."""
         lib = _lib.load()
+        _check_vec(lam, "lam", self.n_src, self.device)
         one = lam.dim() == 1
         l2 = (lam.unsqueeze(0) if one else lam).contiguous()
-        if l2.shape[1] != self.n_src:
-            raise ValueError("lam has the wrong length")
-        if l2.dtype not in (torch.float64, torch.float32):
-            raise ValueError("lam must be float64 or float32")
         s = torch.empty((l2.shape[0], self.m_eval), dtype=l2.dtype, device=self.device)
         dt = _lib.F64 if l2.dtype == torch.float64 else _lib.F32
         with torch.cuda.device(self.device):
@@ -160,12 +172,9 @@ class Tree:
     def matvec(self, u: torch.Tensor, prec: str = "fp64", stream=None) -> torch.Tensor:
         """b = A u; u is (N,) or (nrhs, N), float64 or float32, on the tree's device."""
         lib = _lib.load()
+        _check_vec(u, "u", self.n, self.device)
         one = u.dim() == 1
         u2 = (u.unsqueeze(0) if one else u).contiguous()
-        if u2.shape[1] != self.n:
-            raise ValueError("u has the wrong length")
-        if u2.dtype not in (torch.float64, torch.float32):
-            raise ValueError("u must be float64 or float32")
         b = torch.empty_like(u2)
         dt = _lib.F64 if u2.dtype == torch.float64 else _lib.F32
         with torch.cuda.device(self.device):
@@ -177,9 +186,14 @@ class Tree:
     def rows_exact(self, u: torch.Tensor, rows: torch.Tensor, stream=None) -> torch.Tensor:
         """Exact FP64 rows of A u (direct sums) for the given row indices."""
         lib = _lib.load()
+        _check_vec(u, "u", self.n, self.device)
         one = u.dim() == 1
         u2 = (u.unsqueeze(0) if one else u).to(torch.float64).contiguous()
         rows = rows.to(device=self.device, dtype=torch.int64).contiguous()
+        if rows.dim() != 1:
+            raise ValueError("rows must be a 1-D index tensor")
+        if rows.numel() and (int(rows.min()) < 0 or int(rows.max()) >= self.n):
+            raise ValueError("row index out of range")
         b = torch.empty((u2.shape[0], rows.numel()), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             st = lib.imq_rows_exact(self._h, u2.shape[0], _dptr(u2), self.n, rows.numel(),
@@ -190,40 +204,60 @@ class Tree:
     # ----------------------------------------------------------------- solve
     def solve(self, f: torch.Tensor, tol: float = 1e-10, restart: int = 50,
               max_iters: int = 2000, mixed_ir: bool = False, max_outer: int = 10,
-              a0: Optional[torch.Tensor] = None, stream=None):
-        """GMRES on the fast product: returns (a, stats list)."""
+              a0: Optional[torch.Tensor] = None, history: bool = False, stream=None):
+        """GMRES on the fast product: returns (a, stats).  stats["relres_fast64"]
+        is the final residual with the FP64 fast product (the operator the
+        solver works with), not with the exact matrix."""
         lib = _lib.load()
+        _check_vec(f, "f", self.n, self.device)
         one = f.dim() == 1
         f2 = (f.unsqueeze(0) if one else f).to(torch.float64).contiguous()
-        a = torch.zeros_like(f2) if a0 is None else \
-            (a0.unsqueeze(0) if one else a0).to(torch.float64).contiguous().clone()
+        if a0 is None:
+            a = torch.zeros_like(f2)
+        else:
+            _check_vec(a0, "a0", self.n, self.device)
+            if a0.shape != f.shape:
+                raise ValueError(f"a0 must have the shape of f {tuple(f.shape)} (got {tuple(a0.shape)})")
+            a = (a0.unsqueeze(0) if one else a0).to(torch.float64).contiguous().clone()
         nrhs = f2.shape[0]
+        hist = (ctypes.c_double * (nrhs * int(max_iters)))() if history else None
         opts = _lib.SolveOpts(float(tol), int(restart), int(max_iters), int(bool(mixed_ir)),
-                              int(max_outer))
+                              int(max_outer), hist)
         stats = (_lib.SolveStats * nrhs)()
         with torch.cuda.device(self.device):
             st = lib.imq_solve(self._h, nrhs, _dptr(f2), self.n, _dptr(a), self.n,
                                ctypes.byref(opts), stats, _stream_ptr(stream))
         _lib.check(st, "imq_solve", allow_not_converged=True)
         out = [dict(iters=s.iters, outer_iters=s.outer_iters, converged=bool(s.converged),
-                    relres=s.relres) for s in stats]
+                    relres_fast64=s.relres_fast64) for s in stats]
+        if history:
+            for r, d in enumerate(out):
+                d["history"] = list(hist[r * int(max_iters):r * int(max_iters) + min(d["iters"], int(max_iters))])
         return (a[0] if one else a), (out[0] if one else out)
 
     # ----------------------------------------------------------------- adjoint
     def backward(self, v: torch.Tensor, g: torch.Tensor, prec: str = "fp64", stream=None):
-        """(A g, dL/dc per set, dL/dxy) for the upstream gradient g = dL/d(A v)."""
+        """Adjoint of B = A(c, X) V for upstream G = dL/dB: returns
+        (A G, dL/dc per set, dL/dxy), with v and g of shape (N,) or (nrhs, N)
+        (the derivatives in c and xy summed over the columns)."""
         lib = _lib.load()
+        _check_vec(v, "v", self.n, self.device)
+        _check_vec(g, "g", self.n, self.device)
+        if g.shape != v.shape:
+            raise ValueError(f"g must have the shape of v {tuple(v.shape)} (got {tuple(g.shape)})")
         dt = _lib.F64 if v.dtype == torch.float64 else _lib.F32
-        v = v.contiguous()
-        g = g.to(v.dtype).contiguous()
-        dv = torch.empty_like(v)
+        one = v.dim() == 1
+        v2 = (v.unsqueeze(0) if one else v).contiguous()
+        g2 = (g.unsqueeze(0) if one else g).to(v.dtype).contiguous()
+        nrhs = v2.shape[0]
+        dv = torch.empty_like(v2)
         dc = torch.zeros(self.nsets, dtype=torch.float64, device=self.device)
         dxy = torch.zeros((2, self.n), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
-            st = lib.imq_matvec_backward(self._h, dt, _dptr(v), _dptr(g), _dptr(dv), _dptr(dc),
-                                         _dptr(dxy), PREC[prec], _stream_ptr(stream))
+            st = lib.imq_matvec_backward(self._h, nrhs, dt, _dptr(v2), self.n, _dptr(g2), self.n, _dptr(dv),
+                                         self.n, _dptr(dc), _dptr(dxy), PREC[prec], _stream_ptr(stream))
         _lib.check(st, "imq_matvec_backward")
-        return dv, dc, dxy.t()
+        return (dv[0] if one else dv), dc, dxy.t()
 
     # ----------------------------------------------------------------- info
     def info(self) -> dict:
@@ -289,19 +323,24 @@ def solve(tree: Tree, f: torch.Tensor, **kw):
 
 
 class IMQMatvec(torch.autograd.Function):
-    """b = A(c, X) v with gradients for v, c and X through the adjoint kernels.
+    """B = A(c, X) V with gradients for V, c and X through the adjoint kernels.
 
+    xy: (N, 2) cuda tensor; c: a float or a 0-d tensor (a gradient for c is
+    returned only when c is a tensor that requires it); v: (N,) or (nrhs, N).
     The tree is rebuilt from the saved (X, c) in backward, so no interaction
     list is kept alive between the passes.
     """
 
     @staticmethod
     def forward(ctx, xy, c, v, leaf: int = 64, p: int = 12, prec: str = "fp64"):
-        tree = Tree(xy.detach(), float(c), leaf=leaf, p=p)
+        cval = float(c)
+        tree = Tree(xy.detach(), cval, leaf=leaf, p=p)
         b = tree.matvec(v.detach(), prec)
         tree.close()
         ctx.save_for_backward(xy, v)
-        ctx.c = float(c)
+        ctx.c = cval
+        ctx.c_is_tensor = isinstance(c, torch.Tensor)
+        ctx.c_dtype = c.dtype if ctx.c_is_tensor else None
         ctx.cfg = (leaf, p, prec)
         return b
 
@@ -312,6 +351,11 @@ class IMQMatvec(torch.autograd.Function):
         # the lists are rebuilt here (not kept from forward), with every
         # adaptive W/X interaction in the direct near field
         tree = Tree(xy.detach(), ctx.c, leaf=leaf, p=p, direct_max=1 << 30)
-        dv, dc, dxy = tree.backward(v.detach(), gb.detach(), prec)
+        dv, dc, dxy = tree.backward(v.detach(), gb.detach().to(v.dtype).contiguous(), prec)
         tree.close()
-        return dxy.to(xy.dtype), dc[0].to(torch.float64), dv.to(v.dtype), None, None, None
+        gxy = dxy.to(xy.dtype) if ctx.needs_input_grad[0] else None
+        gc = None
+        if ctx.c_is_tensor and ctx.needs_input_grad[1]:
+            gc = dc[0].to(ctx.c_dtype)
+        gv = dv.to(v.dtype) if ctx.needs_input_grad[2] else None
+        return gxy, gc, gv, None, None, None

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libimq.so")
 
 IMQ_MAX_LEVELS = 31
-IMQ_NSTAGES = 9
+IMQ_NSTAGES = 10
 
 STATUS = {0: "IMQ_OK", 1: "IMQ_ENOTCONVERGED", -1: "IMQ_EINVAL", -2: "IMQ_EDUPLICATE",
           -3: "IMQ_ENOMEM", -4: "IMQ_EHIP", -5: "IMQ_EUNSUPPORTED"}
@@ -27,12 +27,13 @@ class TreeParams(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
-                ("mixed_ir", ctypes.c_int), ("max_outer", ctypes.c_int)]
+                ("mixed_ir", ctypes.c_int), ("max_outer", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double))]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("converged", ctypes.c_int),
-                ("relres", ctypes.c_double)]
+                ("relres_fast64", ctypes.c_double)]
 
 
 class KernelConfig(ctypes.Structure):
@@ -78,7 +79,7 @@ SIGNATURES = {
     "imq_evaluate": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _int, _vp]),
     "imq_rows_exact": (_int, [_vp, _int, _vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "imq_solve": (_int, [_vp, _int, _vp, _i64, _vp, _i64, _p(SolveOpts), _p(SolveStats), _vp]),
-    "imq_matvec_backward": (_int, [_vp, _int, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
+    "imq_matvec_backward": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _int, _vp]),
     "imq_get_tree_info": (_int, [_vp, _p(TreeInfo)]),
     "imq_set_kernel_config": (_int, [_vp, _p(KernelConfig)]),
     "imq_set_level_orders": (_int, [_vp, _int, _p(_int)]),

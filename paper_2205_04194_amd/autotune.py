@@ -6,7 +6,7 @@ compared on a sample of rows with exact FP64 direct sums computed on the GPU
 (``Tree.rows_exact``).  The cost model of Sec. 2.3 is not used; the time of a
 configuration is measured with events.
 
-Search (all on one tree, no rebuild):
+Search on one tree (``tune``, no rebuild):
   1. for each precision, the uniform order p is lowered from the tree's order
      while the sampled error stays within the target;
   2. per level, deepest first, the translation order is lowered while the
@@ -14,6 +14,10 @@ Search (all on one tree, no rebuild):
      levels, whose boxes are small next to c, converge fastest);
   3. the M2L kernel choice (register streaming or staged GEMM) and the staged
      GEMM's pipeline depth and row split are timed and the fastest kept.
+``tune_tree`` then rebuilds the tree at the highest tuned order (multipoles
+need no more), and ``tune_leaf`` repeats all of it for several leaf
+capacities, keeping the fastest tree: the level/leaf trade-off of the cost
+model of Sec. 2.3 (eq. total_cost), measured instead of modelled.
 """
 from __future__ import annotations
 
@@ -123,3 +127,43 @@ def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"
     best.error = _error(tree, u, rows, exact, best.precision)
     best.trials = trials
     return best
+
+
+def tune_tree(xy: torch.Tensor, c, u: torch.Tensor, leaf: int = 64, p: int = 12, target: float = 1e-6,
+              precisions=("fp64",), seed: int = 1, **tree_kw):
+    """Build a tree over ``xy``, tune it with :func:`tune`, and rebuild it at
+    the highest tuned order when that is below ``p`` (P2M, M2M and the W-list
+    evaluations then do less work).  Returns (tree, TuneResult)."""
+    from . import build_tree
+    tree = build_tree(xy, c, leaf=leaf, p=p, **tree_kw)
+    res = tune(tree, u, target=target, precisions=precisions, seed=seed)
+    pmax = max(res.level_orders)
+    if pmax < p:
+        tree.close()
+        tree = build_tree(xy, c, leaf=leaf, p=pmax, **tree_kw)
+        tree.set_level_orders(res.level_orders)
+        tree.set_kernel_config(m2l_kc=res.m2l_kc, m2l_split=res.m2l_split, m2l_mode=res.m2l_mode)
+    return tree, res
+
+
+def tune_leaf(xy: torch.Tensor, c, u: torch.Tensor, leaves=(32, 48, 64), p: int = 12, target: float = 1e-6,
+              precisions=("fp64",), seed: int = 1, reps: int = 10, **tree_kw):
+    """:func:`tune_tree` for every leaf capacity in ``leaves``; the fastest
+    tuned tree is returned (the others are freed) with its TuneResult and a
+    list of per-leaf records (leaf, precision, orders, error, ms)."""
+    best, rec = None, []
+    for leaf in leaves:
+        tree, res = tune_tree(xy, c, u, leaf=leaf, p=p, target=target, precisions=precisions, seed=seed,
+                              **tree_kw)
+        ms = _time(tree, u, res.precision, reps)
+        rec.append({"leaf": leaf, "precision": res.precision, "level_orders": res.level_orders,
+                    "error": res.error, "ms": ms})
+        if best is None or ms < best[2]:
+            if best is not None:
+                best[0].close()
+            best = (tree, res, ms, leaf)
+        else:
+            tree.close()
+    tree, res, _, leaf = best
+    res.leaf = leaf
+    return tree, res, rec

@@ -7,8 +7,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_set>
 #include <vector>
 
 namespace imq {
@@ -22,10 +24,10 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
 imq_status rows_exact(imq_tree_s *t, int nrhs, const double *u, int64_t ldu, int64_t nrows,
                       const int64_t *rows, double *b, int64_t ldb, hipStream_t s);
 imq_status solve_one(imq_tree_s *t, const double *f_user, double *a_user, const imq_solve_opts &o,
-                     imq_solve_stats &stats, hipStream_t s);
+                     imq_solve_stats &stats, double *history, hipStream_t s);
 template <typename T, typename Tio>
 imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, double *dc, double *dxy,
-                          hipStream_t s);
+                          int accumulate, hipStream_t s);
 
 template <typename V>
 static imq_status upload(DevBuf &d, const std::vector<V> &h)
@@ -282,15 +284,59 @@ static void free_tree(imq_tree_s *t)
     delete t;
 }
 
-static imq_status check_tree(imq_tree t)
+// Handles of the trees that exist: a call on a freed handle is rejected with
+// IMQ_EINVAL instead of reading freed memory (an address reused by a later
+// tree is that tree's handle).
+static std::mutex g_live_mu;
+static std::unordered_set<const imq_tree_s *> g_live;
+
+static void live_add(const imq_tree_s *t)
 {
-    if (!t) { set_error("null tree handle"); return IMQ_EINVAL; }
-    g_alloc = t->allocator();                 // the tree's buffers come from its allocator
-    int dev = -1;
-    IMQ_HIP(hipGetDevice(&dev));
-    if (dev != t->device) IMQ_HIP(hipSetDevice(t->device));
-    return IMQ_OK;
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert(t);
 }
+
+static bool live_remove(const imq_tree_s *t)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return g_live.erase(t) > 0;
+}
+
+static bool live_has(const imq_tree_s *t)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return g_live.count(t) > 0;
+}
+
+// Entry of every call on a tree: checks the handle, makes the tree's device
+// current and selects the tree's allocator; the caller's device is current
+// again when the call returns.
+struct TreeCall {
+    imq_status st = IMQ_OK;
+    int prev = -1;
+    explicit TreeCall(imq_tree t)
+    {
+        if (!t) { set_error("null tree handle"); st = IMQ_EINVAL; return; }
+        if (!live_has(t)) { set_error("tree handle was freed or never built"); st = IMQ_EINVAL; return; }
+        g_alloc = t->allocator();                 // the tree's buffers come from its allocator
+        int dev = -1;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess && dev != t->device) {
+            e = hipSetDevice(t->device);
+            if (e == hipSuccess) prev = dev;
+        }
+        if (e != hipSuccess) {
+            set_error(std::string("selecting the tree's device: ") + hipGetErrorString(e));
+            st = IMQ_EHIP;
+        }
+    }
+    ~TreeCall()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    TreeCall(const TreeCall &) = delete;
+    TreeCall &operator=(const TreeCall &) = delete;
+};
 
 namespace {
 // the product's input: the coefficients at the data sites, zero at the
@@ -366,8 +412,8 @@ const char *imq_status_string(imq_status s)
 
 const char *imq_stage_name(int k)
 {
-    static const char *names[IMQ_NSTAGES] = {"gather", "p2m", "m2m", "m2l", "p2l+l2l",
-                                             "p2p", "l2p", "m2p", "scatter"};
+    static const char *names[IMQ_NSTAGES] = {"gather", "p2m", "m2m", "p2l", "m2l",
+                                             "l2l", "p2p", "l2p", "m2p", "scatter"};
     return (k >= 0 && k < IMQ_NSTAGES) ? names[k] : "?";
 }
 
@@ -391,13 +437,19 @@ imq_status imq_build_tree_alloc(int nsets, const int64_t *set_offsets, const dou
     IMQ_HIP(hipMemcpyAsync(hxy.data(), xy, sizeof(double) * 2 * size_t(N), hipMemcpyDeviceToHost, stream));
     IMQ_HIP(hipStreamSynchronize(stream));
     auto *t = new imq_tree_s();
-    IMQ_HIP(hipGetDevice(&t->device));
+    const hipError_t e = hipGetDevice(&t->device);
+    if (e != hipSuccess) {
+        delete t;
+        set_error(std::string("hipGetDevice: ") + hipGetErrorString(e));
+        return IMQ_EHIP;
+    }
     if (alloc) t->alloc = *alloc;
     g_alloc = t->allocator();
     imq_status st = build_host_tree(nsets, set_offsets, hxy.data(), hxy.data() + N, c, *params, t->h);
     if (st != IMQ_OK) { delete t; return st; }
     st = upload_tree(t, xy);
     if (st != IMQ_OK) { free_tree(t); return st; }
+    live_add(t);
     *out = t;
     return IMQ_OK;
 }
@@ -445,8 +497,9 @@ imq_status imq_build_eval_tree(const double *xy_src, int64_t n, const double *xy
 imq_status imq_evaluate(imq_tree t, int nrhs, imq_dtype dtype, const void *lambda, int64_t ldl, void *s,
                         int64_t lds, imq_prec prec, hipStream_t stream)
 {
-    imq_status st = check_tree(t);
-    if (st != IMQ_OK) return st;
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    imq_status st = IMQ_OK;
     if (t->eval_n < 0) { set_error("not an evaluation tree (imq_build_eval_tree)"); return IMQ_EINVAL; }
     if (nrhs < 1 || nrhs > 65535 || !lambda || ldl < t->eval_n || (t->eval_m > 0 && (!s || lds < t->eval_m))) {
         set_error("bad nrhs, pointer or leading dimension");
@@ -463,8 +516,9 @@ imq_status imq_evaluate(imq_tree t, int nrhs, imq_dtype dtype, const void *lambd
 imq_status imq_matvec(imq_tree t, int nrhs, imq_dtype dtype, const void *u, int64_t ldu, void *b,
                       int64_t ldb, imq_prec prec, hipStream_t stream)
 {
-    imq_status st = check_tree(t);
-    if (st != IMQ_OK) return st;
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    imq_status st = IMQ_OK;
     if (nrhs < 1 || !u || !b || ldu < t->h.N || ldb < t->h.N) { set_error("bad nrhs, pointer or leading dimension"); return IMQ_EINVAL; }
     if (dtype == IMQ_F64 && prec == IMQ_PREC_FP64)
         return matvec_typed<double, double>(t, nrhs, (const double *)u, ldu, (double *)b, ldb, stream);
@@ -481,8 +535,9 @@ imq_status imq_matvec(imq_tree t, int nrhs, imq_dtype dtype, const void *u, int6
 imq_status imq_rows_exact(imq_tree t, int nrhs, const double *u, int64_t ldu, int64_t nrows,
                           const int64_t *rows, double *b, int64_t ldb, hipStream_t stream)
 {
-    imq_status st = check_tree(t);
-    if (st != IMQ_OK) return st;
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    imq_status st = IMQ_OK;
     if (nrhs < 1 || nrows < 0 || (nrows > 0 && (!u || !rows || !b)) || ldu < t->h.N || ldb < nrows) {
         set_error("bad argument to imq_rows_exact");
         return IMQ_EINVAL;
@@ -498,7 +553,9 @@ imq_status imq_rows_exact(imq_tree t, int nrhs, const double *u, int64_t ldu, in
 
 imq_status imq_get_tree_info(imq_tree t, imq_tree_info *info)
 {
-    if (!t || !info) { set_error("null argument"); return IMQ_EINVAL; }
+    if (!info) { set_error("null argument"); return IMQ_EINVAL; }
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
     const HostTree &h = t->h;
     info->npoints = h.N;
     info->nboxes = int64_t(h.level.size());
@@ -528,7 +585,9 @@ imq_status imq_get_tree_info(imq_tree t, imq_tree_info *info)
 
 imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
 {
-    if (!t || !cfg) { set_error("null argument"); return IMQ_EINVAL; }
+    if (!cfg) { set_error("null argument"); return IMQ_EINVAL; }
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
     auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
     if (!ok_kc(cfg->m2l_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
         (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32) ||
@@ -543,8 +602,9 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
 
 imq_status imq_set_level_orders(imq_tree t, int nlevels, const int *orders)
 {
-    imq_status st = check_tree(t);
-    if (st != IMQ_OK) return st;
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    imq_status st = IMQ_OK;
     if (nlevels < 0 || (nlevels > 0 && !orders)) { set_error("bad level orders"); return IMQ_EINVAL; }
     HostTree &h = t->h;
     for (int l = 0; l < nlevels && l < h.nlev; ++l)
@@ -559,8 +619,9 @@ imq_status imq_set_level_orders(imq_tree t, int nlevels, const int *orders)
 
 imq_status imq_set_stage_timing(imq_tree t, int on)
 {
-    imq_status st = check_tree(t);
-    if (st != IMQ_OK) return st;
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    imq_status st = IMQ_OK;
     if (on && t->ev.empty()) {
         t->ev.assign(size_t(imq_tree_s::TIMING_RING) * (IMQ_NSTAGES + 1), nullptr);
         for (auto &e : t->ev) IMQ_HIP(hipEventCreate(&e));
@@ -572,8 +633,9 @@ imq_status imq_set_stage_timing(imq_tree t, int on)
 
 imq_status imq_get_stage_times(imq_tree t, double *ms)
 {
-    imq_status st = check_tree(t);
-    if (st != IMQ_OK) return st;
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    imq_status st = IMQ_OK;
     if (!ms) { set_error("null argument"); return IMQ_EINVAL; }
     for (int k = 0; k < IMQ_NSTAGES; ++k) ms[k] = 0.0;
     const int n = t->ev_used;
@@ -591,7 +653,13 @@ imq_status imq_get_stage_times(imq_tree t, double *ms)
 
 void imq_tree_free(imq_tree t)
 {
-    if (t) free_tree(t);
+    if (t && live_remove(t)) {
+        int dev = -1;
+        const bool other = hipGetDevice(&dev) == hipSuccess && dev != t->device &&
+                           hipSetDevice(t->device) == hipSuccess;
+        free_tree(t);
+        if (other) (void)hipSetDevice(dev);
+    }
 }
 
 // ------------------------------------------------------------------ host-only hooks
@@ -666,47 +734,69 @@ int64_t imq_debug_eval_points(int64_t n, const double *xs, const double *ys, int
 imq_status imq_solve(imq_tree t, int nrhs, const double *f, int64_t ldf, double *a, int64_t lda,
                      const imq_solve_opts *opts, imq_solve_stats *stats, hipStream_t stream)
 {
-    imq_status st = check_tree(t);
-    if (st != IMQ_OK) return st;
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    imq_status st = IMQ_OK;
     if (nrhs < 1 || !f || !a || !opts || !stats || ldf < t->h.N || lda < t->h.N) {
         set_error("bad argument to imq_solve");
         return IMQ_EINVAL;
     }
-    if (!(opts->tol > 0.0) || opts->restart < 1 || opts->restart > 256 || opts->max_iters < 1 ||
+    if (!(opts->tol > 0.0) || opts->restart < 1 || opts->restart > 4096 || opts->max_iters < 1 ||
         opts->max_outer < 0) {
-        set_error("solve options out of range (tol > 0, 1 <= restart <= 256, max_iters >= 1)");
+        set_error("solve options out of range (tol > 0, 1 <= restart <= 4096, max_iters >= 1)");
         return IMQ_EINVAL;
     }
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
-        st = solve_one(t, f + size_t(r) * ldf, a + size_t(r) * lda, *opts, stats[r], stream);
+        st = solve_one(t, f + size_t(r) * ldf, a + size_t(r) * lda, *opts, stats[r],
+                       opts->history ? opts->history + size_t(r) * opts->max_iters : nullptr, stream);
         if (st != IMQ_OK) return st;
         all = all && stats[r].converged;
     }
     return all ? IMQ_OK : IMQ_ENOTCONVERGED;
 }
 
-imq_status imq_matvec_backward(imq_tree t, imq_dtype dtype, const void *v, const void *g, void *dv,
-                               double *dc, double *dxy, imq_prec prec, hipStream_t stream)
+imq_status imq_matvec_backward(imq_tree t, int nrhs, imq_dtype dtype, const void *v, int64_t ldv,
+                               const void *g, int64_t ldg, void *dv, int64_t lddv, double *dc, double *dxy,
+                               imq_prec prec, hipStream_t stream)
 {
-    imq_status st = check_tree(t);
-    if (st != IMQ_OK) return st;
-    if (!v || !g || !dv || !dc || !dxy) { set_error("null argument to imq_matvec_backward"); return IMQ_EINVAL; }
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    const int64_t N = t->h.N;
+    if (nrhs < 1 || !v || !g || !dv || !dc || !dxy || ldv < N || ldg < N || lddv < N) {
+        set_error("bad nrhs, pointer or leading dimension in imq_matvec_backward");
+        return IMQ_EINVAL;
+    }
     if (t->nwpairs > 0 || t->nxpairs > 0) {
         set_error("the adjoint needs a tree whose adaptive W/X interactions are summed directly "
                   "(build it with direct_max >= the number of points)");
         return IMQ_EUNSUPPORTED;
     }
-    if (dtype == IMQ_F64 && prec == IMQ_PREC_FP64)
-        return backward_typed<double, double>(t, (const double *)v, (const double *)g, (double *)dv, dc, dxy, stream);
-    if (dtype == IMQ_F32 && prec == IMQ_PREC_FP64)
-        return backward_typed<double, float>(t, (const float *)v, (const float *)g, (float *)dv, dc, dxy, stream);
-    if (dtype == IMQ_F64 && prec == IMQ_PREC_FP32)
-        return backward_typed<float, double>(t, (const double *)v, (const double *)g, (double *)dv, dc, dxy, stream);
-    if (dtype == IMQ_F32 && prec == IMQ_PREC_FP32)
-        return backward_typed<float, float>(t, (const float *)v, (const float *)g, (float *)dv, dc, dxy, stream);
-    set_error("unknown dtype or precision");
-    return IMQ_EINVAL;
+    if ((dtype != IMQ_F64 && dtype != IMQ_F32) || (prec != IMQ_PREC_FP64 && prec != IMQ_PREC_FP32)) {
+        set_error("unknown dtype or precision");
+        return IMQ_EINVAL;
+    }
+    const size_t es = dtype == IMQ_F64 ? sizeof(double) : sizeof(float);
+    for (int r = 0; r < nrhs; ++r) {
+        const char *vr = static_cast<const char *>(v) + size_t(r) * ldv * es;
+        const char *gr = static_cast<const char *>(g) + size_t(r) * ldg * es;
+        char *dvr = static_cast<char *>(dv) + size_t(r) * lddv * es;
+        imq_status st;
+        if (dtype == IMQ_F64 && prec == IMQ_PREC_FP64)
+            st = backward_typed<double, double>(t, (const double *)vr, (const double *)gr, (double *)dvr, dc, dxy,
+                                                r > 0, stream);
+        else if (dtype == IMQ_F32 && prec == IMQ_PREC_FP64)
+            st = backward_typed<double, float>(t, (const float *)vr, (const float *)gr, (float *)dvr, dc, dxy,
+                                               r > 0, stream);
+        else if (dtype == IMQ_F64)
+            st = backward_typed<float, double>(t, (const double *)vr, (const double *)gr, (double *)dvr, dc, dxy,
+                                               r > 0, stream);
+        else
+            st = backward_typed<float, float>(t, (const float *)vr, (const float *)gr, (float *)dvr, dc, dxy,
+                                              r > 0, stream);
+        if (st != IMQ_OK) return st;
+    }
+    return IMQ_OK;
 }
 
 }  // extern "C"

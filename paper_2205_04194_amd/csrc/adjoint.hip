@@ -135,7 +135,8 @@ __global__ __launch_bounds__(64) void k_adjoint_eval(DTree<T> t, const int32_t *
 template <typename T, typename Tout>
 __global__ void k_adjoint_final(int64_t N, const int32_t *__restrict__ perm, const double *__restrict__ scale,
                                 const T *__restrict__ us, const double *__restrict__ out,
-                                Tout *__restrict__ dv, double *__restrict__ dxy, double *__restrict__ dcpart)
+                                Tout *__restrict__ dv, double *__restrict__ dxy, double *__restrict__ dcpart,
+                                int accumulate)
 {
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (i >= N) return;
@@ -143,14 +144,17 @@ __global__ void k_adjoint_final(int64_t N, const int32_t *__restrict__ perm, con
     const double v = double(us[i]), g = double(us[N + i]);
     const int32_t k = perm[i];
     dv[k] = Tout(out[i] * s1);
-    dxy[k] = (g * out[1 * N + i] + v * out[3 * N + i]) * s2;
-    dxy[N + k] = (g * out[2 * N + i] + v * out[4 * N + i]) * s2;
+    const double gx = (g * out[1 * N + i] + v * out[3 * N + i]) * s2;
+    const double gy = (g * out[2 * N + i] + v * out[4 * N + i]) * s2;
+    dxy[k] = accumulate ? dxy[k] + gx : gx;
+    dxy[N + k] = accumulate ? dxy[N + k] + gy : gy;
     dcpart[i] = g * out[5 * N + i] * s2;
 }
 
 // dc[s] = sum of dcpart over the set's points, in a fixed order.
 __global__ __launch_bounds__(256) void k_set_sum(const int64_t *__restrict__ set_off,
-                                                 const double *__restrict__ part, double *__restrict__ dc)
+                                                 const double *__restrict__ part, double *__restrict__ dc,
+                                                 int accumulate)
 {
     __shared__ double red[256];
     const int s = blockIdx.x;
@@ -162,7 +166,7 @@ __global__ __launch_bounds__(256) void k_set_sum(const int64_t *__restrict__ set
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) dc[s] = red[0];
+    if (threadIdx.x == 0) dc[s] = accumulate ? dc[s] + red[0] : red[0];
 }
 
 template <typename V>
@@ -218,7 +222,7 @@ inline dim3 grid1(int64_t n) { return dim3(unsigned((n + 255) / 256)); }
 
 template <typename T, typename Tio>
 imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, double *dc, double *dxy,
-                          hipStream_t s)
+                          int accumulate, hipStream_t s)
 {
     const HostTree &h = t->h;
     const int64_t N = h.N;
@@ -261,19 +265,20 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
     hipLaunchKernelGGL(k_adjoint_eval<T>, dim3(unsigned(h.leaves.size())), dim3(64), 0, s, view,
                        t->leaves.as<int32_t>(), pd.L.as<T>(), Lo, us, out);
     hipLaunchKernelGGL((k_adjoint_final<T, Tio>), grid1(N), dim3(256), 0, s, N, t->perm.as<int32_t>(),
-                       t->pt_scale.as<double>(), us, out, dv, dxy, dcpart);
-    hipLaunchKernelGGL(k_set_sum, dim3(h.nsets), dim3(256), 0, s, t->set_off.as<int64_t>(), dcpart, dc);
+                       t->pt_scale.as<double>(), us, out, dv, dxy, dcpart, accumulate);
+    hipLaunchKernelGGL(k_set_sum, dim3(h.nsets), dim3(256), 0, s, t->set_off.as<int64_t>(), dcpart, dc,
+                       accumulate);
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
 }
 
 template imq_status backward_typed<double, double>(imq_tree_s *, const double *, const double *, double *,
-                                                   double *, double *, hipStream_t);
+                                                   double *, double *, int, hipStream_t);
 template imq_status backward_typed<double, float>(imq_tree_s *, const float *, const float *, float *,
-                                                  double *, double *, hipStream_t);
+                                                  double *, double *, int, hipStream_t);
 template imq_status backward_typed<float, double>(imq_tree_s *, const double *, const double *, double *,
-                                                  double *, double *, hipStream_t);
+                                                  double *, double *, int, hipStream_t);
 template imq_status backward_typed<float, float>(imq_tree_s *, const float *, const float *, float *,
-                                                 double *, double *, hipStream_t);
+                                                 double *, double *, int, hipStream_t);
 
 }  // namespace imq

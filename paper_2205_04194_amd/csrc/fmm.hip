@@ -1120,6 +1120,7 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
     imq_status st;
     if (!overlap) {
         if ((st = prep_locals<T>(t, nrhs, s)) != IMQ_OK) return st;
+        mark(t, 4, s);
     } else {
         if ((st = t->ensure_side()) != IMQ_OK) return st;
         IMQ_HIP(hipEventRecord(t->ev_tfork, s));                  // multipoles complete
@@ -1171,7 +1172,7 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
         }
     }
     IMQ_HIP(hipGetLastError());
-    mark(t, 4, s);
+    mark(t, 5, s);
     int waited = -1;                                               // groups are waited for in order
     auto wait_level = [&](int l) -> imq_status {
         if (l < h.nlev && group_of[l] > waited) {
@@ -1216,14 +1217,14 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
     if (io && !overlap) { set_error("internal: caller-order I/O needs the overlapped product"); return IMQ_EINVAL; }
     if ((st = fmm_upward<T>(t, nrhs, s, overlap, io)) != IMQ_OK) return st;
     if ((st = fmm_translate<T>(t, nrhs, s, overlap)) != IMQ_OK) return st;
-    mark(t, 5, s);
+    mark(t, 6, s);
     if (overlap) {
         IMQ_HIP(hipStreamWaitEvent(s, t->ev_join, 0));
     } else {
         launch_p2p<T, false>(s, unsigned(nleaves), v, nleaves, pd.us.as<T>(), nrhs, bs, t->kcfg.p2p_mode == 1);
         IMQ_HIP(hipGetLastError());
     }
-    mark(t, 6, s);
+    mark(t, 7, s);
     const UserVec uv = io ? *io : UserVec();
     const auto m2p = [&]() -> imq_status {
         if (t->nwpairs > 0) {
@@ -1261,9 +1262,9 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
     IMQ_DISPATCH_P(h.p, IMQ_L2P)
 #undef IMQ_L2P
     IMQ_HIP(hipGetLastError());
-    mark(t, 7, s);
-    if (!uv.out && (st = m2p()) != IMQ_OK) return st;
     mark(t, 8, s);
+    if (!uv.out && (st = m2p()) != IMQ_OK) return st;
+    mark(t, 9, s);
     return IMQ_OK;
 }
 
@@ -1297,14 +1298,15 @@ imq_status alg1_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     mark(t, 3, s);
     mark(t, 4, s);
     mark(t, 5, s);
+    mark(t, 6, s);
     launch_p2p<T, false>(s, unsigned(nleaves), v, nleaves, pd.us.as<T>(), nrhs, bs, false);
     IMQ_HIP(hipGetLastError());
-    mark(t, 6, s);
+    mark(t, 7, s);
     hipLaunchKernelGGL(k_alg1_far<T>, dim3(unsigned(nleaves)), dim3(64), 0, s, v, pd.M.as<T>(), pd.wx.as<T>(),
                        nrhs, bs);
     IMQ_HIP(hipGetLastError());
-    mark(t, 7, s);
     mark(t, 8, s);
+    mark(t, 9, s);
     return IMQ_OK;
 }
 
@@ -1356,7 +1358,7 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
     if (t->kcfg.far_field == 1) {
         if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) == IMQ_OK && (st = alg1_sorted<T>(t, nrhs, s)) == IMQ_OK &&
             (st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) == IMQ_OK)
-            mark(t, 9, s);
+            mark(t, 10, s);
     } else if (!g_cur_events && nrhs < BATCH_RHS_MIN) {
         // overlapped product: L2P, the last stage, writes b in caller order (no
         // separate scatter).  Reading u through the permutation inside P2M
@@ -1372,7 +1374,7 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
     } else if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) == IMQ_OK &&
                (st = fmm_sorted<T>(t, nrhs, s, nullptr)) == IMQ_OK &&
                (st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) == IMQ_OK)
-        mark(t, 9, s);
+        mark(t, 10, s);
     g_cur_events = nullptr;
     return st;
 }

@@ -161,6 +161,9 @@ struct Solver {
     double *tmp, *r, *x, *f, *h, *part;
     double *hh = nullptr;              // pinned host copy of one Hessenberg column
     hipEvent_t ev_h = nullptr;
+    double *hist = nullptr;            // host residual history (optional)
+    int hist_cap = 0, hist_n = 0;
+    double hist_scale = 1.0;           // 1 / ||f|| of the outer system
 
     // y = A x in Morton order, product arithmetic T, vectors of type V
     template <typename T, typename V>
@@ -265,6 +268,7 @@ struct Solver {
                 col[j + 1] = 0.0;
                 g[j + 1] = -sn[j] * g[j];
                 g[j] = cs[j] * g[j];
+                if (hist && hist_n < hist_cap) hist[hist_n++] = std::fabs(g[j + 1]) * hist_scale;
                 k = j + 1;
                 cur = 1 - cur;
                 if (std::fabs(g[j + 1]) <= tol * nf || col[j] == 0.0 || hh[j + 1] == 0.0) break;
@@ -288,7 +292,7 @@ struct Solver {
 }  // namespace
 
 imq_status solve_one(imq_tree_s *t, const double *f_user, double *a_user, const imq_solve_opts &o,
-                     imq_solve_stats &stats, hipStream_t s)
+                     imq_solve_stats &stats, double *history, hipStream_t s)
 {
     Solver S;
     S.t = t;
@@ -336,6 +340,13 @@ imq_status solve_one(imq_tree_s *t, const double *f_user, double *a_user, const 
     int its = 0;
     double rel = 0.0;
     stats = imq_solve_stats{0, 0, 0, 0.0};
+    S.hist = history;
+    S.hist_cap = history ? o.max_iters : 0;
+    {
+        double nf0;
+        if ((st = S.norm(S.f, nf0)) != IMQ_OK) return st;
+        S.hist_scale = nf0 > 0.0 ? 1.0 / nf0 : 0.0;
+    }
     if (!o.mixed_ir) {
         if ((st = S.gmres<double, double>(S.f, S.x, o.tol, o.max_iters, its, rel)) != IMQ_OK) return st;
         stats.iters = its;
@@ -374,8 +385,8 @@ imq_status solve_one(imq_tree_s *t, const double *f_user, double *a_user, const 
     if ((st = S.apply<double, double>(S.x, S.tmp)) != IMQ_OK) return st;
     hipLaunchKernelGGL(k_axpby, grid1(N), dim3(256), 0, s, N, 1.0, S.f, -1.0, S.tmp, S.r);
     if ((st = S.norm(S.r, nr)) != IMQ_OK) return st;
-    stats.relres = nf > 0 ? nr / nf : 0.0;
-    stats.converged = stats.relres <= o.tol;
+    stats.relres_fast64 = nf > 0 ? nr / nf : 0.0;
+    stats.converged = stats.relres_fast64 <= o.tol;
     hipLaunchKernelGGL(k_scatter_f64, grid1(N), dim3(256), 0, s, N, perm, S.x, a_user);
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;

@@ -102,3 +102,45 @@ def test_tree_with_expansion_w_lists_is_refused(imq):
     assert tree.info()["m2p_evals"] > 0
     with pytest.raises(imq.IMQError):
         tree.backward(_dev(np.ones(20000)), _dev(np.ones(20000)))
+
+
+def test_autograd_with_float_c_and_several_columns(imq):
+    """c passed as a Python float gets no gradient (and no error); a 2-D v of
+    nrhs columns gets dv per column and dX summed over the columns."""
+    d = W.grad(2500)
+    xy, c = d["xy"], d["c"]
+    gen = np.random.default_rng(8)
+    V2 = gen.standard_normal((3, len(xy)))
+    F2 = gen.standard_normal((3, len(xy)))
+    X = _dev(xy).requires_grad_(True)
+    V = _dev(V2).requires_grad_(True)
+    b = imq.IMQMatvec.apply(X, c, V, 64, 16, "fp64")
+    assert b.shape == (3, len(xy))
+    loss = ((b - _dev(F2)) ** 2).sum()
+    loss.backward()
+    dX_ref = np.zeros_like(xy)
+    for r in range(3):
+        rdv, _, rdX = oracle.grad(xy, c, V2[r], F2[r])
+        assert _rel(V.grad.cpu().numpy()[r], rdv) < 1e-6
+        dX_ref += rdX
+    assert _rel(X.grad.cpu().numpy(), dX_ref) < 1e-6
+
+
+def test_backward_columns_match_single_column_calls(imq):
+    d = W.grad(3000)
+    xy, c = d["xy"], d["c"]
+    gen = np.random.default_rng(9)
+    V2, G2 = gen.standard_normal((2, len(xy))), gen.standard_normal((2, len(xy)))
+    tree = imq.build_tree(_dev(xy), c, leaf=64, p=16, direct_max=1 << 30)
+    dv, dc, dX = tree.backward(_dev(V2), _dev(G2))
+    parts = [tree.backward(_dev(V2[r]), _dev(G2[r])) for r in range(2)]
+    for r in range(2):
+        assert torch.equal(dv[r], parts[r][0])
+    assert float(dc[0]) == pytest.approx(float(parts[0][1][0] + parts[1][1][0]), rel=1e-14)
+    assert torch.allclose(dX, parts[0][2] + parts[1][2], rtol=1e-13, atol=0)
+    with pytest.raises(ValueError):
+        tree.backward(_dev(V2), _dev(G2[0]))               # g of another shape
+    with pytest.raises(ValueError):
+        tree.backward(_dev(V2[0][:-1]), _dev(G2[0][:-1]))   # short vectors
+    with pytest.raises(ValueError):
+        tree.backward(torch.tensor(V2[0]), torch.tensor(G2[0]))   # host tensors

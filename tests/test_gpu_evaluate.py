@@ -82,8 +82,8 @@ def test_solve_then_evaluate_at_the_data_sites_returns_the_data(imq):
     assert ev.n == len(xs)
     s = ev.evaluate(lam, "fp64").cpu().numpy()[::-1]
     err = _rel(s, f)
-    print(f"solve relres {st['relres']:.2e}, interpolant at the sites vs data {err:.2e}")
-    assert err < 10 * max(st["relres"], 1e-9)
+    print(f"solve relres {st['relres_fast64']:.2e}, interpolant at the sites vs data {err:.2e}")
+    assert err < 10 * max(st["relres_fast64"], 1e-9)
 
 
 def test_evaluation_arguments(imq):

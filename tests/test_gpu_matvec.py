@@ -276,3 +276,27 @@ def test_shift_column_tiles_give_the_same_products(imq):
         assert _rel(out[cols][:, rows], exact) < 1e-5, cols
     assert _rel(out[32], out[16]) < 1e-6
     tree.set_kernel_config()
+
+
+def test_short_or_host_vectors_and_freed_handles_are_rejected(imq):
+    import ctypes
+    from paper_2205_04194_amd import _lib
+    d = W.small(1000)
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=32, p=8)
+    with pytest.raises(ValueError):
+        tree.matvec(_dev(np.ones(999)))
+    with pytest.raises(ValueError):
+        tree.matvec(torch.ones(1000, dtype=torch.float64))          # host memory
+    with pytest.raises(ValueError):
+        tree.solve(_dev(np.ones(999)))
+    with pytest.raises(ValueError):
+        tree.solve(_dev(np.ones(1000)), a0=_dev(np.ones(999)))
+    with pytest.raises(ValueError):
+        tree.rows_exact(_dev(np.ones(1000)), torch.tensor([0, 1000], device="cuda:0"))
+    u = _dev(np.ones(1000))
+    b = torch.empty_like(u)
+    h = tree._h
+    tree.close()
+    st = _lib.load().imq_matvec(h, 1, _lib.F64, ctypes.c_void_p(u.data_ptr()), 1000,
+                                ctypes.c_void_p(b.data_ptr()), 1000, 0, None)
+    assert st == -1 and "freed" in _lib.load().imq_last_error().decode()

@@ -207,7 +207,7 @@ def batched_sets(count: int = 256, lo: int = 1000, hi: int = 20000):
     f = franke(xy[:, 0], xy[:, 1])
     u = uniform_vector(len(xy), rng("batched", 6))
     return dict(name="batched_sets", xy=xy, offsets=offsets, c=cs, f=f, u=u,
-                leaf=32, p=10)
+                leaf=32, p=12)
 
 
 def grad(n: int = 100_000):
