@@ -224,8 +224,8 @@ imq_status imq_matvec_backward(imq_tree tree, int nrhs, imq_dtype dtype, const v
  *  shift_cols : columns (box, rhs) per workgroup of the level-by-level
  *               shifts, 16 or 32 (32 only in FP32; 0 picks by level size)
  *  m2l_mode   : M2L kernel per level: 0 = operands streamed through
- *               registers where a box has at most 80 coefficients (FP32) or
- *               64 (FP64), the staged GEMM above; 1 = staged GEMM everywhere.
+ *               registers where a box has at most 80 coefficients, the
+ *               staged GEMM above; 1 = staged GEMM everywhere.
  *               m2l_kc and m2l_split apply to the staged GEMM only.
  *  p2p_wg     : workgroups of the near-field kernel while it runs alongside
  *               the tree passes (each takes every p2p_wg-th leaf); 0 = 2048

@@ -127,13 +127,12 @@ void pack_m2l_tables(const std::vector<double> &tabs, int KP, std::vector<double
 
 // Expansion-to-local translations of tasks [task0, task0 + ntask), operands
 // streamed through registers class by class (acc: added to out, else stored);
-// for coefficient counts up to kmax <= 80 (FP32) or 64 (FP64), else launches
-// nothing and returns false.
+// for coefficient counts up to kmax <= 80, else launches nothing and returns
+// false.
 template <typename T>
 bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
                        const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk, int KP, int KS,
                        const T *in, T *out);
-
 // Batched translation GEMM (fmm.hip); kc = staged coefficients per step.
 template <typename T>
 void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks, int t0,

@@ -1137,7 +1137,7 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
     std::vector<int> group_of(h.nlev, -1);
     {
         const DevGemm &g = t->g_m2l;
-        const int smax = sizeof(T) == 4 ? 5 : 4;
+        const int smax = 5;
         const auto kind = [&](int l) {
             const int nrb = (h.Klev[l] + 15) / 16;
             return (kc.m2l_mode == 0 && nrb <= smax) ? nrb : 0;

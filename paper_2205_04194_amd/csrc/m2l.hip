@@ -238,6 +238,11 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
         case 2: IMQ_M2LS(2, 1, 4); return true;
         case 3: IMQ_M2LS(3, 1, 4); return true;
         case 4: IMQ_M2LS(4, 1, 4); return true;
+        case 5:      // one row block per workgroup: a whole-row tile would not fit the registers
+            hipLaunchKernelGGL((k_m2l_stream<T, 5, 1, 4, 1>),
+                               dim3(ntask, unsigned((GEMM_TILE * nrhs + 15) / 16), 5), dim3(256), 0, s, tasks,
+                               task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out, acc);
+            return true;
         default: return false;
         }
     }

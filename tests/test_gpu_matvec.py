@@ -155,6 +155,28 @@ def test_translation_kernels_agree_and_match_the_oracle(imq, p):
         assert err < {3: 1e-2, 4: 3e-3, 6: 3e-4, 9: 2e-5, 12: 1e-6}[p]
 
 
+@pytest.mark.parametrize("nrhs", [1, 2, 70])
+def test_streamed_translations_up_to_80_coefficients(imq, nrhs):
+    """The register-streaming M2L kernel at every row-block count (1 to 5: up to
+    80 coefficients per box, FP32 and FP64) on a deep tree with per-level
+    orders from 12 down to 1 and several right-hand sides, against the staged
+    GEMM."""
+    d = W.small(30000)
+    U = _dev(W.uniform_vector(30000, W.rng(68, nrhs), nrhs=nrhs))
+    tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=8, p=11)
+    nlev = tree.info()["nlevels"]
+    orders = [max(1, 11 - 2 * max(0, l - 2)) for l in range(nlev)]
+    tree.set_level_orders(orders)
+    for prec, tol in (("fp64", 1e-13), ("fp32", 2e-6)):
+        tree.set_kernel_config(m2l_mode=1)
+        ref = tree.matvec(U, "fp64")
+        tree.set_kernel_config(m2l_mode=0)
+        b = tree.matvec(U, prec)
+        e = float(torch.linalg.norm(b - ref) / torch.linalg.norm(ref))
+        print(f"orders {orders}, nrhs {nrhs}, {prec}: streamed vs staged GEMM {e:.2e}")
+        assert e < tol
+
+
 def test_mixed_level_orders_use_both_kernels(imq):
     d = W.small(20000)
     u = _dev(d["u"])
