@@ -119,6 +119,25 @@ imq_status imq_matvec(imq_tree tree, int nrhs, imq_dtype dtype, const void *u,
                       int64_t ldu, void *b, int64_t ldb, imq_prec prec,
                       hipStream_t stream);
 
+/* imq_matvec for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and result as imq_matvec (up to the order of the
+ * floating-point sums: the stages run one after another on `stream`, none
+ * beside another), but the product's workspace (gathered weights,
+ * expansions, partial sums, the FP64 accumulator) is a fixed device array of
+ * imq_matvec_noalloc_max_bytes() bytes (128 MiB) that the library holds on
+ * every device it runs on until the process ends, instead of buffers the
+ * tree allocates on first use; the call allocates nothing.  A product that
+ * needs more workspace returns IMQ_EINVAL (about 80 bytes per point and
+ * right-hand side at p = 12 in FP64: some 1.6 million points at one
+ * right-hand side).  Every call on one device shares that array: calls that
+ * overlap in time on one device (other streams, other threads, other trees)
+ * race and must be serialised by the caller. */
+imq_status imq_matvec_noalloc(imq_tree tree, int nrhs, imq_dtype dtype, const void *u,
+                              int64_t ldu, void *b, int64_t ldb, imq_prec prec,
+                              hipStream_t stream);
+size_t imq_matvec_noalloc_max_bytes(void);
+
 /* Exact product restricted to some rows: b[r*ldb + k] = sum_j A_{rows[k], j} u_j
  * for k < nrows (device int64 row indices, caller order).  Direct sums over
  * all points of the row's set in FP64; used to measure the error of the fast

@@ -75,6 +75,8 @@ SIGNATURES = {
     "imq_build_tree": (_int, [_int, _p(_i64), _vp, _p(_dbl), _p(TreeParams), _vp, _p(_vp)]),
     "imq_build_tree_alloc": (_int, [_int, _p(_i64), _vp, _p(_dbl), _p(TreeParams), _p(Allocator), _vp, _p(_vp)]),
     "imq_matvec": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _int, _vp]),
+    "imq_matvec_noalloc": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _int, _vp]),
+    "imq_matvec_noalloc_max_bytes": (ctypes.c_size_t, []),
     "imq_build_eval_tree": (_int, [_vp, _i64, _vp, _i64, _dbl, _p(TreeParams), _vp, _p(_vp)]),
     "imq_evaluate": (_int, [_vp, _int, _int, _vp, _i64, _vp, _i64, _int, _vp]),
     "imq_rows_exact": (_int, [_vp, _int, _vp, _i64, _i64, _vp, _vp, _i64, _vp]),

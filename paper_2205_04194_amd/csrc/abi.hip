@@ -25,6 +25,9 @@ imq_status rows_exact(imq_tree_s *t, int nrhs, const double *u, int64_t ldu, int
                       const int64_t *rows, double *b, int64_t ldb, hipStream_t s);
 imq_status solve_one(imq_tree_s *t, const double *f_user, double *a_user, const imq_solve_opts &o,
                      imq_solve_stats &stats, double *history, hipStream_t s);
+imq_status matvec_noalloc(imq_tree_s *t, int nrhs, imq_dtype dtype, const void *u, int64_t ldu, void *b,
+                          int64_t ldb, imq_prec prec, hipStream_t s);
+size_t noalloc_scratch_bytes();
 template <typename T, typename Tio>
 imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, double *dc, double *dxy,
                           int accumulate, hipStream_t s);
@@ -531,6 +534,20 @@ imq_status imq_matvec(imq_tree t, int nrhs, imq_dtype dtype, const void *u, int6
     set_error("unknown dtype or precision");
     return IMQ_EINVAL;
 }
+
+imq_status imq_matvec_noalloc(imq_tree t, int nrhs, imq_dtype dtype, const void *u, int64_t ldu, void *b,
+                              int64_t ldb, imq_prec prec, hipStream_t stream)
+{
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return call.st;
+    if (nrhs < 1 || !u || !b || ldu < t->h.N || ldb < t->h.N) {
+        set_error("bad nrhs, pointer or leading dimension");
+        return IMQ_EINVAL;
+    }
+    return matvec_noalloc(t, nrhs, dtype, u, ldu, b, ldb, prec, stream);
+}
+
+size_t imq_matvec_noalloc_max_bytes(void) { return noalloc_scratch_bytes(); }
 
 imq_status imq_rows_exact(imq_tree t, int nrhs, const double *u, int64_t ldu, int64_t nrows,
                           const int64_t *rows, double *b, int64_t ldb, hipStream_t stream)

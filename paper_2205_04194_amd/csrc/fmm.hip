@@ -950,6 +950,10 @@ imq_status ensure_workspace(imq_tree_s *t, int nrhs)
 }
 
 static thread_local hipEvent_t *g_cur_events = nullptr;
+// Every stage in order on the caller's stream (no side streams, no events):
+// the product of the entry point that allocates nothing.
+static thread_local bool g_serial = false;
+void set_serial_product(bool on) { g_serial = on; }
 
 static inline void mark(imq_tree_s *, int stage, hipStream_t s)
 {
@@ -1213,7 +1217,7 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
     const int32_t *leaves = t->leaves.as<int32_t>();
     double *bs = t->bs.as<double>();
     imq_status st;
-    const bool overlap = g_cur_events == nullptr;
+    const bool overlap = g_cur_events == nullptr && !g_serial;
     if (io && !overlap) { set_error("internal: caller-order I/O needs the overlapped product"); return IMQ_EINVAL; }
     if ((st = fmm_upward<T>(t, nrhs, s, overlap, io)) != IMQ_OK) return st;
     if ((st = fmm_translate<T>(t, nrhs, s, overlap)) != IMQ_OK) return st;
@@ -1359,7 +1363,7 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
         if ((st = launch_gather<Tio, T>(t, nrhs, u, ldu, s)) == IMQ_OK && (st = alg1_sorted<T>(t, nrhs, s)) == IMQ_OK &&
             (st = launch_scatter<Tio>(t, nrhs, b, ldb, s)) == IMQ_OK)
             mark(t, 10, s);
-    } else if (!g_cur_events && nrhs < BATCH_RHS_MIN) {
+    } else if (!g_cur_events && !g_serial && nrhs < BATCH_RHS_MIN) {
         // overlapped product: L2P, the last stage, writes b in caller order (no
         // separate scatter).  Reading u through the permutation inside P2M
         // instead of gathering it first was measured slower: it puts a second
