@@ -182,9 +182,10 @@ typedef struct {
     int max_outer;     /* cap on refinement steps (mixed_ir only; 0 = 10)    */
     double *history;   /* host, optional (NULL: none): nrhs x max_iters
                           entries; entry r*max_iters + k is column r's GMRES
-                          residual estimate |g_(k+1)| / ||f_r|| after its
-                          inner iteration k (entries from stats[r].iters on
-                          are not written)                                   */
+                          residual estimate |g_(k+1)| / ||f|| after its
+                          inner iteration k, f the system of that iteration
+                          (the refinement's correction systems in mixed_ir);
+                          entries from stats[r].iters on are zero          */
 } imq_solve_opts;
 
 typedef struct {        /* host */
@@ -201,12 +202,17 @@ typedef struct {        /* host */
                            exact rows to measure it.                        */
 } imq_solve_stats;
 
-/* Solve A a = f (eq. interp_system) by restarted GMRES on the fast product.
+/* Solve A a = f (eq. interp_system) by restarted GMRES on the fast product,
+ * all nrhs columns in one Krylov cycle: every Arnoldi step applies the
+ * product to the nrhs basis vectors at once; each column has its own basis,
+ * Hessenberg matrix and Givens rotations (on the device) and stops at its
+ * own tolerance.
  *  f, a : FP64, nrhs columns with leading dimensions ldf, lda; `a` holds the
  *         initial guess on entry (zeros for none) and the solution on exit.
  *  stats: host array of nrhs entries, filled on return.
- * Synchronises `stream` once per GMRES cycle to read the residual.  Returns
- * IMQ_ENOTCONVERGED if some column stopped above tol. */
+ * Synchronises `stream` once per restart and reads one 4-byte count per
+ * Arnoldi step (one step behind the device).  Returns IMQ_ENOTCONVERGED if
+ * some column stopped above tol. */
 imq_status imq_solve(imq_tree tree, int nrhs, const double *f, int64_t ldf,
                      double *a, int64_t lda, const imq_solve_opts *opts,
                      imq_solve_stats *stats, hipStream_t stream);

@@ -23,8 +23,8 @@ imq_status matvec_typed(imq_tree_s *t, int nrhs, const Tio *u, int64_t ldu, Tio 
                         hipStream_t s);
 imq_status rows_exact(imq_tree_s *t, int nrhs, const double *u, int64_t ldu, int64_t nrows,
                       const int64_t *rows, double *b, int64_t ldb, hipStream_t s);
-imq_status solve_one(imq_tree_s *t, const double *f_user, double *a_user, const imq_solve_opts &o,
-                     imq_solve_stats &stats, double *history, hipStream_t s);
+imq_status solve_batched(imq_tree_s *t, int nrhs, const double *f_user, int64_t ldf, double *a_user, int64_t lda,
+                         const imq_solve_opts &o, imq_solve_stats *stats, hipStream_t s);
 imq_status matvec_noalloc(imq_tree_s *t, int nrhs, imq_dtype dtype, const void *u, int64_t ldu, void *b,
                           int64_t ldb, imq_prec prec, hipStream_t s);
 size_t noalloc_scratch_bytes();
@@ -763,13 +763,9 @@ imq_status imq_solve(imq_tree t, int nrhs, const double *f, int64_t ldf, double 
         set_error("solve options out of range (tol > 0, 1 <= restart <= 4096, max_iters >= 1)");
         return IMQ_EINVAL;
     }
+    if ((st = solve_batched(t, nrhs, f, ldf, a, lda, *opts, stats, stream)) != IMQ_OK) return st;
     bool all = true;
-    for (int r = 0; r < nrhs; ++r) {
-        st = solve_one(t, f + size_t(r) * ldf, a + size_t(r) * lda, *opts, stats[r],
-                       opts->history ? opts->history + size_t(r) * opts->max_iters : nullptr, stream);
-        if (st != IMQ_OK) return st;
-        all = all && stats[r].converged;
-    }
+    for (int r = 0; r < nrhs; ++r) all = all && stats[r].converged;
     return all ? IMQ_OK : IMQ_ENOTCONVERGED;
 }
 

@@ -94,3 +94,42 @@ def test_initial_guess_and_several_rhs(imq):
     assert all(s["iters"] == 0 for s in sts2)
     for r in range(2):
         assert oracle.relres(xy, c, a.cpu().numpy()[r], F[r]) < 1e-7
+
+
+def test_batched_columns_match_single_solves(imq):
+    """Five right-hand sides in one Krylov cycle: each column stops at its own
+    tolerance, with the iterations and the residual of its own solve."""
+    xy, c, f = _well_conditioned(n=3000, seed=5)
+    gen = np.random.default_rng(11)
+    F = np.stack([f, np.sin(3 * xy[:, 0]) * np.cos(2 * xy[:, 1]), gen.standard_normal(3000),
+                  np.zeros(3000), 1e-3 * f + xy[:, 1]])
+    tree = imq.build_tree(_dev(xy), c, leaf=32, p=16)
+    A, sts = tree.solve(_dev(F), tol=1e-9, restart=25, max_iters=400, history=True)
+    A = A.cpu().numpy()
+    for r in range(5):
+        a1, s1 = tree.solve(_dev(F[r]), tol=1e-9, restart=25, max_iters=400)
+        st = sts[r]
+        print(f"column {r}: batched {st['iters']} its relres {st['relres_fast64']:.2e}; "
+              f"single {s1['iters']} its relres {s1['relres_fast64']:.2e}")
+        assert st["converged"] and s1["converged"]
+        assert abs(st["iters"] - s1["iters"]) <= 1
+        if r == 3:                                   # zero right-hand side: zero solution, no iterations
+            assert st["iters"] == 0 and not np.any(A[r])
+            continue
+        assert oracle.relres(xy, c, A[r], F[r]) < 1e-7
+        h = np.array(st["history"])
+        assert len(h) == st["iters"] and np.all(h > 0) and h.min() <= 1e-8
+
+
+def test_full_restart_solve_of_many_columns_on_the_gpu_givens(imq):
+    """Restart longer than the iterations needed (one cycle) with 9 columns:
+    the Hessenberg matrices, rotations and back-substitution of all columns on
+    the device give each column's solution to the requested tolerance."""
+    xy, c, _ = _well_conditioned(n=2500, seed=6)
+    F = W.fourier_rhs(xy[:, 0], xy[:, 1], 9, W.rng(45, 1))
+    tree = imq.build_tree(_dev(xy), c, leaf=32, p=16)
+    A, sts = tree.solve(_dev(F), tol=1e-6, restart=200, max_iters=200)
+    A = A.cpu().numpy()
+    for r in range(9):
+        assert sts[r]["converged"]
+        assert oracle.relres(xy, c, A[r], F[r]) <= 1e-6
