@@ -37,13 +37,20 @@ void *imq_debug_host_tree(int nsets, const int64_t *set_offsets, const double *x
  * "xl", "yl", "level", "set", "ix", "iy", "parent", "child0", "nchild",
  * "pos", "begin", "end", "isleaf", "cx", "cy", "level_begin", "leaves",
  * "u_off", "u_idx", "v_off", "v_idx", "v_cls", "w_off", "w_idx", "x_off",
- * "x_idx", "Klev", "side", "cn". */
+ * "x_idx", "Klev", "side", "cn", "sh_par", "sh_kids", "sh_level_begin",
+ * "near_expand", "pt_scale", "pt_leaf", "lox", "loy". */
 int64_t imq_debug_host_tree_size(void *h, const char *what);
 
 /* Copy a named array into `out` (host, large enough); returns 0 or -1. */
 int imq_debug_host_tree_get(void *h, const char *what, void *out);
 
 void imq_debug_host_tree_free(void *h);
+
+/* The same tree built by the device construction (needs a GPU) from HOST
+ * coordinates copied to the device: a handle for the getters above (free it
+ * with imq_debug_host_tree_free), or NULL with *status set. */
+void *imq_debug_device_tree(int nsets, const int64_t *set_offsets, const double *x, const double *y,
+                            const double *c, const imq_tree_params *prm, int *status);
 
 /* The point list of an evaluation tree (host arrays): data sites xs, ys (n)
  * and evaluation points xt, yt (m); writes map[k] for k < m (the index, in

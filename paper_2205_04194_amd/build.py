@@ -24,7 +24,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # per source: the near field's matrix-core results go straight to VGPRs (no
 # copies out of the accumulation registers in its inner loop)
-FILE_FLAGS = {"p2p.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+FILE_FLAGS = {"p2p.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+              # the device tree build repeats the host build's floating-point
+              # steps exactly: no fused multiply-adds
+              "tree_dev.hip": ["-ffp-contract=off"]}
 
 
 def sources():

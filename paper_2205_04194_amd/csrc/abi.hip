@@ -436,9 +436,6 @@ imq_status imq_build_tree_alloc(int nsets, const int64_t *set_offsets, const dou
     if (nsets < 1 || !set_offsets || !xy || !c || !params) { set_error("null argument or nsets < 1"); return IMQ_EINVAL; }
     const int64_t N = set_offsets[nsets];
     if (N < 1) { set_error("no points"); return IMQ_EINVAL; }
-    std::vector<double> hxy(2 * size_t(N));
-    IMQ_HIP(hipMemcpyAsync(hxy.data(), xy, sizeof(double) * 2 * size_t(N), hipMemcpyDeviceToHost, stream));
-    IMQ_HIP(hipStreamSynchronize(stream));
     auto *t = new imq_tree_s();
     const hipError_t e = hipGetDevice(&t->device);
     if (e != hipSuccess) {
@@ -448,7 +445,7 @@ imq_status imq_build_tree_alloc(int nsets, const int64_t *set_offsets, const dou
     }
     if (alloc) t->alloc = *alloc;
     g_alloc = t->allocator();
-    imq_status st = build_host_tree(nsets, set_offsets, hxy.data(), hxy.data() + N, c, *params, t->h);
+    imq_status st = build_device_tree(nsets, set_offsets, xy, c, *params, stream, t->h);
     if (st != IMQ_OK) { delete t; return st; }
     st = upload_tree(t, xy);
     if (st != IMQ_OK) { free_tree(t); return st; }
@@ -711,7 +708,7 @@ static const void *field(const HostTree &h, const char *w, int64_t &n, int &elem
     F(perm) F(xl) F(yl) F(level) F(set) F(ix) F(iy) F(parent) F(child0) F(nchild) F(pos) F(begin)
     F(end) F(isleaf) F(cx) F(cy) F(level_begin) F(leaves) F(u_off) F(u_idx) F(v_off) F(v_idx)
     F(v_cls) F(w_off) F(w_idx) F(x_off) F(x_idx) F(Klev) F(side) F(cn) F(sh_par) F(sh_kids)
-    F(sh_level_begin) F(near_expand)
+    F(sh_level_begin) F(near_expand) F(pt_scale) F(pt_leaf) F(lox) F(loy)
 #undef F
     n = -1;
     elem = 0;
@@ -735,6 +732,31 @@ int imq_debug_host_tree_get(void *hp, const char *what, void *out)
 }
 
 void imq_debug_host_tree_free(void *hp) { delete static_cast<HostTree *>(hp); }
+
+void *imq_debug_device_tree(int nsets, const int64_t *set_offsets, const double *x, const double *y,
+                            const double *c, const imq_tree_params *prm, int *status)
+{
+    const int64_t N = set_offsets[nsets];
+    double *dxy = nullptr;
+    auto fail = [&](imq_status st) -> void * {
+        if (status) *status = st;
+        if (dxy) (void)hipFree(dxy);
+        return nullptr;
+    };
+    if (hipMalloc(reinterpret_cast<void **>(&dxy), sizeof(double) * 2 * size_t(std::max<int64_t>(N, 1))) != hipSuccess)
+        return fail(IMQ_ENOMEM);
+    if (N > 0 && (hipMemcpy(dxy, x, sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess ||
+                  hipMemcpy(dxy + N, y, sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess))
+        return fail(IMQ_EHIP);
+    g_alloc = nullptr;
+    auto *h = new HostTree();
+    const imq_status st = build_device_tree(nsets, set_offsets, dxy, c, *prm, 0, *h);
+    (void)hipFree(dxy);
+    dxy = nullptr;
+    if (status) *status = st;
+    if (st != IMQ_OK) { delete h; return nullptr; }
+    return h;
+}
 
 int64_t imq_debug_eval_points(int64_t n, const double *xs, const double *ys, int64_t m, const double *xt,
                               const double *yt, int64_t *map)

@@ -239,6 +239,11 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io 
 
 template <typename T>
 imq_status ensure_workspace(imq_tree_s *t, int nrhs);
+
+// The host build's tree (build_host_tree) computed on the device from device
+// coordinates; synchronises `s`.
+imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, const double *c,
+                             const imq_tree_params &prm, hipStream_t s, HostTree &t);
 }  // namespace imq
 
 #define IMQ_HIP(call)                                                                 \

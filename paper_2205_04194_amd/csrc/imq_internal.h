@@ -150,6 +150,12 @@ imq_status eval_points(int64_t n, const double *xs, const double *ys, int64_t m,
                        const double *yt, std::vector<double> &x, std::vector<double> &y,
                        std::vector<int64_t> &map);
 
+// Argument checks shared by the host and device builds.
+imq_status check_tree_params(int nsets, const int64_t *set_offsets, const double *c, const imq_tree_params &prm);
+// Translation batches, shift lists, near-field flags and work counts of a
+// tree whose boxes, points and lists are built.
+imq_status finish_host_tree(HostTree &t);
+
 // Returns IMQ_OK, IMQ_EINVAL or IMQ_EDUPLICATE.
 imq_status build_host_tree(int nsets, const int64_t *set_offsets, const double *x,
                            const double *y, const double *c, const imq_tree_params &prm,

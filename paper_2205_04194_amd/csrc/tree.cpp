@@ -117,8 +117,7 @@ static void near_expansion_flags(HostTree &h)
     }
 }
 
-imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const double *y,
-                           const double *c, const imq_tree_params &prm, HostTree &t)
+imq_status check_tree_params(int nsets, const int64_t *off, const double *c, const imq_tree_params &prm)
 {
     if (nsets < 1) { set_error("nsets must be >= 1"); return IMQ_EINVAL; }
     if (off[0] != 0) { set_error("set_offsets[0] must be 0"); return IMQ_EINVAL; }
@@ -126,12 +125,39 @@ imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const
         if (off[s + 1] <= off[s]) { set_error("every set needs at least one point"); return IMQ_EINVAL; }
         if (!(c[s] > 0.0) || !std::isfinite(c[s])) { set_error("shape parameter c must be finite and > 0"); return IMQ_EINVAL; }
     }
-    const int64_t N = off[nsets];
-    if (N > INT32_MAX) { set_error("more than 2^31-1 points"); return IMQ_EINVAL; }
+    if (off[nsets] > INT32_MAX) { set_error("more than 2^31-1 points"); return IMQ_EINVAL; }
     if (prm.order_p < 1 || prm.order_p > PMAX) { set_error("order_p must be in [1, 16]"); return IMQ_EINVAL; }
     if (prm.leaf_max < 1) { set_error("leaf_max must be >= 1"); return IMQ_EINVAL; }
-    int max_level = prm.max_level == 0 ? MORTON_BITS : prm.max_level;
+    const int max_level = prm.max_level == 0 ? MORTON_BITS : prm.max_level;
     if (max_level < 0 || max_level > MORTON_BITS) { set_error("max_level must be in [0, 30]"); return IMQ_EINVAL; }
+    return IMQ_OK;
+}
+
+// What follows the lists: the translation batches and shift lists, the
+// near-field expansion flags, the work counts.
+imq_status finish_host_tree(HostTree &t)
+{
+    build_gemm_lists(t);
+    near_expansion_flags(t);
+    const int nbox = int(t.level.size());
+    auto npts = [&](int b) { return int64_t(t.end[b] - t.begin[b]); };
+    for (int b = 0; b < nbox; ++b) {
+        for (int k = t.u_off[b]; k < t.u_off[b + 1]; ++k) t.p2p_pairs += npts(b) * npts(t.u_idx[k]);
+        t.m2l_pairs += t.v_off[b + 1] - t.v_off[b];
+        t.m2p_evals += int64_t(t.w_off[b + 1] - t.w_off[b]) * npts(b);
+        for (int k = t.x_off[b]; k < t.x_off[b + 1]; ++k) t.p2l_evals += npts(t.x_idx[k]);
+        if (t.parent[b] >= 0) { t.m2m_pairs++; t.l2l_pairs++; }
+    }
+    return IMQ_OK;
+}
+
+imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const double *y,
+                           const double *c, const imq_tree_params &prm, HostTree &t)
+{
+    imq_status st0 = check_tree_params(nsets, off, c, prm);
+    if (st0 != IMQ_OK) return st0;
+    const int64_t N = off[nsets];
+    const int max_level = prm.max_level == 0 ? MORTON_BITS : prm.max_level;
     for (int64_t i = 0; i < N; ++i)
         if (!std::isfinite(x[i]) || !std::isfinite(y[i])) { set_error("non-finite coordinate"); return IMQ_EINVAL; }
 
@@ -358,18 +384,7 @@ imq_status build_host_tree(int nsets, const int64_t *off, const double *x, const
     flatten(W, t.w_off, t.w_idx);
     flatten(X, t.x_off, t.x_idx);
 
-    build_gemm_lists(t);
-    near_expansion_flags(t);
-
-    auto npts = [&](int b) { return int64_t(t.end[b] - t.begin[b]); };
-    for (int b = 0; b < nbox; ++b) {
-        for (int u : U[b]) t.p2p_pairs += npts(b) * npts(u);
-        t.m2l_pairs += int64_t(V[b].size());
-        for (int w : W[b]) { (void)w; t.m2p_evals += npts(b); }
-        for (int xsrc : X[b]) t.p2l_evals += npts(xsrc);
-        if (t.parent[b] >= 0) { t.m2m_pairs++; t.l2l_pairs++; }
-    }
-    return IMQ_OK;
+    return finish_host_tree(t);
 }
 
 // ---- translation batches

@@ -24,7 +24,30 @@ def host_tree(xy_list, c_list, leaf, p=4, max_level=0, level_order=None, direct_
 
 
 _DTYPES = {"xl": np.float64, "yl": np.float64, "cx": np.float64, "cy": np.float64,
-           "side": np.float64, "cn": np.float64}
+           "side": np.float64, "cn": np.float64, "pt_scale": np.float64, "lox": np.float64,
+           "loy": np.float64}
+
+FIELDS = ["perm", "xl", "yl", "pt_scale", "pt_leaf", "level", "set", "ix", "iy", "parent", "child0",
+          "nchild", "pos", "begin", "end", "isleaf", "cx", "cy", "level_begin", "leaves", "u_off", "u_idx",
+          "v_off", "v_idx", "v_cls", "w_off", "w_idx", "x_off", "x_idx", "Klev", "side", "lox", "loy", "cn",
+          "sh_par", "sh_kids", "sh_level_begin", "near_expand"]
+
+
+def device_tree(xy_list, c_list, leaf, p=4, max_level=0, level_order=None, direct_max=0):
+    """The same tree from the device construction (needs a GPU); returns (handle, status)."""
+    lib = _lib.load()
+    xy = np.concatenate(xy_list, axis=0)
+    offs = np.concatenate([[0], np.cumsum([len(a) for a in xy_list])]).astype(np.int64)
+    x = np.ascontiguousarray(xy[:, 0], dtype=np.float64)
+    y = np.ascontiguousarray(xy[:, 1], dtype=np.float64)
+    c = np.ascontiguousarray(c_list, dtype=np.float64)
+    prm = _lib.params(leaf, p, max_level, level_order, direct_max)
+    st = ctypes.c_int(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = lib.imq_debug_device_tree(len(xy_list), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  x.ctypes.data_as(dp), y.ctypes.data_as(dp), c.ctypes.data_as(dp),
+                                  ctypes.byref(prm), ctypes.byref(st))
+    return h, st.value
 
 
 def get(h, name):
