@@ -46,6 +46,12 @@ int imq_debug_host_tree_get(void *h, const char *what, void *out);
 
 void imq_debug_host_tree_free(void *h);
 
+/* The M2L table (set, level, displacement class) of a tree as the
+ * translation kernels read it: layout 0 = FP64 row-major KP x KP, 1 = FP64
+ * in the streaming kernel's lane order, 2 and 3 the same in FP32; copied
+ * into `out` (host, KP*KP elements).  Returns KP, or -1. */
+int imq_debug_tree_table(imq_tree t, int set, int level, int cls, int layout, void *out);
+
 /* The same tree built by the device construction (needs a GPU) from HOST
  * coordinates copied to the device: a handle for the getters above (free it
  * with imq_debug_host_tree_free), or NULL with *status set. */

@@ -96,6 +96,7 @@ SIGNATURES = {
     "imq_debug_host_tree_size": (_i64, [_vp, ctypes.c_char_p]),
     "imq_debug_host_tree_get": (_int, [_vp, ctypes.c_char_p, _vp]),
     "imq_debug_host_tree_free": (None, [_vp]),
+    "imq_debug_tree_table": (_int, [_vp, _int, _int, _int, _int, _vp]),
     "imq_debug_device_tree": (_vp, [_int, _p(_i64), _p(_dbl), _p(_dbl), _p(_dbl), _p(TreeParams), _p(_int)]),
     "imq_debug_eval_points": (_i64, [_i64, _p(_dbl), _p(_dbl), _i64, _p(_dbl), _p(_dbl), _p(_i64)]),
 }

@@ -27,7 +27,9 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 FILE_FLAGS = {"p2p.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
               # the device tree build repeats the host build's floating-point
               # steps exactly: no fused multiply-adds
-              "tree_dev.hip": ["-ffp-contract=off"]}
+              "tree_dev.hip": ["-ffp-contract=off"],
+              # the translation tables repeat the host generation's arithmetic
+              "tables_dev.hip": ["-ffp-contract=off"]}
 
 
 def sources():

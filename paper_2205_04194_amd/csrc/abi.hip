@@ -50,7 +50,7 @@ static std::vector<float> to_f32(const std::vector<V> &v)
 
 // All translation tables of a tree, generated in FP64 on the host.
 static void make_tables(const HostTree &h, std::vector<double> &m2m, std::vector<double> &l2l,
-                        std::vector<double> &m2l, std::vector<double> &wx)
+                        std::vector<double> &wx)
 {
     const int K = h.K, p = h.p;
     const size_t KK = size_t(K) * K;
@@ -62,29 +62,6 @@ static void make_tables(const HostTree &h, std::vector<double> &m2m, std::vector
     }
     wx.assign(K, 0.0);
     make_wx_consts(p, wx.data());
-    const size_t ntab = size_t(h.nsets) * h.nlev * NCLASS;
-    m2l.assign(ntab * KK, 0.0);
-    std::vector<size_t> jobs;
-    for (int s = 0; s < h.nsets; ++s)
-        for (int l = 2; l < h.nlev; ++l)
-            for (int cls = 0; cls < NCLASS; ++cls) {
-                const int dx = cls / 7 - 3, dy = cls % 7 - 3;
-                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
-                jobs.push_back((size_t(s) * h.nlev + l) * NCLASS + cls);
-            }
-    const unsigned nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::vector<std::thread> th;
-    for (unsigned w = 0; w < nthr; ++w)
-        th.emplace_back([&, w]() {
-            for (size_t j = w; j < jobs.size(); j += nthr) {
-                const size_t id = jobs[j];
-                const int cls = int(id % NCLASS);
-                const int l = int((id / NCLASS) % h.nlev);
-                const int s = int(id / NCLASS / h.nlev);
-                make_m2l_table(p, l, cls / 7 - 3, cls % 7 - 3, h.cn[s], m2l.data() + id * KK);
-            }
-        });
-    for (auto &x : th) x.join();
 }
 
 // The near field's view of the U lists: per entry (target leaf b, source
@@ -202,8 +179,8 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     if ((st = upload(t->f64.urec, u_records<double>(h))) != IMQ_OK) return st;
     if ((st = upload(t->f32.urec, u_records<float>(h))) != IMQ_OK) return st;
 
-    std::vector<double> m2m, l2l, m2l, wx;
-    make_tables(h, m2m, l2l, m2l, wx);
+    std::vector<double> m2m, l2l, wx;
+    make_tables(h, m2m, l2l, wx);
     // zero-pad every K x K table to KP x KP for the MFMA tiles
     const int K = h.K, KP = (K + 15) & ~15;
     t->KP = KP;
@@ -218,16 +195,14 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     };
     pad(m2m);
     pad(l2l);
-    pad(m2l);
-    std::vector<double> m2l_pk;
     {
         std::vector<double> pk;
         pack_shift_tables(m2m, KP, pk, t->cut_m2m);
         m2m.swap(pk);
         pack_shift_tables(l2l, KP, pk, t->cut_l2l);
         l2l.swap(pk);
-        pack_m2l_tables(m2l, KP, m2l_pk);
     }
+    if ((st = make_m2l_tables_device(t, KP)) != IMQ_OK) return st;
     {
         const GemmList &g = h.m2l;
         DevGemm &d = t->g_m2l;
@@ -242,13 +217,9 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     if ((st = upload(t->sh_kids, h.sh_kids)) != IMQ_OK) return st;
     if ((st = upload(t->f64.m2m, m2m)) != IMQ_OK) return st;
     if ((st = upload(t->f64.l2l, l2l)) != IMQ_OK) return st;
-    if ((st = upload(t->f64.m2l, m2l)) != IMQ_OK) return st;
-    if ((st = upload(t->f64.m2l_pk, m2l_pk)) != IMQ_OK) return st;
-    if ((st = upload(t->f32.m2l_pk, to_f32(m2l_pk))) != IMQ_OK) return st;
     if ((st = upload(t->f64.wx, wx)) != IMQ_OK) return st;
     if ((st = upload(t->f32.m2m, to_f32(m2m))) != IMQ_OK) return st;
     if ((st = upload(t->f32.l2l, to_f32(l2l))) != IMQ_OK) return st;
-    if ((st = upload(t->f32.m2l, to_f32(m2l))) != IMQ_OK) return st;
     if ((st = upload(t->f32.wx, to_f32(wx))) != IMQ_OK) return st;
     return IMQ_OK;
 }
@@ -732,6 +703,22 @@ int imq_debug_host_tree_get(void *hp, const char *what, void *out)
 }
 
 void imq_debug_host_tree_free(void *hp) { delete static_cast<HostTree *>(hp); }
+
+int imq_debug_tree_table(imq_tree t, int set, int level, int cls, int layout, void *out)
+{
+    TreeCall call(t);
+    if (call.st != IMQ_OK) return -1;
+    const HostTree &h = t->h;
+    if (set < 0 || set >= h.nsets || level < 0 || level >= h.nlev || cls < 0 || cls >= NCLASS || !out) return -1;
+    const size_t PP = size_t(t->KP) * t->KP, id = (size_t(set) * h.nlev + level) * NCLASS + cls;
+    const DevBuf *src[4] = {&t->f64.m2l, &t->f64.m2l_pk, &t->f32.m2l, &t->f32.m2l_pk};
+    if (layout < 0 || layout > 3) return -1;
+    const size_t es = layout < 2 ? sizeof(double) : sizeof(float);
+    if (hipMemcpy(out, static_cast<const char *>(src[layout]->p) + id * PP * es, PP * es, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return -1;
+    return t->KP;
+}
 
 void *imq_debug_device_tree(int nsets, const int64_t *set_offsets, const double *x, const double *y,
                             const double *c, const imq_tree_params *prm, int *status)

@@ -122,8 +122,6 @@ template <typename T, bool SIDE>
 void launch_p2p(hipStream_t s, unsigned grid, const DTree<T> &v, int nleaves, const T *us, int nrhs, double *bs,
                 bool mf);
 
-// M2L tables in the lane order of k_m2l_stream (same size as tabs).
-void pack_m2l_tables(const std::vector<double> &tabs, int KP, std::vector<double> &packed);
 
 // Expansion-to-local translations of tasks [task0, task0 + ntask), operands
 // streamed through registers class by class (acc: added to out, else stored);
@@ -239,6 +237,10 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io 
 
 template <typename T>
 imq_status ensure_workspace(imq_tree_s *t, int nrhs);
+
+// Every M2L table of a built tree (four layouts, both precisions) generated
+// on the device; KP = the padded table edge.
+imq_status make_m2l_tables_device(imq_tree_s *t, int KP);
 
 // The host build's tree (build_host_tree) computed on the device from device
 // coordinates; synchronises `s`.

@@ -54,6 +54,7 @@ static double factorial(int n)
 // c_{n,m} = P_n^m(0) / (n+m)!
 static double cnm(int n, int m) { return legendre_at_zero(n, m) / factorial(n + m); }
 static double eps(int m) { return m == 0 ? 1.0 : 2.0; }
+double legendre_coef(int n, int m) { return cnm(n, m); }
 
 // Regular solid harmonics R_n^m, 0 <= m <= n <= N, by the Cartesian
 // recurrences R_m^m = -(x+iy)/(2m) R_{m-1}^{m-1},

@@ -62,6 +62,7 @@ void make_m2l_odd_table(int p, int level, int dx, int dy, double cnorm, double *
 void make_l2l_odd_table(int p, int pos, double *T);
 inline int Kodd(int p) { return p * (p + 1) / 2; }
 double legendre_at_zero(int n, int m);     // P_n^m(0), Condon-Shortley sign
+double legendre_coef(int n, int m);        // P_n^m(0) / (n+m)!
 
 // ------------------------------------------------------------------ tree
 

@@ -183,22 +183,6 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
 
 }  // namespace
 
-void pack_m2l_tables(const std::vector<double> &tabs, int KP, std::vector<double> &packed)
-{
-    const int nrb = KP / 16;
-    const size_t PP = size_t(KP) * KP;
-    const size_t ntab = tabs.size() / PP;
-    packed.assign(tabs.size(), 0.0);
-    for (size_t tb = 0; tb < ntab; ++tb)
-        for (int rb = 0; rb < nrb; ++rb)
-            for (int ci = 0; ci < nrb; ++ci)
-                for (int l = 0; l < 64; ++l)
-                    for (int j = 0; j < 4; ++j)
-                        packed[tb * PP + ((size_t(rb) * nrb + ci) * 64 + l) * 4 + j] =
-                            tabs[tb * PP + size_t(rb * 16 + l % 16) * KP + ci * 16 + 4 * (l / 16) + j];
-}
-
-
 template <typename T>
 bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
                        const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk, int KP, int KS,

@@ -80,3 +80,49 @@ def test_errors_match():
 def test_mixture1m():
     d = W.mixture1m()
     assert _same_trees([d["xy"]], [d["c"]], 64, p=12) == 0
+
+
+@pytest.mark.parametrize("p", [3, 8, 12, 16])
+def test_device_translation_tables_equal_the_host_tables(p):
+    """The M2L tables generated on the device (four layouts) against the host
+    generation of the same operator, for a two-set forest with different c."""
+    import ctypes
+    from paper_2205_04194_amd import _lib
+    import paper_2205_04194_amd as imq
+    g = W.rng(92, p)
+    sets = [W.uniform_points(3000, g), W.uniform_points(2000, g) * 3.0]
+    cs = [0.05, 0.4]
+    offs = [0, 3000, 5000]
+    tree = imq.build_tree(torch.tensor(np.concatenate(sets), device="cuda:0"), cs, leaf=16, p=p,
+                          set_offsets=offs)
+    K = (p + 1) * (p + 2) // 2
+    KP = (K + 15) // 16 * 16
+    nlev = tree.info()["nlevels"]
+    side = [np.ptp(s_, axis=0).max() * (1 + 2.0 ** -20) for s_ in sets]
+    lib = _lib.load()
+    checked = 0
+    for s_ in range(2):
+        cn = cs[s_] / side[s_]
+        for l in (2, nlev - 1):
+            for cls in (0, 3 * 7 + 1, 48, 2 * 7 + 5):
+                dx, dy = cls // 7 - 3, cls % 7 - 3
+                ref = H.table(2, p, level=l, dx=dx, dy=dy, cnorm=cn).reshape(K, K)
+                refp = np.zeros((KP, KP))
+                refp[:K, :K] = ref
+                out = [np.empty(KP * KP, dtype=np.float64 if lay < 2 else np.float32) for lay in range(4)]
+                for lay in range(4):
+                    assert lib.imq_debug_tree_table(tree._h, s_, l, cls, lay,
+                                                    out[lay].ctypes.data_as(ctypes.c_void_p)) == KP
+                t64 = out[0].reshape(KP, KP)
+                err = np.abs(t64 - refp).max() / np.abs(refp).max()
+                assert err <= 1e-15, (s_, l, cls, err)
+                assert np.array_equal(out[2].reshape(KP, KP), t64.astype(np.float32))
+                # lane order: element j of lane q of chunk (rb, ci) is T[16 rb + q % 16][16 ci + 4 (q / 16) + j]
+                pk = out[1].reshape(KP // 16, KP // 16, 64, 4)
+                rb, ci, q, j = np.meshgrid(np.arange(KP // 16), np.arange(KP // 16), np.arange(64), np.arange(4),
+                                           indexing="ij")
+                assert np.array_equal(pk, t64[16 * rb + q % 16, 16 * ci + 4 * (q // 16) + j])
+                assert np.array_equal(out[3], out[1].astype(np.float32))
+                checked += 1
+    assert checked == 16
+    tree.close()
