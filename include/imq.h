@@ -250,7 +250,11 @@ imq_status imq_matvec_backward(imq_tree tree, int nrhs, imq_dtype dtype, const v
  *               shifts, 16 or 32 (32 only in FP32; 0 picks by level size)
  *  m2l_mode   : M2L kernel per level: 0 = operands streamed through
  *               registers where a box has at most 80 coefficients, the
- *               staged GEMM above; 1 = staged GEMM everywhere.
+ *               staged GEMM above; 1 = staged GEMM everywhere; 2 = as 0,
+ *               with the FP32 products of the streamed levels taken on the
+ *               BF16 matrix cores: each operand split into three BF16 parts
+ *               (24 significant bits in all), six part products summed in
+ *               FP32 (the FP64 product runs as 0).
  *               m2l_kc and m2l_split apply to the staged GEMM only.
  *  p2p_wg     : workgroups of the near-field kernel while it runs alongside
  *               the tree passes (each takes every p2p_wg-th leaf); 0 = 2048

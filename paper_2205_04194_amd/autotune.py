@@ -61,7 +61,7 @@ def _time(tree, u, prec, reps=5):
 
 def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"),
          nrows: int = 1000, safety: float = 0.8, seed: int = 0,
-         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1)) -> TuneResult:
+         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1, 2)) -> TuneResult:
     """Fastest configuration of ``tree`` whose sampled-row relative 2-norm
     error is at most ``safety * target``; the tree is left configured."""
     n = tree.n
@@ -108,6 +108,8 @@ def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"
         # 3. translation kernels and the launch shape of the staged GEMM
         shape, ms = (0, 0, 0), float("inf")
         for mode in modes:
+            if prec == "fp64" and mode == 2:       # the BF16 form serves FP32 only
+                continue
             for kc in kcs:
                 if prec == "fp64" and kc > 32:
                     continue

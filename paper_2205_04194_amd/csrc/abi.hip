@@ -238,7 +238,7 @@ static void free_tree(imq_tree_s *t)
         dev_free(g->tasks); dev_free(g->tbox); dev_free(g->tab); dev_free(g->src);
     }
     for (PrecData *pd : {&t->f64, &t->f32}) {
-        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->urec, &pd->m2m, &pd->l2l, &pd->m2l, &pd->m2l_pk, &pd->wx, &pd->us, &pd->M, &pd->L,
+        DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->urec, &pd->m2m, &pd->l2l, &pd->m2l, &pd->m2l_pk, &pd->m2l_bf3, &pd->wx, &pd->us, &pd->M, &pd->L,
                         &pd->Lx, &pd->m2l_odd, &pd->l2l_odd, &pd->Lodd};
         for (DevBuf *b : pb) dev_free(*b);
     }
@@ -576,7 +576,7 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
     auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
     if (!ok_kc(cfg->m2l_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
         (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32) ||
-        cfg->m2l_mode < 0 || cfg->m2l_mode > 1 || cfg->p2p_wg < 0 || cfg->p2p_mode < 0 || cfg->p2p_mode > 1 ||
+        cfg->m2l_mode < 0 || cfg->m2l_mode > 2 || cfg->p2p_wg < 0 || cfg->p2p_mode < 0 || cfg->p2p_mode > 1 ||
         cfg->far_field < 0 || cfg->far_field > 1) {
         set_error("kernel config out of range");
         return IMQ_EINVAL;

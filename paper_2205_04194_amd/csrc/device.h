@@ -83,6 +83,7 @@ struct PrecData {              // everything that exists once per arithmetic typ
     DevBuf m2m, l2l;           // shift tables, 4 quadrants, packed for k_shift
     DevBuf m2l;                // translation tables, zero-padded to KP x KP each
     DevBuf m2l_pk;             // the same, packed for k_m2l_stream
+    DevBuf m2l_bf3;            // FP32 only: the packed tables as three BF16 parts per entry
     DevBuf us, M, L;           // workspace
     size_t ws_nrhs = 0;
     DevBuf Lx;                 // per-pair local expansions of the X lists
@@ -127,10 +128,12 @@ void launch_p2p(hipStream_t s, unsigned grid, const DTree<T> &v, int nleaves, co
 // streamed through registers class by class (acc: added to out, else stored);
 // for coefficient counts up to kmax <= 80, else launches nothing and returns
 // false.
+// Abf (FP32 only, else null): the tables as three BF16 parts per entry, read
+// by the BF16 matrix-core form instead of Apk.
 template <typename T>
 bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
-                       const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk, int KP, int KS,
-                       const T *in, T *out);
+                       const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk,
+                       const uint16_t *Abf, int KP, int KS, const T *in, T *out);
 // Batched translation GEMM (fmm.hip); kc = staged coefficients per step.
 template <typename T>
 void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks, int t0,

@@ -1135,8 +1135,9 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
         IMQ_HIP(hipStreamWaitEvent(s, t->ev_prep, 0));              // L cleared, X lists added
         IMQ_HIP(hipStreamWaitEvent(t->side[2], t->ev_prep, 0));
     }
-    // Per level: the register-streaming kernel (mode 0, up to 80 coefficients
-    // in FP32 and 64 in FP64) or the staged GEMM; consecutive levels of one
+    // Per level: the register-streaming kernel (modes 0 and 2, up to 80
+    // coefficients; mode 2 runs the FP32 products on the BF16 matrix cores
+    // from three-part operands) or the staged GEMM; consecutive levels of one
     // kind and row-block count share a launch (a group).
     std::vector<int> group_of(h.nlev, -1);
     {
@@ -1144,7 +1145,7 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
         const int smax = 5;
         const auto kind = [&](int l) {
             const int nrb = (h.Klev[l] + 15) / 16;
-            return (kc.m2l_mode == 0 && nrb <= smax) ? nrb : 0;
+            return (kc.m2l_mode != 1 && nrb <= smax) ? nrb : 0;
         };
         int ngroup = 0;
         for (int l = 0; l < h.nlev;) {
@@ -1160,9 +1161,11 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
             }
             const int nt = g.level_task_begin[l2] - t0;
             bool done = false;
+            const uint16_t *abf = (sizeof(T) == 4 && kc.m2l_mode == 2) ? pd.m2l_bf3.as<uint16_t>() : nullptr;
             if (k > 0)
                 done = launch_m2l_stream<T>(gs, 1, kmax, nt, t0, nrhs, g.tasks.as<GemmTask>(), g.tbox.as<int32_t>(),
-                                            g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.m2l_pk.as<T>(), KP, KS, M, L);
+                                            g.tab.as<int32_t>(), g.src.as<int32_t>(), pd.m2l_pk.as<T>(), abf, KP, KS, M,
+                                            L);
             if (!done)
                 launch_gemm<T>(gs, kc.m2l_kc > 0 ? kc.m2l_kc : 32, kc.m2l_split > 0 ? kc.m2l_split : 1, nt, nrhs,
                                g.tasks.as<GemmTask>(), t0, g.tbox.as<int32_t>(), g.tab.as<int32_t>(),

@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace imq {
 
 namespace {
@@ -37,15 +39,55 @@ namespace {
 // workgroup computes: small levels spread over NRB / RBW times more
 // workgroups, each reading only its rows of every table.  Register use:
 // RBW*NRB + 2*NCB*NRB four-value quads.
-template <typename T, int NRB, int NCB, int NW, int RBW>
+// BF (FP32 products): the table is read as three BF16 parts per entry (hi,
+// mid, lo: hi = bf16(t), mid = bf16(t - hi), lo = bf16(t - hi - mid), 24
+// significant bits in all), the source quads are split the same way in
+// registers, and each four-coefficient step is six BF16 matrix-core
+// products (v_mfma_f32_16x16x16_bf16: the quad of a lane is exactly its A or
+// B operand) accumulated in FP32: hi.hi + hi.mid + mid.hi + hi.lo + lo.hi +
+// mid.mid, the dropped products being below 2^-24 of the result.  Split
+// table records: per (table, row block, input chunk, lane) 12 BF16 values,
+// hi[4] mid[4] lo[4].
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+struct BfQ {
+    bf4 h, m, l;
+};
+
+__device__ __forceinline__ BfQ split3(const Quad<float> &x)
+{
+    const fv4 v{x.v[0], x.v[1], x.v[2], x.v[3]};
+    BfQ o;
+    o.h = __builtin_convertvector(v, bf4);
+    const fv4 r1 = v - __builtin_convertvector(o.h, fv4);
+    o.m = __builtin_convertvector(r1, bf4);
+    const fv4 r2 = r1 - __builtin_convertvector(o.m, fv4);
+    o.l = __builtin_convertvector(r2, bf4);
+    return o;
+}
+
+__device__ __forceinline__ f32x4 mac_bf3(const BfQ &a, const BfQ &b, f32x4 c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.m, b.m, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.l, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.l, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.m, b.h, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.m, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.h, b.h, c, 0, 0, 0);
+    return c;
+}
+
+template <typename T, int NRB, int NCB, int NW, int RBW, bool BF = false>
 __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restrict__ tasks, int task0,
                                                     const int32_t *__restrict__ tbox,
                                                     const int32_t *__restrict__ tab,
                                                     const int32_t *__restrict__ src, const T *__restrict__ Apk,
+                                                    const uint16_t *__restrict__ Abf,
                                                     int nrbT, int nrhs, int KS, const T *__restrict__ in,
                                                     T *__restrict__ out, int add)
 {
     static_assert(NRB % RBW == 0, "whole row-block groups");
+    static_assert(!BF || sizeof(T) == 4, "BF16 parts of FP32 operands");
     constexpr int TC = 16 * NCB;
     constexpr int LDR = RBW * 16 + 1;
     using acc_t = typename Mfma<T>::acc_t;
@@ -113,6 +155,29 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
         const int tb = has(k) ? tab[tk.tab0 + w + NW * k] : 0;
         return Apk + (size_t(tb) * nrbT + rb0) * nrbT * 256 + lane * 4;
     };
+    auto table_bf = [&](int k) -> const uint16_t * {
+        const int tb = has(k) ? tab[tk.tab0 + w + NW * k] : 0;
+        return Abf + ((size_t(tb) * nrbT + rb0) * nrbT * 64 + lane) * 12;
+    };
+    using AQ = typename std::conditional<BF, BfQ, Q>::type;
+    // the table operand of row block rb, input chunk ci
+    auto load_a = [&](const void *A, int rb, int ci) -> AQ {
+        if constexpr (BF) {
+            const uint2 *r = reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(A) +
+                                                             size_t(rb * nrbT + ci) * 64 * 12);
+            BfQ o;
+            o.h = __builtin_bit_cast(bf4, r[0]);
+            o.m = __builtin_bit_cast(bf4, r[1]);
+            o.l = __builtin_bit_cast(bf4, r[2]);
+            return o;
+        } else {
+            return *reinterpret_cast<const Q *>(static_cast<const T *>(A) + (rb * nrbT + ci) * 256);
+        }
+    };
+    auto table_any = [&](int k) -> const void * {
+        if constexpr (BF) return table_bf(k);
+        else return table(k);
+    };
 
     acc_t acc[RBW][NCB];
 #pragma unroll
@@ -122,34 +187,52 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[rb][cb][v] = T(0);
 
-    Q a[RBW][NRB];
+    AQ a[RBW][NRB];
     Q bc[NCB][NRB], bn[NCB][NRB];
     int sbc[NCB], sbn[NCB], sbnn[NCB];
     source(0, sbc);
     source(1, sbn);
-    const T *Ac = table(0);
+    const void *Ac = table_any(0);
 #pragma unroll
     for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
-        for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = *reinterpret_cast<const Q *>(Ac + (rb * nrbT + ci) * 256);
+        for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = load_a(Ac, rb, ci);
     load_b(sbc, bc);
     for (int k = 0; k < SPW; ++k) {
         const bool act = has(k);                      // wave-uniform
-        const T *An = table(k + 1);
+        const void *An = table_any(k + 1);
         load_b(sbn, bn);
         source(k + 2, sbnn);
+        if constexpr (BF) {
+            BfQ bs[NCB][NRB];
 #pragma unroll
-        for (int rb = 0; rb < RBW; ++rb) {
-            if (act)
+            for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-                for (int ci = 0; ci < NRB; ++ci)
+                for (int ci = 0; ci < NRB; ++ci) bs[cb][ci] = split3(bc[cb][ci]);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+            for (int rb = 0; rb < RBW; ++rb) {
+                if (act)
 #pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb)
-                            acc[rb][cb] = Mfma<T>::mac(a[rb][ci].v[j], bc[cb][ci].v[j], acc[rb][cb]);
+                    for (int ci = 0; ci < NRB; ++ci)
 #pragma unroll
-            for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = *reinterpret_cast<const Q *>(An + (rb * nrbT + ci) * 256);
+                        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mac_bf3(a[rb][ci], bs[cb][ci], acc[rb][cb]);
+#pragma unroll
+                for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = load_a(An, rb, ci);
+            }
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < RBW; ++rb) {
+                if (act)
+#pragma unroll
+                    for (int ci = 0; ci < NRB; ++ci)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int cb = 0; cb < NCB; ++cb)
+                                acc[rb][cb] = Mfma<T>::mac(a[rb][ci].v[j], bc[cb][ci].v[j], acc[rb][cb]);
+#pragma unroll
+                for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = load_a(An, rb, ci);
+            }
         }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
@@ -185,8 +268,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
 
 template <typename T>
 bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
-                       const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk, int KP, int KS,
-                       const T *in, T *out)
+                       const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk,
+                       const uint16_t *Abf, int KP, int KS, const T *in, T *out)
 {
     const int nrb = (kmax + 15) / 16;
     if (ntask <= 0) return true;
@@ -197,15 +280,22 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
     // (one row block per workgroup).  16 target columns per workgroup
     // everywhere: at the fine levels (up to 48 coefficients) 32 columns gave
     // half the workgroups and a 7% slower M2L stage.
-#define IMQ_M2LS(NRB, NCB, NW)                                                                             \
+#define IMQ_M2LS_BF(NRB, NCB, NW, BF)                                                                      \
     do {                                                                                                   \
         const unsigned ny = unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB));                      \
         if (NRB > 1 && size_t(ntask) * ny < 512)                                                           \
-            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, 1>), dim3(ntask, ny, NRB), dim3(64 * NW), 0, s, \
-                               tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out, acc);             \
+            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, 1, BF>), dim3(ntask, ny, NRB), dim3(64 * NW), 0, \
+                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc);     \
         else                                                                                               \
-            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, NRB>), dim3(ntask, ny, 1), dim3(64 * NW), 0, s, \
-                               tasks, task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out, acc);             \
+            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, NRB, BF>), dim3(ntask, ny, 1), dim3(64 * NW), 0,  \
+                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc);     \
+    } while (0)
+#define IMQ_M2LS(NRB, NCB, NW)                                                                             \
+    do {                                                                                                   \
+        if constexpr (sizeof(T) == 4) {                                                                    \
+            if (Abf) { IMQ_M2LS_BF(NRB, NCB, NW, true); break; }                                           \
+        }                                                                                                  \
+        IMQ_M2LS_BF(NRB, NCB, NW, false);                                                                  \
     } while (0)
     if constexpr (sizeof(T) == 4) {
         switch (nrb) {
@@ -225,19 +315,20 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
         case 5:      // one row block per workgroup: a whole-row tile would not fit the registers
             hipLaunchKernelGGL((k_m2l_stream<T, 5, 1, 4, 1>),
                                dim3(ntask, unsigned((GEMM_TILE * nrhs + 15) / 16), 5), dim3(256), 0, s, tasks,
-                               task0, tbox, tab, src, Apk, KP / 16, nrhs, KS, in, out, acc);
+                               task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc);
             return true;
         default: return false;
         }
     }
 #undef IMQ_M2LS
+#undef IMQ_M2LS_BF
 }
 
 template bool launch_m2l_stream<float>(hipStream_t, int, int, int, int, int, const GemmTask *, const int32_t *,
-                                       const int32_t *, const int32_t *, const float *, int, int, const float *,
-                                       float *);
+                                       const int32_t *, const int32_t *, const float *, const uint16_t *, int, int,
+                                       const float *, float *);
 template bool launch_m2l_stream<double>(hipStream_t, int, int, int, int, int, const GemmTask *, const int32_t *,
-                                        const int32_t *, const int32_t *, const double *, int, int, const double *,
-                                        double *);
+                                        const int32_t *, const int32_t *, const double *, const uint16_t *, int, int,
+                                        const double *, double *);
 
 }  // namespace imq

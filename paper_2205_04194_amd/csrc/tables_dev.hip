@@ -9,9 +9,10 @@
 // matrix on the stored n+m-even coefficients.  One workgroup per table:
 // the harmonics up to degree 2p by the same recurrences (one thread per
 // order m after the diagonal), then one thread per (output, input)
-// coefficient pair writes its 2 x 2 real block into the four layouts the
+// coefficient pair writes its 2 x 2 real block into the layouts the
 // translation kernels read: FP64 and FP32, row-major zero-padded to KP x KP
-// (staged GEMM) and in the lane order of the register-streaming kernel.
+// (staged GEMM) and in the lane order of the register-streaming kernel, and
+// the FP32 lane order once more as three BF16 parts per entry.
 // A forest of many sets has one table set per set (its own c): generating
 // them here takes milliseconds where the host took seconds, and nothing is
 // uploaded.  The arithmetic repeats the host's operations in its order
@@ -64,7 +65,8 @@ __device__ __forceinline__ void decode(int r, int &n, int &m, bool &im)
 __global__ __launch_bounds__(256) void k_m2l_tables(int p, int nlev, const double *__restrict__ cn,
                                                     const double *__restrict__ cnm, int KP,
                                                     double *__restrict__ t64, double *__restrict__ pk64,
-                                                    float *__restrict__ t32, float *__restrict__ pk32)
+                                                    float *__restrict__ t32, float *__restrict__ pk32,
+                                                    uint16_t *__restrict__ bf3)
 {
     __shared__ Cx H[NH];
     __shared__ Cx diag[2 * PMAX + 1];
@@ -102,12 +104,23 @@ __global__ __launch_bounds__(256) void k_m2l_tables(int p, int nlev, const doubl
     double *P64 = pk64 + size_t(id) * PP;
     float *T32 = t32 + size_t(id) * PP;
     float *P32 = pk32 + size_t(id) * PP;
+    uint16_t *B3 = bf3 + size_t(id) * PP * 3;
     auto store = [&](int r, int c, double v) {
-        const size_t pkx = ((size_t(r / 16) * nrb + c / 16) * 64 + ((c % 16) / 4) * 16 + r % 16) * 4 + c % 4;
+        const size_t rec = (size_t(r / 16) * nrb + c / 16) * 64 + ((c % 16) / 4) * 16 + r % 16;
+        const size_t pkx = rec * 4 + c % 4;
         T64[size_t(r) * KP + c] = v;
         P64[pkx] = v;
-        T32[size_t(r) * KP + c] = float(v);
-        P32[pkx] = float(v);
+        const float f = float(v);
+        T32[size_t(r) * KP + c] = f;
+        P32[pkx] = f;
+        // the FP32 value as three BF16 parts (each difference exact in FP32)
+        const __bf16 hi = __bf16(f);
+        const float r1 = f - float(hi);
+        const __bf16 mid = __bf16(r1);
+        const __bf16 lo = __bf16(r1 - float(mid));
+        B3[rec * 12 + c % 4] = __builtin_bit_cast(uint16_t, hi);
+        B3[rec * 12 + 4 + c % 4] = __builtin_bit_cast(uint16_t, mid);
+        B3[rec * 12 + 8 + c % 4] = __builtin_bit_cast(uint16_t, lo);
     };
     const int K = (p + 1) * (p + 2) / 2;
     // one thread per real entry (r, c): output coefficient (j, k) (cosine or
@@ -162,10 +175,12 @@ imq_status make_m2l_tables_device(imq_tree_s *t, int KP)
     IMQ_HIP(hipMemset(t->f64.m2l_pk.p, 0, sizeof(double) * ntab * PP));
     IMQ_HIP(hipMemset(t->f32.m2l.p, 0, sizeof(float) * ntab * PP));
     IMQ_HIP(hipMemset(t->f32.m2l_pk.p, 0, sizeof(float) * ntab * PP));
+    IMQ_HIP(dev_alloc(t->f32.m2l_bf3, sizeof(uint16_t) * 3 * ntab * PP));
+    IMQ_HIP(hipMemset(t->f32.m2l_bf3.p, 0, sizeof(uint16_t) * 3 * ntab * PP));
     if (ntab > 0)
         hipLaunchKernelGGL(k_m2l_tables, dim3(unsigned(ntab)), dim3(256), 0, 0, p, h.nlev, d_cn.as<double>(),
                            d_cnm.as<double>(), KP, t->f64.m2l.as<double>(), t->f64.m2l_pk.as<double>(),
-                           t->f32.m2l.as<float>(), t->f32.m2l_pk.as<float>());
+                           t->f32.m2l.as<float>(), t->f32.m2l_pk.as<float>(), t->f32.m2l_bf3.as<uint16_t>());
     IMQ_HIP(hipGetLastError());
     IMQ_HIP(hipDeviceSynchronize());
     return IMQ_OK;

@@ -134,21 +134,24 @@ def test_invalid_arguments_raise(imq):
 
 @pytest.mark.parametrize("p", [3, 4, 6, 9, 12])
 def test_translation_kernels_agree_and_match_the_oracle(imq, p):
-    """The two M2L kernels (operands streamed through registers, staged GEMM)
-    compute the same truncated sums, so they differ by rounding only; both stay
-    within the truncation error of order p against the oracle."""
+    """The M2L kernels (operands streamed through registers, staged GEMM, and
+    the streamed FP32 products on the BF16 matrix cores from three-part
+    operands) compute the same truncated sums, so they differ by rounding
+    only; all stay within the truncation error of order p against the
+    oracle."""
     d = W.small(6000)
     U = W.uniform_vector(6000, W.rng(67, p), nrhs=3)
     tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=16, p=p)
     ref = oracle.matvec(d["xy"], d["c"], U)
     out = {}
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         tree.set_kernel_config(m2l_mode=mode)
         out[mode, "fp64"] = tree.matvec(_dev(U), "fp64").cpu().numpy()
         out[mode, "fp32"] = tree.matvec(_dev(U), "fp32").cpu().numpy()
     for r in range(3):
         assert _rel(out[0, "fp64"][r], out[1, "fp64"][r]) < 1e-12
-        for mode in (0, 1):
+        assert _rel(out[2, "fp64"][r], out[0, "fp64"][r]) < 1e-13
+        for mode in (0, 1, 2):
             assert _rel(out[mode, "fp32"][r], out[1, "fp64"][r]) < 2e-6
         err = _rel(out[0, "fp64"][r], ref[r])
         print(f"p={p} rhs {r}: rel err vs oracle {err:.3e}")
@@ -158,22 +161,22 @@ def test_translation_kernels_agree_and_match_the_oracle(imq, p):
 @pytest.mark.parametrize("nrhs", [1, 2, 70])
 def test_streamed_translations_up_to_80_coefficients(imq, nrhs):
     """The register-streaming M2L kernel at every row-block count (1 to 5: up to
-    80 coefficients per box, FP32 and FP64) on a deep tree with per-level
-    orders from 12 down to 1 and several right-hand sides, against the staged
-    GEMM."""
+    80 coefficients per box; FP64, FP32, and FP32 on the BF16 matrix cores) on
+    a deep tree with per-level orders from 12 down to 1 and several
+    right-hand sides, against the staged GEMM."""
     d = W.small(30000)
     U = _dev(W.uniform_vector(30000, W.rng(68, nrhs), nrhs=nrhs))
     tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=8, p=11)
     nlev = tree.info()["nlevels"]
     orders = [max(1, 11 - 2 * max(0, l - 2)) for l in range(nlev)]
     tree.set_level_orders(orders)
-    for prec, tol in (("fp64", 1e-13), ("fp32", 2e-6)):
-        tree.set_kernel_config(m2l_mode=1)
-        ref = tree.matvec(U, "fp64")
-        tree.set_kernel_config(m2l_mode=0)
+    tree.set_kernel_config(m2l_mode=1)
+    ref = tree.matvec(U, "fp64")
+    for mode, prec, tol in ((0, "fp64", 1e-13), (0, "fp32", 2e-6), (2, "fp32", 2e-6)):
+        tree.set_kernel_config(m2l_mode=mode)
         b = tree.matvec(U, prec)
         e = float(torch.linalg.norm(b - ref) / torch.linalg.norm(ref))
-        print(f"orders {orders}, nrhs {nrhs}, {prec}: streamed vs staged GEMM {e:.2e}")
+        print(f"orders {orders}, nrhs {nrhs}, mode {mode} {prec}: streamed vs staged GEMM {e:.2e}")
         assert e < tol
 
 
