@@ -120,6 +120,7 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
         for (size_t i = 0; i < lr.size(); ++i) {
             const int b = h.leaves[i];
             lr[i] = LeafRec{b, h.begin[b], h.end[b], h.level[b]};
+            t->max_leaf = std::max(t->max_leaf, h.end[b] - h.begin[b]);
         }
         if ((st = upload(t->leafrec, lr)) != IMQ_OK) return st;
         // every box that can be a V-list source, with the leaves under it: a

@@ -181,6 +181,7 @@ struct imq_tree_s {
     imq::DevBuf u_off, u_idx, v_off, v_idx, v_cls, w_off, w_idx, x_off, x_idx, Klev, cn, leaves;
     imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
     imq::DevBuf leafrec;                   // LeafRec per leaf
+    int max_leaf = 0;                      // most points in one leaf
     imq::DevBuf boxrec;                    // BoxRec per box at levels >= need_m (Algorithm 1 mode)
     imq::DevBuf boxleaf;                   // leaf-list indices in point order (BoxRec ranges)
     int nboxrec = 0;

@@ -136,51 +136,210 @@ __device__ __forceinline__ T lds_dot(const T *a, int ld, int k, const T *w, int 
 }
 
 // P2M: Mt[n,m] = sum_j u_j |w_j|^(n-m) conj(w_j)^m over a leaf's points.
-// One wave per leaf: each lane writes its point's monomials as one row of
-// an LDS matrix (odd row stride), then each lane sums one coefficient's
-// column against the weights of every right-hand side.  recs: the leaves,
-// one per workgroup.
-constexpr int P2M_CHUNK = 32;      // points staged per round (LDS per wave halves vs 64)
+// With n = m + 2e the coefficient is sum_j (u_j |w_j|^(2e)) conj(w_j)^m:
+// each lane (a point of the chunk) writes its powers conj(w)^m, m <= P, and
+// u |w|^(2e), e <= P/2, as one row of an LDS matrix (odd row stride, 3P/2 + 3
+// values where the monomials would be (P+1)(P+2)/2), and each lane then
+// forms its coefficients as sums over the rows of the product of two entries
+// (the same entry for every lane of one m or one e: mostly broadcast reads).
+// With caller-order weights the kernels also store them in point order (us),
+// for the stages that read them there.
+constexpr int P2M_CHUNK = 64;      // points staged per round
+constexpr int LEAF_WG_MAX = 4096;  // workgroups of the leaf-by-leaf kernels (P2M, L2P)
+template <int P> constexpr int p2m_ld() { return (2 * (P + 1) + P / 2 + 1) | 1; }
 
+// The chunk's rows and the coefficient sums, shared by both P2M kernels.
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const LeafRec *__restrict__ recs, const T *__restrict__ us,
-                                            int nrhs, T *__restrict__ M, int ld, UserVec io)
-{
-    extern __shared__ unsigned char smem_raw[];
-    T *mono = reinterpret_cast<T *>(smem_raw);   // [P2M_CHUNK][ld]
-    T *su = mono + P2M_CHUNK * ld;               // [P2M_CHUNK]
-    const LeafRec lr = recs[blockIdx.x];
-    const int b = lr.box, beg = lr.begin, end = lr.end;
-    const T inv_s = pow2i<T>(lr.level);
-    constexpr int K = (P + 1) * (P + 2) / 2;
-    const int lane = threadIdx.x;
-    for (int c0 = beg; c0 < end; c0 += P2M_CHUNK) {
-        const int n = min(P2M_CHUNK, end - c0);
-        // the point and its first weight are requested together, by every
-        // lane (lanes past the chunk read its first point): no branch around
-        // the loads
-        const int ip = c0 + (lane < n ? lane : 0);
-        const T x = t.xl[ip], y = t.yl[ip];
-        const T u0 = io.in ? T(io.get(0, ip)) : us[ip];
-        __syncthreads();
-        if (lane < n) {
-            T *row = mono + lane * ld;
-            monomials<P>(x * inv_s, -y * inv_s, [&](int k, T v, bool) { row[k] = v; });
-            su[lane] = u0;
-        }
-        for (int r = 0; r < nrhs; ++r) {
-            if (r > 0) {
-                __syncthreads();
-                if (lane < n) su[lane] = io.in ? T(io.get(r, c0 + lane)) : us[r * t.N + c0 + lane];
-            }
-            __syncthreads();
-            for (int k = lane; k < K; k += 64) {
-                const T v = lds_dot(mono, ld, k, su, n);
-                T &dst = M[(int64_t(b) * nrhs + r) * t.KS + k];
-                dst = (c0 == beg) ? v : dst + v;
-            }
+struct P2MRows {
+    static constexpr int K = (P + 1) * (P + 2) / 2;
+    static constexpr int LD = p2m_ld<P>();
+    static constexpr int EOFF = 2 * (P + 1);      // row: conj(w)^m (re, im) for m <= P, then u |w|^(2e)
+    static constexpr int NE = P / 2 + 1;
+    static constexpr int NKL = (K + 63) / 64;
+    int wo[NKL], eo[NKL];                         // entries of coefficient lane + 64 i
+    __device__ __forceinline__ explicit P2MRows(int lane)
+    {
+#pragma unroll
+        for (int i = 0; i < NKL; ++i) {
+            const int k = min(lane + 64 * i, K - 1);
+            int n = 0;
+            while ((n + 1) * (n + 2) / 2 <= k) ++n;
+            // stored order: n ascending; for each n, m = n mod 2, n mod 2 + 2,
+            // ..., cosine then sine part for m > 0
+            const int o = k - n * (n + 1) / 2;
+            const int m = (n & 1) ? 2 * (o / 2) + 1 : 2 * ((o + 1) / 2);
+            const int re_o = m > 0 ? m - 1 : 0;
+            wo[i] = 2 * m + (o != re_o ? 1 : 0);
+            eo[i] = EOFF + (n - m) / 2;
         }
     }
+    // row of one point: w = (x, -y) / s, weight u
+    __device__ __forceinline__ static void write(T *row, T wx, T wy, T u)
+    {
+        const T rr = wx * wx + wy * wy;
+        T pr = T(1), pi = T(0);
+#pragma unroll
+        for (int m = 0; m <= P; ++m) {
+            row[2 * m] = pr;
+            row[2 * m + 1] = pi;
+            const T t_ = pr * wx - pi * wy;
+            pi = pr * wy + pi * wx;
+            pr = t_;
+        }
+        T q = u;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            row[EOFF + e] = q;
+            q *= rr;
+        }
+    }
+    // acc[i] += sum over rows j < n of S[j][wo[i]] * S[j][eo[i]], four rows a step
+    __device__ __forceinline__ void sums(const T *S, int n, T *acc) const
+    {
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            const T *a = S + j * LD;
+#pragma unroll
+            for (int i = 0; i < NKL; ++i)
+                acc[i] += (a[wo[i]] * a[eo[i]] + a[LD + wo[i]] * a[LD + eo[i]]) +
+                          (a[2 * LD + wo[i]] * a[2 * LD + eo[i]] + a[3 * LD + wo[i]] * a[3 * LD + eo[i]]);
+        }
+        for (; j < n; ++j)
+#pragma unroll
+            for (int i = 0; i < NKL; ++i) acc[i] += S[j * LD + wo[i]] * S[j * LD + eo[i]];
+    }
+};
+
+// IN: where the weights are read: 0 = us (point order), 1 = the caller's FP64
+// vector, 2 = the caller's FP32 vector (caller order, through io.perm).
+template <typename T, int IN>
+__device__ __forceinline__ T p2m_weight(const UserVec &io, const T *us, int64_t N, int j, int r)
+{
+    if constexpr (IN == 0) return us[r * N + j];
+    else if constexpr (IN == 1) return T(static_cast<const double *>(io.in)[r * io.ldu + j]);
+    else return T(static_cast<const float *>(io.in)[r * io.ldu + j]);
+}
+
+// One right-hand side, leaves of at most 64 points (one chunk).  recs: the
+// leaves; workgroup g takes leaves g, g + G, ... (G workgroups).  The point
+// and weight of the next leaf are requested before the current leaf is
+// worked on, and the point and caller-order index of the leaf after it one
+// leaf earlier still, so neither the loads nor the gather of caller-order
+// weights (two dependent loads) stall the wave; no other load is issued in
+// the loop.
+template <typename T, int P, int IN>
+__global__ __launch_bounds__(64) void k_p2m_pipe(DTree<T> t, const LeafRec *__restrict__ recs, int nrec,
+                                                 T *__restrict__ us, T *__restrict__ M, UserVec io)
+{
+    using R = P2MRows<T, P>;
+    __shared__ T S[P2M_CHUNK * R::LD];
+    const int lane = threadIdx.x;
+    const int G = gridDim.x;
+    int li = blockIdx.x;
+    if (li >= nrec) return;
+    const R rows(lane);
+    struct Pa {                                      // point, caller-order index of its weight
+        T x, y;
+        int j;
+    };
+    struct Pb {                                      // point, weight
+        T x, y, u;
+    };
+    // lanes past the leaf read its first point, an empty leaf point 0
+    auto stage_a = [&](const LeafRec &r) -> Pa {
+        const int ip = r.end > r.begin ? r.begin + (lane < r.end - r.begin ? lane : 0) : 0;
+        if constexpr (IN == 0) return Pa{t.xl[ip], t.yl[ip], ip};
+        else return Pa{t.xl[ip], t.yl[ip], io.perm[ip]};
+    };
+    auto stage_b = [&](const Pa &a) -> Pb { return Pb{a.x, a.y, p2m_weight<T, IN>(io, us, t.N, a.j, 0)}; };
+    // records of the current leaf and the two after it (the current one
+    // stands in past the end: loaded again, not used)
+    LeafRec lr = recs[li];
+    LeafRec r1 = li + G < nrec ? recs[li + G] : lr;
+    LeafRec r2 = li + 2 * G < nrec ? recs[li + 2 * G] : lr;
+    Pb cur = stage_b(stage_a(lr));
+    Pa nxa = stage_a(r1);
+    for (;;) {
+        const bool more = li + G < nrec;
+        const Pb nxb = stage_b(nxa);
+        const Pa nna = stage_a(r2);
+        const int n = lr.end - lr.begin;
+        if (IN != 0 && lane < n) us[lr.begin + lane] = cur.u;
+        __syncthreads();                             // the previous leaf's rows are no longer read
+        if (lane < n) {
+            const T inv_s = pow2i<T>(lr.level);
+            R::write(S + lane * R::LD, cur.x * inv_s, -cur.y * inv_s, cur.u);
+        }
+        __syncthreads();
+        T acc[R::NKL];
+#pragma unroll
+        for (int i = 0; i < R::NKL; ++i) acc[i] = T(0);
+        rows.sums(S, n, acc);
+#pragma unroll
+        for (int i = 0; i < R::NKL; ++i)
+            if (lane + 64 * i < R::K) M[int64_t(lr.box) * t.KS + lane + 64 * i] = acc[i];
+        if (!more) break;
+        li += G;
+        lr = r1;
+        r1 = r2;
+        r2 = li + 2 * G < nrec ? recs[li + 2 * G] : lr;
+        cur = nxb;
+        nxa = nna;
+    }
+}
+
+// Any number of right-hand sides (below the matrix-core form's) and leaf
+// size: one leaf per workgroup, chunk by chunk.
+template <typename T, int P, int IN>
+__global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const LeafRec *__restrict__ recs, T *__restrict__ us,
+                                            int nrhs, T *__restrict__ M, UserVec io)
+{
+    using R = P2MRows<T, P>;
+    __shared__ T S[P2M_CHUNK * R::LD];
+    const int lane = threadIdx.x;
+    const R rows(lane);
+    const LeafRec lr = recs[blockIdx.x];
+    const T inv_s = pow2i<T>(lr.level);
+    for (int r = 0; r < nrhs; ++r) {
+        T acc[R::NKL];
+#pragma unroll
+        for (int i = 0; i < R::NKL; ++i) acc[i] = T(0);
+        for (int c0 = lr.begin; c0 < lr.end; c0 += P2M_CHUNK) {
+            const int n = min(P2M_CHUNK, lr.end - c0);
+            const int ip = c0 + (lane < n ? lane : 0);
+            const T x = t.xl[ip], y = t.yl[ip];
+            const T u = p2m_weight<T, IN>(io, us, t.N, IN == 0 ? ip : io.perm[ip], r);
+            if (IN != 0 && lane < n) us[r * t.N + ip] = u;
+            __syncthreads();
+            if (lane < n) R::write(S + lane * R::LD, x * inv_s, -y * inv_s, u);
+            __syncthreads();
+            rows.sums(S, n, acc);
+        }
+#pragma unroll
+        for (int i = 0; i < R::NKL; ++i)
+            if (lane + 64 * i < R::K) M[(int64_t(lr.box) * nrhs + r) * t.KS + lane + 64 * i] = acc[i];
+    }
+}
+
+template <typename T, int P, int IN>
+void launch_p2m_in(hipStream_t s, int nleaves, int max_leaf, const DTree<T> &v, const LeafRec *recs, T *us,
+                   int nrhs, T *M, const UserVec &uv)
+{
+    if (nrhs == 1 && max_leaf <= P2M_CHUNK)
+        hipLaunchKernelGGL((k_p2m_pipe<T, P, IN>), dim3(unsigned(std::min(nleaves, LEAF_WG_MAX))), dim3(64), 0, s,
+                           v, recs, nleaves, us, M, uv);
+    else
+        hipLaunchKernelGGL((k_p2m<T, P, IN>), dim3(unsigned(nleaves)), dim3(64), 0, s, v, recs, us, nrhs, M, uv);
+}
+
+template <typename T, int P>
+void launch_p2m(hipStream_t s, int nleaves, int max_leaf, const DTree<T> &v, const LeafRec *recs, T *us, int nrhs,
+                T *M, const UserVec &uv)
+{
+    if (nleaves <= 0) return;
+    if (!uv.in) launch_p2m_in<T, P, 0>(s, nleaves, max_leaf, v, recs, us, nrhs, M, uv);
+    else if (!uv.f32) launch_p2m_in<T, P, 1>(s, nleaves, max_leaf, v, recs, us, nrhs, M, uv);
+    else launch_p2m_in<T, P, 2>(s, nleaves, max_leaf, v, recs, us, nrhs, M, uv);
 }
 
 // P2M of any box from its own points (Algorithm 1 mode): the leaves under
@@ -497,47 +656,27 @@ struct M2PParts {
 // the kernel is instantiated for the tree's order P and switches, per leaf,
 // to the fully unrolled evaluation of order Q.  The expansion is staged in LDS.
 template <typename T, int Q>
-__device__ __forceinline__ void l2p_leaf(const DTree<T> &t, const LeafRec &lr, T *Ls, const T *__restrict__ L,
-                                         int nrhs, double *__restrict__ bs, int add, const UserVec &io,
-                                         const M2PParts &wp)
+__device__ __forceinline__ T l2p_eval(T x, T y, const T *Ls)
 {
-    constexpr int K = (Q + 1) * (Q + 2) / 2;
-    const T inv_s = pow2i<T>(lr.level);
-    for (int i0 = lr.begin; i0 < lr.end; i0 += blockDim.x) {
-        const int i = i0 + threadIdx.x;
-        const bool ok = i < lr.end;
-        for (int r = 0; r < nrhs; ++r) {
-            __syncthreads();                     // the previous expansion is no longer read
-            // the point, the partial result and the expansion are requested together
-            const T x = ok ? t.xl[i] * inv_s : T(0), y = ok ? t.yl[i] * inv_s : T(0);
-            const double prev = (ok && add) ? bs[r * t.N + i] : 0.0;
-            for (int k = threadIdx.x; k < K; k += blockDim.x) Ls[k] = L[(size_t(lr.box) * nrhs + r) * t.KS + k];
-            __syncthreads();
-            if (!ok) continue;
-            T acc = T(0);
-            // real part of Lt * monomial: Re*Re - Im*Im
-            monomials<Q>(x, y, [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
-            double val = prev + double(acc);
-            if (wp.Pw)                            // the leaf's W-list evaluations, in list order
-                for (int kp = t.w_off[lr.box]; kp < t.w_off[lr.box + 1]; ++kp)
-                    val += wp.Pw[size_t(r) * wp.nscr + wp.w_scr[kp] + (i - lr.begin)];
-            if (io.out) io.put(r, i, val);
-            else bs[r * t.N + i] = val;
-        }
-    }
+    T acc = T(0);
+    // real part of Lt * monomial: Re*Re - Im*Im
+    monomials<Q>(x, y, [&](int k, T v, bool im) { acc += im ? -Ls[k] * v : Ls[k] * v; });
+    return acc;
+}
+
+// the order q with (q+1)(q+2)/2 = Kl
+__device__ __forceinline__ int order_of(int Kl)
+{
+    int q = 0;
+    while ((q + 2) * (q + 3) / 2 <= Kl) ++q;
+    return q;
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_l2p(DTree<T> t, LevelK lk, const T *__restrict__ L, int nrhs,
-                                            double *__restrict__ bs, int add, UserVec io, M2PParts wp)
+__device__ __forceinline__ T l2p_value(int q, T x, T y, const T *Ls)
 {
-    __shared__ T Ls[(P + 1) * (P + 2) / 2];
-    const LeafRec lr = t.leafrec[blockIdx.x];
-    const int Kl = lk.K[lr.level];
-    int q = 0;                                   // order with (q+1)(q+2)/2 = Kl
-    while ((q + 2) * (q + 3) / 2 <= Kl) ++q;
 #define IMQ_L2P_Q(Q) \
-    case Q: if constexpr (Q <= P) { l2p_leaf<T, Q>(t, lr, Ls, L, nrhs, bs, add, io, wp); return; } break;
+    case Q: if constexpr (Q <= P) return l2p_eval<T, Q>(x, y, Ls); else break;
     switch (q) {
         IMQ_L2P_Q(1) IMQ_L2P_Q(2) IMQ_L2P_Q(3) IMQ_L2P_Q(4) IMQ_L2P_Q(5) IMQ_L2P_Q(6) IMQ_L2P_Q(7)
         IMQ_L2P_Q(8) IMQ_L2P_Q(9) IMQ_L2P_Q(10) IMQ_L2P_Q(11) IMQ_L2P_Q(12) IMQ_L2P_Q(13) IMQ_L2P_Q(14)
@@ -545,7 +684,136 @@ __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, LevelK lk, const T *__re
         default: break;
     }
 #undef IMQ_L2P_Q
-    l2p_leaf<T, P>(t, lr, Ls, L, nrhs, bs, add, io, wp);
+    return l2p_eval<T, P>(x, y, Ls);
+}
+
+// Adds the leaf's W-list evaluations (in list order) and stores the result.
+template <typename T>
+__device__ __forceinline__ void l2p_store(const DTree<T> &t, const LeafRec &lr, int r, int i, double val,
+                                          double *__restrict__ bs, const UserVec &io, const M2PParts &wp)
+{
+    if (wp.Pw)
+        for (int kp = t.w_off[lr.box]; kp < t.w_off[lr.box + 1]; ++kp)
+            val += wp.Pw[size_t(r) * wp.nscr + wp.w_scr[kp] + (i - lr.begin)];
+    if (io.out) io.put(r, i, val);
+    else bs[r * t.N + i] = val;
+}
+
+// Any number of right-hand sides (below the matrix-core form's) and leaf
+// size: one leaf per workgroup.
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_l2p(DTree<T> t, LevelK lk, const T *__restrict__ L, int nrhs,
+                                            double *__restrict__ bs, int add, UserVec io, M2PParts wp)
+{
+    constexpr int KP = (P + 1) * (P + 2) / 2;
+    __shared__ T Ls[KP];
+    const LeafRec lr = t.leafrec[blockIdx.x];
+    const int Kl = lk.K[lr.level];
+    const int q = order_of(Kl);
+    const T inv_s = pow2i<T>(lr.level);
+    for (int i0 = lr.begin; i0 < lr.end; i0 += 64) {
+        const int i = i0 + threadIdx.x;
+        const bool ok = i < lr.end;
+        for (int r = 0; r < nrhs; ++r) {
+            __syncthreads();                     // the previous expansion is no longer read
+            // the point, the partial result and the expansion are requested together
+            const T x = ok ? t.xl[i] * inv_s : T(0), y = ok ? t.yl[i] * inv_s : T(0);
+            const double prev = (ok && add) ? bs[r * t.N + i] : 0.0;
+            for (int k = threadIdx.x; k < KP; k += 64) Ls[k] = k < Kl ? L[(size_t(lr.box) * nrhs + r) * t.KS + k] : T(0);
+            __syncthreads();
+            if (ok) l2p_store(t, lr, r, i, prev + double(l2p_value<T, P>(q, x, y, Ls)), bs, io, wp);
+        }
+    }
+}
+
+// One right-hand side, leaves of at most 64 points.  Workgroup g takes leaves
+// g, g + G, ... (G workgroups) and requests the next leaf's points, partial
+// results, expansion and caller-order output slots before it evaluates the
+// current one.
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_l2p_pipe(DTree<T> t, const LeafRec *__restrict__ recs, LevelK lk,
+                                                 const T *__restrict__ L, double *__restrict__ bs, int add, UserVec io,
+                                                 M2PParts wp, const int32_t *__restrict__ w_off, int nrec)
+{
+    constexpr int KP = (P + 1) * (P + 2) / 2;
+    constexpr int NL = (KP + 63) / 64;
+    __shared__ T Ls[KP];
+    const int lane = threadIdx.x;
+    const int G = gridDim.x;
+    int li = blockIdx.x;
+    if (li >= nrec) return;
+    struct Pass {
+        T x, y;
+        double prev;
+        int dst;                                  // caller-order slot and scale (io.out)
+        double sc;
+        T l[NL];
+    };
+    // every lane loads: lanes past the leaf read point 0, coefficients past
+    // the level's count read coefficient 0 and are zeroed
+    auto load = [&](const LeafRec &lr, Pass &o) {
+        const int i = lr.begin + lane;
+        const int ii = i < lr.end ? i : 0;
+        o.x = t.xl[ii];
+        o.y = t.yl[ii];
+        o.prev = add ? bs[ii] : 0.0;
+        o.dst = io.out ? io.perm[ii] : ii;
+        o.sc = io.out ? io.scale[ii] : 1.0;
+        const int Kl = lk.K[lr.level];
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            const int k = lane + 64 * j;
+            const T v = L[size_t(lr.box) * t.KS + (k < Kl ? k : 0)];
+            o.l[j] = k < Kl ? v : T(0);
+        }
+    };
+    LeafRec lr = recs[li];
+    LeafRec nr = li + G < nrec ? recs[li + G] : lr;
+    Pass cur;
+    load(lr, cur);
+    for (;;) {
+        const bool more = li + G < nrec;
+        Pass nx;
+        load(nr, nx);                              // the next leaf (the current one again at the end)
+        __syncthreads();                           // the previous expansion is no longer read
+#pragma unroll
+        for (int j = 0; j < NL; ++j)
+            if (lane + 64 * j < KP) Ls[lane + 64 * j] = cur.l[j];
+        __syncthreads();
+        const int i = lr.begin + lane;
+        if (i < lr.end) {
+            const T inv_s = pow2i<T>(lr.level);
+            double val = cur.prev + double(l2p_value<T, P>(order_of(lk.K[lr.level]), cur.x * inv_s,
+                                                           cur.y * inv_s, Ls));
+            if (wp.Pw)
+                for (int kp = w_off[lr.box]; kp < w_off[lr.box + 1]; ++kp)
+                    val += wp.Pw[wp.w_scr[kp] + (i - lr.begin)];
+            if (io.out) {
+                val *= cur.sc;
+                if (io.f32) static_cast<float *>(io.out)[cur.dst] = float(val);
+                else static_cast<double *>(io.out)[cur.dst] = val;
+            } else {
+                bs[i] = val;
+            }
+        }
+        if (!more) break;
+        li += G;
+        lr = nr;
+        nr = li + G < nrec ? recs[li + G] : lr;
+        cur = nx;
+    }
+}
+
+template <typename T, int P>
+void launch_l2p(hipStream_t s, int nleaves, int max_leaf, const DTree<T> &v, const LevelK &lk, const T *L, int nrhs,
+                double *bs, const UserVec &uv, const M2PParts &wp)
+{
+    if (nleaves <= 0) return;
+    if (nrhs == 1 && max_leaf <= 64)
+        hipLaunchKernelGGL((k_l2p_pipe<T, P>), dim3(unsigned(std::min(nleaves, LEAF_WG_MAX))), dim3(64), 0, s, v,
+                           v.leafrec, lk, L, bs, 1, uv, wp, v.w_off, nleaves);
+    else
+        hipLaunchKernelGGL((k_l2p<T, P>), dim3(unsigned(nleaves)), dim3(64), 0, s, v, lk, L, nrhs, bs, 1, uv, wp);
 }
 
 // Many right-hand sides: the leaf expansions and their evaluation as
@@ -1007,7 +1275,6 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
     DTree<T> v = make_view<T>(t);
     const int nleaves = int(h.leaves.size());
     const int K = h.K, KS = coef_stride(K);
-    const int ld = K | 1;                                      // odd LDS row stride
     T *M = pd.M.as<T>();
     mark(t, 1, s);
     const UserVec uv = io ? *io : UserVec();
@@ -1015,7 +1282,10 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
         imq_status st = t->ensure_side();
         if (st != IMQ_OK) return st;
         IMQ_HIP(hipEventRecord(t->ev_start, s));
-        if (uv.in) {       // P2M reads the caller's weights; the Morton-order copy is for P2P and P2L
+        // P2M reads the caller's weights; the point-order copy is for P2P and
+        // P2L.  With few right-hand sides P2M stores that copy itself (ev_start
+        // is then recorded after it), else a gather on side[0] makes it.
+        if (uv.in && nrhs >= BATCH_RHS_MIN) {
             IMQ_HIP(hipStreamWaitEvent(t->side[0], t->ev_start, 0));
             const int64_t N = h.N;
             const dim3 gg(unsigned((N + 255) / 256), nrhs);
@@ -1029,7 +1299,6 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
             IMQ_HIP(hipEventRecord(t->ev_start, t->side[0]));   // now: the copy is ready
         }
     }
-    const size_t lds_p2m = (size_t(P2M_CHUNK) * ld + P2M_CHUNK) * sizeof(T);
     constexpr int RB = sizeof(T) == 4 ? 64 : 32;
     const dim3 gb(unsigned(nleaves), unsigned((nrhs + RB - 1) / RB));
 #define IMQ_P2M(PP)                                                                                    \
@@ -1037,11 +1306,11 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
         hipLaunchKernelGGL((k_p2m_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, t->leaves.as<int32_t>(),     \
                            pd.us.as<T>(), nrhs, M);                                                    \
     else                                                                                               \
-        hipLaunchKernelGGL((k_p2m<T, PP>), dim3(nleaves), dim3(64), lds_p2m, s, v, t->leafrec.as<LeafRec>(),   \
-                           pd.us.as<T>(), nrhs, M, ld, uv)
+        launch_p2m<T, PP>(s, nleaves, t->max_leaf, v, t->leafrec.as<LeafRec>(), pd.us.as<T>(), nrhs, M, uv)
     IMQ_DISPATCH_P(h.p, IMQ_P2M)
 #undef IMQ_P2M
     IMQ_HIP(hipGetLastError());
+    if (fork && uv.in && nrhs < BATCH_RHS_MIN) IMQ_HIP(hipEventRecord(t->ev_start, s));
     mark(t, 2, s);
     if (fork) {
         // Queued after P2M so that P2M's workgroups are dispatched first: clear L
@@ -1265,7 +1534,7 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
     if (nrhs >= BATCH_RHS_MIN)                                                                         \
         hipLaunchKernelGGL((k_l2p_mfma<T, PP, RB>), gb, dim3(64), 0, s, v, leaves, pd.L.as<T>(), nrhs, bs); \
     else                                                                                               \
-        hipLaunchKernelGGL((k_l2p<T, PP>), dim3(nleaves), dim3(64), 0, s, v, lk, pd.L.as<T>(), nrhs, bs, 1, uv, wp)
+        launch_l2p<T, PP>(s, nleaves, t->max_leaf, v, lk, pd.L.as<T>(), nrhs, bs, uv, wp)
     IMQ_DISPATCH_P(h.p, IMQ_L2P)
 #undef IMQ_L2P
     IMQ_HIP(hipGetLastError());

@@ -100,7 +100,8 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
     const int ncols = tk.nbox * nrhs;
     const int col0 = blockIdx.y * TC;
     if (col0 >= ncols) return;                       // uniform over the workgroup
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // the wave index as a scalar: the class tables' indices are then scalar loads
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i16 = lane & 15, q = lane >> 4;
     const int kin = tk.kin, kout = tk.kout;
     const int rb0 = blockIdx.z * RBW;                // first output row block of the workgroup
@@ -122,11 +123,17 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
         bl[cb] = gc < ncols ? gc / nrhs : -1;
         rr[cb] = gc < ncols ? gc - bl[cb] * nrhs : 0;
     }
+    // source box of class k of this wave for each column (-1: none); the load
+    // is unconditional (entry 0 of the task where there is no source) so that
+    // no branch separates the loads of the classes
     auto source = [&](int k, int *sb) {
         const int sl = w + NW * k;
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-            sb[cb] = (k < SPW && sl < nslot && bl[cb] >= 0) ? src[tk.src0 + bl[cb] * nslot + sl] : -1;
+        for (int cb = 0; cb < NCB; ++cb) {
+            const bool ok = k < SPW && sl < nslot && bl[cb] >= 0;
+            const int v = src[tk.src0 + (ok ? bl[cb] * nslot + sl : 0)];
+            sb[cb] = ok ? v : -1;
+        }
     };
     // Every lane loads every quad (a missing source or a coefficient past kin
     // reads box 0 or coefficient 0 and is zeroed after the load): no branch
@@ -148,16 +155,16 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
             }
         }
     };
-    // class k of this wave exists (wave-uniform); its table slice, or table
-    // 0 when it does not (loaded all the same, and not used)
+    // class k of this wave exists (wave-uniform)
     auto has = [&](int k) { return k < SPW && w + NW * k < nslot; };
+    // table index of class k (the task's first class where the wave has no
+    // class k: loaded all the same, and not used)
+    auto tindex = [&](int k) { return tab[tk.tab0 + (has(k) ? w + NW * k : 0)]; };
     auto table = [&](int k) -> const T * {
-        const int tb = has(k) ? tab[tk.tab0 + w + NW * k] : 0;
-        return Apk + (size_t(tb) * nrbT + rb0) * nrbT * 256 + lane * 4;
+        return Apk + (size_t(tindex(k)) * nrbT + rb0) * nrbT * 256 + lane * 4;
     };
     auto table_bf = [&](int k) -> const uint16_t * {
-        const int tb = has(k) ? tab[tk.tab0 + w + NW * k] : 0;
-        return Abf + ((size_t(tb) * nrbT + rb0) * nrbT * 64 + lane) * 12;
+        return Abf + ((size_t(tindex(k)) * nrbT + rb0) * nrbT * 64 + lane) * 12;
     };
     using AQ = typename std::conditional<BF, BfQ, Q>::type;
     // the table operand of row block rb, input chunk ci
@@ -187,59 +194,65 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[rb][cb][v] = T(0);
 
-    AQ a[RBW][NRB];
-    Q bc[NCB][NRB], bn[NCB][NRB];
-    int sbc[NCB], sbn[NCB], sbnn[NCB];
-    source(0, sbc);
-    source(1, sbn);
-    const void *Ac = table_any(0);
+    // Loads run PD classes ahead of the matrix cores (as many as about 128
+    // registers of operands allow, all of the wave's classes where they fit):
+    // the source indices of every class first, then the table slices and
+    // source expansions of classes 0 .. PD-1, and the slot of class k is
+    // refilled with class k + PD as soon as class k is consumed.  A wave
+    // thus waits about two memory latencies in all instead of one per class.
+    constexpr int QV = int(sizeof(T));                 // registers per quad: 4 (FP32), 8 (FP64)
+    constexpr int AV = BF ? 6 : QV;
+    constexpr int STEPV = RBW * NRB * AV + NCB * NRB * QV;
+    constexpr int PD = STEPV * SPW <= 128 ? SPW : (128 / STEPV < 1 ? 1 : 128 / STEPV);
+    int sidx[SPW][NCB];
 #pragma unroll
-    for (int rb = 0; rb < RBW; ++rb)
+    for (int k = 0; k < SPW; ++k) source(k, sidx[k]);
+    // the class tables of the wave: scalar loads, all issued before the first wait
+    const void *tptr[SPW];
 #pragma unroll
-        for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = load_a(Ac, rb, ci);
-    load_b(sbc, bc);
+    for (int k = 0; k < SPW; ++k) tptr[k] = table_any(k);
+    AQ a[PD][RBW][NRB];
+    Q b[PD][NCB][NRB];
+    auto issue = [&](int k, int d) {
+        const void *A = tptr[k];
+#pragma unroll
+        for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+            for (int ci = 0; ci < NRB; ++ci) a[d][rb][ci] = load_a(A, rb, ci);
+        load_b(sidx[k], b[d]);
+    };
+#pragma unroll
+    for (int d = 0; d < PD; ++d) issue(d, d);
+#pragma unroll
     for (int k = 0; k < SPW; ++k) {
-        const bool act = has(k);                      // wave-uniform
-        const void *An = table_any(k + 1);
-        load_b(sbn, bn);
-        source(k + 2, sbnn);
-        if constexpr (BF) {
-            BfQ bs[NCB][NRB];
+        const int d = k % PD;
+        if (has(k)) {                                  // wave-uniform
+            if constexpr (BF) {
+                BfQ bs[NCB][NRB];
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
+                for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-                for (int ci = 0; ci < NRB; ++ci) bs[cb][ci] = split3(bc[cb][ci]);
+                    for (int ci = 0; ci < NRB; ++ci) bs[cb][ci] = split3(b[d][cb][ci]);
 #pragma unroll
-            for (int rb = 0; rb < RBW; ++rb) {
-                if (act)
+                for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
                     for (int ci = 0; ci < NRB; ++ci)
 #pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mac_bf3(a[rb][ci], bs[cb][ci], acc[rb][cb]);
+                        for (int cb = 0; cb < NCB; ++cb)
+                            acc[rb][cb] = mac_bf3(a[d][rb][ci], bs[cb][ci], acc[rb][cb]);
+            } else {
 #pragma unroll
-                for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = load_a(An, rb, ci);
-            }
-        } else {
-#pragma unroll
-            for (int rb = 0; rb < RBW; ++rb) {
-                if (act)
+                for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
                     for (int ci = 0; ci < NRB; ++ci)
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
 #pragma unroll
                             for (int cb = 0; cb < NCB; ++cb)
-                                acc[rb][cb] = Mfma<T>::mac(a[rb][ci].v[j], bc[cb][ci].v[j], acc[rb][cb]);
-#pragma unroll
-                for (int ci = 0; ci < NRB; ++ci) a[rb][ci] = load_a(An, rb, ci);
+                                acc[rb][cb] = Mfma<T>::mac(a[d][rb][ci].v[j], b[d][cb][ci].v[j], acc[rb][cb]);
             }
         }
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-#pragma unroll
-            for (int ci = 0; ci < NRB; ++ci) bc[cb][ci] = bn[cb][ci];
-            sbn[cb] = sbnn[cb];
-        }
+        if (k + PD < SPW) issue(k + PD, d);
     }
 
 #pragma unroll
