@@ -186,6 +186,13 @@ typedef struct {
                           inner iteration k, f the system of that iteration
                           (the refinement's correction systems in mixed_ir);
                           entries from stats[r].iters on are zero          */
+    int precond;       /* 0: none; 1: leaf block-Jacobi on the right,
+                          A M^-1 y = f, a = M^-1 y, M = blockdiag(A_bb)
+                          over runs of at most 64 points of each leaf (the
+                          structure-based preconditioning the paper leaves
+                          for future work, Sec. 4).  Built on the first
+                          preconditioned solve and kept in the tree: FP64
+                          inverses, sum of n_b^2 doubles.                   */
 } imq_solve_opts;
 
 typedef struct {        /* host */

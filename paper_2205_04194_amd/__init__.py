@@ -204,10 +204,12 @@ class Tree:
     # ----------------------------------------------------------------- solve
     def solve(self, f: torch.Tensor, tol: float = 1e-10, restart: int = 50,
               max_iters: int = 2000, mixed_ir: bool = False, max_outer: int = 10,
-              a0: Optional[torch.Tensor] = None, history: bool = False, stream=None):
+              a0: Optional[torch.Tensor] = None, history: bool = False, precond: str = "none",
+              stream=None):
         """GMRES on the fast product: returns (a, stats).  stats["relres_fast64"]
         is the final residual with the FP64 fast product (the operator the
-        solver works with), not with the exact matrix."""
+        solver works with), not with the exact matrix.  precond: "none" or
+        "block_jacobi" (leaf blocks, on the right)."""
         lib = _lib.load()
         _check_vec(f, "f", self.n, self.device)
         one = f.dim() == 1
@@ -221,8 +223,11 @@ class Tree:
             a = (a0.unsqueeze(0) if one else a0).to(torch.float64).contiguous().clone()
         nrhs = f2.shape[0]
         hist = (ctypes.c_double * (nrhs * int(max_iters)))() if history else None
+        pcs = {"none": 0, "block_jacobi": 1}
+        if precond not in pcs:
+            raise ValueError(f"precond must be one of {sorted(pcs)} (got {precond!r})")
         opts = _lib.SolveOpts(float(tol), int(restart), int(max_iters), int(bool(mixed_ir)),
-                              int(max_outer), hist)
+                              int(max_outer), hist, pcs[precond])
         stats = (_lib.SolveStats * nrhs)()
         with torch.cuda.device(self.device):
             st = lib.imq_solve(self._h, nrhs, _dptr(f2), self.n, _dptr(a), self.n,

@@ -28,7 +28,7 @@ class TreeParams(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
                 ("mixed_ir", ctypes.c_int), ("max_outer", ctypes.c_int),
-                ("history", ctypes.POINTER(ctypes.c_double))]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("precond", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):

@@ -231,7 +231,7 @@ static void free_tree(imq_tree_s *t)
     DevBuf *bufs[] = {&t->perm, &t->pt_scale, &t->level, &t->set, &t->parent, &t->child0, &t->nchild,
                       &t->pos, &t->begin, &t->end, &t->cx, &t->cy, &t->u_off, &t->u_idx, &t->v_off,
                       &t->v_idx, &t->v_cls, &t->w_off, &t->w_idx, &t->x_off, &t->x_idx, &t->Klev,
-                      &t->cn, &t->leaves, &t->leafrec, &t->boxrec, &t->boxleaf, &t->nleaf, &t->xy_user, &t->set_off, &t->bs, &t->sol,
+                      &t->cn, &t->leaves, &t->leafrec, &t->boxrec, &t->boxleaf, &t->nleaf, &t->xy_user, &t->set_off, &t->bs, &t->sol, &t->bj_runs, &t->bj_inv,
                       &t->w_tgt, &t->w_scr, &t->w_leaves, &t->x_tgt, &t->x_boxes, &t->Pw, &t->adj,
                       &t->sh_par, &t->sh_kids, &t->eval_map, &t->eval_u, &t->eval_b};
     for (DevBuf *b : bufs) dev_free(*b);
@@ -769,8 +769,8 @@ imq_status imq_solve(imq_tree t, int nrhs, const double *f, int64_t ldf, double 
         return IMQ_EINVAL;
     }
     if (!(opts->tol > 0.0) || opts->restart < 1 || opts->restart > 4096 || opts->max_iters < 1 ||
-        opts->max_outer < 0) {
-        set_error("solve options out of range (tol > 0, 1 <= restart <= 4096, max_iters >= 1)");
+        opts->max_outer < 0 || opts->precond < 0 || opts->precond > 1) {
+        set_error("solve options out of range (tol > 0, 1 <= restart <= 4096, max_iters >= 1, precond 0 or 1)");
         return IMQ_EINVAL;
     }
     if ((st = solve_batched(t, nrhs, f, ldf, a, lda, *opts, stats, stream)) != IMQ_OK) return st;

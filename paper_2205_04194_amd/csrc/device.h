@@ -29,6 +29,14 @@ struct alignas(16) LeafRec {
     int box, begin, end, level;
 };
 
+// One run of the leaf block-Jacobi preconditioner: points [begin, begin + n)
+// of the tree's order (within one leaf), the set, and the offset of its
+// n x n inverse.
+struct alignas(8) BJRun {
+    int begin, n, set, pad;
+    int64_t off;
+};
+
 // A box whose multipole is formed from its own points (Algorithm 1 mode):
 // the leaves under it are entries [leaf0, leaf1) of the point-ordered leaf
 // index list (one 16-byte load).
@@ -128,6 +136,12 @@ void launch_p2p(hipStream_t s, unsigned grid, const DTree<T> &v, int nleaves, co
 // streamed through registers class by class (acc: added to out, else stored);
 // for coefficient counts up to kmax <= 80, else launches nothing and returns
 // false.
+// Leaf block-Jacobi preconditioner: its runs and inverses (once per tree),
+// and out = M^-1 in for nrhs columns of length N in the tree's point order.
+imq_status precond_setup(imq_tree_s *t, hipStream_t s);
+template <typename V>
+imq_status precond_apply(imq_tree_s *t, int nrhs, const V *in, V *out, hipStream_t s);
+
 // Abf (FP32 only, else null): the tables as three BF16 parts per entry, read
 // by the BF16 matrix-core form instead of Apk.
 template <typename T>
@@ -218,6 +232,9 @@ struct imq_tree_s {
     // solver workspace
     imq::DevBuf sol;
     size_t sol_bytes = 0;
+    // leaf block-Jacobi preconditioner (built on the first preconditioned solve)
+    imq::DevBuf bj_runs, bj_inv;
+    int nbj = 0;
     // adjoint: per-point fields and partial sums; odd tables generated on first use
     imq::DevBuf adj;
     bool odd_ready = false;

@@ -22,6 +22,10 @@
 // converged changes nothing.  One synchronisation per restart reads the
 // number of columns still to solve.
 //
+// Preconditioning (optional): the leaf block-Jacobi M of precond.hip on the
+// right, A M^-1 y = f with x = M^-1 y, so the residual estimates and the
+// explicit residuals stay those of A x = f.
+//
 // Precision: the FP64 solver keeps its basis in FP64; the inner solver of
 // the refinement (FP32 products, inner tolerance >= 1e-6) keeps its basis in
 // FP32, which halves the memory traffic of the orthogonalisation.  Dot
@@ -318,6 +322,8 @@ struct Solver {
     int nrhs, m, nb;
     void *Vraw, *wraw;                 // basis (m+1) x nrhs x N and one product block, FP64-sized
     double *tmp, *r, *x, *f, *d, *e;   // nrhs x N each
+    void *zraw;                        // M^-1 of a basis vector (right preconditioning), FP64-sized
+    bool pc = false;                   // leaf block-Jacobi right preconditioner
     double *h1, *h2, *nrm, *part, *H, *csn, *snn, *g, *y, *tolv;
     ColState *st;
     int *active, *active_all, *nact;
@@ -341,6 +347,17 @@ struct Solver {
                            yout);
         IMQ_HIP(hipGetLastError());
         return IMQ_OK;
+    }
+
+    // y = A M^-1 x (y = A x without the preconditioner)
+    template <typename T, typename V>
+    imq_status apply_pc(const V *xin, V *yout)
+    {
+        if (!pc) return apply<T, V>(xin, yout);
+        V *z = static_cast<V *>(zraw);
+        imq_status st_ = precond_apply<V>(t, nrhs, xin, z, s);
+        if (st_ != IMQ_OK) return st_;
+        return apply<T, V>(z, yout);
     }
 
     // hout[c * ldh + v] = V_v[c] . w[c], v < nv, for the columns act marks
@@ -377,7 +394,7 @@ struct Solver {
             if (hcount[0] == 0 || steps >= maxit) return IMQ_OK;
             hipLaunchKernelGGL((k_normalize<double, V>), grid2(), dim3(TPB), 0, s, N, r, nrm, active, Vb);
             const int mc = std::min(m, maxit - steps);      // steps of this cycle
-            if ((st_ = apply<T, V>(Vb, w)) != IMQ_OK) return st_;
+            if ((st_ = apply_pc<T, V>(Vb, w)) != IMQ_OK) return st_;
             int j = 0;
             while (j < mc) {
                 V *vn = Vb + size_t(j + 1) * nrhs * N;
@@ -395,14 +412,21 @@ struct Solver {
                 IMQ_HIP(hipEventRecord(ev[j & 1], s));
                 // the next step's product runs while the host waits for this step's count
                 if (j + 1 < mc)
-                    if ((st_ = apply<T, V>(vn, w)) != IMQ_OK) return st_;
+                    if ((st_ = apply_pc<T, V>(vn, w)) != IMQ_OK) return st_;
                 IMQ_HIP(hipEventSynchronize(ev[j & 1]));
                 ++j;
                 if (hcount[(j - 1) & 1] == 0) break;
             }
             steps += j;
             hipLaunchKernelGGL(k_backsub, dim3(nrhs), dim3(TPB), 0, s, m, H, g, st, y);
-            hipLaunchKernelGGL(k_add_Vy<V>, grid2(), dim3(TPB), 0, s, N, nrhs, Vb, y, m, st, xs);
+            if (!pc) {
+                hipLaunchKernelGGL(k_add_Vy<V>, grid2(), dim3(TPB), 0, s, N, nrhs, Vb, y, m, st, xs);
+            } else {                               // x += M^-1 (V y), through tmp and r (free here)
+                hipLaunchKernelGGL(k_fill0<double>, grid2(), dim3(TPB), 0, s, N, tmp);
+                hipLaunchKernelGGL(k_add_Vy<V>, grid2(), dim3(TPB), 0, s, N, nrhs, Vb, y, m, st, tmp);
+                if ((st_ = precond_apply<double>(t, nrhs, tmp, r, s)) != IMQ_OK) return st_;
+                hipLaunchKernelGGL(k_add, grid2(), dim3(TPB), 0, s, N, r, xs);
+            }
             IMQ_HIP(hipGetLastError());
         }
     }
@@ -440,7 +464,7 @@ imq_status solve_batched(imq_tree_s *t, int nrhs, const double *f_user, int64_t 
     const size_t nsmall = size_t(nrhs) * (2 * size_t(m + 1) + 1 + size_t(m) * (m + 1) + 2 * size_t(m) + (m + 1) +
                                           m + 1) +
                           size_t(nrhs) * (m + 1) * S.nb + nrhs * hist_cap;
-    const size_t need = sizeof(double) * (size_t(m + 2) * vecs + 6 * vecs + nsmall) + sizeof(ColState) * nrhs +
+    const size_t need = sizeof(double) * (size_t(m + 2) * vecs + 7 * vecs + nsmall) + sizeof(ColState) * nrhs +
                         sizeof(int) * (2 * size_t(nrhs) + 2) + 256;
     if (t->sol_bytes < need) {
         IMQ_HIP(dev_alloc(t->sol, need));
@@ -455,7 +479,8 @@ imq_status solve_batched(imq_tree_s *t, int nrhs, const double *f_user, int64_t 
     S.f = S.x + vecs;
     S.d = S.f + vecs;
     S.e = S.d + vecs;
-    double *p = S.e + vecs;
+    S.zraw = S.e + vecs;
+    double *p = S.e + 2 * vecs;
     S.h1 = p; p += size_t(nrhs) * (m + 1);
     S.h2 = p; p += size_t(nrhs) * (m + 1);
     S.nrm = p; p += nrhs;
@@ -508,6 +533,10 @@ imq_status solve_batched(imq_tree_s *t, int nrhs, const double *f_user, int64_t 
     IMQ_HIP(hipGetLastError());
 
     imq_status st;
+    if (o.precond == 1) {
+        if ((st = precond_setup(t, s)) != IMQ_OK) return st;
+        S.pc = true;
+    }
     int steps = 0, outer = 0;
     std::vector<double> nf(nrhs), nr(nrhs);
     if (!o.mixed_ir) {
