@@ -265,10 +265,11 @@ imq_status imq_matvec_backward(imq_tree tree, int nrhs, imq_dtype dtype, const v
  *               m2l_kc and m2l_split apply to the staged GEMM only.
  *  p2p_wg     : workgroups of the near-field kernel while it runs alongside
  *               the tree passes (each takes every p2p_wg-th leaf); 0 = 2048
- *  p2p_mode   : near field in FP32 with one right-hand side: 0 = vector form
- *               everywhere; 1 = matrix-core form (squared distances as a
- *               rank-4 product) for the leaves whose neighbourhood is small
- *               against c, vector form for the rest
+ *  p2p_mode   : near field with one right-hand side (FP32 or FP64): 0 =
+ *               vector form everywhere; 1 = matrix-core form (squared
+ *               distances as a rank-4 product on the FP32 or FP64 matrix
+ *               cores) for the leaves whose neighbourhood is small against
+ *               c, vector form for the rest
  *  far_field  : 0 = the tree passes above (multipole shifts, translations to
  *               local expansions, local evaluation); 1 = the paper's
  *               Algorithm 1 (Sec. 2.2): the multipole of every box from its

@@ -1,6 +1,6 @@
 // Near field (P2P, the U lists): the direct sums of the kernel over each
-// leaf's adjacent leaves, in a vector form and, for FP32 and one right-hand
-// side, a matrix-core form.
+// leaf's adjacent leaves, in a vector form and, for one right-hand side, a
+// matrix-core form (FP32 or FP64 matrix cores).
 #include "device.h"
 #include "mfma.h"
 
@@ -44,18 +44,29 @@ struct alignas(16) SRec {
     T ox, oy;
 };
 
-// LDS of one workgroup.  MF: the kernel instance that also holds the
-// matrix-core form (its stage is separate, so that the vector-form instance
-// keeps its small footprint and its occupancy).
-template <typename T, int NR, bool MF>
-struct alignas(32) P2PStage {                  // every array starts on a 32-byte boundary
+// LDS of one workgroup.  MF: the kernel instance that also has the
+// matrix-core form; a leaf uses one form, so the two forms' source stages
+// share their memory.
+template <typename T, int NR>
+struct alignas(32) P2PVecStage {               // every array starts on a 32-byte boundary
     // vector form: the chunk's sources (and |x|^2 for the expanded
     // distances), read back four at a time
     T x[P2P_LDS], y[P2P_LDS], w[P2P_LDS], u[NR][P2P_LDS];
-    // matrix-core form (FP32, one right-hand side): per source |x|^2, x, y and
-    // a row of zeros (written once), and the weights
-    float B[MF ? 4 : 1][MF ? P2P_MF_LD : 4];
-    float U[MF ? P2P_CHUNK : 4];
+};
+template <typename T>
+struct alignas(32) P2PMfStage {
+    // matrix-core form (one right-hand side): per source |x|^2, x, y and a
+    // row of zeros (written once per leaf), and the weights in the order the
+    // matrix-core result holds the sources
+    T B[4][P2P_MF_LD];
+    T U[P2P_CHUNK];
+};
+template <typename T, int NR, bool MF>
+struct alignas(32) P2PStage {
+    union {
+        P2PVecStage<T, NR> v;
+        P2PMfStage<T> m;
+    };
     // staging: 1 + the entry that starts at each slot of the chunk (else 0),
     // and per entry of the batch the offset from slot number to point index
     // and the centre offset
@@ -198,20 +209,20 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
 #pragma unroll
             for (int q = 0; q < NR; ++q) acc[rr][q] = 0.0;
         auto store = [&](int e, T x, T y, const T (&u)[NR]) {
-            sh.x[e] = x;
-            sh.y[e] = y;
-            if constexpr (EXP) sh.w[e] = fma(x, x, y * y);
+            sh.v.x[e] = x;
+            sh.v.y[e] = y;
+            if constexpr (EXP) sh.v.w[e] = fma(x, x, y * y);
 #pragma unroll
-            for (int q = 0; q < NR; ++q) sh.u[q][e] = u[q];
+            for (int q = 0; q < NR; ++q) sh.v.u[q][e] = u[q];
         };
         auto consume = [&](int n) {
             const int per = ((n + G - 1) / G + 3) & ~3;   // sources per group, multiple of 4
             for (int e = P2P_CHUNK / 4 + lane; e < per * G / 4; e += 64) {
-                reinterpret_cast<V4 *>(sh.x)[e] = V4{T(0), T(0), T(0), T(0)};
-                reinterpret_cast<V4 *>(sh.y)[e] = V4{T(0), T(0), T(0), T(0)};
-                if constexpr (EXP) reinterpret_cast<V4 *>(sh.w)[e] = V4{T(0), T(0), T(0), T(0)};
+                reinterpret_cast<V4 *>(sh.v.x)[e] = V4{T(0), T(0), T(0), T(0)};
+                reinterpret_cast<V4 *>(sh.v.y)[e] = V4{T(0), T(0), T(0), T(0)};
+                if constexpr (EXP) reinterpret_cast<V4 *>(sh.v.w)[e] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-                for (int q = 0; q < NR; ++q) reinterpret_cast<V4 *>(sh.u[q])[e] = V4{T(0), T(0), T(0), T(0)};
+                for (int q = 0; q < NR; ++q) reinterpret_cast<V4 *>(sh.v.u[q])[e] = V4{T(0), T(0), T(0), T(0)};
             }
             __syncthreads();
             if (grp < G) {
@@ -221,9 +232,9 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
 #pragma unroll
                     for (int q = 0; q < NR; ++q) part[rr][q] = T(0);
                 const int nq = __builtin_amdgcn_readfirstlane(per >> 2);   // the same in every lane
-                const V4 *px = reinterpret_cast<const V4 *>(sh.x) + grp * nq;
-                const V4 *py = reinterpret_cast<const V4 *>(sh.y) + grp * nq;
-                const V4 *pw = reinterpret_cast<const V4 *>(sh.w) + grp * nq;
+                const V4 *px = reinterpret_cast<const V4 *>(sh.v.x) + grp * nq;
+                const V4 *py = reinterpret_cast<const V4 *>(sh.v.y) + grp * nq;
+                const V4 *pw = reinterpret_cast<const V4 *>(sh.v.w) + grp * nq;
                 for (int it = 0; it < nq; ++it) {
                     const V4 X = px[it], Y = py[it];
                     V4 W;
@@ -242,7 +253,7 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
                         }
 #pragma unroll
                         for (int q = 0; q < NR; ++q) {
-                            const V4 U = reinterpret_cast<const V4 *>(sh.u[q])[grp * nq + it];
+                            const V4 U = reinterpret_cast<const V4 *>(sh.v.u[q])[grp * nq + it];
 #pragma unroll
                             for (int k = 0; k < 4; ++k) part[rr][q] += U[k] * kv[k];
                         }
@@ -271,7 +282,7 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
     }
 }
 
-// Matrix-core form (FP32, one right-hand side), up to 16 TT targets.  With
+// Matrix-core form (one right-hand side), up to 16 TT targets.  With
 // every coordinate relative to the target leaf's centre,
 //     |x_i - x_j|^2 + c^2 = (|x_i|^2 + c^2) + |x_j|^2 - 2 x_i . x_j,
 // so the squared distances of 16 sources x 16 targets are one matrix-core
@@ -283,67 +294,82 @@ __device__ __forceinline__ void p2p_block(const DTree<T> &t, const NearLeaf &nl,
 // small against c.
 // Lane l (q = l / 16, c16 = l % 16) supplies entry (c16, q) of the source
 // matrix and (q, c16) of the target matrix; item v of the result is the pair
-// (source 16 s + 4 q + v, target 16 tt + c16), so a lane sums its target over
-// four sources per tile and the four lane groups are added at the end.
+// (source 16 s + row(q, v), target 16 tt + c16) (row = 4 q + v in FP32,
+// 4 v + q in FP64), so a lane sums its target over four sources per tile and
+// the four lane groups are added at the end.
 // Padding sources have weight 0 and padding targets |x_i|^2 + c^2 = 1, so
 // every squared distance stays positive.
-template <int TT>
-__device__ __forceinline__ void p2p_block_mf(const DTree<float> &t, const NearLeaf &nl, int t0, int ntc,
-                                             const float *__restrict__ us, double *__restrict__ bs, int add,
-                                             P2PStage<float, 1, true> &sh)
+template <typename T, int TT>
+__device__ __forceinline__ void p2p_block_mf(const DTree<T> &t, const NearLeaf &nl, int t0, int ntc,
+                                             const T *__restrict__ us, double *__restrict__ bs, int add,
+                                             P2PStage<T, 1, true> &sh)
 {
+    using acc_t = typename Mfma<T>::acc_t;
     const int lane = threadIdx.x, q = lane >> 4, c16 = lane & 15;
-    const float c2 = float(nl.c2);
-    float bt[TT];
-    f32x4 ci[TT];
+    const T c2 = T(nl.c2);
+    T bt[TT];
+    acc_t ci[TT];
     double acc[TT];
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
         const int i = 16 * tt + c16;
-        float xi = 0.f, yi = 0.f, ai = 1.f;
+        T xi = T(0), yi = T(0), ai = T(1);
         if (i < ntc) {
             xi = t.xl[t0 + i];
             yi = t.yl[t0 + i];
-            ai = fmaf(xi, xi, fmaf(yi, yi, c2));
+            ai = fma(xi, xi, fma(yi, yi, c2));
         }
-        bt[tt] = q == 0 ? 1.f : q == 1 ? -2.f * xi : q == 2 ? -2.f * yi : 0.f;
-        ci[tt] = f32x4{ai, ai, ai, ai};
+        bt[tt] = q == 0 ? T(1) : q == 1 ? T(-2) * xi : q == 2 ? T(-2) * yi : T(0);
+        ci[tt] = acc_t{ai, ai, ai, ai};
         acc[tt] = 0.0;
     }
-    auto store = [&](int e, float x, float y, const float (&u)[1]) {
-        sh.B[0][e] = fmaf(x, x, y * y);
-        sh.B[1][e] = x;
-        sh.B[2][e] = y;
-        sh.U[e] = u[0];
+    // the zero row of the source matrix (the stage is shared with the vector
+    // form, which may have used it since)
+    for (int e = threadIdx.x; e < P2P_MF_LD; e += 64) sh.m.B[3][e] = T(0);
+    // item v of a lane's result holds source Mfma<T>::row(q, v) of the tile:
+    // the weights are stored so that four consecutive ones are those
+    auto upos = [](int e) {
+        const int sl = e & 15;
+        int pos = sl;
+        for (int qq = 0; qq < 4; ++qq)
+            for (int v = 0; v < 4; ++v)
+                if (Mfma<T>::row(qq, v) == sl) pos = 4 * qq + v;
+        return (e & ~15) + pos;
+    };
+    auto store = [&](int e, T x, T y, const T (&u)[1]) {
+        sh.m.B[0][e] = fma(x, x, y * y);
+        sh.m.B[1][e] = x;
+        sh.m.B[2][e] = y;
+        sh.m.U[upos(e)] = u[0];
     };
     auto consume = [&](int n) {
         const int nt = __builtin_amdgcn_readfirstlane((n + 15) >> 4);   // 16-source tiles
         __syncthreads();
-        float part[TT];
+        T part[TT];
 #pragma unroll
-        for (int tt = 0; tt < TT; ++tt) part[tt] = 0.f;
+        for (int tt = 0; tt < TT; ++tt) part[tt] = T(0);
         // Software pipelined: while the vector unit works on tile s, the
         // matrix-core step of tile s + 1 and the LDS reads of tile s + 2
         // (source entries) and s + 1 (weights) are in flight; indices past the
         // last tile re-read it.  The scheduling barriers keep the compiler from
         // sinking the reads back next to their use.
-        auto lda = [&](int s) { return sh.B[q][16 * min(s, nt - 1) + c16]; };
-        auto ldu = [&](int s) { return *reinterpret_cast<const f32x4 *>(&sh.U[16 * min(s, nt - 1) + 4 * q]); };
-        auto mma = [&](float a, f32x4 (&r)[TT]) {
+        auto lda = [&](int s) { return sh.m.B[q][16 * min(s, nt - 1) + c16]; };
+        auto ldu = [&](int s) { return *reinterpret_cast<const acc_t *>(&sh.m.U[16 * min(s, nt - 1) + 4 * q]); };
+        auto mma = [&](T a, acc_t (&r)[TT]) {
 #pragma unroll
-            for (int tt = 0; tt < TT; ++tt) r[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bt[tt], ci[tt], 0, 0, 0);
+            for (int tt = 0; tt < TT; ++tt) r[tt] = Mfma<T>::mac(a, bt[tt], ci[tt]);
         };
-        auto use = [&](const f32x4 (&r)[TT], const f32x4 &u) {
+        auto use = [&](const acc_t (&r)[TT], const acc_t &u) {
 #pragma unroll
             for (int tt = 0; tt < TT; ++tt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) part[tt] = fmaf(u[v], rsqrt_fast(r[tt][v]), part[tt]);
+                for (int v = 0; v < 4; ++v) part[tt] = fma(u[v], rsqrt_fast(r[tt][v]), part[tt]);
         };
         // two tiles per trip with the registers of the two in alternation
-        f32x4 rA[TT], rB[TT];
+        acc_t rA[TT], rB[TT];
         mma(lda(0), rA);
-        float aA, aB = lda(1);
-        f32x4 uA = ldu(0), uB;
+        T aA, aB = lda(1);
+        acc_t uA = ldu(0), uB;
         for (int s = 0; s < nt; s += 2) {
             mma(aB, rB);                         // tile s + 1
             __builtin_amdgcn_sched_barrier(0);
@@ -363,7 +389,7 @@ __device__ __forceinline__ void p2p_block_mf(const DTree<float> &t, const NearLe
         for (int tt = 0; tt < TT; ++tt) acc[tt] += double(part[tt]);
         __syncthreads();
     };
-    p2p_sources<float, 1, true>(t, nl.u0, nl.u1, us, 0, 1, sh, store, consume);
+    p2p_sources<T, 1, true>(t, nl.u0, nl.u1, us, 0, 1, sh, store, consume);
 #pragma unroll
     for (int tt = 0; tt < TT; ++tt) {
         double s = acc[tt];
@@ -377,17 +403,14 @@ __device__ __forceinline__ void p2p_block_mf(const DTree<float> &t, const NearLe
     }
 }
 
-// MF (FP32, one right-hand side only): leaves flagged in the NearLeaf
-// records take the matrix-core form.
+// MF (one right-hand side only): leaves flagged in the NearLeaf records take
+// the matrix-core form.
 template <typename T, bool SIDE, int NR, bool MF>
 __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, int nleaves, const T *__restrict__ us, int nrhs,
                                             double *__restrict__ bs, int add)
 {
-    static_assert(!MF || (NR == 1 && sizeof(T) == 4), "matrix-core form: FP32, one right-hand side");
+    static_assert(!MF || NR == 1, "matrix-core form: one right-hand side");
     __shared__ P2PStage<T, NR, MF> sh;
-    if constexpr (MF) {
-        for (int e = threadIdx.x; e < P2P_MF_LD; e += 64) sh.B[3][e] = 0.f;   // never written again
-    }
     // Leaves are dealt round robin (as the hardware deals workgroups to the
     // XCDs): the kernel is ALU-bound, and giving each XCD a contiguous eighth of
     // the Morton order for L2 locality unbalances clustered inputs (measured
@@ -399,10 +422,10 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, int nleaves, const T *__
                 for (int t0 = nl.begin; t0 < nl.end; t0 += 64) {
                     const int ntc = min(64, nl.end - t0);
                     switch ((ntc + 15) >> 4) {
-                    case 1: p2p_block_mf<1>(t, nl, t0, ntc, us, bs, add, sh); break;
-                    case 2: p2p_block_mf<2>(t, nl, t0, ntc, us, bs, add, sh); break;
-                    case 3: p2p_block_mf<3>(t, nl, t0, ntc, us, bs, add, sh); break;
-                    default: p2p_block_mf<4>(t, nl, t0, ntc, us, bs, add, sh); break;
+                    case 1: p2p_block_mf<T, 1>(t, nl, t0, ntc, us, bs, add, sh); break;
+                    case 2: p2p_block_mf<T, 2>(t, nl, t0, ntc, us, bs, add, sh); break;
+                    case 3: p2p_block_mf<T, 3>(t, nl, t0, ntc, us, bs, add, sh); break;
+                    default: p2p_block_mf<T, 4>(t, nl, t0, ntc, us, bs, add, sh); break;
                     }
                 }
                 continue;
@@ -439,11 +462,9 @@ template <typename T, bool SIDE>
 void launch_p2p(hipStream_t s, unsigned grid, const DTree<T> &v, int nleaves, const T *us, int nrhs, double *bs,
                 bool mf)
 {
-    if constexpr (sizeof(T) == 4) {
-        if (nrhs == 1 && mf) {
-            hipLaunchKernelGGL((k_p2p<T, SIDE, 1, true>), dim3(grid), dim3(64), 0, s, v, nleaves, us, nrhs, bs, 0);
-            return;
-        }
+    if (nrhs == 1 && mf) {
+        hipLaunchKernelGGL((k_p2p<T, SIDE, 1, true>), dim3(grid), dim3(64), 0, s, v, nleaves, us, nrhs, bs, 0);
+        return;
     }
     if (nrhs == 1)
         hipLaunchKernelGGL((k_p2p<T, SIDE, 1, false>), dim3(grid), dim3(64), 0, s, v, nleaves, us, nrhs, bs, 0);

@@ -225,10 +225,11 @@ def test_batched_right_hand_sides_match_single_products(imq, nrhs):
 def test_near_field_forms_match_the_oracle(imq, c):
     """The near field takes, per leaf, direct differences or the expansion of
     the squared distance about the leaf's centre (where its rounding bound
-    allows), on the vector unit (default) or, with p2p_mode = 1 in FP32 and one
-    right-hand side, as a rank-4 matrix-core product.  Both kernels must give
-    the product to the FP32 target and agree with each other to rounding; the
-    mixture at c = 0.03 has leaves of both kinds, at c = 0.3 nearly all expand."""
+    allows), on the vector unit (default) or, with p2p_mode = 1 and one
+    right-hand side, as a rank-4 product on the FP32 or FP64 matrix cores.
+    Both kernels must give the product to the precision's target and agree
+    with each other to rounding; the mixture at c = 0.03 has leaves of both
+    kinds, at c = 0.3 nearly all expand."""
     n = 20000
     g = W.rng(92, 3)
     xy = W.mixture_points(n, W.rng(92, 1), g)
@@ -236,14 +237,17 @@ def test_near_field_forms_match_the_oracle(imq, c):
     tree = imq.build_tree(_dev(xy), c, leaf=32, p=12)
     rows = np.arange(0, n, 41)
     exact = oracle.matvec(xy, c, u, xy_targets=xy[rows])
-    out = {}
-    for mode in (0, 1):
-        tree.set_kernel_config(p2p_mode=mode)
-        out[mode] = tree.matvec(_dev(u), "fp32").cpu().numpy()
-        err = _rel(out[mode][rows], exact)
-        print(f"c={c} p2p_mode={mode}: rel err vs oracle {err:.3e}")
-        assert err < 1e-5
-    assert _rel(out[1], out[0]) < 1e-6
+    for prec, tol, agree in (("fp32", 1e-5, 1e-6), ("fp64", 1e-6, 1e-13)):
+        out = {}
+        for mode in (0, 1):
+            tree.set_kernel_config(p2p_mode=mode)
+            out[mode] = tree.matvec(_dev(u), prec).cpu().numpy()
+            err = _rel(out[mode][rows], exact)
+            print(f"c={c} {prec} p2p_mode={mode}: rel err vs oracle {err:.3e}")
+            assert err < tol
+        d = _rel(out[1], out[0])
+        print(f"c={c} {prec}: forms differ by {d:.2e}")
+        assert d < agree
     tree.set_kernel_config()
 
 
