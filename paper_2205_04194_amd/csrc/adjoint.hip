@@ -11,7 +11,8 @@
 // g: the n+m-even local coefficients give the potential and its in-plane
 // gradient, the n+m-odd ones (extra translation tables) the vertical
 // derivative, which is d/dc in the lifted picture.  The near field is summed
-// directly with the same formulas.  Adaptive W/X lists are not expanded
+// directly with the same formulas, each neighbour leaf's points staged
+// through LDS 64 at a time.  Adaptive W/X lists are not expanded
 // here: the tree must route them to the direct sum (direct_max >= N).
 #include "device.h"
 
@@ -65,70 +66,92 @@ __global__ __launch_bounds__(64) void k_adjoint_eval(DTree<T> t, const int32_t *
     const T *Lg = L + (size_t(b) * 2 + 1) * t.KS;
     const T *Lov = Lo + (size_t(b) * 2 + 0) * t.KS;
     const int64_t N = t.N;
-    for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
-        const T xi = t.xl[i], yi = t.yl[i];
-        // far field from the local expansions
-        const T wx = xi * inv_s, wy = yi * inv_s;
-        const T r2 = wx * wx + wy * wy;
-        T potg = 0, gvx = 0, gvy = 0, ggx = 0, ggy = 0, dzv = 0;
-        T pmr = 1, pmi = 0, p1r = 0, p1i = 0;              // W^m, W^(m-1)
-        for (int m = 0; m <= P; ++m) {
-            T tr = pmr, ti = pmi;                            // r2^q W^m
-            T sr = p1r, si = p1i;                            // r2^q W^(m-1)
-            T qr = 0, qi = 0;                                // r2^(q-1) W^m
-            for (int n = m, q = 0; n <= P; n += 2, ++q) {
-                const int k = cidx_e(n, m);
-                const T dxr = T(2 * q) * wx * qr + T(m) * sr, dxi = T(2 * q) * wx * qi + T(m) * si;
-                const T dyr = T(2 * q) * wy * qr - T(m) * si, dyi = T(2 * q) * wy * qi + T(m) * sr;
-                const T lvr = Lv[k], lvi = m > 0 ? Lv[k + 1] : T(0);
-                const T lgr = Lg[k], lgi = m > 0 ? Lg[k + 1] : T(0);
-                potg += lgr * tr - lgi * ti;
-                ggx += lgr * dxr - lgi * dxi;
-                ggy += lgr * dyr - lgi * dyi;
-                gvx += lvr * dxr - lvi * dxi;
-                gvy += lvr * dyr - lvi * dyi;
-                if (n + 1 <= P) {
-                    const int ko = cidx_o(n + 1, m);
-                    const T lor = Lov[ko], loi = m > 0 ? Lov[ko + 1] : T(0);
-                    dzv += lor * tr - loi * ti;
+    // the near field's sources, staged 64 points at a time
+    __shared__ T sx[64], sy[64], sv[64], sg[64];
+    for (int i0 = t.begin[b]; i0 < t.end[b]; i0 += 64) {
+        const int i = i0 + threadIdx.x;
+        const bool ok = i < t.end[b];
+        const T xi = ok ? t.xl[i] : T(0), yi = ok ? t.yl[i] : T(0);
+        double o0 = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0, o5 = 0;
+        if (ok) {
+            // far field from the local expansions
+            const T wx = xi * inv_s, wy = yi * inv_s;
+            const T r2 = wx * wx + wy * wy;
+            T potg = 0, gvx = 0, gvy = 0, ggx = 0, ggy = 0, dzv = 0;
+            T pmr = 1, pmi = 0, p1r = 0, p1i = 0;              // W^m, W^(m-1)
+            for (int m = 0; m <= P; ++m) {
+                T tr = pmr, ti = pmi;                            // r2^q W^m
+                T sr = p1r, si = p1i;                            // r2^q W^(m-1)
+                T qr = 0, qi = 0;                                // r2^(q-1) W^m
+                for (int n = m, q = 0; n <= P; n += 2, ++q) {
+                    const int k = cidx_e(n, m);
+                    const T dxr = T(2 * q) * wx * qr + T(m) * sr, dxi = T(2 * q) * wx * qi + T(m) * si;
+                    const T dyr = T(2 * q) * wy * qr - T(m) * si, dyi = T(2 * q) * wy * qi + T(m) * sr;
+                    const T lvr = Lv[k], lvi = m > 0 ? Lv[k + 1] : T(0);
+                    const T lgr = Lg[k], lgi = m > 0 ? Lg[k + 1] : T(0);
+                    potg += lgr * tr - lgi * ti;
+                    ggx += lgr * dxr - lgi * dxi;
+                    ggy += lgr * dyr - lgi * dyi;
+                    gvx += lvr * dxr - lvi * dxi;
+                    gvy += lvr * dyr - lvi * dyi;
+                    if (n + 1 <= P) {
+                        const int ko = cidx_o(n + 1, m);
+                        const T lor = Lov[ko], loi = m > 0 ? Lov[ko + 1] : T(0);
+                        dzv += lor * tr - loi * ti;
+                    }
+                    qr = tr; qi = ti;
+                    tr *= r2; ti *= r2;
+                    sr *= r2; si *= r2;
                 }
-                qr = tr; qi = ti;
-                tr *= r2; ti *= r2;
-                sr *= r2; si *= r2;
+                p1r = pmr; p1i = pmi;
+                const T nr = pmr * wx - pmi * wy;
+                pmi = pmr * wy + pmi * wx;
+                pmr = nr;
             }
-            p1r = pmr; p1i = pmi;
-            const T nr = pmr * wx - pmi * wy;
-            pmi = pmr * wy + pmi * wx;
-            pmr = nr;
+            o0 = double(potg); o1 = double(gvx * inv_s); o2 = double(gvy * inv_s);
+            o3 = double(ggx * inv_s); o4 = double(ggy * inv_s); o5 = double(dzv);
         }
-        double o0 = double(potg), o1 = double(gvx * inv_s), o2 = double(gvy * inv_s);
-        double o3 = double(ggx * inv_s), o4 = double(ggy * inv_s), o5 = double(dzv);
-        // near field, summed directly
+        // near field, summed directly: each U-list leaf's points through LDS
         for (int uu = t.u_off[b]; uu < t.u_off[b + 1]; ++uu) {
             const int a = t.u_idx[uu];
             const T px = xi + T(t.cx[b] - t.cx[a]), py = yi + T(t.cy[b] - t.cy[a]);
             T s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
-            for (int j = t.begin[a]; j < t.end[a]; ++j) {
-                const T dx = px - t.xl[j], dy = py - t.yl[j];
-                const T ir = T(1) / sqrt(dx * dx + dy * dy + c2);
-                const T ir3 = ir * ir * ir;
-                const T vj = us[j], gj = us[N + j];
-                s0 += gj * ir;
-                s1 -= vj * dx * ir3;
-                s2 -= vj * dy * ir3;
-                s3 -= gj * dx * ir3;
-                s4 -= gj * dy * ir3;
-                s5 -= cc * vj * ir3;
+            for (int j0 = t.begin[a]; j0 < t.end[a]; j0 += 64) {
+                const int nj = min(64, t.end[a] - j0);
+                __syncthreads();                         // the previous chunk is no longer read
+                if (threadIdx.x < nj) {
+                    const int j = j0 + threadIdx.x;
+                    sx[threadIdx.x] = t.xl[j];
+                    sy[threadIdx.x] = t.yl[j];
+                    sv[threadIdx.x] = us[j];
+                    sg[threadIdx.x] = us[N + j];
+                }
+                __syncthreads();
+                if (ok)
+                    for (int jj = 0; jj < nj; ++jj) {
+                        const T dx = px - sx[jj], dy = py - sy[jj];
+                        const T ir = T(1) / sqrt(dx * dx + dy * dy + c2);
+                        const T ir3 = ir * ir * ir;
+                        const T vj = sv[jj], gj = sg[jj];
+                        s0 += gj * ir;
+                        s1 -= vj * dx * ir3;
+                        s2 -= vj * dy * ir3;
+                        s3 -= gj * dx * ir3;
+                        s4 -= gj * dy * ir3;
+                        s5 -= cc * vj * ir3;
+                    }
             }
             o0 += double(s0); o1 += double(s1); o2 += double(s2);
             o3 += double(s3); o4 += double(s4); o5 += double(s5);
         }
-        out[0 * N + i] = o0;
-        out[1 * N + i] = o1;
-        out[2 * N + i] = o2;
-        out[3 * N + i] = o3;
-        out[4 * N + i] = o4;
-        out[5 * N + i] = o5;
+        if (ok) {
+            out[0 * N + i] = o0;
+            out[1 * N + i] = o1;
+            out[2 * N + i] = o2;
+            out[3 * N + i] = o3;
+            out[4 * N + i] = o4;
+            out[5 * N + i] = o5;
+        }
     }
 }
 
@@ -151,22 +174,36 @@ __global__ void k_adjoint_final(int64_t N, const int32_t *__restrict__ perm, con
     dcpart[i] = g * out[5 * N + i] * s2;
 }
 
-// dc[s] = sum of dcpart over the set's points, in a fixed order.
-__global__ __launch_bounds__(256) void k_set_sum(const int64_t *__restrict__ set_off,
-                                                 const double *__restrict__ part, double *__restrict__ dc,
-                                                 int accumulate)
+// dc[s] = sum of dcpart over the set's points, in a fixed order: SETSUM_NB
+// contiguous slices of each set summed by as many workgroups, then the
+// slices' sums in slice order.
+constexpr int SETSUM_NB = 64;
+
+__global__ __launch_bounds__(256) void k_set_partial(const int64_t *__restrict__ set_off,
+                                                     const double *__restrict__ part, double *__restrict__ partial)
 {
     __shared__ double red[256];
-    const int s = blockIdx.x;
+    const int s = blockIdx.x, blk = blockIdx.y;
+    const int64_t a = set_off[s], n = set_off[s + 1] - a;
+    const int64_t lo = a + n * blk / SETSUM_NB, hi = a + n * (blk + 1) / SETSUM_NB;
     double acc = 0.0;
-    for (int64_t i = set_off[s] + threadIdx.x; i < set_off[s + 1]; i += blockDim.x) acc += part[i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += part[i];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) dc[s] = accumulate ? dc[s] + red[0] : red[0];
+    if (threadIdx.x == 0) partial[size_t(s) * SETSUM_NB + blk] = red[0];
+}
+
+__global__ void k_set_final(int nsets, const double *__restrict__ partial, double *__restrict__ dc, int accumulate)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsets) return;
+    double acc = 0.0;
+    for (int b = 0; b < SETSUM_NB; ++b) acc += partial[size_t(s) * SETSUM_NB + b];
+    dc[s] = accumulate ? dc[s] + acc : acc;
 }
 
 template <typename V>
@@ -234,10 +271,12 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
     PrecData &pd = prec_data<T>(t);
     const size_t lo_bytes = sizeof(T) * size_t(nbox) * 2 * KS;
     if (pd.Lodd.bytes < lo_bytes) IMQ_HIP(dev_alloc(pd.Lodd, lo_bytes));
-    if (t->adj.bytes < sizeof(double) * 7 * size_t(N)) IMQ_HIP(dev_alloc(t->adj, sizeof(double) * 7 * size_t(N)));
+    const size_t adj_bytes = sizeof(double) * (7 * size_t(N) + size_t(h.nsets) * SETSUM_NB);
+    if (t->adj.bytes < adj_bytes) IMQ_HIP(dev_alloc(t->adj, adj_bytes));
     T *us = pd.us.as<T>();
     double *out = t->adj.as<double>();
     double *dcpart = out + 6 * N;
+    double *dcslice = out + 7 * N;
 
     hipLaunchKernelGGL((k_gather2<Tio, T>), grid1(N), dim3(256), 0, s, N, t->perm.as<int32_t>(), v, g, us);
     IMQ_HIP(hipGetLastError());
@@ -266,7 +305,9 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
                        t->leaves.as<int32_t>(), pd.L.as<T>(), Lo, us, out);
     hipLaunchKernelGGL((k_adjoint_final<T, Tio>), grid1(N), dim3(256), 0, s, N, t->perm.as<int32_t>(),
                        t->pt_scale.as<double>(), us, out, dv, dxy, dcpart, accumulate);
-    hipLaunchKernelGGL(k_set_sum, dim3(h.nsets), dim3(256), 0, s, t->set_off.as<int64_t>(), dcpart, dc,
+    hipLaunchKernelGGL(k_set_partial, dim3(h.nsets, SETSUM_NB), dim3(256), 0, s, t->set_off.as<int64_t>(), dcpart,
+                       dcslice);
+    hipLaunchKernelGGL(k_set_final, dim3(unsigned((h.nsets + 255) / 256)), dim3(256), 0, s, h.nsets, dcslice, dc,
                        accumulate);
     IMQ_HIP(hipGetLastError());
     return IMQ_OK;
