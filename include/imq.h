@@ -238,11 +238,12 @@ imq_status imq_solve(imq_tree tree, int nrhs, const double *f, int64_t ldf,
  *  dc   : device FP64, nsets entries (written, summed over the columns)
  *  dxy  : device FP64 SoA 2 x Ntot: d/dx then d/dy (written, summed over the
  *         columns)
- * The interaction lists are those of `tree`, which must sum its adaptive W/X
- * interactions directly (built with direct_max >= Ntot), else
- * IMQ_EUNSUPPORTED.  The vertical derivative uses translation tables to the
- * n+m-odd local coefficients, generated on the first call.  IMQ_EINVAL for
- * nrhs < 1, a null pointer or a leading dimension below Ntot. */
+ * The interaction lists are those of `tree`, adaptive W/X lists included
+ * (an X-list leaf enters the odd local coefficients from its points, a
+ * W-list box's multipole is evaluated with its derivatives at the leaf's
+ * points).  The vertical derivative uses translation tables to the n+m-odd
+ * local coefficients, generated on the first call.  IMQ_EINVAL for nrhs < 1,
+ * a null pointer or a leading dimension below Ntot. */
 imq_status imq_matvec_backward(imq_tree tree, int nrhs, imq_dtype dtype, const void *v, int64_t ldv,
                                const void *g, int64_t ldg, void *dv, int64_t lddv, double *dc,
                                double *dxy, imq_prec prec, hipStream_t stream);

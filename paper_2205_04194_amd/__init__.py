@@ -353,9 +353,8 @@ class IMQMatvec(torch.autograd.Function):
     def backward(ctx, gb):
         xy, v = ctx.saved_tensors
         leaf, p, prec = ctx.cfg
-        # the lists are rebuilt here (not kept from forward), with every
-        # adaptive W/X interaction in the direct near field
-        tree = Tree(xy.detach(), ctx.c, leaf=leaf, p=p, direct_max=1 << 30)
+        # the lists are rebuilt here (not kept from forward)
+        tree = Tree(xy.detach(), ctx.c, leaf=leaf, p=p)
         dv, dc, dxy = tree.backward(v.detach(), gb.detach().to(v.dtype).contiguous(), prec)
         tree.close()
         gxy = dxy.to(xy.dtype) if ctx.needs_input_grad[0] else None

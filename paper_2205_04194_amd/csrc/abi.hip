@@ -240,7 +240,7 @@ static void free_tree(imq_tree_s *t)
     }
     for (PrecData *pd : {&t->f64, &t->f32}) {
         DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->urec, &pd->m2m, &pd->l2l, &pd->m2l, &pd->m2l_pk, &pd->m2l_bf3, &pd->wx, &pd->us, &pd->M, &pd->L,
-                        &pd->Lx, &pd->m2l_odd, &pd->l2l_odd, &pd->Lodd};
+                        &pd->Lx, &pd->m2l_odd, &pd->l2l_odd, &pd->Lodd, &pd->wxo};
         for (DevBuf *b : pb) dev_free(*b);
     }
     for (auto &e : t->ev)
@@ -789,11 +789,6 @@ imq_status imq_matvec_backward(imq_tree t, int nrhs, imq_dtype dtype, const void
     if (nrhs < 1 || !v || !g || !dv || !dc || !dxy || ldv < N || ldg < N || lddv < N) {
         set_error("bad nrhs, pointer or leading dimension in imq_matvec_backward");
         return IMQ_EINVAL;
-    }
-    if (t->nwpairs > 0 || t->nxpairs > 0) {
-        set_error("the adjoint needs a tree whose adaptive W/X interactions are summed directly "
-                  "(build it with direct_max >= the number of points)");
-        return IMQ_EUNSUPPORTED;
     }
     if ((dtype != IMQ_F64 && dtype != IMQ_F32) || (prec != IMQ_PREC_FP64 && prec != IMQ_PREC_FP32)) {
         set_error("unknown dtype or precision");

@@ -12,12 +12,25 @@
 // gradient, the n+m-odd ones (extra translation tables) the vertical
 // derivative, which is d/dc in the lifted picture.  The near field is summed
 // directly with the same formulas, each neighbour leaf's points staged
-// through LDS 64 at a time.  Adaptive W/X lists are not expanded
-// here: the tree must route them to the direct sum (direct_max >= N).
+// through LDS 64 at a time.
+//
+// Adaptive lists.  An X-list leaf's points enter the target box's even local
+// coefficients with the forward pass (P2L) and its odd ones here, from the
+// n+m-odd irregular harmonics of the points.  A W-list box's multipole is
+// evaluated at the leaf's points with its derivatives, from the ladder
+// relations of the irregular solid harmonics (normalisation of the table
+// generator): with d+ = d/dx + i d/dy,
+//     d+ I_n^m = I_{n+1}^{m+1},   d/dz I_n^m = -I_{n+1}^m   (every m),
+// so for a real field sum_{n,m} M_n^m I_n^m (all m, M_n^{-m} = (-1)^m conj M_n^m)
+//     d+ phi   = sum_{n, m>=0} M_n^m I_{n+1}^{m+1} - sum_{n, m>=1} conj(M_n^m I_{n+1}^{m-1})
+//     dphi/dz  = -sum_{n, m>=0} eps_m Re(M_n^m I_{n+1}^m),
+// the gradient being (Re d+ phi, Im d+ phi); the harmonics are needed to
+// order P+1, both parities.
 #include "device.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -30,6 +43,95 @@ namespace {
 
 __device__ __forceinline__ int cidx_e(int n, int m) { return n * (n + 1) / 2 + (m > 0 ? m - 1 : 0); }
 __device__ __forceinline__ int cidx_o(int j, int k) { return j * (j - 1) / 2 + (k > 0 ? k - 1 : 0); }
+
+template <typename T> __device__ __forceinline__ T rsqrt_a(T x) { return T(1) / sqrt(x); }
+
+// Irregular solid harmonics I_n^m(v), 0 <= m <= n <= NMAX, both parities:
+// I_0^0 = 1/|v|, I_m^m = -(2m-1)(vx + i vy)/|v|^2 I_{m-1}^{m-1} and
+// |v|^2 I_n^m = (2n-1) vz I_{n-1}^m - (n+m-1)(n-m-1) I_{n-2}^m; f(n, m, re, im).
+template <typename T, typename F>
+__device__ __forceinline__ void irregular_all(int NMAX, T vx, T vy, T vz, F &&f)
+{
+    const T r2 = vx * vx + vy * vy + vz * vz;
+    const T inv_r2 = T(1) / r2;
+    T mr = rsqrt_a(r2), mi = T(0);
+    for (int m = 0; m <= NMAX; ++m) {
+        if (m > 0) {
+            const T a = -T(2 * m - 1) * inv_r2;
+            const T nr = a * (vx * mr - vy * mi);
+            mi = a * (vx * mi + vy * mr);
+            mr = nr;
+        }
+        T p2r = 0, p2i = 0, p1r = mr, p1i = mi;
+        f(m, m, mr, mi);
+        for (int n = m + 1; n <= NMAX; ++n) {
+            const T a = T(2 * n - 1) * vz;
+            const T b = T((n + m - 1) * (n - m - 1));
+            const T cr = (a * p1r - b * p2r) * inv_r2;
+            const T ci = (a * p1i - b * p2i) * inv_r2;
+            f(n, m, cr, ci);
+            p2r = p1r; p2i = p1i; p1r = cr; p1i = ci;
+        }
+    }
+}
+
+// Odd local coefficients of the v weights from the X lists: one workgroup
+// per target box b, its X-list leaves in list order,
+//     Lo[b][j,k] += (1/s^2) eps_k c_{j-1,k} sum_i v_i conj(I_j^k((y_i - z_b)/s)),
+// j+k odd, with the sources c below the target plane (vz = -c/s); wxo holds
+// eps_k c_{j-1,k} in the odd layout.  Points go through LDS in chunks of 32.
+constexpr int X_CH = 32;
+constexpr int KODD_MAX = PMAX * (PMAX + 1) / 2;
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2l_odd(DTree<T> t, const int32_t *__restrict__ xboxes,
+                                                const T *__restrict__ us, const T *__restrict__ wxo, int Ko,
+                                                T *__restrict__ Lo)
+{
+    __shared__ T mono[X_CH][KODD_MAX | 1];
+    __shared__ T su[X_CH];
+    const int b = xboxes[blockIdx.x];
+    const int P = t.P, lane = threadIdx.x;
+    const double inv_sd = ldexp(1.0, t.level[b]);
+    const T inv_s = T(inv_sd);
+    const T vz = T(-t.cn[t.set[b]] * inv_sd);
+    T acc[(KODD_MAX + 63) / 64] = {};
+    for (int kp = t.x_off[b]; kp < t.x_off[b + 1]; ++kp) {
+        const int a = t.x_idx[kp];
+        const T ox = T((t.cx[a] - t.cx[b]) * inv_sd), oy = T((t.cy[a] - t.cy[b]) * inv_sd);
+        for (int c0 = t.begin[a]; c0 < t.end[a]; c0 += X_CH) {
+            const int n = min(X_CH, t.end[a] - c0);
+            __syncthreads();                       // the previous chunk is no longer read
+            if (lane < n) {
+                T *row = mono[lane];
+                irregular_all<T>(P, t.xl[c0 + lane] * inv_s + ox, t.yl[c0 + lane] * inv_s + oy, vz,
+                                 [&](int j, int k, T re, T im) {
+                                     if ((j + k) & 1) {
+                                         const int o = cidx_o(j, k);
+                                         row[o] = re;
+                                         if (k > 0) row[o + 1] = -im;
+                                     }
+                                 });
+                su[lane] = us[c0 + lane];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < (KODD_MAX + 63) / 64; ++q) {
+                const int o = lane + 64 * q;
+                if (o < Ko) {
+                    T s = T(0);
+                    for (int i = 0; i < n; ++i) s += mono[i][o] * su[i];
+                    acc[q] += s;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < (KODD_MAX + 63) / 64; ++q) {
+        const int o = lane + 64 * q;
+        if (o < Ko) Lo[size_t(b) * 2 * t.KS + o] += acc[q] * wxo[o] * inv_s * inv_s;
+    }
+}
 
 template <typename T>
 __global__ void k_zero(size_t n, T *__restrict__ p)
@@ -51,9 +153,11 @@ __global__ void k_gather2(int64_t N, const int32_t *__restrict__ perm, const Tin
 
 // Per target (normalised units): out[0] = potential of g, out[1..2] = grad of
 // the v field, out[3..4] = grad of the g field, out[5] = d/dc of the v field.
+// M (premultiplied by wx = eps_m c_{nm}) feeds the W-list evaluations.
 template <typename T>
 __global__ __launch_bounds__(64) void k_adjoint_eval(DTree<T> t, const int32_t *__restrict__ leaves,
                                                      const T *__restrict__ L, const T *__restrict__ Lo,
+                                                     const T *__restrict__ M, const T *__restrict__ wx,
                                                      const T *__restrict__ us, double *__restrict__ out)
 {
     const int b = leaves[blockIdx.x];
@@ -66,8 +170,11 @@ __global__ __launch_bounds__(64) void k_adjoint_eval(DTree<T> t, const int32_t *
     const T *Lg = L + (size_t(b) * 2 + 1) * t.KS;
     const T *Lov = Lo + (size_t(b) * 2 + 0) * t.KS;
     const int64_t N = t.N;
-    // the near field's sources, staged 64 points at a time
+    // the near field's sources, staged 64 points at a time; a W-list box's
+    // multipoles of v and g
     __shared__ T sx[64], sy[64], sv[64], sg[64];
+    __shared__ T mwv[KMAX + 1], mwg[KMAX + 1];
+    const int K = t.K;
     for (int i0 = t.begin[b]; i0 < t.end[b]; i0 += 64) {
         const int i = i0 + threadIdx.x;
         const bool ok = i < t.end[b];
@@ -110,6 +217,54 @@ __global__ __launch_bounds__(64) void k_adjoint_eval(DTree<T> t, const int32_t *
             }
             o0 = double(potg); o1 = double(gvx * inv_s); o2 = double(gvy * inv_s);
             o3 = double(ggx * inv_s); o4 = double(ggy * inv_s); o5 = double(dzv);
+        }
+        // W list: each box's multipole expansions at the leaf's points
+        for (int ww = t.w_off[b]; ww < t.w_off[b + 1]; ++ww) {
+            const int a = t.w_idx[ww];
+            __syncthreads();                             // the previous box is no longer read
+            for (int k = threadIdx.x; k < K; k += 64) {
+                mwv[k] = M[(size_t(a) * 2 + 0) * t.KS + k] * wx[k];
+                mwg[k] = M[(size_t(a) * 2 + 1) * t.KS + k] * wx[k];
+            }
+            __syncthreads();
+            if (ok) {
+                const double ia_d = ldexp(1.0, t.level[a]);
+                const T ia = T(ia_d);
+                const T vx = xi * ia + T((t.cx[b] - t.cx[a]) * ia_d);
+                const T vy = yi * ia + T((t.cy[b] - t.cy[a]) * ia_d);
+                T pg = 0, dz = 0, dvr = 0, dvi = 0, dgr = 0, dgi = 0;
+                irregular_all<T>(P + 1, vx, vy, T(cnd * ia_d), [&](int n, int m, T re, T im) {
+                    if (((n + m) & 1) == 0) {
+                        if (n <= P) {                        // potential of g
+                            const int k = cidx_e(n, m);
+                            pg += mwg[k] * re - (m > 0 ? mwg[k + 1] * im : T(0));
+                        }
+                        if (m >= 1) {                        // M_{n-1}^{m-1} I_n^m
+                            const int k = cidx_e(n - 1, m - 1);
+                            const T h = m == 1 ? T(1) : T(0.5);
+                            const T vr = h * mwv[k], vi = m > 1 ? h * mwv[k + 1] : T(0);
+                            const T gr = h * mwg[k], gi = m > 1 ? h * mwg[k + 1] : T(0);
+                            dvr += vr * re - vi * im; dvi += vr * im + vi * re;
+                            dgr += gr * re - gi * im; dgi += gr * im + gi * re;
+                        }
+                        if (m + 2 <= n) {                    // -conj(M_{n-1}^{m+1} I_n^m)
+                            const int k = cidx_e(n - 1, m + 1);
+                            const T vr = T(0.5) * mwv[k], vi = T(0.5) * mwv[k + 1];
+                            const T gr = T(0.5) * mwg[k], gi = T(0.5) * mwg[k + 1];
+                            dvr -= vr * re - vi * im; dvi += vr * im + vi * re;
+                            dgr -= gr * re - gi * im; dgi += gr * im + gi * re;
+                        }
+                    } else {                                 // -eps_m Re(M_{n-1}^m I_n^m)
+                        const int k = cidx_e(n - 1, m);
+                        dz -= mwv[k] * re - (m > 0 ? mwv[k + 1] * im : T(0));
+                    }
+                });
+                const double ia2 = ia_d * ia_d;
+                o0 += double(pg) * ia_d;
+                o1 += double(dvr) * ia2; o2 += double(dvi) * ia2;
+                o3 += double(dgr) * ia2; o4 += double(dgi) * ia2;
+                o5 += double(dz) * ia2;
+            }
         }
         // near field, summed directly: each U-list leaf's points through LDS
         for (int uu = t.u_off[b]; uu < t.u_off[b + 1]; ++uu) {
@@ -243,8 +398,19 @@ imq_status ensure_odd_tables(imq_tree_s *t)
                 make_m2l_odd_table(p, l, dx, dy, h.cn[s], tmp.data());
                 pad_into(tmp, m2l.data() + ((size_t(s) * h.nlev + l) * NCLASS + cls) * PP);
             }
-    std::vector<float> m2l32(m2l.begin(), m2l.end()), l2l32(l2l.begin(), l2l.end());
+    // eps_k c_{j-1,k} per odd coefficient (the X-list odd P2L)
+    std::vector<double> wxo(std::max(Kodd(p), 1), 0.0);
+    for (int j = 1; j <= p; ++j)
+        for (int k = (j + 1) & 1; k <= j - 1; k += 2) {
+            const int o = j * (j - 1) / 2 + (k > 0 ? k - 1 : 0);
+            const double v = (k == 0 ? 1.0 : 2.0) * legendre_coef(j - 1, k);
+            wxo[o] = v;
+            if (k > 0) wxo[o + 1] = v;
+        }
+    std::vector<float> m2l32(m2l.begin(), m2l.end()), l2l32(l2l.begin(), l2l.end()), wxo32(wxo.begin(), wxo.end());
     imq_status st;
+    if ((st = upload_vec(t->f64.wxo, wxo)) != IMQ_OK) return st;
+    if ((st = upload_vec(t->f32.wxo, wxo32)) != IMQ_OK) return st;
     if ((st = upload_vec(t->f64.m2l_odd, m2l)) != IMQ_OK) return st;
     if ((st = upload_vec(t->f64.l2l_odd, l2l)) != IMQ_OK) return st;
     if ((st = upload_vec(t->f32.m2l_odd, m2l32)) != IMQ_OK) return st;
@@ -293,6 +459,9 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
         launch_gemm<T>(s, 32, 1, t->g_m2l.ntasks, 2, t->g_m2l.tasks.as<GemmTask>(), 0, t->g_m2l.tbox.as<int32_t>(),
                        t->g_m2l.tab.as<int32_t>(), t->g_m2l.src.as<int32_t>(), pd.m2l_odd.as<T>(), KP, KS,
                        pd.M.as<T>(), Lo, 0, 0, Ko);
+    if (t->nxboxes > 0)
+        hipLaunchKernelGGL(k_p2l_odd<T>, dim3(unsigned(t->nxboxes)), dim3(64), 0, s, make_view<T>(t),
+                           t->x_boxes.as<int32_t>(), us, pd.wxo.as<T>(), Ko, Lo);
     for (int l = std::max(h.need_l, 0); l + 1 < h.nlev; ++l) {
         const int p0 = h.sh_level_begin[l], np = h.sh_level_begin[l + 1] - p0;
         launch_shift<T>(s, false, t->kcfg.shift_cols, np, 2, t->sh_par.as<int32_t>() + p0,
@@ -302,7 +471,7 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
     IMQ_HIP(hipGetLastError());
     DTree<T> view = make_view<T>(t);
     hipLaunchKernelGGL(k_adjoint_eval<T>, dim3(unsigned(h.leaves.size())), dim3(64), 0, s, view,
-                       t->leaves.as<int32_t>(), pd.L.as<T>(), Lo, us, out);
+                       t->leaves.as<int32_t>(), pd.L.as<T>(), Lo, pd.M.as<T>(), pd.wx.as<T>(), us, out);
     hipLaunchKernelGGL((k_adjoint_final<T, Tio>), grid1(N), dim3(256), 0, s, N, t->perm.as<int32_t>(),
                        t->pt_scale.as<double>(), us, out, dv, dxy, dcpart, accumulate);
     hipLaunchKernelGGL(k_set_partial, dim3(h.nsets, SETSUM_NB), dim3(256), 0, s, t->set_off.as<int64_t>(), dcpart,

@@ -99,6 +99,7 @@ struct PrecData {              // everything that exists once per arithmetic typ
     DevBuf m2l_odd, l2l_odd;   // adjoint: tables to the n+m-odd local coefficients
                                // (l2l_odd packed like l2l)
     DevBuf Lodd;               // adjoint: odd local coefficients
+    DevBuf wxo;                // adjoint: eps_k c_{j-1,k} per odd coefficient
 };
 
 // Per row block of a packed shift table: the 16-coefficient input chunks

@@ -96,12 +96,31 @@ def test_several_sets_get_their_own_dc(imq):
         assert _rel(dX.cpu().numpy()[a:e], rdX) < 1e-6
 
 
-def test_tree_with_expansion_w_lists_is_refused(imq):
-    xy = W.mixture_points(20000, W.rng("mixture1m", 3), W.rng(55, 2))
-    tree = imq.build_tree(_dev(xy), 0.02, leaf=64, p=8, direct_max=-1)
-    assert tree.info()["m2p_evals"] > 0
-    with pytest.raises(imq.IMQError):
-        tree.backward(_dev(np.ones(20000)), _dev(np.ones(20000)))
+@pytest.mark.parametrize("direct_max", [-1, 0])
+def test_adjoint_with_expansion_w_and_x_lists(imq, direct_max):
+    """Clustered points: the adaptive W/X interactions go through expansions
+    (all of them with direct_max = -1, the large ones with the default), so
+    the W-list derivative evaluations and the X-list odd coefficients are
+    exercised; the result must match the dense gradient as on uniform trees."""
+    n, c = 20000, 0.02
+    xy = W.mixture_points(n, W.rng("mixture1m", 3), W.rng(55, 2))
+    gen = np.random.default_rng(21)
+    v, g = gen.standard_normal(n), gen.standard_normal(n)
+    ref_dv, ref_dc, ref_dX = oracle.grad_given_g(xy, c, v, g)
+    tree = imq.build_tree(_dev(xy), c, leaf=64, p=16, direct_max=direct_max)
+    info = tree.info()
+    assert info["m2p_evals"] > 0 and info["p2l_evals"] > 0
+    dv, dc, dX = tree.backward(_dev(v), _dev(g), prec="fp64")
+    print(f"direct_max {direct_max}: m2p {info['m2p_evals']} p2l {info['p2l_evals']}: "
+          f"dv {_rel(dv.cpu().numpy(), ref_dv):.2e} dc {abs(float(dc[0]) - ref_dc) / abs(ref_dc):.2e} "
+          f"dX {_rel(dX.cpu().numpy(), ref_dX):.2e}")
+    assert _rel(dv.cpu().numpy(), ref_dv) < 1e-6
+    assert abs(float(dc[0]) - ref_dc) / abs(ref_dc) < 1e-6
+    assert _rel(dX.cpu().numpy(), ref_dX) < 1e-6
+    dv32, dc32, dX32 = tree.backward(_dev(v), _dev(g), prec="fp32")
+    assert _rel(dv32.cpu().numpy(), ref_dv) < 1e-5
+    assert abs(float(dc32[0]) - ref_dc) / abs(ref_dc) < 1e-4
+    assert _rel(dX32.cpu().numpy(), ref_dX) < 1e-4
 
 
 def test_autograd_with_float_c_and_several_columns(imq):
