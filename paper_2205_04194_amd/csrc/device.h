@@ -180,6 +180,13 @@ struct UserVec {
     }
 };
 
+// The tree passes (gather, P2M, the shifts, the translations, L2P, M2P,
+// scatter) form a chain of dependent launches; the near field runs beside
+// them as independent bulk work.  Their waves take a higher issue priority
+// than the near field's on a shared SIMD, so the chain advances as soon as
+// its waves are ready (the wave's own priority, not the queue's).
+__device__ __forceinline__ void tree_pass_priority() { __builtin_amdgcn_s_setprio(2); }
+
 struct DevGemm {               // device copy of a GemmList
     DevBuf tasks, tbox, tab, src;
     std::vector<int32_t> level_task_begin;

@@ -67,6 +67,7 @@ template <typename Tin, typename T>
 __global__ void k_gather(int64_t N, const int32_t *__restrict__ perm, const Tin *__restrict__ u,
                          int64_t ldu, T *__restrict__ us)
 {
+    tree_pass_priority();
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     const int r = blockIdx.y;
     if (i < N) us[r * N + i] = T(u[r * ldu + perm[i]]);
@@ -76,6 +77,7 @@ template <typename Tout>
 __global__ void k_scatter(int64_t N, const int32_t *__restrict__ perm, const double *__restrict__ scale,
                           const double *__restrict__ bs, Tout *__restrict__ b, int64_t ldb)
 {
+    tree_pass_priority();
     const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     const int r = blockIdx.y;
     if (i < N) b[r * ldb + perm[i]] = Tout(bs[r * N + i] * scale[i]);
@@ -231,6 +233,7 @@ template <typename T, int P, int IN>
 __global__ __launch_bounds__(64) void k_p2m_pipe(DTree<T> t, const LeafRec *__restrict__ recs, int nrec,
                                                  T *__restrict__ us, T *__restrict__ M, UserVec io)
 {
+    tree_pass_priority();
     using R = P2MRows<T, P>;
     __shared__ T S[P2M_CHUNK * R::LD];
     const int lane = threadIdx.x;
@@ -294,6 +297,7 @@ template <typename T, int P, int IN>
 __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const LeafRec *__restrict__ recs, T *__restrict__ us,
                                             int nrhs, T *__restrict__ M, UserVec io)
 {
+    tree_pass_priority();
     using R = P2MRows<T, P>;
     __shared__ T S[P2M_CHUNK * R::LD];
     const int lane = threadIdx.x;
@@ -351,6 +355,7 @@ __global__ __launch_bounds__(64) void k_p2m_box(DTree<T> t, const BoxRec *__rest
                                                 const int32_t *__restrict__ lord, const T *__restrict__ us,
                                                 int nrhs, T *__restrict__ M, int ld)
 {
+    tree_pass_priority();
     extern __shared__ unsigned char smem_raw[];
     T *mono = reinterpret_cast<T *>(smem_raw);   // [P2M_CHUNK][ld]
     T *su = mono + P2M_CHUNK * ld;               // [P2M_CHUNK]
@@ -406,6 +411,7 @@ __global__ __launch_bounds__(64) void k_p2l_pairs(DTree<T> t, const int32_t *__r
                                                   const T *__restrict__ wx, T *__restrict__ Lx, int ld,
                                                   int npairs)
 {
+    tree_pass_priority();
     extern __shared__ unsigned char smem_raw[];
     T *mono = reinterpret_cast<T *>(smem_raw);   // [64][ld]
     T *su = mono + 64 * ld;
@@ -446,6 +452,7 @@ template <typename T>
 __global__ void k_p2l_reduce(DTree<T> t, const int32_t *__restrict__ xboxes, int nrhs,
                              const T *__restrict__ Lx, int npairs, T *__restrict__ L)
 {
+    tree_pass_priority();
     const int b = xboxes[blockIdx.x];
     const int K = t.K;
     for (int r = 0; r < nrhs; ++r)
@@ -484,6 +491,7 @@ __global__ __launch_bounds__(256) void k_gemm_tasks(const GemmTask *__restrict__
                                                     const T *__restrict__ in, T *__restrict__ out,
                                                     int accumulate, int kin_ovr, int kout_ovr)
 {
+    tree_pass_priority();
     using S = GemmStage<T, KC_, MAXRB>;
     constexpr int KC = S::KC, LD = S::LD;
     __shared__ T As[MAXRB * 16 * LD];
@@ -638,6 +646,7 @@ void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const Ge
 template <typename T>
 __global__ void k_fill(size_t n, T *__restrict__ p, T v)
 {
+    tree_pass_priority();
     const size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x;
     if (i < n) p[i] = v;
 }
@@ -705,6 +714,7 @@ template <typename T, int P>
 __global__ __launch_bounds__(64) void k_l2p(DTree<T> t, LevelK lk, const T *__restrict__ L, int nrhs,
                                             double *__restrict__ bs, int add, UserVec io, M2PParts wp)
 {
+    tree_pass_priority();
     constexpr int KP = (P + 1) * (P + 2) / 2;
     __shared__ T Ls[KP];
     const LeafRec lr = t.leafrec[blockIdx.x];
@@ -735,6 +745,7 @@ __global__ __launch_bounds__(64) void k_l2p_pipe(DTree<T> t, const LeafRec *__re
                                                  const T *__restrict__ L, double *__restrict__ bs, int add, UserVec io,
                                                  M2PParts wp, const int32_t *__restrict__ w_off, int nrec)
 {
+    tree_pass_priority();
     constexpr int KP = (P + 1) * (P + 2) / 2;
     constexpr int NL = (KP + 63) / 64;
     __shared__ T Ls[KP];
@@ -833,6 +844,7 @@ template <typename T, int P, int RB>
 __global__ __launch_bounds__(64) void k_p2m_mfma(DTree<T> t, const int32_t *__restrict__ leaves,
                                                  const T *__restrict__ us, int nrhs, T *__restrict__ M)
 {
+    tree_pass_priority();
     constexpr int K = (P + 1) * (P + 2) / 2, NRB = (K + 15) / 16, LDM = mono_ld<K>();
     constexpr int NCB = RB / 16, LDU = 64 + 2;
     using acc_t = typename Mfma<T>::acc_t;
@@ -909,6 +921,7 @@ template <typename T, int P, int RB>
 __global__ __launch_bounds__(64) void k_l2p_mfma(DTree<T> t, const int32_t *__restrict__ leaves,
                                                  const T *__restrict__ L, int nrhs, double *__restrict__ bs)
 {
+    tree_pass_priority();
     constexpr int K = (P + 1) * (P + 2) / 2, NRB = (K + 15) / 16, LDM = mono_ld<K>();
     constexpr int NCB = RB / 16, LDL = NRB * 16 + 2;
     using acc_t = typename Mfma<T>::acc_t;
@@ -1000,6 +1013,7 @@ __global__ __launch_bounds__(64) void k_m2p_pairs(DTree<T> t, const int32_t *__r
                                                   const T *__restrict__ M, const T *__restrict__ wx,
                                                   int nrhs, double *__restrict__ Pw, int nscr)
 {
+    tree_pass_priority();
     __shared__ T mw[KMAX + 1];
     const int kp = blockIdx.x;
     const int b = w_tgt[kp], a = t.w_idx[kp];
@@ -1033,6 +1047,7 @@ __global__ __launch_bounds__(64) void k_m2p_reduce(DTree<T> t, const int32_t *__
                                                    const double *__restrict__ Pw, int nscr,
                                                    double *__restrict__ bs)
 {
+    tree_pass_priority();
     const int b = wleaves[blockIdx.x];
     for (int r = 0; r < nrhs; ++r)
         for (int i = t.begin[b] + threadIdx.x; i < t.end[b]; i += blockDim.x) {
@@ -1055,6 +1070,7 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_alg1_far(DTree<T> t, const T *__restrict__ M, const T *__restrict__ wx,
                                                  int nrhs, double *__restrict__ bs)
 {
+    tree_pass_priority();
     __shared__ T mw[KMAX + 1];
     const LeafRec lr = t.leafrec[blockIdx.x];
     const int P = t.P, K = t.K, lane = threadIdx.x;

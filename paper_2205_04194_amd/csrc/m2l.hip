@@ -86,6 +86,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
                                                     int nrbT, int nrhs, int KS, const T *__restrict__ in,
                                                     T *__restrict__ out, int add)
 {
+    tree_pass_priority();
     static_assert(NRB % RBW == 0, "whole row-block groups");
     static_assert(!BF || sizeof(T) == 4, "BF16 parts of FP32 operands");
     constexpr int TC = 16 * NCB;

@@ -35,6 +35,7 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
                                                const T *__restrict__ in, int ldin, T *__restrict__ out,
                                                int ldout)
 {
+    tree_pass_priority();
     constexpr int TC = 16 * NCB;
     constexpr int KPC = NRB * 16;
     constexpr int LD = KPC + (sizeof(T) == 4 ? 2 : 1);     // LDS row stride
