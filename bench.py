@@ -505,7 +505,7 @@ def headline(args, dev, d):
         ti = tr.info()
         tuned[prec] = {"ms_per_step": ms, "rel_err": e, "stage_ms": st, "leaf": leaf, "p": ti["order_p"],
                        "level_orders": res.level_orders, "m2l_mode": res.m2l_mode, "m2l_kc": res.m2l_kc,
-                       "m2l_split": res.m2l_split, "tune_s": t_tune, "leaf_search": rec,
+                       "m2l_split": res.m2l_split, "p2p_wg": res.p2p_wg, "tune_s": t_tune, "leaf_search": rec,
                        "roofline": _stage_roofline(ti, st, prec, n), "info": ti}
         log(f"tuned {prec} leaf {leaf} orders {res.level_orders}: {ms:.3f} ms/product, rel err {e:.2e} "
             f"(fresh weights, {len(rows)} rows), stages " + " ".join(f"{k}={v:.3f}" for k, v in st.items()))
@@ -577,7 +577,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "c": d["c"], "leaf": r.get("leaf"), "p": r.get("p"),
                    "nrhs": 1, "precision": "fp64", "level_orders": r.get("level_orders"),
-                   "m2l_mode": r.get("m2l_mode"), "m2l_kc": r.get("m2l_kc"), "m2l_split": r.get("m2l_split")},
+                   "m2l_mode": r.get("m2l_mode"), "m2l_kc": r.get("m2l_kc"), "m2l_split": r.get("m2l_split"),
+                   "p2p_wg": r.get("p2p_wg")},
         "rel_err_sampled_rows": r["rel_err"],
         "rel_err_note": f"relative 2-norm over {min(args.rows, n)} sampled rows against exact FP64 sums, "
                         "on weights the tuner did not see",

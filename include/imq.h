@@ -265,7 +265,7 @@ imq_status imq_matvec_backward(imq_tree tree, int nrhs, imq_dtype dtype, const v
  *               FP32 (the FP64 product runs as 0).
  *               m2l_kc and m2l_split apply to the staged GEMM only.
  *  p2p_wg     : workgroups of the near-field kernel while it runs alongside
- *               the tree passes (each takes every p2p_wg-th leaf); 0 = 2048
+ *               the tree passes (each takes every p2p_wg-th leaf); 0 = 3072
  *  p2p_mode   : near field with one right-hand side (FP32 or FP64): 0 =
  *               vector form everywhere; 1 = matrix-core form (squared
  *               distances as a rank-4 product on the FP32 or FP64 matrix

@@ -13,7 +13,9 @@ Search on one tree (``tune``, no rebuild):
      error stays within the target (the lifted vertical offset c makes deep
      levels, whose boxes are small next to c, converge fastest);
   3. the M2L kernel choice (register streaming or staged GEMM) and the staged
-     GEMM's pipeline depth and row split are timed and the fastest kept.
+     GEMM's pipeline depth and row split are timed and the fastest kept;
+  4. so is the number of near-field workgroups running beside the tree
+     passes (their share of the CUs).
 ``tune_tree`` then rebuilds the tree at the highest tuned order (multipoles
 need no more), and ``tune_leaf`` repeats all of it for several leaf
 capacities, keeping the fastest tree: the level/leaf trade-off of the cost
@@ -39,6 +41,7 @@ class TuneResult:
     ms: float
     m2l_mode: int = 0
     trials: List[dict] = field(default_factory=list)
+    p2p_wg: int = 0
 
 
 def _error(tree, u, rows, exact, prec):
@@ -61,7 +64,7 @@ def _time(tree, u, prec, reps=5):
 
 def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"),
          nrows: int = 1000, safety: float = 0.8, seed: int = 0,
-         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1, 2)) -> TuneResult:
+         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1, 2), p2p_wgs=(2048, 2560, 3072, 3584)) -> TuneResult:
     """Fastest configuration of ``tree`` whose sampled-row relative 2-norm
     error is at most ``safety * target``; the tree is left configured."""
     n = tree.n
@@ -119,13 +122,22 @@ def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"
                     trials.append({"prec": prec, "m2l_mode": mode, "m2l_kc": kc, "m2l_split": sp, "ms": t})
                     if t < ms:
                         shape, ms = (kc, sp, mode), t
-        res = TuneResult(prec, list(orders), shape[0], shape[1], err, ms, m2l_mode=shape[2])
+        # 4. workgroups of the near field running beside the tree passes
+        wg = 0
+        for w in p2p_wgs:
+            tree.set_kernel_config(m2l_kc=shape[0], m2l_split=shape[1], m2l_mode=shape[2], p2p_wg=w)
+            t = _time(tree, u, prec)
+            trials.append({"prec": prec, "p2p_wg": w, "ms": t})
+            if t < ms:
+                wg, ms = w, t
+        res = TuneResult(prec, list(orders), shape[0], shape[1], err, ms, m2l_mode=shape[2], p2p_wg=wg)
         if best is None or res.ms < best.ms:
             best = res
     if best is None:
         raise RuntimeError(f"no precision reaches the target {target:g} at order {pmax}")
     tree.set_level_orders(best.level_orders)
-    tree.set_kernel_config(m2l_kc=best.m2l_kc, m2l_split=best.m2l_split, m2l_mode=best.m2l_mode)
+    tree.set_kernel_config(m2l_kc=best.m2l_kc, m2l_split=best.m2l_split, m2l_mode=best.m2l_mode,
+                           p2p_wg=best.p2p_wg)
     best.error = _error(tree, u, rows, exact, best.precision)
     best.trials = trials
     return best
@@ -144,7 +156,8 @@ def tune_tree(xy: torch.Tensor, c, u: torch.Tensor, leaf: int = 64, p: int = 12,
         tree.close()
         tree = build_tree(xy, c, leaf=leaf, p=pmax, **tree_kw)
         tree.set_level_orders(res.level_orders)
-        tree.set_kernel_config(m2l_kc=res.m2l_kc, m2l_split=res.m2l_split, m2l_mode=res.m2l_mode)
+        tree.set_kernel_config(m2l_kc=res.m2l_kc, m2l_split=res.m2l_split, m2l_mode=res.m2l_mode,
+                               p2p_wg=res.p2p_wg)
     return tree, res
 
 

@@ -187,6 +187,11 @@ struct UserVec {
 // its waves are ready (the wave's own priority, not the queue's).
 __device__ __forceinline__ void tree_pass_priority() { __builtin_amdgcn_s_setprio(2); }
 
+// Workgroups of the near field while it runs beside the tree passes (each
+// walks every P2P_WG_DEFAULT-th leaf); twelve per CU measured best on the
+// clustered 1M-point product, the autotuner searches around it.
+constexpr int P2P_WG_DEFAULT = 3072;
+
 struct DevGemm {               // device copy of a GemmList
     DevBuf tasks, tbox, tab, src;
     std::vector<int32_t> level_task_begin;

@@ -147,34 +147,28 @@ __device__ __forceinline__ T lds_dot(const T *a, int ld, int k, const T *w, int 
 // With caller-order weights the kernels also store them in point order (us),
 // for the stages that read them there.
 constexpr int P2M_CHUNK = 64;      // points staged per round
+constexpr int P2M_PIPE_CH = 32;    // the same in the one-column kernel (occupancy)
+constexpr int P2M_PIPE_WG = 8192;  // its workgroups
 constexpr int LEAF_WG_MAX = 4096;  // workgroups of the leaf-by-leaf kernels (P2M, L2P)
 template <int P> constexpr int p2m_ld() { return (2 * (P + 1) + P / 2 + 1) | 1; }
 
 // The chunk's rows and the coefficient sums, shared by both P2M kernels.
+// A point's row holds the monomials conj(w)^m (re, im) for m <= P and the
+// weighted radial powers u |w|^(2e), e <= P/2; coefficient (n, m) of the
+// leaf is the sum over points of  conj(w)^m  times  u |w|^(n-m).  Over a
+// chunk this is one small matrix product on the matrix cores,
+//     C[w][e] = sum_j  row_j[w] row_j[EOFF + e]     (2(P+1) x points) x (points x (P/2+1)),
+// four points per 16x16x4 step, and coefficient (n, m) is C[2m (+1)][(n-m)/2].
 template <typename T, int P>
 struct P2MRows {
     static constexpr int K = (P + 1) * (P + 2) / 2;
     static constexpr int LD = p2m_ld<P>();
-    static constexpr int EOFF = 2 * (P + 1);      // row: conj(w)^m (re, im) for m <= P, then u |w|^(2e)
+    static constexpr int NW = 2 * (P + 1);        // monomial entries of a row
+    static constexpr int EOFF = NW;               // then u |w|^(2e)
     static constexpr int NE = P / 2 + 1;
-    static constexpr int NKL = (K + 63) / 64;
-    int wo[NKL], eo[NKL];                         // entries of coefficient lane + 64 i
-    __device__ __forceinline__ explicit P2MRows(int lane)
-    {
-#pragma unroll
-        for (int i = 0; i < NKL; ++i) {
-            const int k = min(lane + 64 * i, K - 1);
-            int n = 0;
-            while ((n + 1) * (n + 2) / 2 <= k) ++n;
-            // stored order: n ascending; for each n, m = n mod 2, n mod 2 + 2,
-            // ..., cosine then sine part for m > 0
-            const int o = k - n * (n + 1) / 2;
-            const int m = (n & 1) ? 2 * (o / 2) + 1 : 2 * ((o + 1) / 2);
-            const int re_o = m > 0 ? m - 1 : 0;
-            wo[i] = 2 * m + (o != re_o ? 1 : 0);
-            eo[i] = EOFF + (n - m) / 2;
-        }
-    }
+    static constexpr int NT = (NW + 15) / 16;     // 16-row tiles of C
+    static_assert(NE <= 16, "radial powers per column tile");
+    using acc_t = typename Mfma<T>::acc_t;
     // row of one point: w = (x, -y) / s, weight u
     __device__ __forceinline__ static void write(T *row, T wx, T wy, T u)
     {
@@ -195,20 +189,48 @@ struct P2MRows {
             q *= rr;
         }
     }
-    // acc[i] += sum over rows j < n of S[j][wo[i]] * S[j][eo[i]], four rows a step
-    __device__ __forceinline__ void sums(const T *S, int n, T *acc) const
+    __device__ __forceinline__ static void clear(acc_t (&acc)[NT])
     {
-        int j = 0;
-        for (; j + 4 <= n; j += 4) {
-            const T *a = S + j * LD;
 #pragma unroll
-            for (int i = 0; i < NKL; ++i)
-                acc[i] += (a[wo[i]] * a[eo[i]] + a[LD + wo[i]] * a[LD + eo[i]]) +
-                          (a[2 * LD + wo[i]] * a[2 * LD + eo[i]] + a[3 * LD + wo[i]] * a[3 * LD + eo[i]]);
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][v] = T(0);
+    }
+    // acc += C over the rows j < n of S (n a multiple of 4 at most the rows
+    // S holds, or less than that): lane l feeds row l%16 of
+    // each tile and radial power l%16 of point 4 s + l/16 in step s; rows
+    // past n and entries past the row's count enter as zeros
+    __device__ __forceinline__ static void sums(const T *S, int n, int lane, acc_t (&acc)[NT])
+    {
+        const int r16 = lane & 15, q = lane >> 4;
+        for (int j0 = 0; j0 < n; j0 += 4) {
+            const int j = j0 + q;                     // a row of S: j0 < n, j0 % 4 == 0
+            const T *row = S + j * LD;
+            const bool ok = j < n;
+            const T bv = row[EOFF + (r16 < NE ? r16 : 0)];
+            const T b = (ok && r16 < NE) ? bv : T(0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int w = 16 * t + r16;
+                const T av = row[w < NW ? w : 0];
+                acc[t] = Mfma<T>::mac((ok && w < NW) ? av : T(0), b, acc[t]);
+            }
         }
-        for (; j < n; ++j)
+    }
+    // M[k] for the coefficients this lane holds: C[w][e] with w = 2m + part,
+    // n = m + 2e, stored at n(n+1)/2 + max(m-1, 0) + part
+    __device__ __forceinline__ static void store(const acc_t (&acc)[NT], int lane, T *__restrict__ Mb)
+    {
+        const int e = lane & 15, q = lane >> 4;
 #pragma unroll
-            for (int i = 0; i < NKL; ++i) acc[i] += S[j * LD + wo[i]] * S[j * LD + eo[i]];
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int w = 16 * t + Mfma<T>::row(q, v);
+                const int m = w >> 1, part = w & 1, n = m + 2 * e;
+                if (w < NW && e < NE && n <= P && (m > 0 || part == 0))
+                    Mb[n * (n + 1) / 2 + (m > 0 ? m - 1 : 0) + part] = acc[t][v];
+            }
     }
 };
 
@@ -222,7 +244,9 @@ __device__ __forceinline__ T p2m_weight(const UserVec &io, const T *us, int64_t 
     else return T(static_cast<const float *>(io.in)[r * io.ldu + j]);
 }
 
-// One right-hand side, leaves of at most 64 points (one chunk).  recs: the
+// One right-hand side, leaves of at most 64 points (a lane per point; the
+// rows go through LDS P2M_PIPE_CH at a time, which keeps the LDS of a
+// workgroup small enough for many leaves in flight per CU).  recs: the
 // leaves; workgroup g takes leaves g, g + G, ... (G workgroups).  The point
 // and weight of the next leaf are requested before the current leaf is
 // worked on, and the point and caller-order index of the leaf after it one
@@ -235,12 +259,11 @@ __global__ __launch_bounds__(64) void k_p2m_pipe(DTree<T> t, const LeafRec *__re
 {
     tree_pass_priority();
     using R = P2MRows<T, P>;
-    __shared__ T S[P2M_CHUNK * R::LD];
+    __shared__ T S[P2M_PIPE_CH * R::LD];
     const int lane = threadIdx.x;
     const int G = gridDim.x;
     int li = blockIdx.x;
     if (li >= nrec) return;
-    const R rows(lane);
     struct Pa {                                      // point, caller-order index of its weight
         T x, y;
         int j;
@@ -268,19 +291,18 @@ __global__ __launch_bounds__(64) void k_p2m_pipe(DTree<T> t, const LeafRec *__re
         const Pa nna = stage_a(r2);
         const int n = lr.end - lr.begin;
         if (IN != 0 && lane < n) us[lr.begin + lane] = cur.u;
-        __syncthreads();                             // the previous leaf's rows are no longer read
-        if (lane < n) {
-            const T inv_s = pow2i<T>(lr.level);
-            R::write(S + lane * R::LD, cur.x * inv_s, -cur.y * inv_s, cur.u);
+        typename R::acc_t acc[R::NT];
+        R::clear(acc);
+        for (int c = 0; c < n; c += P2M_PIPE_CH) {
+            __syncthreads();                         // the previous rows are no longer read
+            if (lane >= c && lane < c + P2M_PIPE_CH && lane < n) {
+                const T inv_s = pow2i<T>(lr.level);
+                R::write(S + (lane - c) * R::LD, cur.x * inv_s, -cur.y * inv_s, cur.u);
+            }
+            __syncthreads();
+            R::sums(S, min(P2M_PIPE_CH, n - c), lane, acc);
         }
-        __syncthreads();
-        T acc[R::NKL];
-#pragma unroll
-        for (int i = 0; i < R::NKL; ++i) acc[i] = T(0);
-        rows.sums(S, n, acc);
-#pragma unroll
-        for (int i = 0; i < R::NKL; ++i)
-            if (lane + 64 * i < R::K) M[int64_t(lr.box) * t.KS + lane + 64 * i] = acc[i];
+        R::store(acc, lane, M + int64_t(lr.box) * t.KS);
         if (!more) break;
         li += G;
         lr = r1;
@@ -301,13 +323,11 @@ __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const LeafRec *__restric
     using R = P2MRows<T, P>;
     __shared__ T S[P2M_CHUNK * R::LD];
     const int lane = threadIdx.x;
-    const R rows(lane);
     const LeafRec lr = recs[blockIdx.x];
     const T inv_s = pow2i<T>(lr.level);
     for (int r = 0; r < nrhs; ++r) {
-        T acc[R::NKL];
-#pragma unroll
-        for (int i = 0; i < R::NKL; ++i) acc[i] = T(0);
+        typename R::acc_t acc[R::NT];
+        R::clear(acc);
         for (int c0 = lr.begin; c0 < lr.end; c0 += P2M_CHUNK) {
             const int n = min(P2M_CHUNK, lr.end - c0);
             const int ip = c0 + (lane < n ? lane : 0);
@@ -317,11 +337,9 @@ __global__ __launch_bounds__(64) void k_p2m(DTree<T> t, const LeafRec *__restric
             __syncthreads();
             if (lane < n) R::write(S + lane * R::LD, x * inv_s, -y * inv_s, u);
             __syncthreads();
-            rows.sums(S, n, acc);
+            R::sums(S, n, lane, acc);
         }
-#pragma unroll
-        for (int i = 0; i < R::NKL; ++i)
-            if (lane + 64 * i < R::K) M[(int64_t(lr.box) * nrhs + r) * t.KS + lane + 64 * i] = acc[i];
+        R::store(acc, lane, M + (int64_t(lr.box) * nrhs + r) * t.KS);
     }
 }
 
@@ -330,7 +348,7 @@ void launch_p2m_in(hipStream_t s, int nleaves, int max_leaf, const DTree<T> &v, 
                    int nrhs, T *M, const UserVec &uv)
 {
     if (nrhs == 1 && max_leaf <= P2M_CHUNK)
-        hipLaunchKernelGGL((k_p2m_pipe<T, P, IN>), dim3(unsigned(std::min(nleaves, LEAF_WG_MAX))), dim3(64), 0, s,
+        hipLaunchKernelGGL((k_p2m_pipe<T, P, IN>), dim3(unsigned(std::min(nleaves, P2M_PIPE_WG))), dim3(64), 0, s,
                            v, recs, nleaves, us, M, uv);
     else
         hipLaunchKernelGGL((k_p2m<T, P, IN>), dim3(unsigned(nleaves)), dim3(64), 0, s, v, recs, us, nrhs, M, uv);
@@ -1275,7 +1293,7 @@ imq_status fork_p2p(imq_tree_s *t, int nrhs, hipStream_t s)
     IMQ_HIP(hipEventRecord(t->ev_fork, s));
     IMQ_HIP(hipStreamWaitEvent(t->side[0], t->ev_fork, 0));
     const int nleaves = int(t->h.leaves.size());
-    const int wg = t->kcfg.p2p_wg > 0 ? t->kcfg.p2p_wg : 2048;
+    const int wg = t->kcfg.p2p_wg > 0 ? t->kcfg.p2p_wg : P2P_WG_DEFAULT;
     launch_p2p<T, true>(t->side[0], unsigned(std::min(nleaves, wg)), make_view<T>(t), nleaves, pd.us.as<T>(),
                         nrhs, t->bs.as<double>(), t->kcfg.p2p_mode == 1);
     IMQ_HIP(hipGetLastError());

@@ -31,7 +31,8 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
 
-constexpr int P2P_CHUNK = 256;                 // sources staged per round
+constexpr int P2P_CHUNK = 128;                 // sources staged per round (a small stage leaves LDS
+                                               // to the tree passes running alongside)
 constexpr int P2P_LDS = P2P_CHUNK + 64;        // + padding to a multiple of 4 per lane group
 constexpr int P2P_MF_LD = P2P_CHUNK + 16;      // row stride of the matrix-core stage (bank offset)
 
@@ -90,9 +91,9 @@ __device__ __forceinline__ int wave_max_scan(int v)
 }
 
 // The sources of a target leaf (U-list entries [u0, u1)), staged a chunk of
-// up to 256 at a time.  The entry records are read 64 at a time, one per
+// up to P2P_CHUNK at a time.  The entry records are read 64 at a time, one per
 // lane, and a wave prefix sum numbers the batch's sources consecutively.
-// Lane l gathers slots l, l + 64, l + 128, l + 192 of a chunk (each load of
+// Lane l gathers slots l, l + 64, ... of a chunk (each load of
 // the wave covers consecutive points), with every load of the chunk in flight
 // at once.  A slot's entry comes from marking each entry's first slot in LDS
 // and a running maximum over the slots (across the wave for each group of
@@ -123,7 +124,7 @@ __device__ __forceinline__ void p2p_sources(const DTree<T> &t, int u0, int u1, c
         int carry = 0;                               // 1 + entry of the slot before the group
         for (int c0 = 0; c0 < total; c0 += P2P_CHUNK) {
             const int n = min(P2P_CHUNK, total - c0);
-            *reinterpret_cast<int4 *>(&sh.mk[4 * lane]) = make_int4(0, 0, 0, 0);
+            if (4 * lane < P2P_CHUNK) *reinterpret_cast<int4 *>(&sh.mk[4 * lane]) = make_int4(0, 0, 0, 0);
             __syncthreads();
             if (ur.cnt > 0 && off >= c0 && off < c0 + P2P_CHUNK) sh.mk[off - c0] = lane + 1;
             __syncthreads();
