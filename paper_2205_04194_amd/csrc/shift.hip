@@ -26,8 +26,12 @@ namespace {
 // Workgroup = 4 waves; wave w owns quadrant w.  A tile is TC = 16*NCB columns
 // (parent box, right-hand side) times RBS row blocks of 16 output coefficients
 // (blockIdx.y picks the row blocks).  Packed table layout: element j of lane l of
-// (quadrant, row block rb, chunk ch) is T[16 rb + l%16][16 ch + 4 j + l/16],
-// so one load of four values per lane feeds four 16x16x4 steps.
+// (quadrant, row block rb, chunk ch) is T[16 rb + l%16][16 ch + 4 (l/16) + j],
+// so one load of four values per lane feeds four 16x16x4 steps, and the
+// source coefficients a lane feeds in them are four consecutive ones.
+// M2M: each wave reads its quadrant's children straight into registers (no
+// source is shared between waves), and the four partial results are summed
+// in LDS; L2L: the parents, which all four waves read, are staged in LDS.
 template <typename T, int NRB, int NCB, int RBS, bool UP>
 __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
                                                const int32_t *__restrict__ kids, int npar, int nrhs,
@@ -38,13 +42,13 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
     tree_pass_priority();
     constexpr int TC = 16 * NCB;
     constexpr int KPC = NRB * 16;
-    constexpr int LD = KPC + (sizeof(T) == 4 ? 2 : 1);     // LDS row stride
-    constexpr int NROW = (UP ? 4 : 1) * TC;                 // staged source columns
-    constexpr int NBT = NROW * KPC / 256;                   // staged values per thread
+    constexpr int LD = KPC + (sizeof(T) == 4 ? 2 : 1);     // LDS row stride of the staged parents
+    constexpr int RLD = RBS * 16 + 1;                       // row stride of the quadrant sums
+    constexpr int NBT = TC * KPC / 256;                     // staged values per thread
     constexpr int BATCH = sizeof(T) == 4 ? 32 : 16;
     using acc_t = typename Mfma<T>::acc_t;
     using Q = Quad<T>;
-    __shared__ T Bs[NROW * LD];
+    __shared__ T Bs[UP ? 4 * TC * RLD : TC * LD];
     __shared__ int s_ci[4][TC];     // column of the child in quadrant q (-1: none)
     __shared__ int s_pc[TC];        // column of the parent
 
@@ -69,7 +73,7 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
 
     // This workgroup's row blocks rb0 + [0, RBS): their whole table slice is
     // loaded into registers up front (it does not depend on the columns), so
-    // the matrix-core loop never waits on memory.
+    // the matrix-core loop never waits on memory for it.
     const int rb0 = blockIdx.y * RBS;
     const int nrb = min((kout + 15) >> 4, rb0 + RBS) - rb0;
     const int nchk = (kin + 15) >> 4;
@@ -88,51 +92,51 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
             if (ch >= lo[r] && ch < hi[r]) a[r][ch] = *reinterpret_cast<const Q *>(Aw + (r * NRB + ch) * 256);
     __syncthreads();
 
-    // stage the source expansions: row = (quadrant, column) or column, k fastest
-    constexpr int TPR = 256 / NROW;                         // threads per staged row
-    constexpr int FPT = KPC / TPR;                          // values per thread
-    if constexpr (sizeof(T) == 4 && 256 % NROW == 0 && FPT % 4 == 0) {
-        // one row per TPR threads, FPT/4 four-value loads each (one column
-        // lookup per thread instead of one per value)
-        const int row = tid / TPR, k0 = (tid % TPR) * FPT;
-        const int col = UP ? s_ci[row / TC][row % TC] : s_pc[row];
-        // every thread loads (a missing child reads column 0, coefficients
-        // past kin read coefficient 0; both are zeroed): no branch around the
-        // loads
-        const T *base = in + size_t(col >= 0 ? col : 0) * ldin;
-        Q v[FPT / 4];
+    if constexpr (!UP) {
+        // stage the parents: row = column, k fastest
+        constexpr int TPR = 256 / TC;                       // threads per staged row
+        constexpr int FPT = KPC / TPR;                      // values per thread
+        if constexpr (sizeof(T) == 4 && 256 % TC == 0 && FPT % 4 == 0) {
+            // one row per TPR threads, FPT/4 four-value loads each (a missing
+            // parent reads column 0, coefficients past kin read coefficient 0;
+            // both are zeroed): no branch around the loads
+            const int row = tid / TPR, k0 = (tid % TPR) * FPT;
+            const int col = s_pc[row];
+            const T *base = in + size_t(col >= 0 ? col : 0) * ldin;
+            Q v[FPT / 4];
 #pragma unroll
-        for (int j = 0; j < FPT / 4; ++j) {
-            const int k = k0 + 4 * j;
-            // k + 3 < ldin when k < kin: the stride is a multiple of 4 and covers kin
-            v[j] = *reinterpret_cast<const Q *>(base + (k < kin ? k : 0));
+            for (int j = 0; j < FPT / 4; ++j) {
+                const int k = k0 + 4 * j;
+                // k + 3 < ldin when k < kin: the stride is a multiple of 4 and covers kin
+                v[j] = *reinterpret_cast<const Q *>(base + (k < kin ? k : 0));
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (col < 0 || k + e >= kin) v[j].v[e] = T(0);
+                for (int e = 0; e < 4; ++e)
+                    if (col < 0 || k + e >= kin) v[j].v[e] = T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < FPT / 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Bs[row * LD + k0 + 4 * j + e] = v[j].v[e];
+        } else
+#pragma unroll
+        for (int j0 = 0; j0 < NBT; j0 += BATCH) {
+            T v[BATCH];
+#pragma unroll
+            for (int j = 0; j < BATCH; ++j)
+                if (j0 + j < NBT) {
+                    const int e = tid + 256 * (j0 + j);
+                    const int row = e / KPC, k = e - row * KPC;
+                    const int col = s_pc[row];
+                    v[j] = (col >= 0 && k < kin) ? in[size_t(col) * ldin + k] : T(0);
+                }
+#pragma unroll
+            for (int j = 0; j < BATCH; ++j)
+                if (j0 + j < NBT) {
+                    const int e = tid + 256 * (j0 + j);
+                    const int row = e / KPC, k = e - row * KPC;
+                    Bs[row * LD + k] = v[j];
+                }
         }
-#pragma unroll
-        for (int j = 0; j < FPT / 4; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) Bs[row * LD + k0 + 4 * j + e] = v[j].v[e];
-    } else
-#pragma unroll
-    for (int j0 = 0; j0 < NBT; j0 += BATCH) {
-        T v[BATCH];
-#pragma unroll
-        for (int j = 0; j < BATCH; ++j)
-            if (j0 + j < NBT) {
-                const int e = tid + 256 * (j0 + j);
-                const int row = e / KPC, k = e - row * KPC;
-                const int col = UP ? s_ci[row / TC][row % TC] : s_pc[row];
-                v[j] = (col >= 0 && k < kin) ? in[size_t(col) * ldin + k] : T(0);
-            }
-#pragma unroll
-        for (int j = 0; j < BATCH; ++j)
-            if (j0 + j < NBT) {
-                const int e = tid + 256 * (j0 + j);
-                const int row = e / KPC, k = e - row * KPC;
-                Bs[row * LD + k] = v[j];
-            }
     }
 
     // wave-uniform: does quadrant w have a child in this tile?
@@ -159,44 +163,47 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
                     }
         }
     }
-    __syncthreads();
 
-    if (on) {
-        const T *Bw = Bs + ((UP ? w * TC : 0) + i16) * LD + q;
+    if constexpr (UP) {
+        if (on) {
+            // the children of this quadrant, every chunk requested at once
+            // (a missing child reads column 0, coefficients past kin read
+            // coefficient 0; both are zeroed)
+            Q b[NRB][NCB];
 #pragma unroll
-        for (int ch = 0; ch < NRB; ++ch) {
-            bool use = false;
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int ci = s_ci[w][cb * 16 + i16];
+                const T *src = in + size_t(ci >= 0 ? ci : 0) * ldin;
 #pragma unroll
-            for (int r = 0; r < RBS; ++r) use |= ch >= lo[r] && ch < hi[r];
-            if (!use) continue;
-            T b[NCB][4];
+                for (int ch = 0; ch < NRB; ++ch) {
+                    const int k0 = 16 * ch + 4 * q;
+                    // k0 + 3 < ldin when k0 < kin: the stride is a multiple of 4 and covers kin
+                    b[ch][cb] = *reinterpret_cast<const Q *>(src + (k0 < kin ? k0 : 0));
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
+                    for (int e = 0; e < 4; ++e)
+                        if (ci < 0 || k0 + e >= kin) b[ch][cb].v[e] = T(0);
+                }
+            }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[cb][j] = Bw[cb * 16 * LD + ch * 16 + 4 * j];
+            for (int ch = 0; ch < NRB; ++ch)
 #pragma unroll
-            for (int r = 0; r < RBS; ++r)
-                if (ch >= lo[r] && ch < hi[r])
+                for (int r = 0; r < RBS; ++r)
+                    if (ch >= lo[r] && ch < hi[r])
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                        for (int j = 0; j < 4; ++j)
 #pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb)
-                            acc[r][cb] = Mfma<T>::mac(a[r][ch].v[j], b[cb][j], acc[r][cb]);
+                            for (int cb = 0; cb < NCB; ++cb)
+                                acc[r][cb] = Mfma<T>::mac(a[r][ch].v[j], b[ch][cb].v[j], acc[r][cb]);
         }
-    }
-
-    if (UP) {
         // sum the four quadrants' partial results in LDS (fixed order)
-        __syncthreads();
         T *red = Bs;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int rb = 0; rb < RBS; ++rb)
-                if (rb < nrb)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        red[(w * TC + cb * 16 + i16) * LD + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
+                for (int v = 0; v < 4; ++v)
+                    red[(w * TC + cb * 16 + i16) * RLD + rb * 16 + Mfma<T>::row(q, v)] = acc[rb][cb][v];
         __syncthreads();
         const int row0 = rb0 * 16, nrow = min(kout - row0, nrb * 16);
         constexpr int NR = RBS * 16;                         // rows of a tile: the index math is by a constant
@@ -204,22 +211,46 @@ __global__ __launch_bounds__(256) void k_shift(const int32_t *__restrict__ par,
             const int c = e / NR, k = e - c * NR;
             const int pc = s_pc[c];
             if (pc < 0 || k >= nrow) continue;
-            out[size_t(pc) * ldout + row0 + k] =
-                ((red[c * LD + k] + red[(TC + c) * LD + k]) + red[(2 * TC + c) * LD + k]) + red[(3 * TC + c) * LD + k];
+            out[size_t(pc) * ldout + row0 + k] = ((red[c * RLD + k] + red[(TC + c) * RLD + k]) +
+                                                  red[(2 * TC + c) * RLD + k]) + red[(3 * TC + c) * RLD + k];
         }
-    } else if (on) {
+    } else {
+        __syncthreads();
+        if (on) {
+            const T *Bw = Bs + i16 * LD + 4 * q;
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-            const int ci = s_ci[w][cb * 16 + i16];
-            if (ci < 0) continue;
+            for (int ch = 0; ch < NRB; ++ch) {
+                bool use = false;
 #pragma unroll
-            for (int rb = 0; rb < RBS; ++rb)
-                if (rb < nrb)
+                for (int r = 0; r < RBS; ++r) use |= ch >= lo[r] && ch < hi[r];
+                if (!use) continue;
+                T b[NCB][4];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = (rb0 + rb) * 16 + Mfma<T>::row(q, v);
-                        if (row < kout) out[size_t(ci) * ldout + row] = acc[rb][cb][v];
-                    }
+                for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) b[cb][j] = Bw[cb * 16 * LD + ch * 16 + j];
+#pragma unroll
+                for (int r = 0; r < RBS; ++r)
+                    if (ch >= lo[r] && ch < hi[r])
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int cb = 0; cb < NCB; ++cb)
+                                acc[r][cb] = Mfma<T>::mac(a[r][ch].v[j], b[cb][j], acc[r][cb]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int ci = s_ci[w][cb * 16 + i16];
+                if (ci < 0) continue;
+#pragma unroll
+                for (int rb = 0; rb < RBS; ++rb)
+                    if (rb < nrb)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = (rb0 + rb) * 16 + Mfma<T>::row(q, v);
+                            if (row < kout) out[size_t(ci) * ldout + row] = acc[rb][cb][v];
+                        }
+            }
         }
     }
 }
@@ -239,7 +270,7 @@ void pack_shift_tables(const std::vector<double> &tabs, int KP, std::vector<doub
             for (int ch = 0; ch < nrb; ++ch)
                 for (int l = 0; l < 64; ++l)
                     for (int j = 0; j < 4; ++j) {
-                        const double x = tabs[tb * PP + size_t(rb * 16 + l % 16) * KP + ch * 16 + 4 * j + l / 16];
+                        const double x = tabs[tb * PP + size_t(rb * 16 + l % 16) * KP + ch * 16 + 4 * (l / 16) + j];
                         packed[tb * PP + ((size_t(rb) * nrb + ch) * 64 + l) * 4 + j] = x;
                         if (x != 0.0) { lo = std::min(lo, ch); hi = std::max(hi, ch + 1); }
                     }
