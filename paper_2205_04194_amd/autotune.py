@@ -49,17 +49,24 @@ def _error(tree, u, rows, exact, prec):
     return float(torch.linalg.norm(b[..., rows] - exact) / torch.linalg.norm(exact))
 
 
-def _time(tree, u, prec, reps=5):
-    tree.matvec(u, prec)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
+def _time(tree, u, prec, reps=5, batches=2):
+    """ms per product: the fastest of `batches` event-timed runs of `reps`
+    back-to-back products, after two untimed ones (single runs differ by a
+    few percent, enough to pick the wrong one of two close candidates)."""
+    for _ in range(2):
         tree.matvec(u, prec)
-    e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    best = float("inf")
+    for _ in range(batches):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            tree.matvec(u, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / reps)
+    return best
 
 
 def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"),
@@ -162,7 +169,7 @@ def tune_tree(xy: torch.Tensor, c, u: torch.Tensor, leaf: int = 64, p: int = 12,
 
 
 def tune_leaf(xy: torch.Tensor, c, u: torch.Tensor, leaves=(32, 48, 64), p: int = 12, target: float = 1e-6,
-              precisions=("fp64",), seed: int = 1, reps: int = 10, **tree_kw):
+              precisions=("fp64",), seed: int = 1, reps: int = 20, **tree_kw):
     """:func:`tune_tree` for every leaf capacity in ``leaves``; the fastest
     tuned tree is returned (the others are freed) with its TuneResult and a
     list of per-leaf records (leaf, precision, orders, error, ms)."""
@@ -170,7 +177,7 @@ def tune_leaf(xy: torch.Tensor, c, u: torch.Tensor, leaves=(32, 48, 64), p: int 
     for leaf in leaves:
         tree, res = tune_tree(xy, c, u, leaf=leaf, p=p, target=target, precisions=precisions, seed=seed,
                               **tree_kw)
-        ms = _time(tree, u, res.precision, reps)
+        ms = _time(tree, u, res.precision, reps, batches=3)
         rec.append({"leaf": leaf, "precision": res.precision, "level_orders": res.level_orders,
                     "error": res.error, "ms": ms})
         if best is None or ms < best[2]:

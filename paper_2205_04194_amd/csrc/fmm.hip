@@ -1361,7 +1361,10 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
     // level is the widest.  Measured on the 1M mixture (product ms, alternating
     // runs on one GPU) by the number of shift levels queued before the fork:
     // 0: 0.289-0.296, 1: 0.292-0.295, 2: 0.297-0.298, 3: 0.304; with all
-    // eight queued first the product took 0.374 (an earlier kernel set).
+    // eight queued first the product took 0.374 (an earlier kernel set).  0
+    // and 1 are within the noise of these runs (and of a later FP64 repeat
+    // with raised tree-pass priority: 0.485-0.491 against 0.491-0.493 ms);
+    // later forks are measurably slower.
     constexpr int P2P_FORK_AFTER = 1;
     int nshift = 0;
     bool forked = !fork;
