@@ -431,12 +431,13 @@ def _stage_roofline(info, stages, prec, n, nrhs=1):
     return out
 
 
-def _traffic(kernel_key, workload, prec):
+def _traffic(kernel_key, workload, leaf, prec):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     record (profiles/traffic_records.md: FETCH_SIZE and WRITE_SIZE of the
     kernel, scaled by what the counters read for a plain copy of known size),
     used only while the kernel's source is the one the counters were taken
-    on (its SHA-256 prefix is part of the record); else None."""
+    on (its SHA-256 prefix is part of the record) and the workload and leaf
+    capacity are the record's; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_records.md")
     src = {"p2p": "p2p.hip", "m2l": "m2l.hip", "p2m": "fmm.hip", "l2p": "fmm.hip"}[kernel_key]
@@ -447,10 +448,10 @@ def _traffic(kernel_key, workload, prec):
     for line in open(path):
         parts = line.strip().strip("|").split("|") if line.startswith("|") else []
         parts = [p.strip() for p in parts]
-        if len(parts) >= 5 and parts[0] == kernel_key and parts[1] == workload and parts[2] == prec \
-                and parts[3] == sha:
+        if len(parts) >= 6 and parts[0] == kernel_key and parts[1] == workload and parts[2] == str(leaf) \
+                and parts[3] == prec and parts[4] == sha:
             try:
-                return float(parts[4])
+                return float(parts[5])
             except ValueError:
                 return None
     return None
@@ -552,7 +553,7 @@ def main():
     roofs = r.get("roofline")
     if roofs:
         for k, v in roofs.items():
-            v["traffic"] = _traffic(k, args.workload, "fp64")
+            v["traffic"] = _traffic(k, args.workload, r.get("leaf"), "fp64")
         # the parsed entry: the stage that takes longest of the near field and the translations
         top = max(("p2p", "m2l"), key=lambda k: roofs[k]["ms"])
         roof = {key: roofs[top][key] for key in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic")}

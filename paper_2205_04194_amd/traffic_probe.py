@@ -1,23 +1,25 @@
 """HBM traffic of the product's kernels from rocprofv3 counters.
 
-    run     one FP64 and one FP32 product of the 1M-point mixture with the
-            tuned level orders, stage by stage (each kernel alone on the
-            stream), then a device-to-device copy of 256 MiB: the calibration,
-            whose bytes are known
+    run [leaf]
+            one FP64 and one FP32 product of the 1M-point mixture with the
+            tuned level orders and leaf capacity `leaf` (default 48), stage by
+            stage (each kernel alone on the stream), then a device-to-device
+            copy of 256 MiB: the calibration, whose bytes are known
     stats   mean duration per (kernel, grid) from a rocprofv3 kernel trace
             (CSV), to read one configuration's launches apart from others
     counters  every counter of the dispatches of one kernel from a --pmc run
     report  from two rocprofv3 --pmc databases of `run` (FETCH_SIZE, then
-            WRITE_SIZE; KiB per dispatch), the bytes per launch of the
-            near-field, translation, P2M and L2P kernels, each counter scaled
-            by what it reads for the copy (2^28 bytes read, 2^28 written),
-            printed as the table rows the benchmark looks up (kernel,
-            workload, precision, SHA-256 prefix of the kernel's source, bytes)
+            WRITE_SIZE; KiB per dispatch) and the leaf capacity of the run, the
+            bytes per launch of the near-field, translation, P2M and L2P
+            kernels, each counter scaled by what it reads for the copy (2^28
+            bytes read, 2^28 written), printed as the table rows the benchmark
+            looks up (kernel, workload, leaf, precision, SHA-256 prefix of the
+            kernel's source, bytes)
 
 Usage (REPO = the repository root):
-    rocprofv3 --pmc FETCH_SIZE -d OUT1 -o run -- python3 REPO/paper_2205_04194_amd/traffic_probe.py run
-    rocprofv3 --pmc WRITE_SIZE -d OUT2 -o run -- python3 REPO/paper_2205_04194_amd/traffic_probe.py run
-    python3 REPO/paper_2205_04194_amd/traffic_probe.py report OUT1/.../run_results.db OUT2/.../run_results.db
+    rocprofv3 --pmc FETCH_SIZE -d OUT1 -o run -- python3 REPO/paper_2205_04194_amd/traffic_probe.py run 64
+    rocprofv3 --pmc WRITE_SIZE -d OUT2 -o run -- python3 REPO/paper_2205_04194_amd/traffic_probe.py run 64
+    python3 REPO/paper_2205_04194_amd/traffic_probe.py report OUT1/.../run_results.db OUT2/.../run_results.db 64
     python3 REPO/paper_2205_04194_amd/traffic_probe.py stats OUT/.../run_kernel_trace.csv
     python3 REPO/paper_2205_04194_amd/traffic_probe.py counters OUT/.../run_results.db 'k_p2p<double'
 """
@@ -44,14 +46,14 @@ KERNELS = {
 }
 
 
-def run() -> None:
+def run(leaf: int = LEAF) -> None:
     import torch
     sys.path.insert(0, ROOT)
     import workloads as W
     import paper_2205_04194_amd as imq
     d = W.mixture1m()
     dev = torch.device("cuda:0")
-    tree = imq.build_tree(torch.tensor(d["xy"], device=dev), d["c"], leaf=LEAF, p=max(ORDERS))
+    tree = imq.build_tree(torch.tensor(d["xy"], device=dev), d["c"], leaf=leaf, p=max(ORDERS))
     tree.set_level_orders(ORDERS[:tree.info()["nlevels"]])
     tree.set_stage_timing(True)                 # every stage alone, in order, on one stream
     for prec in ("fp64", "fp32"):
@@ -78,7 +80,7 @@ def _dispatches(db: str, counter: str):
     return [tuple(v) for _, v in sorted(out.items())]
 
 
-def report(db_fetch: str, db_write: str) -> None:
+def report(db_fetch: str, db_write: str, leaf: int = LEAF) -> None:
     f = _dispatches(db_fetch, "FETCH_SIZE")
     w = _dispatches(db_write, "WRITE_SIZE")
     # the calibration copy: the last dispatch of each run
@@ -96,7 +98,7 @@ def report(db_fetch: str, db_write: str) -> None:
             nb = (sum(fb) * sf + sum(wb) * sw) * 1024.0     # bytes of the product's launches
             with open(os.path.join(HERE, "csrc", srcf), "rb") as fh:
                 sha = hashlib.sha256(fh.read()).hexdigest()[:16]
-            print(f"| {key} | mixture1m | {prec} | {sha} | {nb:.4g} |   ({len(fb)} launches: "
+            print(f"| {key} | mixture1m | {leaf} | {prec} | {sha} | {nb:.4g} |   ({len(fb)} launches: "
                   f"fetch {sum(fb) * sf / 1024:.1f} MiB, write {sum(wb) * sw / 1024:.1f} MiB)")
 
 
@@ -140,10 +142,10 @@ def counters(db: str, pattern: str) -> None:
 
 
 if __name__ == "__main__":
-    if len(sys.argv) >= 2 and sys.argv[1] == "run":
-        run()
-    elif len(sys.argv) == 4 and sys.argv[1] == "report":
-        report(sys.argv[2], sys.argv[3])
+    if len(sys.argv) in (2, 3) and sys.argv[1] == "run":
+        run(int(sys.argv[2]) if len(sys.argv) == 3 else LEAF)
+    elif len(sys.argv) in (4, 5) and sys.argv[1] == "report":
+        report(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) == 5 else LEAF)
     elif len(sys.argv) == 3 and sys.argv[1] == "stats":
         stats(sys.argv[2])
     elif len(sys.argv) == 4 and sys.argv[1] == "counters":
