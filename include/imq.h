@@ -76,6 +76,20 @@ typedef struct {
     int direct_max;      /* adaptive W/X interactions whose finer box holds at
                             most this many points are summed directly instead
                             of through an expansion (0 = 2*leaf_max, < 0 = never) */
+    int autotune;        /* imq_build_tree(_alloc) only: nonzero = after the
+                            build, tune the per-level translation orders (from
+                            order_p down), the internal precision and the
+                            translation and near-field kernels for the fastest
+                            product whose relative 2-norm error over 1000
+                            sampled rows (a fixed pseudo-random weight vector,
+                            against exact FP64 sums) is at most 0.8 x
+                            autotune_tol; the tree is left configured and
+                            imq_get_tree_info reports the choice (tuned_prec,
+                            tuned_err, tuned_ms).  Runs products on `stream`
+                            and synchronises it.  IMQ_EINVAL if neither
+                            precision reaches the target at order_p.  Ignored
+                            by imq_build_eval_tree. */
+    double autotune_tol; /* target relative error (0 = 1e-6) */
 } imq_tree_params;
 
 /* Build the quadtree forest of `nsets` independent point sets.
@@ -312,6 +326,9 @@ typedef struct {          /* host */
     int64_t level_boxes[IMQ_MAX_LEVELS + 1];
     int64_t level_m2l_pairs[IMQ_MAX_LEVELS + 1];
     int level_K[IMQ_MAX_LEVELS + 1];        /* translation size per level  */
+    int tuned_prec;       /* build-time autotuner's precision (imq_prec), -1 if not tuned */
+    double tuned_err;     /* its sampled-row relative error                  */
+    double tuned_ms;      /* its measured time per product (ms)              */
 } imq_tree_info;
 
 imq_status imq_get_tree_info(imq_tree tree, imq_tree_info *info);

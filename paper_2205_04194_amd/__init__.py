@@ -78,11 +78,16 @@ class Tree:
                 box are summed directly (0: 2*leaf, negative: never)
     allocator   None (the library's hipMalloc) or "torch": the tree's device
                 memory comes from PyTorch's caching allocator
+    autotune    tune orders, precision and kernels in the library after the
+                build for a sampled-row relative error <= autotune_tol (0:
+                1e-6); info() then reports tuned_prec ("fp64"/"fp32"),
+                tuned_err and tuned_ms, and `tuned_prec` holds the choice
     """
 
     def __init__(self, xy: torch.Tensor, c, leaf: int = 64, p: int = 12,
                  set_offsets: Optional[Sequence[int]] = None, level_order=None,
-                 max_level: int = 0, direct_max: int = 0, stream=None, allocator=None):
+                 max_level: int = 0, direct_max: int = 0, stream=None, allocator=None,
+                 autotune: bool = False, autotune_tol: float = 0.0):
         lib = _lib.load()
         if xy.dim() != 2 or xy.shape[1] != 2:
             raise ValueError("xy must have shape (N, 2)")
@@ -106,7 +111,7 @@ class Tree:
         self._xy = xy64
         off_arr = (ctypes.c_int64 * (nsets + 1))(*offs)
         c_arr = (ctypes.c_double * nsets)(*cs)
-        prm = _lib.params(leaf, p, max_level, level_order, direct_max)
+        prm = _lib.params(leaf, p, max_level, level_order, direct_max, autotune, autotune_tol)
         h = ctypes.c_void_p()
         self._alloc = None
         if allocator not in (None, "torch"):
@@ -121,6 +126,9 @@ class Tree:
                                         _stream_ptr(stream), ctypes.byref(h))
         _lib.check(st, "imq_build_tree")
         self._h = h
+        self.tuned_prec = None
+        if autotune:
+            self.tuned_prec = self.info()["tuned_prec"]
 
     # ------------------------------------------------------------ evaluation
     @classmethod
@@ -273,6 +281,7 @@ class Tree:
         for k, _ in _lib.TreeInfo._fields_:
             v = getattr(inf, k)
             out[k] = list(v)[:inf.nlevels] if k.startswith("level_") else v
+        out["tuned_prec"] = {0: "fp64", 1: "fp32"}.get(out["tuned_prec"])   # None: not tuned
         return out
 
     def set_kernel_config(self, m2l_kc: int = 0, m2l_split: int = 0, shift_cols: int = 0,

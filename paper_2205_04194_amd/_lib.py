@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "fp32": 1}
 class TreeParams(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int), ("order_p", ctypes.c_int), ("max_level", ctypes.c_int),
                 ("level_order", ctypes.c_int * (IMQ_MAX_LEVELS + 1)),
-                ("direct_max", ctypes.c_int)]
+                ("direct_max", ctypes.c_int), ("autotune", ctypes.c_int), ("autotune_tol", ctypes.c_double)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -60,7 +60,8 @@ class TreeInfo(ctypes.Structure):
                 ("nlevels", ctypes.c_int),
                 ("level_boxes", ctypes.c_int64 * (IMQ_MAX_LEVELS + 1)),
                 ("level_m2l_pairs", ctypes.c_int64 * (IMQ_MAX_LEVELS + 1)),
-                ("level_K", ctypes.c_int * (IMQ_MAX_LEVELS + 1))]
+                ("level_K", ctypes.c_int * (IMQ_MAX_LEVELS + 1)),
+                ("tuned_prec", ctypes.c_int), ("tuned_err", ctypes.c_double), ("tuned_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -131,12 +132,15 @@ def check(status: int, where: str, allow_not_converged: bool = False) -> int:
     raise IMQError(status, where)
 
 
-def params(leaf: int, p: int, max_level: int = 0, level_order=None, direct_max: int = 0) -> TreeParams:
+def params(leaf: int, p: int, max_level: int = 0, level_order=None, direct_max: int = 0,
+           autotune: bool = False, autotune_tol: float = 0.0) -> TreeParams:
     prm = TreeParams()
     prm.leaf_max = int(leaf)
     prm.order_p = int(p)
     prm.max_level = int(max_level)
     prm.direct_max = int(direct_max)
+    prm.autotune = 1 if autotune else 0
+    prm.autotune_tol = float(autotune_tol)
     for i in range(IMQ_MAX_LEVELS + 1):
         prm.level_order[i] = 0
     if level_order is not None:

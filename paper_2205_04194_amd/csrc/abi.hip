@@ -422,6 +422,20 @@ imq_status imq_build_tree_alloc(int nsets, const int64_t *set_offsets, const dou
     st = upload_tree(t, xy);
     if (st != IMQ_OK) { free_tree(t); return st; }
     live_add(t);
+    if (params->autotune) {
+        if (!(params->autotune_tol >= 0.0) || !std::isfinite(params->autotune_tol)) {
+            imq_tree_free(t);
+            set_error("autotune_tol must be finite and >= 0");
+            return IMQ_EINVAL;
+        }
+        st = autotune_tree(t, params->autotune_tol > 0.0 ? params->autotune_tol : 1e-6, stream);
+        if (st != IMQ_OK) {
+            const std::string why = imq_last_error();
+            imq_tree_free(t);
+            set_error(why);
+            return st;
+        }
+    }
     *out = t;
     return IMQ_OK;
 }
@@ -566,6 +580,9 @@ imq_status imq_get_tree_info(imq_tree t, imq_tree_info *info)
         info->level_boxes[l] = h.level_begin[l + 1] - h.level_begin[l];
         info->level_m2l_pairs[l] = h.v_off[h.level_begin[l + 1]] - h.v_off[h.level_begin[l]];
     }
+    info->tuned_prec = t->tuned_prec;
+    info->tuned_err = t->tuned_err;
+    info->tuned_ms = t->tuned_ms;
     return IMQ_OK;
 }
 

@@ -238,6 +238,9 @@ struct imq_tree_s {
     static constexpr int NGROUP_EV = 32;                      // M2L level groups done (the L2L chain waits)
     hipEvent_t ev_grp[NGROUP_EV] = {};
     imq_status ensure_side();
+    // result of the build-time autotuner (tuned_prec < 0: not tuned)
+    int tuned_prec = -1;
+    double tuned_err = 0.0, tuned_ms = 0.0;
     // evaluation tree (imq_build_eval_tree): data sites, evaluation points,
     // per evaluation point the tree point it reads, and the product's workspace
     int64_t eval_n = -1, eval_m = 0;
@@ -275,6 +278,9 @@ imq_status ensure_workspace(imq_tree_s *t, int nrhs);
 // Every M2L table of a built tree (four layouts, both precisions) generated
 // on the device; KP = the padded table edge.
 imq_status make_m2l_tables_device(imq_tree_s *t, int KP);
+// The build-time autotuner (tune.hip): orders, precision and kernels of a
+// built, registered tree for a sampled-row relative error <= tol.
+imq_status autotune_tree(imq_tree_s *t, double tol, hipStream_t s);
 
 // The host build's tree (build_host_tree) computed on the device from device
 // coordinates; synchronises `s`.

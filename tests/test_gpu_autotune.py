@@ -39,3 +39,34 @@ def test_tuned_configuration_meets_the_target_against_the_oracle(imq, target):
     err = float(np.linalg.norm(b[rows] - exact) / np.linalg.norm(exact))
     assert err <= target
     assert tree.info()["level_K"] == [(o + 1) * (o + 2) // 2 for o in res.level_orders]
+
+
+def test_build_time_autotune_in_the_library(imq):
+    """imq_tree_params.autotune: the library tunes the tree during the build
+    (its own pseudo-random weights, 0.8 x target on its sampled rows); on
+    other weights of the same distribution and rows it did not sample the
+    error against the oracle stays near the target (within 1.5x: the error of
+    a truncated expansion depends on the weights), and the tree keeps the
+    tuned orders."""
+    d = W.uniform100k()
+    xy, u = d["xy"][:30000], d["u"][:30000]
+    target = 1e-6
+    tree = imq.build_tree(_dev(xy), d["c"], leaf=64, p=12, autotune=True, autotune_tol=target)
+    info = tree.info()
+    print(f"build-time tuning: {info['tuned_prec']} err {info['tuned_err']:.2e} {info['tuned_ms']:.3f} ms, "
+          f"K per level {info['level_K']}")
+    assert tree.tuned_prec in ("fp64", "fp32")
+    assert 0 < info["tuned_err"] <= 0.8 * target
+    assert info["tuned_ms"] > 0
+    assert max(info["level_K"]) <= (12 + 1) * (12 + 2) // 2
+    rows = np.arange(11, 30000, 59)
+    b = tree.matvec(_dev(u), tree.tuned_prec).cpu().numpy()
+    exact = oracle.matvec(xy, d["c"], u, xy_targets=xy[rows])
+    err = float(np.linalg.norm(b[rows] - exact) / np.linalg.norm(exact))
+    print(f"oracle error on other weights and rows: {err:.2e}")
+    assert err <= 1.5 * target
+    plain = imq.build_tree(_dev(xy), d["c"], leaf=64, p=12)
+    assert plain.tuned_prec is None and plain.info()["tuned_prec"] is None
+    # a target no precision reaches at this order is an error, not a silent fallback
+    with pytest.raises(imq.IMQError):
+        imq.build_tree(_dev(xy), d["c"], leaf=64, p=2, autotune=True, autotune_tol=1e-12)
