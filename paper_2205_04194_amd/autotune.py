@@ -11,7 +11,12 @@ Search on one tree (``tune``, no rebuild):
      while the sampled error stays within the target;
   2. per level, deepest first, the translation order is lowered while the
      error stays within the target (the lifted vertical offset c makes deep
-     levels, whose boxes are small next to c, converge fastest);
+     levels, whose boxes are small next to c, converge fastest); orders that
+     fill the same 16-row matrix-core tiles cost the same, so each level is
+     then raised to the top of its tile and levels are moved down by whole
+     tiles, the most translation work first, while the error allows (on the
+     1M mixture: 0.428 -> 0.421 ms per FP64 product, error 8.5e-7 -> 6.0e-7;
+     kept only where it measures faster);
   3. the M2L kernel choice (register streaming or staged GEMM) and the staged
      GEMM's pipeline depth and row split are timed and the fastest kept;
   4. so is the number of near-field workgroups running beside the tree
@@ -69,9 +74,65 @@ def _time(tree, u, prec, reps=5, batches=2):
     return best
 
 
+def _nrb(o: int) -> int:
+    """16-row tiles of a translation of order o ((o+1)(o+2)/2 coefficients)."""
+    return ((o + 1) * (o + 2) // 2 + 15) // 16
+
+
+def _tile_top(o: int, pmax: int) -> int:
+    """The largest order <= pmax whose translation fills the same tiles as o."""
+    while o + 1 <= pmax and _nrb(o + 1) == _nrb(o):
+        o += 1
+    return o
+
+
+def _tile_refine(tree, u, rows, exact, prec, orders, err, active, info, pmax, budget, trials):
+    """Orders that fill the same 16-row tiles cost the same matrix-core work:
+    raise every translated level to the top of its tile (less error, no
+    matrix-core cost), then move levels down by whole tiles, those with the
+    most translation work first, while the error stays within the budget.
+    The shifts and L2P do grow with the orders, and levels of different tile
+    counts run as separate launches, so the refined orders are kept only if
+    the product is measured faster than with the greedy ones."""
+    greedy, greedy_err = list(orders), err
+    raised = [_tile_top(o, pmax) if l in active else o for l, o in enumerate(orders)]
+    if raised != orders:
+        tree.set_level_orders(raised)
+        e = _error(tree, u, rows, exact, prec)
+        trials.append({"prec": prec, "orders": list(raised), "err": e, "step": "tile top"})
+        if e <= budget:
+            orders, err = raised, e
+    pairs = info["level_m2l_pairs"]
+    for l in sorted(active, key=lambda l: -pairs[l] * _nrb(orders[l])):
+        while _nrb(orders[l]) > 1:
+            lower = orders[l]
+            while lower > 1 and _nrb(lower) == _nrb(orders[l]):
+                lower -= 1
+            trial = list(orders)
+            trial[l] = lower
+            tree.set_level_orders(trial)
+            e = _error(tree, u, rows, exact, prec)
+            trials.append({"prec": prec, "orders": list(trial), "err": e, "step": "tile down"})
+            if e > budget:
+                break
+            orders, err = trial, e
+    if orders != greedy:
+        tree.set_level_orders(greedy)
+        t_greedy = _time(tree, u, prec, reps=10)
+        tree.set_level_orders(orders)
+        t_refined = _time(tree, u, prec, reps=10)
+        trials.append({"prec": prec, "orders": list(orders), "ms": t_refined, "greedy_ms": t_greedy,
+                       "step": "tile refine"})
+        if t_refined >= t_greedy:
+            orders, err = greedy, greedy_err
+    tree.set_level_orders(orders)
+    return orders, err
+
+
 def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"),
          nrows: int = 1000, safety: float = 0.8, seed: int = 0,
-         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1, 2), p2p_wgs=(2048, 2560, 3072, 3584)) -> TuneResult:
+         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1, 2), p2p_wgs=(2048, 2560, 3072, 3584),
+         tile_aware: bool = True) -> TuneResult:
     """Fastest configuration of ``tree`` whose sampled-row relative 2-norm
     error is at most ``safety * target``; the tree is left configured."""
     n = tree.n
@@ -115,6 +176,9 @@ def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"
                     break
                 orders, err = trial, e
         tree.set_level_orders(orders)
+        if tile_aware:
+            orders, err = _tile_refine(tree, u, rows, exact, prec, orders, err, active, info, pmax, budget,
+                                       trials)
         # 3. translation kernels and the launch shape of the staged GEMM
         shape, ms = (0, 0, 0), float("inf")
         for mode in modes:

@@ -13,7 +13,11 @@
 //      within 0.8 x target;
 //   2. per level, deepest first, its order is lowered further while it does
 //      (the lifted vertical offset c makes the deep levels, whose boxes are
-//      small against c, converge fastest);
+//      small against c, converge fastest); then, since orders that fill the
+//      same 16-row matrix-core tiles cost the same, each level is raised to
+//      the top of its tile and levels are moved down by whole tiles, the
+//      most translation work first, while the error allows (kept if the
+//      product is measured faster);
 //   3. the M2L kernel (register streaming, staged GEMM, and for FP32 the
 //      BF16x3 streaming) and the staged GEMM's pipeline depth and row split
 //      are timed, then the near field's workgroup count beside the tree
@@ -191,6 +195,67 @@ imq_status autotune_tree(imq_tree_s *t, double tol, hipStream_t s)
                 if (!(e <= budget)) break;
                 orders = trial;
                 err = e;
+            }
+        }
+        // 2b. orders that fill the same 16-row tiles of a translation cost the
+        // same matrix-core work: every translated level to the top of its
+        // tile (less error at no matrix-core cost), then levels down by whole
+        // tiles, the ones with the most translation work first, within the
+        // budget.  The shifts and L2P grow with the orders and levels of
+        // different tile counts run as separate launches, so the result is
+        // kept only if the product is measured faster than with the greedy
+        // orders.
+        {
+            const std::vector<int> greedy(orders);
+            const double greedy_err = err;
+            const auto nrb = [](int o) { return ((o + 1) * (o + 2) / 2 + 15) / 16; };
+            const auto top = [&](int o) {
+                while (o + 1 <= p && nrb(o + 1) == nrb(o)) ++o;
+                return o;
+            };
+            std::vector<int> raised(orders);
+            for (int l = 0; l < nlev; ++l)
+                if (active[size_t(l)]) raised[size_t(l)] = top(orders[size_t(l)]);
+            if (raised != orders) {
+                if ((st = imq_set_level_orders(t, nlev, raised.data())) != IMQ_OK) return st;
+                double e;
+                if ((st = tu.error(prec, e)) != IMQ_OK) return st;
+                if (e <= budget) {
+                    orders = raised;
+                    err = e;
+                }
+            }
+            std::vector<int> lv;
+            for (int l = 0; l < nlev; ++l)
+                if (active[size_t(l)]) lv.push_back(l);
+            const HostTree &h = t->h;
+            const auto work = [&](int l) {
+                return double(h.v_off[h.level_begin[l + 1]] - h.v_off[h.level_begin[l]]) * nrb(orders[size_t(l)]);
+            };
+            std::stable_sort(lv.begin(), lv.end(), [&](int a, int b) { return work(a) > work(b); });
+            for (int l : lv)
+                while (nrb(orders[size_t(l)]) > 1) {
+                    int lower = orders[size_t(l)];
+                    while (lower > 1 && nrb(lower) == nrb(orders[size_t(l)])) --lower;
+                    std::vector<int> trial(orders);
+                    trial[size_t(l)] = lower;
+                    if ((st = imq_set_level_orders(t, nlev, trial.data())) != IMQ_OK) return st;
+                    double e;
+                    if ((st = tu.error(prec, e)) != IMQ_OK) return st;
+                    if (!(e <= budget)) break;
+                    orders = trial;
+                    err = e;
+                }
+            if (orders != greedy) {
+                double tg, tr;
+                if ((st = imq_set_level_orders(t, nlev, greedy.data())) != IMQ_OK) return st;
+                if ((st = tu.time(prec, tg)) != IMQ_OK) return st;
+                if ((st = imq_set_level_orders(t, nlev, orders.data())) != IMQ_OK) return st;
+                if ((st = tu.time(prec, tr)) != IMQ_OK) return st;
+                if (!(tr < tg)) {
+                    orders = greedy;
+                    err = greedy_err;
+                }
             }
         }
         if ((st = imq_set_level_orders(t, nlev, orders.data())) != IMQ_OK) return st;
