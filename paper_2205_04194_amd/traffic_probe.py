@@ -34,7 +34,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 COPY_BYTES = 1 << 28
-ORDERS = [11, 11, 11, 11, 11, 10, 9, 7, 5, 3, 3]   # the tuned FP64 orders of the benchmark
+ORDERS = [11, 11, 11, 11, 11, 11, 8, 6, 6, 4, 4]   # the tuned FP64 orders of the benchmark
 LEAF = 48
 
 # kernel key -> (name pattern of the stage-timed launch, source file)
