@@ -276,7 +276,11 @@ imq_status imq_matvec_backward(imq_tree tree, int nrhs, imq_dtype dtype, const v
  *               with the FP32 products of the streamed levels taken on the
  *               BF16 matrix cores: each operand split into three BF16 parts
  *               (24 significant bits in all), six part products summed in
- *               FP32 (the FP64 product runs as 0).
+ *               FP32 (the FP64 product runs as 0); 3 = operands streamed
+ *               through registers at every level up to 160 coefficients (p
+ *               <= 16; one output row block per workgroup above 80), which
+ *               the wide expansions of high orders favour on some trees and
+ *               not on others (the autotuner times it).
  *               m2l_kc and m2l_split apply to the staged GEMM only.
  *  p2p_wg     : workgroups of the near-field kernel while it runs alongside
  *               the tree passes (each takes every p2p_wg-th leaf); 0 = 3072

@@ -131,7 +131,7 @@ def _tile_refine(tree, u, rows, exact, prec, orders, err, active, info, pmax, bu
 
 def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"),
          nrows: int = 1000, safety: float = 0.8, seed: int = 0,
-         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1, 2), p2p_wgs=(2048, 2560, 3072, 3584),
+         kcs=(16, 32, 64), splits=(1, 2), modes=(0, 1, 2, 3), p2p_wgs=(2048, 2560, 3072, 3584),
          tile_aware: bool = True) -> TuneResult:
     """Fastest configuration of ``tree`` whose sampled-row relative 2-norm
     error is at most ``safety * target``; the tree is left configured."""
@@ -181,13 +181,16 @@ def tune(tree, u: torch.Tensor, target: float = 1e-6, precisions=("fp32", "fp64"
                                        trials)
         # 3. translation kernels and the launch shape of the staged GEMM
         shape, ms = (0, 0, 0), float("inf")
+        wide = max(orders) >= 12                   # translations above 80 coefficients
         for mode in modes:
             if prec == "fp64" and mode == 2:       # the BF16 form serves FP32 only
                 continue
-            for kc in kcs:
+            if mode == 3 and not wide:             # the same kernels as mode 0
+                continue
+            for kc in (kcs if mode != 3 else kcs[:1]):   # mode 3 has no staged GEMM
                 if prec == "fp64" and kc > 32:
                     continue
-                for sp in splits:
+                for sp in (splits if mode != 3 else splits[:1]):
                     tree.set_kernel_config(m2l_kc=kc, m2l_split=sp, m2l_mode=mode)
                     t = _time(tree, u, prec)
                     trials.append({"prec": prec, "m2l_mode": mode, "m2l_kc": kc, "m2l_split": sp, "ms": t})

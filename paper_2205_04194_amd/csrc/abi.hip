@@ -594,7 +594,7 @@ imq_status imq_set_kernel_config(imq_tree t, const imq_kernel_config *cfg)
     auto ok_kc = [](int v) { return v == 0 || v == 16 || v == 32 || v == 64; };
     if (!ok_kc(cfg->m2l_kc) || cfg->m2l_split < 0 || cfg->m2l_split > 10 ||
         (cfg->shift_cols != 0 && cfg->shift_cols != 16 && cfg->shift_cols != 32) ||
-        cfg->m2l_mode < 0 || cfg->m2l_mode > 2 || cfg->p2p_wg < 0 || cfg->p2p_mode < 0 || cfg->p2p_mode > 1 ||
+        cfg->m2l_mode < 0 || cfg->m2l_mode > 3 || cfg->p2p_wg < 0 || cfg->p2p_mode < 0 || cfg->p2p_mode > 1 ||
         cfg->far_field < 0 || cfg->far_field > 1) {
         set_error("kernel config out of range");
         return IMQ_EINVAL;

@@ -1448,7 +1448,8 @@ imq_status fmm_translate(imq_tree_s *t, int nrhs, hipStream_t s, bool overlap)
     std::vector<int> group_of(h.nlev, -1);
     {
         const DevGemm &g = t->g_m2l;
-        const int smax = 5;
+        // streamed up to 80 coefficients (modes 0, 2) or 160 (mode 3)
+        const int smax = kc.m2l_mode == 3 ? 10 : 5;
         const auto kind = [&](int l) {
             const int nrb = (h.Klev[l] + 15) / 16;
             return (kc.m2l_mode != 1 && nrb <= smax) ? nrb : 0;

@@ -321,6 +321,14 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
         }                                                                                                  \
         IMQ_M2LS_BF(NRB, NCB, NW, false);                                                                  \
     } while (0)
+    // 96 to 160 coefficients (m2l_mode 3): one row block per workgroup, the
+    // FP32 and FP64 products on their own matrix cores
+#define IMQ_M2LS_ROW(NRB)                                                                                  \
+    case NRB:                                                                                              \
+        hipLaunchKernelGGL((k_m2l_stream<T, NRB, 1, 4, 1>),                                                \
+                           dim3((ntask + 7) & ~7, unsigned((GEMM_TILE * nrhs + 15) / 16), NRB), dim3(256), 0, s, \
+                           tasks, task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc, ntask); \
+        return true;
     if constexpr (sizeof(T) == 4) {
         switch (nrb) {
         case 1: IMQ_M2LS(1, 1, 4); return true;
@@ -328,6 +336,7 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
         case 3: IMQ_M2LS(3, 1, 4); return true;
         case 4: IMQ_M2LS(4, 1, 4); return true;
         case 5: IMQ_M2LS(5, 1, 4); return true;
+        IMQ_M2LS_ROW(6) IMQ_M2LS_ROW(7) IMQ_M2LS_ROW(8) IMQ_M2LS_ROW(9) IMQ_M2LS_ROW(10)
         default: return false;
         }
     } else {
@@ -341,9 +350,11 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
                                dim3((ntask + 7) & ~7, unsigned((GEMM_TILE * nrhs + 15) / 16), 5), dim3(256), 0, s, tasks,
                                task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc, ntask);
             return true;
+        IMQ_M2LS_ROW(6) IMQ_M2LS_ROW(7) IMQ_M2LS_ROW(8) IMQ_M2LS_ROW(9) IMQ_M2LS_ROW(10)
         default: return false;
         }
     }
+#undef IMQ_M2LS_ROW
 #undef IMQ_M2LS
 #undef IMQ_M2LS_BF
 }

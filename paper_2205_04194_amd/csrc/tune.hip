@@ -262,11 +262,15 @@ imq_status autotune_tree(imq_tree_s *t, double tol, hipStream_t s)
         // 3. kernels and launch shapes
         imq_kernel_config bk{};
         double bms = 1e30;
-        for (int mode : {0, 1, 2}) {
+        const bool wide = *std::max_element(orders.begin(), orders.end()) >= 12;   // above 80 coefficients
+        for (int mode : {0, 1, 2, 3}) {
             if (prec == IMQ_PREC_FP64 && mode == 2) continue;      // the BF16 parts serve FP32 only
+            if (mode == 3 && !wide) continue;                      // the same kernels as mode 0
             for (int kcv : {16, 32, 64}) {
                 if (prec == IMQ_PREC_FP64 && kcv > 32) continue;
+                if (mode == 3 && kcv != 16) continue;              // mode 3 has no staged GEMM
                 for (int sp : {1, 2}) {
+                    if (mode == 3 && sp != 1) continue;
                     imq_kernel_config c{};
                     c.m2l_mode = mode;
                     c.m2l_kc = kcv;

@@ -132,7 +132,7 @@ def test_invalid_arguments_raise(imq):
         tree.matvec(_dev(np.zeros(11)))
 
 
-@pytest.mark.parametrize("p", [3, 4, 6, 9, 12])
+@pytest.mark.parametrize("p", [3, 4, 6, 9, 12, 16])
 def test_translation_kernels_agree_and_match_the_oracle(imq, p):
     """The M2L kernels (operands streamed through registers, staged GEMM, and
     the streamed FP32 products on the BF16 matrix cores from three-part
@@ -144,18 +144,19 @@ def test_translation_kernels_agree_and_match_the_oracle(imq, p):
     tree = imq.build_tree(_dev(d["xy"]), d["c"], leaf=16, p=p)
     ref = oracle.matvec(d["xy"], d["c"], U)
     out = {}
-    for mode in (0, 1, 2):
+    for mode in (0, 1, 2, 3):
         tree.set_kernel_config(m2l_mode=mode)
         out[mode, "fp64"] = tree.matvec(_dev(U), "fp64").cpu().numpy()
         out[mode, "fp32"] = tree.matvec(_dev(U), "fp32").cpu().numpy()
     for r in range(3):
         assert _rel(out[0, "fp64"][r], out[1, "fp64"][r]) < 1e-12
         assert _rel(out[2, "fp64"][r], out[0, "fp64"][r]) < 1e-13
-        for mode in (0, 1, 2):
+        assert _rel(out[3, "fp64"][r], out[1, "fp64"][r]) < 1e-12
+        for mode in (0, 1, 2, 3):
             assert _rel(out[mode, "fp32"][r], out[1, "fp64"][r]) < 2e-6
         err = _rel(out[0, "fp64"][r], ref[r])
         print(f"p={p} rhs {r}: rel err vs oracle {err:.3e}")
-        assert err < {3: 1e-2, 4: 3e-3, 6: 3e-4, 9: 2e-5, 12: 1e-6}[p]
+        assert err < {3: 1e-2, 4: 3e-3, 6: 3e-4, 9: 2e-5, 12: 1e-6, 16: 1e-7}[p]
 
 
 @pytest.mark.parametrize("nrhs", [1, 2, 70])
@@ -172,7 +173,8 @@ def test_streamed_translations_up_to_80_coefficients(imq, nrhs):
     tree.set_level_orders(orders)
     tree.set_kernel_config(m2l_mode=1)
     ref = tree.matvec(U, "fp64")
-    for mode, prec, tol in ((0, "fp64", 1e-13), (0, "fp32", 2e-6), (2, "fp32", 2e-6)):
+    for mode, prec, tol in ((0, "fp64", 1e-13), (0, "fp32", 2e-6), (2, "fp32", 2e-6), (3, "fp64", 1e-13),
+                            (3, "fp32", 2e-6)):
         tree.set_kernel_config(m2l_mode=mode)
         b = tree.matvec(U, prec)
         e = float(torch.linalg.norm(b - ref) / torch.linalg.norm(ref))
