@@ -240,7 +240,7 @@ static void free_tree(imq_tree_s *t)
     }
     for (PrecData *pd : {&t->f64, &t->f32}) {
         DevBuf *pb[] = {&pd->xl, &pd->yl, &pd->urec, &pd->m2m, &pd->l2l, &pd->m2l, &pd->m2l_pk, &pd->m2l_bf3, &pd->wx, &pd->us, &pd->M, &pd->L,
-                        &pd->Lx, &pd->m2l_odd, &pd->l2l_odd, &pd->Lodd, &pd->wxo};
+                        &pd->Lx, &pd->m2l_odd, &pd->l2l_odd, &pd->m2l_odd_pk, &pd->Lodd, &pd->wxo};
         for (DevBuf *b : pb) dev_free(*b);
     }
     for (auto &e : t->ev)

@@ -407,8 +407,24 @@ imq_status ensure_odd_tables(imq_tree_s *t)
             wxo[o] = v;
             if (k > 0) wxo[o + 1] = v;
         }
+    // the translation tables also in the streamed kernel's lane order: entry
+    // (r, c) of a table at record (r/16 * nrb + c/16) * 64 + (c%16)/4 * 16 + r%16,
+    // element c%4
+    std::vector<double> m2l_pk(m2l.size(), 0.0);
+    {
+        const int nrb = KP / 16;
+        for (size_t tb = 0; tb < ntab; ++tb)
+            for (int r = 0; r < KP; ++r)
+                for (int c = 0; c < KP; ++c) {
+                    const size_t rec = (size_t(r / 16) * nrb + c / 16) * 64 + size_t((c % 16) / 4) * 16 + r % 16;
+                    m2l_pk[tb * PP + rec * 4 + c % 4] = m2l[tb * PP + size_t(r) * KP + c];
+                }
+    }
     std::vector<float> m2l32(m2l.begin(), m2l.end()), l2l32(l2l.begin(), l2l.end()), wxo32(wxo.begin(), wxo.end());
+    std::vector<float> m2l_pk32(m2l_pk.begin(), m2l_pk.end());
     imq_status st;
+    if ((st = upload_vec(t->f64.m2l_odd_pk, m2l_pk)) != IMQ_OK) return st;
+    if ((st = upload_vec(t->f32.m2l_odd_pk, m2l_pk32)) != IMQ_OK) return st;
     if ((st = upload_vec(t->f64.wxo, wxo)) != IMQ_OK) return st;
     if ((st = upload_vec(t->f32.wxo, wxo32)) != IMQ_OK) return st;
     if ((st = upload_vec(t->f64.m2l_odd, m2l)) != IMQ_OK) return st;
@@ -455,7 +471,15 @@ imq_status backward_typed(imq_tree_s *t, const Tio *v, const Tio *g, Tio *dv, do
         const size_t n = size_t(nbox) * 2 * KS;
         hipLaunchKernelGGL(k_zero<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, Lo);
     }
-    if (t->g_m2l.ntasks > 0)
+    // streamed when the tree's kernel choice streams every level (m2l_mode 3;
+    // output rows: the odd coefficients), else the staged GEMM
+    bool streamed = false;
+    if (t->g_m2l.ntasks > 0 && t->kcfg.m2l_mode == 3)
+        streamed = launch_m2l_stream<T>(s, 0, K, t->g_m2l.ntasks, 0, 2, t->g_m2l.tasks.as<GemmTask>(),
+                                        t->g_m2l.tbox.as<int32_t>(), t->g_m2l.tab.as<int32_t>(),
+                                        t->g_m2l.src.as<int32_t>(), pd.m2l_odd_pk.as<T>(), nullptr, KP, KS,
+                                        pd.M.as<T>(), Lo, Ko);
+    if (t->g_m2l.ntasks > 0 && !streamed)
         launch_gemm<T>(s, 32, 1, t->g_m2l.ntasks, 2, t->g_m2l.tasks.as<GemmTask>(), 0, t->g_m2l.tbox.as<int32_t>(),
                        t->g_m2l.tab.as<int32_t>(), t->g_m2l.src.as<int32_t>(), pd.m2l_odd.as<T>(), KP, KS,
                        pd.M.as<T>(), Lo, 0, 0, Ko);

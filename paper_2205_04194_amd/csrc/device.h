@@ -98,6 +98,7 @@ struct PrecData {              // everything that exists once per arithmetic typ
     size_t lx_nrhs = 0;
     DevBuf m2l_odd, l2l_odd;   // adjoint: tables to the n+m-odd local coefficients
                                // (l2l_odd packed like l2l)
+    DevBuf m2l_odd_pk;         // adjoint: m2l_odd in the streamed kernel's lane order
     DevBuf Lodd;               // adjoint: odd local coefficients
     DevBuf wxo;                // adjoint: eps_k c_{j-1,k} per odd coefficient
 };
@@ -144,11 +145,12 @@ template <typename V>
 imq_status precond_apply(imq_tree_s *t, int nrhs, const V *in, V *out, hipStream_t s);
 
 // Abf (FP32 only, else null): the tables as three BF16 parts per entry, read
-// by the BF16 matrix-core form instead of Apk.
+// by the BF16 matrix-core form instead of Apk.  kout_ovr > 0: output rows per
+// box (tables with another output layout), else the tasks' own.
 template <typename T>
 bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
                        const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk,
-                       const uint16_t *Abf, int KP, int KS, const T *in, T *out);
+                       const uint16_t *Abf, int KP, int KS, const T *in, T *out, int kout_ovr = 0);
 // Batched translation GEMM (fmm.hip); kc = staged coefficients per step.
 template <typename T>
 void launch_gemm(hipStream_t s, int kc, int split, int ntask, int nrhs, const GemmTask *tasks, int t0,

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
                                                     const int32_t *__restrict__ src, const T *__restrict__ Apk,
                                                     const uint16_t *__restrict__ Abf,
                                                     int nrbT, int nrhs, int KS, const T *__restrict__ in,
-                                                    T *__restrict__ out, int add, int ntask)
+                                                    T *__restrict__ out, int add, int ntask, int kout_ovr)
 {
     tree_pass_priority();
     static_assert(NRB % RBW == 0, "whole row-block groups");
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
     // the wave index as a scalar: the class tables' indices are then scalar loads
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i16 = lane & 15, q = lane >> 4;
-    const int kin = tk.kin, kout = tk.kout;
+    const int kin = tk.kin, kout = kout_ovr > 0 ? kout_ovr : tk.kout;   // override: other tables' output rows
     const int rb0 = blockIdx.z * RBW;                // first output row block of the workgroup
     if (rb0 * 16 >= kout) return;                    // uniform over the workgroup
     const int nslot = tk.nslot;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(64 * NW) void k_m2l_stream(const GemmTask *__restri
 template <typename T>
 bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, int nrhs, const GemmTask *tasks,
                        const int32_t *tbox, const int32_t *tab, const int32_t *src, const T *Apk,
-                       const uint16_t *Abf, int KP, int KS, const T *in, T *out)
+                       const uint16_t *Abf, int KP, int KS, const T *in, T *out, int kout_ovr)
 {
     const int nrb = (kmax + 15) / 16;
     if (ntask <= 0) return true;
@@ -309,10 +309,10 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
         const unsigned ny = unsigned((GEMM_TILE * nrhs + 16 * NCB - 1) / (16 * NCB));                      \
         if (NRB > 1 && size_t(ntask) * ny < 512)                                                           \
             hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, 1, BF>), dim3((ntask + 7) & ~7, ny, NRB), dim3(64 * NW), 0, \
-                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc, ntask);     \
+                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc, ntask, kout_ovr);     \
         else                                                                                               \
             hipLaunchKernelGGL((k_m2l_stream<T, NRB, NCB, NW, NRB, BF>), dim3((ntask + 7) & ~7, ny, 1), dim3(64 * NW), 0,  \
-                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc, ntask);     \
+                               s, tasks, task0, tbox, tab, src, Apk, Abf, KP / 16, nrhs, KS, in, out, acc, ntask, kout_ovr);     \
     } while (0)
 #define IMQ_M2LS(NRB, NCB, NW)                                                                             \
     do {                                                                                                   \
@@ -327,7 +327,7 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
     case NRB:                                                                                              \
         hipLaunchKernelGGL((k_m2l_stream<T, NRB, 1, 4, 1>),                                                \
                            dim3((ntask + 7) & ~7, unsigned((GEMM_TILE * nrhs + 15) / 16), NRB), dim3(256), 0, s, \
-                           tasks, task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc, ntask); \
+                           tasks, task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc, ntask, kout_ovr); \
         return true;
     if constexpr (sizeof(T) == 4) {
         switch (nrb) {
@@ -348,7 +348,7 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
         case 5:      // one row block per workgroup: a whole-row tile would not fit the registers
             hipLaunchKernelGGL((k_m2l_stream<T, 5, 1, 4, 1>),
                                dim3((ntask + 7) & ~7, unsigned((GEMM_TILE * nrhs + 15) / 16), 5), dim3(256), 0, s, tasks,
-                               task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc, ntask);
+                               task0, tbox, tab, src, Apk, nullptr, KP / 16, nrhs, KS, in, out, acc, ntask, kout_ovr);
             return true;
         IMQ_M2LS_ROW(6) IMQ_M2LS_ROW(7) IMQ_M2LS_ROW(8) IMQ_M2LS_ROW(9) IMQ_M2LS_ROW(10)
         default: return false;
@@ -361,9 +361,9 @@ bool launch_m2l_stream(hipStream_t s, int acc, int kmax, int ntask, int task0, i
 
 template bool launch_m2l_stream<float>(hipStream_t, int, int, int, int, int, const GemmTask *, const int32_t *,
                                        const int32_t *, const int32_t *, const float *, const uint16_t *, int, int,
-                                       const float *, float *);
+                                       const float *, float *, int);
 template bool launch_m2l_stream<double>(hipStream_t, int, int, int, int, int, const GemmTask *, const int32_t *,
                                         const int32_t *, const int32_t *, const double *, const uint16_t *, int, int,
-                                        const double *, double *);
+                                        const double *, double *, int);
 
 }  // namespace imq
