@@ -106,12 +106,20 @@ static std::vector<NearLeaf> near_leaves(const HostTree &h)
     return sorted;
 }
 
+__global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ o)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = float(a[i]);
+}
+
+// The tree's device arrays from its host build; the per-point arrays (perm,
+// scale, FP64 leaf-local coordinates) are already on the device.
 static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
 {
     const HostTree &h = t->h;
     imq_status st;
 #define UP(field) if ((st = upload(t->field, h.field)) != IMQ_OK) return st
-    UP(perm); UP(pt_scale); UP(level); UP(set); UP(parent); UP(child0); UP(nchild); UP(pos);
+    UP(level); UP(set); UP(parent); UP(child0); UP(nchild); UP(pos);
     UP(begin); UP(end); UP(cx); UP(cy); UP(u_off); UP(u_idx); UP(v_off); UP(v_idx); UP(v_cls);
     UP(w_off); UP(w_idx); UP(x_off); UP(x_idx); UP(Klev); UP(leaves);
 #undef UP
@@ -173,10 +181,15 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
     IMQ_HIP(dev_alloc(t->xy_user, sizeof(double) * 2 * size_t(h.N)));
     IMQ_HIP(hipMemcpy(t->xy_user.p, xy_dev, sizeof(double) * 2 * size_t(h.N), hipMemcpyDeviceToDevice));
 
-    if ((st = upload(t->f64.xl, h.xl)) != IMQ_OK) return st;
-    if ((st = upload(t->f64.yl, h.yl)) != IMQ_OK) return st;
-    if ((st = upload(t->f32.xl, to_f32(h.xl))) != IMQ_OK) return st;
-    if ((st = upload(t->f32.yl, to_f32(h.yl))) != IMQ_OK) return st;
+    IMQ_HIP(dev_alloc(t->f32.xl, sizeof(float) * size_t(h.N)));
+    IMQ_HIP(dev_alloc(t->f32.yl, sizeof(float) * size_t(h.N)));
+    const unsigned nb = unsigned((h.N + 255) / 256);
+    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(256), 0, nullptr, h.N, t->f64.xl.as<const double>(),
+                       t->f32.xl.as<float>());
+    hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(256), 0, nullptr, h.N, t->f64.yl.as<const double>(),
+                       t->f32.yl.as<float>());
+    IMQ_HIP(hipGetLastError());
+    IMQ_HIP(hipStreamSynchronize(nullptr));
     if ((st = upload(t->f64.urec, u_records<double>(h))) != IMQ_OK) return st;
     if ((st = upload(t->f32.urec, u_records<float>(h))) != IMQ_OK) return st;
 
@@ -417,8 +430,9 @@ imq_status imq_build_tree_alloc(int nsets, const int64_t *set_offsets, const dou
     }
     if (alloc) t->alloc = *alloc;
     g_alloc = t->allocator();
-    imq_status st = build_device_tree(nsets, set_offsets, xy, c, *params, stream, t->h);
-    if (st != IMQ_OK) { delete t; return st; }
+    const DeviceKeep keep{&t->perm, &t->f64.xl, &t->f64.yl, &t->pt_scale};
+    imq_status st = build_device_tree(nsets, set_offsets, xy, c, *params, stream, t->h, &keep);
+    if (st != IMQ_OK) { free_tree(t); return st; }
     st = upload_tree(t, xy);
     if (st != IMQ_OK) { free_tree(t); return st; }
     live_add(t);

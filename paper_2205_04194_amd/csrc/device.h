@@ -284,10 +284,18 @@ imq_status make_m2l_tables_device(imq_tree_s *t, int KP);
 // built, registered tree for a sampled-row relative error <= tol.
 imq_status autotune_tree(imq_tree_s *t, double tol, hipStream_t s);
 
+// Device buffers that receive a build's per-point arrays in tree order:
+// the permutation (int32), the leaf-local coordinates and the scale 1/side
+// (double).
+struct DeviceKeep {
+    DevBuf *perm, *xl, *yl, *scale;
+};
 // The host build's tree (build_host_tree) computed on the device from device
-// coordinates; synchronises `s`.
+// coordinates; synchronises `s`.  With keep the per-point arrays stay on the
+// device (and are not copied into t).
 imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, const double *c,
-                             const imq_tree_params &prm, hipStream_t s, HostTree &t);
+                             const imq_tree_params &prm, hipStream_t s, HostTree &t,
+                             const DeviceKeep *keep = nullptr);
 }  // namespace imq
 
 #define IMQ_HIP(call)                                                                 \

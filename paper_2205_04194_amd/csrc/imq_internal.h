@@ -154,8 +154,10 @@ imq_status eval_points(int64_t n, const double *xs, const double *ys, int64_t m,
 // Argument checks shared by the host and device builds.
 imq_status check_tree_params(int nsets, const int64_t *set_offsets, const double *c, const imq_tree_params &prm);
 // Translation batches, shift lists, near-field flags and work counts of a
-// tree whose boxes, points and lists are built.
-imq_status finish_host_tree(HostTree &t);
+// tree whose boxes, points and lists are built.  leaf_r2: per leaf (in the
+// order of t.leaves) the largest squared distance of its points from the
+// leaf's centre; null: computed from t.xl and t.yl.
+imq_status finish_host_tree(HostTree &t, const std::vector<double> *leaf_r2 = nullptr);
 
 // Returns IMQ_OK, IMQ_EINVAL or IMQ_EDUPLICATE.
 imq_status build_host_tree(int nsets, const int64_t *set_offsets, const double *x,

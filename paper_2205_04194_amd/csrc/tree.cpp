@@ -21,7 +21,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <functional>
 #include <cstring>
 #include <numeric>
 #include <unordered_map>
@@ -97,13 +96,24 @@ struct Builder {
 // NEAR_EXPAND_RATIO, so at most about 3 units.
 static constexpr double NEAR_EXPAND_RATIO = 2.0;
 
-static void near_expansion_flags(HostTree &h)
+static void near_expansion_flags(HostTree &h, const std::vector<double> *leaf_r2)
 {
     const int nbox = int(h.level.size());
     std::vector<double> rad(nbox, 0.0);
-    for (int b : h.leaves)
-        for (int i = h.begin[b]; i < h.end[b]; ++i)
-            rad[b] = std::max(rad[b], std::sqrt(h.xl[i] * h.xl[i] + h.yl[i] * h.yl[i]));
+    for (size_t l = 0; l < h.leaves.size(); ++l) {
+        const int b = h.leaves[l];
+        double r2 = 0.0;
+        if (leaf_r2) {
+            r2 = (*leaf_r2)[l];
+        } else {
+            for (int i = h.begin[b]; i < h.end[b]; ++i) {
+                const double xx = h.xl[i] * h.xl[i];
+                const double yy = h.yl[i] * h.yl[i];
+                r2 = std::max(r2, xx + yy);
+            }
+        }
+        rad[b] = std::sqrt(r2);                   // the largest distance: sqrt is monotone
+    }
     h.near_expand.assign(h.leaves.size(), 0);
     for (size_t l = 0; l < h.leaves.size(); ++l) {
         const int b = h.leaves[l];
@@ -135,10 +145,10 @@ imq_status check_tree_params(int nsets, const int64_t *off, const double *c, con
 
 // What follows the lists: the translation batches and shift lists, the
 // near-field expansion flags, the work counts.
-imq_status finish_host_tree(HostTree &t)
+imq_status finish_host_tree(HostTree &t, const std::vector<double> *leaf_r2)
 {
     build_gemm_lists(t);
-    near_expansion_flags(t);
+    near_expansion_flags(t, leaf_r2);
     const int nbox = int(t.level.size());
     auto npts = [&](int b) { return int64_t(t.end[b] - t.begin[b]); };
     for (int b = 0; b < nbox; ++b) {
@@ -403,9 +413,10 @@ static void v_classes(int pos, std::vector<int> &cls)
             if (std::max(std::abs(dx), std::abs(dy)) >= 2) cls.push_back(class_of(dx, dy));
 }
 
-static void add_tasks(GemmList &g, const std::vector<int32_t> &boxes, int nslot, int kin, int kout,
-                      int level, const std::vector<int32_t> &tabs,
-                      const std::function<int32_t(int32_t, int)> &source)
+// Tasks of up to GEMM_TILE consecutive targets; src holds nslot sources per
+// target, in the order of boxes.
+static void add_tasks(GemmList &g, const std::vector<int32_t> &boxes, const std::vector<int32_t> &src, int nslot,
+                      int kin, int kout, int level, const std::vector<int32_t> &tabs)
 {
     for (size_t b0 = 0; b0 < boxes.size(); b0 += GEMM_TILE) {
         GemmTask k;
@@ -418,11 +429,8 @@ static void add_tasks(GemmList &g, const std::vector<int32_t> &boxes, int nslot,
         k.src0 = int32_t(g.src.size());
         k.level = level;
         g.tab.insert(g.tab.end(), tabs.begin(), tabs.end());
-        for (int i = 0; i < k.nbox; ++i) {
-            const int32_t b = boxes[b0 + i];
-            g.tbox.push_back(b);
-            for (int s = 0; s < nslot; ++s) g.src.push_back(source(b, s));
-        }
+        g.tbox.insert(g.tbox.end(), boxes.begin() + b0, boxes.begin() + b0 + k.nbox);
+        g.src.insert(g.src.end(), src.begin() + b0 * nslot, src.begin() + (b0 + k.nbox) * nslot);
         g.tasks.push_back(k);
     }
 }
@@ -457,27 +465,52 @@ void build_gemm_lists(HostTree &t)
         }
     }
     t.sh_level_begin[L] = int32_t(t.sh_par.size());
-    // expansion-to-local: (set, level, position) groups, 27 slots
-    std::vector<int> cls;
+    // expansion-to-local: (set, level, position) groups, 27 slots; slot of
+    // every displacement class at each child position (-1: not a V class)
+    std::vector<int> cls[4];
+    int slot_of[4][NCLASS];
+    for (int pos = 0; pos < 4; ++pos) {
+        v_classes(pos, cls[pos]);
+        std::fill(slot_of[pos], slot_of[pos] + NCLASS, -1);
+        for (int i = 0; i < int(cls[pos].size()); ++i) slot_of[pos][cls[pos][i]] = i;
+    }
     t.m2l.level_task_begin.assign(L + 1, 0);
+    std::vector<int32_t> tgt, grp, src, tabs, cnt;
     for (int l = 0; l < L; ++l) {
         t.m2l.level_task_begin[l] = int32_t(t.m2l.tasks.size());
-        for (int s = 0; s < t.nsets; ++s)
-            for (int pos = 0; pos < 4; ++pos) {
-                std::vector<int32_t> tgt;
-                for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
-                    if (t.set[b] == s && t.pos[b] == pos && t.v_off[b + 1] > t.v_off[b]) tgt.push_back(b);
-                if (tgt.empty()) continue;
-                v_classes(pos, cls);
-                std::vector<int32_t> tabs;
-                for (int c : cls) tabs.push_back((s * L + l) * NCLASS + c);
-                add_tasks(t.m2l, tgt, int(cls.size()), t.Klev[l], t.Klev[l], l, tabs,
-                          [&](int32_t b, int slot) -> int32_t {
-                              for (int v = t.v_off[b]; v < t.v_off[b + 1]; ++v)
-                                  if (t.v_cls[v] == cls[slot]) return t.v_idx[v];
-                              return -1;
-                          });
+        // the level's targets in (set, position, box) order: a counting sort
+        // on set * 4 + position
+        cnt.assign(size_t(t.nsets) * 4 + 1, 0);
+        int ntgt = 0;
+        for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
+            if (t.v_off[b + 1] > t.v_off[b]) {
+                ++cnt[size_t(t.set[b]) * 4 + t.pos[b] + 1];
+                ++ntgt;
             }
+        for (size_t k = 1; k < cnt.size(); ++k) cnt[k] += cnt[k - 1];
+        tgt.resize(ntgt);
+        for (int b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
+            if (t.v_off[b + 1] > t.v_off[b]) tgt[cnt[size_t(t.set[b]) * 4 + t.pos[b]]++] = b;
+        for (size_t g0 = 0; g0 < tgt.size();) {
+            const int s = t.set[tgt[g0]], pos = t.pos[tgt[g0]];
+            size_t g1 = g0;
+            while (g1 < tgt.size() && t.set[tgt[g1]] == s && t.pos[tgt[g1]] == pos) ++g1;
+            const int nslot = int(cls[pos].size());
+            grp.assign(tgt.begin() + g0, tgt.begin() + g1);
+            src.assign(grp.size() * nslot, -1);
+            for (size_t i = 0; i < grp.size(); ++i) {
+                const int32_t b = grp[i];
+                int32_t *row = src.data() + i * nslot;
+                for (int v = t.v_off[b]; v < t.v_off[b + 1]; ++v) {
+                    const int sl = slot_of[pos][t.v_cls[v]];
+                    if (sl >= 0 && row[sl] < 0) row[sl] = t.v_idx[v];
+                }
+            }
+            tabs.clear();
+            for (int c : cls[pos]) tabs.push_back((s * L + l) * NCLASS + c);
+            add_tasks(t.m2l, grp, src, nslot, t.Klev[l], t.Klev[l], l, tabs);
+            g0 = g1;
+        }
     }
     t.m2l.level_task_begin[L] = int32_t(t.m2l.tasks.size());
 }

@@ -146,8 +146,10 @@ __global__ void k_normal(int64_t N, int nsets, const int64_t *__restrict__ off, 
 // One level of boxes (structure of arrays; box i of the level is box
 // base + i of the forest).
 struct LevelBoxes {
-    DevBuf set, ix, iy, beg, end, parent, pos;    // int32
-    DevBuf child0, nchild, cnt, first, cut;       // split results (cut: 5 per box)
+    int32_t *set = nullptr, *ix = nullptr, *iy = nullptr, *beg = nullptr, *end = nullptr, *parent = nullptr,
+            *pos = nullptr;
+    int32_t *child0 = nullptr, *nchild = nullptr, *cnt = nullptr, *first = nullptr,
+            *cut = nullptr;                       // split results (cut: 5 per box)
     int n = 0;
 };
 
@@ -219,18 +221,25 @@ __global__ void k_points(const int32_t *__restrict__ leaves, const int32_t *__re
                          const int32_t *__restrict__ beg, const int32_t *__restrict__ end,
                          const double *__restrict__ geo, const double *__restrict__ xn, const double *__restrict__ yn,
                          double *__restrict__ xl, double *__restrict__ yl, double *__restrict__ scale,
-                         int32_t *__restrict__ pt_leaf)
+                         int32_t *__restrict__ pt_leaf, double *__restrict__ leaf_r2)
 {
     const int b = leaves[blockIdx.x];
     const double sz = ldexp(1.0, -level[b]);
     const double cx = (double(ix[b]) + 0.5) * sz, cy = (double(iy[b]) + 0.5) * sz;
     const double sc = 1.0 / geo[3 * set[b] + 2];
+    double r2 = 0.0;
     for (int i = beg[b] + threadIdx.x; i < end[b]; i += blockDim.x) {
-        xl[i] = xn[i] - cx;
-        yl[i] = yn[i] - cy;
+        const double x = xn[i] - cx, y = yn[i] - cy;
+        xl[i] = x;
+        yl[i] = y;
         scale[i] = sc;
         pt_leaf[i] = b;
+        const double xx = x * x, yy = y * y;
+        r2 = fmax(r2, xx + yy);
     }
+    // the leaf's largest squared distance from its centre (one wave per leaf)
+    for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o));
+    if (threadIdx.x == 0) leaf_r2[blockIdx.x] = r2;
 }
 
 // ---- interaction lists
@@ -457,24 +466,35 @@ __global__ void k_sum3(int n, const int32_t *__restrict__ a, const int32_t *__re
     if (i < n) out[i] = a[i] + b[i] + c[i];
 }
 
-// Temporaries of one build, freed on every path.
+// Temporaries of one build, freed on every path: carved from a few large
+// chunks (256-byte aligned pieces), so a build makes a handful of device
+// allocations instead of one per array.
 struct Scratch {
-    std::vector<DevBuf> bufs;
+    static constexpr size_t CHUNK = size_t(32) << 20;
+    std::vector<DevBuf> chunks;
+    size_t used = 0;                              // bytes taken from chunks.back()
     ~Scratch()
     {
-        for (DevBuf &b : bufs) dev_free(b);
+        for (DevBuf &b : chunks) dev_free(b);
     }
     template <typename V>
     V *get(size_t n, imq_status &st)
     {
-        bufs.emplace_back();
-        const hipError_t e = dev_alloc(bufs.back(), sizeof(V) * std::max<size_t>(n, 1));
-        if (e != hipSuccess) {
-            set_error(std::string("device tree build: ") + hipGetErrorString(e));
-            st = e == hipErrorOutOfMemory ? IMQ_ENOMEM : IMQ_EHIP;
-            return nullptr;
+        const size_t bytes = (sizeof(V) * std::max<size_t>(n, 1) + 255) & ~size_t(255);
+        if (chunks.empty() || used + bytes > chunks.back().bytes) {
+            chunks.emplace_back();
+            const hipError_t e = dev_alloc(chunks.back(), std::max(bytes, CHUNK));
+            if (e != hipSuccess) {
+                chunks.pop_back();
+                set_error(std::string("device tree build: ") + hipGetErrorString(e));
+                st = e == hipErrorOutOfMemory ? IMQ_ENOMEM : IMQ_EHIP;
+                return nullptr;
+            }
+            used = 0;
         }
-        return bufs.back().as<V>();
+        V *p = reinterpret_cast<V *>(static_cast<char *>(chunks.back().p) + used);
+        used += bytes;
+        return p;
     }
 };
 
@@ -510,9 +530,12 @@ imq_status scan(Scratch &S, const int32_t *cnt, int32_t *off, int n, hipStream_t
 // The forest of tree.cpp's build_host_tree, computed on the device from the
 // device coordinates xy (x then y, N each); on return t holds the same
 // partition, point order, coordinates and interaction lists as the host
-// build (its remaining fields are filled by finish_host_tree).
+// build (its remaining fields are filled by finish_host_tree).  With keep,
+// the per-point arrays (perm, leaf-local x and y, scale) stay on the device
+// in keep's buffers, allocated here, and t's copies of them (and of
+// pt_leaf) are left empty.
 imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, const double *c,
-                             const imq_tree_params &prm, hipStream_t s, HostTree &t)
+                             const imq_tree_params &prm, hipStream_t s, HostTree &t, const DeviceKeep *keep)
 {
     imq_status st = check_tree_params(nsets, off, c, prm);
     if (st != IMQ_OK) return st;
@@ -559,7 +582,14 @@ imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, co
     TMP(key0, uint64_t, N);
     TMP(idx0, int32_t, N);
     TMP(key, uint64_t, N);
-    TMP(perm, int32_t, N);
+    int32_t *perm = nullptr;
+    if (keep) {
+        IMQ_HIP(dev_alloc(*keep->perm, sizeof(int32_t) * N));
+        perm = keep->perm->as<int32_t>();
+    } else {
+        TMP(perm_tmp, int32_t, N);
+        perm = perm_tmp;
+    }
     hipLaunchKernelGGL(k_keys, dim3(nblk(N)), dim3(TB), 0, s, N, nsets, d_off, x, y, d_geo, key0, idx0);
     {
         size_t bytes = 0;
@@ -612,61 +642,50 @@ imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, co
             beg[k] = int32_t(off[k]);
             en[k] = int32_t(off[k + 1]);
         }
-        for (DevBuf *b : {&L0.set, &L0.ix, &L0.iy, &L0.beg, &L0.end, &L0.parent, &L0.pos})
-            IMQ_HIP(dev_alloc(*b, sizeof(int32_t) * nsets));
-        if ((st = to_dev(L0.set.as<int32_t>(), sset, s)) != IMQ_OK) return st;
-        if ((st = to_dev(L0.ix.as<int32_t>(), zero, s)) != IMQ_OK) return st;
-        if ((st = to_dev(L0.iy.as<int32_t>(), zero, s)) != IMQ_OK) return st;
-        if ((st = to_dev(L0.beg.as<int32_t>(), beg, s)) != IMQ_OK) return st;
-        if ((st = to_dev(L0.end.as<int32_t>(), en, s)) != IMQ_OK) return st;
-        if ((st = to_dev(L0.parent.as<int32_t>(), par, s)) != IMQ_OK) return st;
-        if ((st = to_dev(L0.pos.as<int32_t>(), zero, s)) != IMQ_OK) return st;
+        for (int32_t **b : {&L0.set, &L0.ix, &L0.iy, &L0.beg, &L0.end, &L0.parent, &L0.pos})
+            if (!(*b = S.get<int32_t>(nsets, st))) return st;
+        if ((st = to_dev(L0.set, sset, s)) != IMQ_OK) return st;
+        if ((st = to_dev(L0.ix, zero, s)) != IMQ_OK) return st;
+        if ((st = to_dev(L0.iy, zero, s)) != IMQ_OK) return st;
+        if ((st = to_dev(L0.beg, beg, s)) != IMQ_OK) return st;
+        if ((st = to_dev(L0.end, en, s)) != IMQ_OK) return st;
+        if ((st = to_dev(L0.parent, par, s)) != IMQ_OK) return st;
+        if ((st = to_dev(L0.pos, zero, s)) != IMQ_OK) return st;
         IMQ_HIP(hipStreamSynchronize(s));             // the host vectors go out of scope
     }
-    struct FreeLevels {
-        std::vector<LevelBoxes> &lv;
-        ~FreeLevels()
-        {
-            for (LevelBoxes &L : lv)
-                for (DevBuf *b : {&L.set, &L.ix, &L.iy, &L.beg, &L.end, &L.parent, &L.pos, &L.child0, &L.nchild,
-                                  &L.cnt, &L.first, &L.cut})
-                    dev_free(*b);
-        }
-    } free_levels{lv};
     t.level_begin.push_back(0);
     int base = 0;
     for (int l = 0;; ++l) {
         LevelBoxes &L = lv[l];
         const int n = L.n;
         t.level_begin.push_back(base + n);
-        for (DevBuf *b : {&L.child0, &L.nchild}) IMQ_HIP(dev_alloc(*b, sizeof(int32_t) * n));
+        for (int32_t **b : {&L.child0, &L.nchild})
+            if (!(*b = S.get<int32_t>(n, st))) return st;
         if (l >= max_level) {
             std::vector<int32_t> m1(n, -1), z(n, 0);
-            if ((st = to_dev(L.child0.as<int32_t>(), m1, s)) != IMQ_OK) return st;
-            if ((st = to_dev(L.nchild.as<int32_t>(), z, s)) != IMQ_OK) return st;
+            if ((st = to_dev(L.child0, m1, s)) != IMQ_OK) return st;
+            if ((st = to_dev(L.nchild, z, s)) != IMQ_OK) return st;
             IMQ_HIP(hipStreamSynchronize(s));
             break;
         }
-        IMQ_HIP(dev_alloc(L.cnt, sizeof(int32_t) * (n + 1)));
-        IMQ_HIP(dev_alloc(L.first, sizeof(int32_t) * (n + 1)));
-        IMQ_HIP(dev_alloc(L.cut, sizeof(int32_t) * 5 * size_t(n)));
-        IMQ_HIP(hipMemsetAsync(L.cnt.p, 0, sizeof(int32_t) * (n + 1), s));
-        hipLaunchKernelGGL(k_split_count, dim3(nblk(n)), dim3(TB), 0, s, n, l, prm.leaf_max, L.beg.as<int32_t>(),
-                           L.end.as<int32_t>(), key, L.cnt.as<int32_t>(), L.cut.as<int32_t>());
-        if ((st = scan(S, L.cnt.as<int32_t>(), L.first.as<int32_t>(), n, s)) != IMQ_OK) return st;
+        if (!(L.cnt = S.get<int32_t>(size_t(n) + 1, st))) return st;
+        if (!(L.first = S.get<int32_t>(size_t(n) + 1, st))) return st;
+        if (!(L.cut = S.get<int32_t>(5 * size_t(n), st))) return st;
+        IMQ_HIP(hipMemsetAsync(L.cnt, 0, sizeof(int32_t) * (n + 1), s));
+        hipLaunchKernelGGL(k_split_count, dim3(nblk(n)), dim3(TB), 0, s, n, l, prm.leaf_max, L.beg, L.end, key,
+                           L.cnt, L.cut);
+        if ((st = scan(S, L.cnt, L.first, n, s)) != IMQ_OK) return st;
         int32_t total = 0;
-        IMQ_HIP(hipMemcpyAsync(&total, L.first.as<int32_t>() + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        IMQ_HIP(hipMemcpyAsync(&total, L.first + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         IMQ_HIP(hipStreamSynchronize(s));
         LevelBoxes nx;
         nx.n = total;
         if (total > 0)
-            for (DevBuf *b : {&nx.set, &nx.ix, &nx.iy, &nx.beg, &nx.end, &nx.parent, &nx.pos})
-                IMQ_HIP(dev_alloc(*b, sizeof(int32_t) * total));
-        hipLaunchKernelGGL(k_split_fill, dim3(nblk(n)), dim3(TB), 0, s, n, base + n, L.set.as<int32_t>(),
-                           L.ix.as<int32_t>(), L.iy.as<int32_t>(), base, L.cnt.as<int32_t>(), L.first.as<int32_t>(),
-                           L.cut.as<int32_t>(), L.child0.as<int32_t>(), L.nchild.as<int32_t>(), nx.set.as<int32_t>(),
-                           nx.ix.as<int32_t>(), nx.iy.as<int32_t>(), nx.beg.as<int32_t>(), nx.end.as<int32_t>(),
-                           nx.parent.as<int32_t>(), nx.pos.as<int32_t>());
+            for (int32_t **b : {&nx.set, &nx.ix, &nx.iy, &nx.beg, &nx.end, &nx.parent, &nx.pos})
+                if (!(*b = S.get<int32_t>(total, st))) return st;
+        hipLaunchKernelGGL(k_split_fill, dim3(nblk(n)), dim3(TB), 0, s, n, base + n, L.set, L.ix, L.iy, base, L.cnt,
+                           L.first, L.cut, L.child0, L.nchild, nx.set, nx.ix, nx.iy, nx.beg, nx.end, nx.parent,
+                           nx.pos);
         IMQ_HIP(hipGetLastError());
         base += n;
         if (total == 0) break;
@@ -696,12 +715,12 @@ imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, co
         for (int l = 0; l < t.nlev; ++l) {
             const LevelBoxes &L = lv[l];
             const size_t bytes = sizeof(int32_t) * L.n;
-            const std::pair<int32_t *, const DevBuf *> cp[] = {{d_set, &L.set}, {d_ix, &L.ix}, {d_iy, &L.iy},
-                                                              {d_par, &L.parent}, {d_c0, &L.child0},
-                                                              {d_nc, &L.nchild}, {d_pos, &L.pos}, {d_beg, &L.beg},
-                                                              {d_end, &L.end}};
+            const std::pair<int32_t *, const int32_t *> cp[] = {{d_set, L.set}, {d_ix, L.ix}, {d_iy, L.iy},
+                                                               {d_par, L.parent}, {d_c0, L.child0},
+                                                               {d_nc, L.nchild}, {d_pos, L.pos}, {d_beg, L.beg},
+                                                               {d_end, L.end}};
             for (const auto &e : cp)
-                IMQ_HIP(hipMemcpyAsync(e.first + o, e.second->p, bytes, hipMemcpyDeviceToDevice, s));
+                IMQ_HIP(hipMemcpyAsync(e.first + o, e.second, bytes, hipMemcpyDeviceToDevice, s));
             o += L.n;
         }
         t.level = lvl;
@@ -762,12 +781,24 @@ imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, co
     }
 
     // ---- points
-    TMP(d_xl, double, N);
-    TMP(d_yl, double, N);
-    TMP(d_sc, double, N);
+    double *d_xl = nullptr, *d_yl = nullptr, *d_sc = nullptr;
+    if (keep) {
+        for (DevBuf *b : {keep->xl, keep->yl, keep->scale}) IMQ_HIP(dev_alloc(*b, sizeof(double) * N));
+        d_xl = keep->xl->as<double>();
+        d_yl = keep->yl->as<double>();
+        d_sc = keep->scale->as<double>();
+    } else {
+        TMP(xl_tmp, double, N);
+        TMP(yl_tmp, double, N);
+        TMP(sc_tmp, double, N);
+        d_xl = xl_tmp;
+        d_yl = yl_tmp;
+        d_sc = sc_tmp;
+    }
     TMP(d_pl, int32_t, N);
+    TMP(d_r2, double, nleaves);
     hipLaunchKernelGGL(k_points, dim3(nleaves), dim3(64), 0, s, d_leaves, d_level, d_set, d_ix, d_iy, d_beg, d_end,
-                       d_geo, xn, yn, d_xl, d_yl, d_sc, d_pl);
+                       d_geo, xn, yn, d_xl, d_yl, d_sc, d_pl, d_r2);
     IMQ_HIP(hipGetLastError());
 
     // ---- lists
@@ -841,11 +872,15 @@ imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, co
     IMQ_HIP(hipGetLastError());
 
     // ---- back to the host tree
-    if ((st = to_host(t.xl, d_xl, N, s)) != IMQ_OK) return st;
-    if ((st = to_host(t.yl, d_yl, N, s)) != IMQ_OK) return st;
-    if ((st = to_host(t.pt_scale, d_sc, N, s)) != IMQ_OK) return st;
-    if ((st = to_host(t.pt_leaf, d_pl, N, s)) != IMQ_OK) return st;
-    if ((st = to_host(t.perm, perm, N, s)) != IMQ_OK) return st;
+    if (!keep) {
+        if ((st = to_host(t.xl, d_xl, N, s)) != IMQ_OK) return st;
+        if ((st = to_host(t.yl, d_yl, N, s)) != IMQ_OK) return st;
+        if ((st = to_host(t.pt_scale, d_sc, N, s)) != IMQ_OK) return st;
+        if ((st = to_host(t.pt_leaf, d_pl, N, s)) != IMQ_OK) return st;
+        if ((st = to_host(t.perm, perm, N, s)) != IMQ_OK) return st;
+    }
+    std::vector<double> leaf_r2;
+    if ((st = to_host(leaf_r2, d_r2, nleaves, s)) != IMQ_OK) return st;
     if ((st = to_host(t.u_off, u_off, nbox + 1, s)) != IMQ_OK) return st;
     if ((st = to_host(t.u_idx, u_idx, tot2[0], s)) != IMQ_OK) return st;
     if ((st = to_host(t.v_off, v_off, nbox + 1, s)) != IMQ_OK) return st;
@@ -857,7 +892,7 @@ imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, co
     if ((st = to_host(t.x_idx, x_idx, tot2[2], s)) != IMQ_OK) return st;
     IMQ_HIP(hipStreamSynchronize(s));
 #undef TMP
-    return finish_host_tree(t);
+    return finish_host_tree(t, &leaf_r2);
 }
 
 }  // namespace imq
