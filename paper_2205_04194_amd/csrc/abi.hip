@@ -64,21 +64,6 @@ static void make_tables(const HostTree &h, std::vector<double> &m2m, std::vector
     make_wx_consts(p, wx.data());
 }
 
-// The near field's view of the U lists: per entry (target leaf b, source
-// leaf a) the points of a and the offset of its centre from b's.
-template <typename T>
-static std::vector<URec<T>> u_records(const HostTree &h)
-{
-    std::vector<URec<T>> r(h.u_idx.size());
-    const int nbox = int(h.level.size());
-    for (int b = 0; b < nbox; ++b)
-        for (int k = h.u_off[b]; k < h.u_off[b + 1]; ++k) {
-            const int a = h.u_idx[k];
-            r[k] = URec<T>{h.begin[a], h.end[a] - h.begin[a], T(h.cx[a] - h.cx[b]), T(h.cy[a] - h.cy[b])};
-        }
-    return r;
-}
-
 // The near field's per-leaf records (the expansion flag comes from the host tree).
 static std::vector<NearLeaf> near_leaves(const HostTree &h)
 {
@@ -138,11 +123,20 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
         std::sort(lord.begin(), lord.end(), [&](int32_t a, int32_t b) { return lr[a].begin < lr[b].begin; });
         for (size_t i = 0; i < lr.size(); ++i) lbeg[i] = lr[lord[i]].begin;
         if ((st = upload(t->boxleaf, lord)) != IMQ_OK) return st;
+        // first leaf at or after a point: a forward scan while the queries
+        // ascend (boxes of a level come in point order), else a binary search
+        size_t at = 0;
+        auto first_leaf = [&](int32_t v) -> int {
+            if (at > 0 && lbeg[at - 1] >= v) at = size_t(std::lower_bound(lbeg.begin(), lbeg.end(), v) - lbeg.begin());
+            while (at < lbeg.size() && lbeg[at] < v) ++at;
+            return int(at);
+        };
         std::vector<BoxRec> br;
+        br.reserve(h.level.size());
         for (int b = 0; b < int(h.level.size()); ++b) {
             if (h.level[b] < h.need_m) continue;
-            const int l0 = int(std::lower_bound(lbeg.begin(), lbeg.end(), h.begin[b]) - lbeg.begin());
-            const int l1 = int(std::lower_bound(lbeg.begin(), lbeg.end(), h.end[b]) - lbeg.begin());
+            const int l0 = first_leaf(h.begin[b]);
+            const int l1 = first_leaf(h.end[b]);
             br.push_back(BoxRec{b, l0, l1, h.level[b]});
         }
         if ((st = upload(t->boxrec, br)) != IMQ_OK) return st;
@@ -190,8 +184,6 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
                        t->f32.yl.as<float>());
     IMQ_HIP(hipGetLastError());
     IMQ_HIP(hipStreamSynchronize(nullptr));
-    if ((st = upload(t->f64.urec, u_records<double>(h))) != IMQ_OK) return st;
-    if ((st = upload(t->f32.urec, u_records<float>(h))) != IMQ_OK) return st;
 
     std::vector<double> m2m, l2l, wx;
     make_tables(h, m2m, l2l, wx);
@@ -430,7 +422,7 @@ imq_status imq_build_tree_alloc(int nsets, const int64_t *set_offsets, const dou
     }
     if (alloc) t->alloc = *alloc;
     g_alloc = t->allocator();
-    const DeviceKeep keep{&t->perm, &t->f64.xl, &t->f64.yl, &t->pt_scale};
+    const DeviceKeep keep{&t->perm, &t->f64.xl, &t->f64.yl, &t->pt_scale, &t->f64.urec, &t->f32.urec};
     imq_status st = build_device_tree(nsets, set_offsets, xy, c, *params, stream, t->h, &keep);
     if (st != IMQ_OK) { free_tree(t); return st; }
     st = upload_tree(t, xy);

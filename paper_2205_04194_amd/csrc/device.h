@@ -286,9 +286,9 @@ imq_status autotune_tree(imq_tree_s *t, double tol, hipStream_t s);
 
 // Device buffers that receive a build's per-point arrays in tree order:
 // the permutation (int32), the leaf-local coordinates and the scale 1/side
-// (double).
+// (double); and the near field's U-list records (URec<double>, URec<float>).
 struct DeviceKeep {
-    DevBuf *perm, *xl, *yl, *scale;
+    DevBuf *perm, *xl, *yl, *scale, *urec64, *urec32;
 };
 // The host build's tree (build_host_tree) computed on the device from device
 // coordinates; synchronises `s`.  With keep the per-point arrays stay on the

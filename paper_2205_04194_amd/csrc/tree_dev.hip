@@ -64,15 +64,17 @@ __device__ __forceinline__ int set_of(const int64_t *off, int nsets, int64_t i)
 }
 
 // per set: min and max of x and y (exact whatever the order), and a flag
-// for a coordinate that is not finite
+// for a coordinate that is not finite; gridDim.x blocks per set (blockIdx.y)
+// each write their partial bounds, k_bounds_final combines them
 __global__ __launch_bounds__(TB) void k_bounds(const int64_t *__restrict__ off, const double *__restrict__ x,
-                                               const double *__restrict__ y, double *__restrict__ bnd,
+                                               const double *__restrict__ y, double *__restrict__ part,
                                                int *__restrict__ bad)
 {
     __shared__ double r[4][TB];
-    const int s = blockIdx.x;
+    const int s = blockIdx.y;
     double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
-    for (int64_t i = off[s] + threadIdx.x; i < off[s + 1]; i += TB) {
+    for (int64_t i = off[s] + int64_t(blockIdx.x) * TB + threadIdx.x; i < off[s + 1];
+         i += int64_t(gridDim.x) * TB) {
         const double a = x[i], b = y[i];
         if (!isfinite(a) || !isfinite(b)) atomicOr(bad, 1);
         x0 = fmin(x0, a); x1 = fmax(x1, a);
@@ -89,7 +91,20 @@ __global__ __launch_bounds__(TB) void k_bounds(const int64_t *__restrict__ off, 
         }
         __syncthreads();
     }
-    if (threadIdx.x < 4) bnd[4 * s + threadIdx.x] = r[threadIdx.x][0];
+    if (threadIdx.x < 4) part[(size_t(s) * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = r[threadIdx.x][0];
+}
+
+__global__ void k_bounds_final(int nsets, int nblk_set, const double *__restrict__ part, double *__restrict__ bnd)
+{
+    const int s = blockIdx.x * TB + threadIdx.x;
+    if (s >= nsets) return;
+    const double *q = part + size_t(s) * nblk_set * 4;
+    double x0 = q[0], x1 = q[1], y0 = q[2], y1 = q[3];
+    for (int g = 1; g < nblk_set; ++g) {
+        x0 = fmin(x0, q[4 * g]); x1 = fmax(x1, q[4 * g + 1]);
+        y0 = fmin(y0, q[4 * g + 2]); y1 = fmax(y1, q[4 * g + 3]);
+    }
+    bnd[4 * s] = x0; bnd[4 * s + 1] = x1; bnd[4 * s + 2] = y0; bnd[4 * s + 3] = y1;
 }
 
 // Morton key of the point quantised in its set's square (the host's
@@ -240,6 +255,29 @@ __global__ void k_points(const int32_t *__restrict__ leaves, const int32_t *__re
     // the leaf's largest squared distance from its centre (one wave per leaf)
     for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o));
     if (threadIdx.x == 0) leaf_r2[blockIdx.x] = r2;
+}
+
+// the near field's record of every U-list entry, in both precisions: the
+// source leaf's points and its centre minus the target's (the host's
+// expressions for the centres)
+__global__ void k_urec(int nbox, const int32_t *__restrict__ level, const int32_t *__restrict__ ix,
+                       const int32_t *__restrict__ iy, const int32_t *__restrict__ beg,
+                       const int32_t *__restrict__ end, const int32_t *__restrict__ u_off,
+                       const int32_t *__restrict__ u_idx, URec<double> *__restrict__ r64,
+                       URec<float> *__restrict__ r32)
+{
+    const int b = blockIdx.x * TB + threadIdx.x;
+    if (b >= nbox) return;
+    const double sb = ldexp(1.0, -level[b]);
+    const double cxb = (double(ix[b]) + 0.5) * sb, cyb = (double(iy[b]) + 0.5) * sb;
+    for (int k = u_off[b]; k < u_off[b + 1]; ++k) {
+        const int a = u_idx[k];
+        const double sa = ldexp(1.0, -level[a]);
+        const double cxa = (double(ix[a]) + 0.5) * sa, cya = (double(iy[a]) + 0.5) * sa;
+        const double ox = cxa - cxb, oy = cya - cyb;
+        r64[k] = URec<double>{beg[a], end[a] - beg[a], ox, oy};
+        r32[k] = URec<float>{beg[a], end[a] - beg[a], float(ox), float(oy)};
+    }
 }
 
 // ---- interaction lists
@@ -533,7 +571,8 @@ imq_status scan(Scratch &S, const int32_t *cnt, int32_t *off, int n, hipStream_t
 // build (its remaining fields are filled by finish_host_tree).  With keep,
 // the per-point arrays (perm, leaf-local x and y, scale) stay on the device
 // in keep's buffers, allocated here, and t's copies of them (and of
-// pt_leaf) are left empty.
+// pt_leaf) are left empty; the near field's U-list records are made there
+// too.
 imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, const double *c,
                              const imq_tree_params &prm, hipStream_t s, HostTree &t, const DeviceKeep *keep)
 {
@@ -558,10 +597,15 @@ imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, co
     TMP(d_off, int64_t, nsets + 1);
     IMQ_HIP(hipMemcpyAsync(d_off, off, sizeof(int64_t) * (nsets + 1), hipMemcpyHostToDevice, s));
     // ---- bounding squares
+    int64_t max_set = 0;
+    for (int k = 0; k < nsets; ++k) max_set = std::max(max_set, off[k + 1] - off[k]);
+    const int nbs = int(std::min<int64_t>(256, std::max<int64_t>(1, (max_set + 16 * TB - 1) / (16 * TB))));
+    TMP(d_part, double, 4 * size_t(nsets) * nbs);
     TMP(d_bnd, double, 4 * nsets);
     TMP(d_bad, int, 1);
     IMQ_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_bounds, dim3(nsets), dim3(TB), 0, s, d_off, x, y, d_bnd, d_bad);
+    hipLaunchKernelGGL(k_bounds, dim3(nbs, nsets), dim3(TB), 0, s, d_off, x, y, d_part, d_bad);
+    hipLaunchKernelGGL(k_bounds_final, dim3(nblk(nsets)), dim3(TB), 0, s, nsets, nbs, d_part, d_bnd);
     std::vector<double> bnd(4 * size_t(nsets));
     int bad = 0;
     IMQ_HIP(hipMemcpyAsync(bnd.data(), d_bnd, sizeof(double) * bnd.size(), hipMemcpyDeviceToHost, s));
@@ -870,6 +914,13 @@ imq_status build_device_tree(int nsets, const int64_t *off, const double *xy, co
     hipLaunchKernelGGL(k_sort_lists, dim3(nblk(nbox)), dim3(TB), 0, s, nbox, u_off, u_idx);
     hipLaunchKernelGGL(k_sort_lists, dim3(nblk(nbox)), dim3(TB), 0, s, nbox, x_off, x_idx);
     IMQ_HIP(hipGetLastError());
+    if (keep) {
+        IMQ_HIP(dev_alloc(*keep->urec64, sizeof(URec<double>) * std::max(tot2[0], 1)));
+        IMQ_HIP(dev_alloc(*keep->urec32, sizeof(URec<float>) * std::max(tot2[0], 1)));
+        hipLaunchKernelGGL(k_urec, dim3(nblk(nbox)), dim3(TB), 0, s, nbox, d_level, d_ix, d_iy, d_beg, d_end, u_off,
+                           u_idx, keep->urec64->as<URec<double>>(), keep->urec32->as<URec<float>>());
+        IMQ_HIP(hipGetLastError());
+    }
 
     // ---- back to the host tree
     if (!keep) {
