@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -103,6 +104,8 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
 {
     const HostTree &h = t->h;
     imq_status st;
+    // the near field's leaf order (costs and a sort) on a second thread
+    std::future<std::vector<NearLeaf>> nleaf = std::async(std::launch::async, [&h] { return near_leaves(h); });
 #define UP(field) if ((st = upload(t->field, h.field)) != IMQ_OK) return st
     UP(level); UP(set); UP(parent); UP(child0); UP(nchild); UP(pos);
     UP(begin); UP(end); UP(cx); UP(cy); UP(u_off); UP(u_idx); UP(v_off); UP(v_idx); UP(v_cls);
@@ -141,7 +144,7 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
         }
         if ((st = upload(t->boxrec, br)) != IMQ_OK) return st;
         t->nboxrec = int(br.size());
-        if ((st = upload(t->nleaf, near_leaves(h))) != IMQ_OK) return st;
+        if ((st = upload(t->nleaf, nleaf.get())) != IMQ_OK) return st;
     }
     {   // W and X lists as flat pairs
         std::vector<int32_t> w_tgt, w_scr, w_leaves, x_tgt, x_boxes;

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 
 namespace imq {
@@ -147,8 +148,10 @@ imq_status check_tree_params(int nsets, const int64_t *off, const double *c, con
 // near-field expansion flags, the work counts.
 imq_status finish_host_tree(HostTree &t, const std::vector<double> *leaf_r2)
 {
+    // the flags and the batches write disjoint fields: built side by side
+    std::thread flags([&] { near_expansion_flags(t, leaf_r2); });
     build_gemm_lists(t);
-    near_expansion_flags(t, leaf_r2);
+    flags.join();
     const int nbox = int(t.level.size());
     auto npts = [&](int b) { return int64_t(t.end[b] - t.begin[b]); };
     for (int b = 0; b < nbox; ++b) {
@@ -475,6 +478,12 @@ void build_gemm_lists(HostTree &t)
         for (int i = 0; i < int(cls[pos].size()); ++i) slot_of[pos][cls[pos][i]] = i;
     }
     t.m2l.level_task_begin.assign(L + 1, 0);
+    {
+        size_t ntgt = 0;
+        for (int b = 0; b < nbox; ++b) ntgt += t.v_off[b + 1] > t.v_off[b] ? 1 : 0;
+        t.m2l.tbox.reserve(ntgt);
+        t.m2l.src.reserve(ntgt * 27);
+    }
     std::vector<int32_t> tgt, grp, src, tabs, cnt;
     for (int l = 0; l < L; ++l) {
         t.m2l.level_task_begin[l] = int32_t(t.m2l.tasks.size());
