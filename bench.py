@@ -200,6 +200,19 @@ def batched_solve_extra(dev, iters=100, singles=4):
     return out
 
 
+def _warm_build_s(build) -> float:
+    """Wall time of one more tree build (the first build also pays one-time
+    set-up); the tree is freed at once."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = build()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t.close()
+    return dt
+
+
 def _tuned_run(tree, U, steps, nrows=300):
     """Autotune, then time `steps` products; error over sampled rows of every column."""
     import torch
@@ -268,9 +281,11 @@ def batched_extras(dev, steps):
                           set_offsets=list(d["offsets"]))
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    tb_warm = _warm_build_s(lambda: imq.build_tree(torch.tensor(d["xy"], device=dev), list(d["c"]), leaf=d["leaf"],
+                                                   p=d["p"], set_offsets=list(d["offsets"])))
     r = _tuned_run(tree, u, steps)
     r.update({"workload": "batched_sets", "nsets": len(d["c"]), "N_total": len(d["xy"]),
-              "tree_build_s": tb, "products_per_s": 1e3 / r["ms_per_step"]})
+              "tree_build_s": tb, "tree_build_warm_s": tb_warm, "products_per_s": 1e3 / r["ms_per_step"]})
     r["graph_ms_per_step"] = _graph_ms(tree, u, r["precision"], steps)
     log(f"batched 256 sets, captured in one HIP graph: {r['graph_ms_per_step']:.3f} ms per replay")
     tree.close()
@@ -483,6 +498,7 @@ def headline(args, dev, d):
     tree = imq.build_tree(xy, d["c"], leaf=args.leaf, p=args.p)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
+    t_build_warm = _warm_build_s(lambda: imq.build_tree(xy, d["c"], leaf=args.leaf, p=args.p))
     info = tree.info()
     log(f"tree: {info['nboxes']} boxes, {info['nleaves']} leaves, depth {info['depth']}, build {t_build:.2f} s")
     exact = tree.rows_exact(u_chk, rows)
@@ -519,7 +535,7 @@ def headline(args, dev, d):
         log(f"tuned {prec} leaf {leaf} orders {res.level_orders}: {ms:.3f} ms/product, rel err {e:.2e} "
             f"(fresh weights, {len(rows)} rows), stages " + " ".join(f"{k}={v:.3f}" for k, v in st.items()))
         tr.close()
-    return {"t_build": t_build, "uniform": uniform, "tuned": tuned}
+    return {"t_build": t_build, "t_build_warm": t_build_warm, "uniform": uniform, "tuned": tuned}
 
 
 def main():
@@ -592,6 +608,7 @@ def main():
         "rel_err_note": f"relative 2-norm over {min(args.rows, n)} sampled rows against exact FP64 sums, "
                         "on weights the tuner did not see",
         "tree_build_s": h["t_build"],
+        "tree_build_warm_s": h["t_build_warm"],
         "stage_ms": r["stage_ms"],
         "uniform_order": {p: {"ms_per_step": v["ms_per_step"], "rel_err": v["rel_err"]}
                           for p, v in h["uniform"].items()},
