@@ -528,11 +528,14 @@ def headline(args, dev, d):
         e = err_of(tr, prec)
         ms, st = time_products(tr, u, prec, args.steps, args.warmup)
         ti = tr.info()
-        tuned[prec] = {"ms_per_step": ms, "rel_err": e, "stage_ms": st, "leaf": leaf, "p": ti["order_p"],
+        g_ms = _graph_ms(tr, u, prec, args.steps)
+        tuned[prec] = {"ms_per_step": ms, "graph_ms_per_step": g_ms, "rel_err": e, "stage_ms": st, "leaf": leaf,
+                       "p": ti["order_p"],
                        "level_orders": res.level_orders, "m2l_mode": res.m2l_mode, "m2l_kc": res.m2l_kc,
                        "m2l_split": res.m2l_split, "p2p_wg": res.p2p_wg, "tune_s": t_tune, "leaf_search": rec,
                        "roofline": _stage_roofline(ti, st, prec, n), "info": ti}
-        log(f"tuned {prec} leaf {leaf} orders {res.level_orders}: {ms:.3f} ms/product, rel err {e:.2e} "
+        log(f"tuned {prec} leaf {leaf} orders {res.level_orders}: {ms:.3f} ms/product ({g_ms:.3f} as a HIP graph "
+            f"replay), rel err {e:.2e} "
             f"(fresh weights, {len(rows)} rows), stages " + " ".join(f"{k}={v:.3f}" for k, v in st.items()))
         tr.close()
     return {"t_build": t_build, "t_build_warm": t_build_warm, "uniform": uniform, "tuned": tuned}
@@ -612,7 +615,9 @@ def main():
         "stage_ms": r["stage_ms"],
         "uniform_order": {p: {"ms_per_step": v["ms_per_step"], "rel_err": v["rel_err"]}
                           for p, v in h["uniform"].items()},
+        "graph_ms_per_step": r["graph_ms_per_step"],
         "fp32_tuned": {"value": 1e3 / f32["ms_per_step"], "unit": "matvec/s", "ms_per_step": f32["ms_per_step"],
+                       "graph_ms_per_step": f32["graph_ms_per_step"],
                        "rel_err_sampled_rows": f32["rel_err"], "level_orders": f32["level_orders"],
                        "leaf": f32["leaf"], "p": f32["p"], "stage_ms": f32["stage_ms"],
                        "roofline": f32["roofline"]},
