@@ -1360,11 +1360,11 @@ imq_status fmm_upward(imq_tree_s *t, int nrhs, hipStream_t s, bool fork, const U
     // it slows every latency-bound shift launch it runs beside, and the finest
     // level is the widest.  Measured on the 1M mixture (product ms, alternating
     // runs on one GPU) by the number of shift levels queued before the fork:
-    // 0: 0.289-0.296, 1: 0.292-0.295, 2: 0.297-0.298, 3: 0.304; with all
-    // eight queued first the product took 0.374 (an earlier kernel set).  0
-    // and 1 are within the noise of these runs (and of a later FP64 repeat
-    // with raised tree-pass priority: 0.485-0.491 against 0.491-0.493 ms);
-    // later forks are measurably slower.
+    // FP32 (an earlier kernel set) 0: 0.289-0.296, 1: 0.292-0.295, 2:
+    // 0.297-0.298, 3: 0.304, all eight: 0.374; FP64 with the tuned orders,
+    // best of five batches of 40, two or three alternations each: 0: 0.454,
+    // 1: 0.414-0.416, 2: 0.419-0.420, 3: 0.456-0.457 (FP32 0.276-0.286 for
+    // all four).
     constexpr int P2P_FORK_AFTER = 1;
     int nshift = 0;
     bool forked = !fork;
