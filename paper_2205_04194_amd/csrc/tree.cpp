@@ -24,7 +24,6 @@
 #include <cstring>
 #include <numeric>
 #include <thread>
-#include <unordered_map>
 
 namespace imq {
 
@@ -528,41 +527,58 @@ imq_status eval_points(int64_t n, const double *xs, const double *ys, int64_t m,
                        const double *yt, std::vector<double> &x, std::vector<double> &y,
                        std::vector<int64_t> &map)
 {
-    struct KeyHash {
-        size_t operator()(const std::pair<uint64_t, uint64_t> &k) const
-        {
-            return size_t(k.first * 0x9E3779B97F4A7C15ull ^ (k.second + 0x632BE59BD9B4E019ull + (k.first << 6)));
-        }
+    // Open-addressing hash of the kept points by their coordinates' bit
+    // patterns (-0 read as +0: the same point); a slot holds a point index.
+    auto bits = [](double a) {
+        a += 0.0;                                // -0 -> +0
+        uint64_t k;
+        std::memcpy(&k, &a, 8);
+        return k;
     };
-    auto key = [](double a, double b) {
-        a += 0.0;                                // -0 -> +0: the same point
-        b += 0.0;
-        uint64_t ka, kb;
-        std::memcpy(&ka, &a, 8);
-        std::memcpy(&kb, &b, 8);
-        return std::make_pair(ka, kb);
+    auto hash = [](uint64_t kx, uint64_t ky) {
+        uint64_t h = kx * 0x9E3779B97F4A7C15ull ^ (ky + 0x632BE59BD9B4E019ull + (kx << 6));
+        h ^= h >> 29;
+        h *= 0xBF58476D1CE4E5B9ull;
+        return h ^ (h >> 32);
     };
-    std::unordered_map<std::pair<uint64_t, uint64_t>, int64_t, KeyHash> seen;
-    seen.reserve(size_t(n + m));
+    size_t cap = 16;
+    while (cap < 2 * size_t(n + m)) cap <<= 1;
+    std::vector<int64_t> slot(cap, -1);
     x.assign(xs, xs + n);
     y.assign(ys, ys + n);
+    x.reserve(size_t(n + m));
+    y.reserve(size_t(n + m));
     map.assign(size_t(m), -1);
+    // index of the kept point at (a, b), or -1 with `at` the empty slot for it
+    auto find = [&](double a, double b, size_t &at) -> int64_t {
+        const uint64_t ka = bits(a), kb = bits(b);
+        for (size_t h = hash(ka, kb) & (cap - 1);; h = (h + 1) & (cap - 1)) {
+            const int64_t i = slot[h];
+            if (i < 0) { at = h; return -1; }
+            if (bits(x[size_t(i)]) == ka && bits(y[size_t(i)]) == kb) return i;
+        }
+    };
     for (int64_t i = 0; i < n; ++i) {
         if (!std::isfinite(xs[i]) || !std::isfinite(ys[i])) { set_error("non-finite data site"); return IMQ_EINVAL; }
-        if (!seen.emplace(key(xs[i], ys[i]), i).second) {
-            set_error("duplicate data sites: points " + std::to_string(seen[key(xs[i], ys[i])]) + " and " +
-                      std::to_string(i));
+        size_t at = 0;
+        const int64_t j = find(xs[i], ys[i], at);
+        if (j >= 0) {
+            set_error("duplicate data sites: points " + std::to_string(j) + " and " + std::to_string(i));
             return IMQ_EDUPLICATE;
         }
+        slot[at] = i;
     }
     for (int64_t k = 0; k < m; ++k) {
         if (!std::isfinite(xt[k]) || !std::isfinite(yt[k])) { set_error("non-finite evaluation point"); return IMQ_EINVAL; }
-        const auto r = seen.emplace(key(xt[k], yt[k]), int64_t(x.size()));
-        if (r.second) {
+        size_t at = 0;
+        int64_t j = find(xt[k], yt[k], at);
+        if (j < 0) {
+            j = int64_t(x.size());
             x.push_back(xt[k]);
             y.push_back(yt[k]);
+            slot[at] = j;
         }
-        map[size_t(k)] = r.first->second;
+        map[size_t(k)] = j;
     }
     return IMQ_OK;
 }
