@@ -65,31 +65,51 @@ static void make_tables(const HostTree &h, std::vector<double> &m2m, std::vector
     make_wx_consts(p, wx.data());
 }
 
-// The near field's per-leaf records (the expansion flag comes from the host tree).
+// The near field's per-leaf records (the expansion flag comes from the host
+// tree), arranged for the eight XCDs.  The workgroups of a launch are dealt
+// to the XCDs in turn, so with a grid that is a multiple of 8 the records at
+// slots r, r + 8, r + 16, ... are all summed on XCD r.  The leaves in point
+// (Morton) order are cut into 8 runs of about equal cost (targets x U-list
+// sources); run r takes the slots of XCD r, largest leaf first (the tail is
+// made of cheap leaves), and empty records pad the shorter runs.  An XCD's
+// sources then come from one region of the plane and stay in its L2, instead
+// of every XCD reading the whole point set.
 static std::vector<NearLeaf> near_leaves(const HostTree &h)
 {
-    std::vector<NearLeaf> nl(h.leaves.size());
-    for (size_t l = 0; l < h.leaves.size(); ++l) {
+    const size_t n = h.leaves.size();
+    std::vector<NearLeaf> nl(n);
+    std::vector<int64_t> cost(n);
+    int64_t total = 0;
+    for (size_t l = 0; l < n; ++l) {
         const int b = h.leaves[l];
         const double cn = h.cn[h.set[b]];
         nl[l] = NearLeaf{h.begin[b], h.end[b], h.u_off[b], h.u_off[b + 1], cn * cn, h.near_expand[l], 0};
-    }
-    // Largest first (pairs = targets x U-list sources): the near field deals
-    // its records round robin to a fixed set of workgroups, so the costly
-    // leaves start first and the tail is made of cheap ones (measured: the
-    // near-field launch 97 -> 92 us on the 1M mixture).
-    std::vector<int64_t> cost(nl.size());
-    for (size_t l = 0; l < nl.size(); ++l) {
         int64_t src = 0;
         for (int u = nl[l].u0; u < nl[l].u1; ++u) src += h.end[h.u_idx[u]] - h.begin[h.u_idx[u]];
         cost[l] = src * (nl[l].end - nl[l].begin);
+        total += cost[l];
     }
-    std::vector<size_t> ord(nl.size());
-    for (size_t l = 0; l < ord.size(); ++l) ord[l] = l;
-    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<NearLeaf> sorted(nl.size());
-    for (size_t l = 0; l < ord.size(); ++l) sorted[l] = nl[ord[l]];
-    return sorted;
+    std::vector<size_t> ord(n);
+    for (size_t l = 0; l < n; ++l) ord[l] = l;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return nl[a].begin < nl[b].begin; });
+    constexpr int NX = 8;
+    std::vector<size_t> run[NX];
+    int64_t acc = 0;
+    for (size_t k : ord) {
+        // the run that holds the middle of this leaf's share of the cost
+        const double mid = total > 0 ? (double(acc) + 0.5 * double(cost[k])) / double(total) : 0.0;
+        run[std::min(NX - 1, int(mid * NX))].push_back(k);
+        acc += cost[k];
+    }
+    size_t most = 0;
+    for (auto &r : run) {
+        std::stable_sort(r.begin(), r.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+        most = std::max(most, r.size());
+    }
+    std::vector<NearLeaf> out(NX * most, NearLeaf{0, 0, 0, 0, 1.0, 0, 0});
+    for (int r = 0; r < NX; ++r)
+        for (size_t j = 0; j < run[r].size(); ++j) out[NX * j + r] = nl[run[r][j]];
+    return out;
 }
 
 __global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ o)
@@ -144,7 +164,9 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
         }
         if ((st = upload(t->boxrec, br)) != IMQ_OK) return st;
         t->nboxrec = int(br.size());
-        if ((st = upload(t->nleaf, nleaf.get())) != IMQ_OK) return st;
+        const std::vector<NearLeaf> recs = nleaf.get();
+        t->nnear = int(recs.size());
+        if ((st = upload(t->nleaf, recs)) != IMQ_OK) return st;
     }
     {   // W and X lists as flat pairs
         std::vector<int32_t> w_tgt, w_scr, w_leaves, x_tgt, x_boxes;

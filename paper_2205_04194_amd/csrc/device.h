@@ -211,6 +211,7 @@ struct imq_tree_s {
     imq::DevBuf xy_user, set_off;          // caller-order FP64 copy, for exact rows
     imq::DevBuf leafrec;                   // LeafRec per leaf
     int max_leaf = 0;                      // most points in one leaf
+    int nnear = 0;                         // near-field leaf records (empty ones included)
     imq::DevBuf boxrec;                    // BoxRec per box at levels >= need_m (Algorithm 1 mode)
     imq::DevBuf boxleaf;                   // leaf-list indices in point order (BoxRec ranges)
     int nboxrec = 0;

@@ -1292,9 +1292,9 @@ imq_status fork_p2p(imq_tree_s *t, int nrhs, hipStream_t s)
     PrecData &pd = prec_data<T>(t);
     IMQ_HIP(hipEventRecord(t->ev_fork, s));
     IMQ_HIP(hipStreamWaitEvent(t->side[0], t->ev_fork, 0));
-    const int nleaves = int(t->h.leaves.size());
+    const int nrec = t->nnear;
     const int wg = t->kcfg.p2p_wg > 0 ? t->kcfg.p2p_wg : P2P_WG_DEFAULT;
-    launch_p2p<T, true>(t->side[0], unsigned(std::min(nleaves, wg)), make_view<T>(t), nleaves, pd.us.as<T>(),
+    launch_p2p<T, true>(t->side[0], unsigned(std::min(nrec, wg)), make_view<T>(t), nrec, pd.us.as<T>(),
                         nrhs, t->bs.as<double>(), t->kcfg.p2p_mode == 1);
     IMQ_HIP(hipGetLastError());
     IMQ_HIP(hipEventRecord(t->ev_join, t->side[0]));
@@ -1535,7 +1535,7 @@ imq_status fmm_sorted(imq_tree_s *t, int nrhs, hipStream_t s, const UserVec *io)
     if (overlap) {
         IMQ_HIP(hipStreamWaitEvent(s, t->ev_join, 0));
     } else {
-        launch_p2p<T, false>(s, unsigned(nleaves), v, nleaves, pd.us.as<T>(), nrhs, bs, t->kcfg.p2p_mode == 1);
+        launch_p2p<T, false>(s, unsigned(t->nnear), v, t->nnear, pd.us.as<T>(), nrhs, bs, t->kcfg.p2p_mode == 1);
         IMQ_HIP(hipGetLastError());
     }
     mark(t, 7, s);
@@ -1613,7 +1613,7 @@ imq_status alg1_sorted(imq_tree_s *t, int nrhs, hipStream_t s)
     mark(t, 4, s);
     mark(t, 5, s);
     mark(t, 6, s);
-    launch_p2p<T, false>(s, unsigned(nleaves), v, nleaves, pd.us.as<T>(), nrhs, bs, false);
+    launch_p2p<T, false>(s, unsigned(t->nnear), v, t->nnear, pd.us.as<T>(), nrhs, bs, false);
     IMQ_HIP(hipGetLastError());
     mark(t, 7, s);
     hipLaunchKernelGGL(k_alg1_far<T>, dim3(unsigned(nleaves)), dim3(64), 0, s, v, pd.M.as<T>(), pd.wx.as<T>(),

@@ -412,10 +412,10 @@ __global__ __launch_bounds__(64) void k_p2p(DTree<T> t, int nleaves, const T *__
 {
     static_assert(!MF || NR == 1, "matrix-core form: one right-hand side");
     __shared__ P2PStage<T, NR, MF> sh;
-    // Leaves are dealt round robin (as the hardware deals workgroups to the
-    // XCDs): the kernel is ALU-bound, and giving each XCD a contiguous eighth of
-    // the Morton order for L2 locality unbalances clustered inputs (measured
-    // slower on the mixture workload).
+    // Leaf records are dealt round robin, as the hardware deals workgroups to
+    // the XCDs: record lf runs on XCD lf mod 8 when the grid is a multiple of
+    // 8, and the host arranges the records for that (equal-cost runs of the
+    // Morton order, one per XCD; empty records have no targets).
     for (int lf = blockIdx.x; lf < nleaves; lf += gridDim.x) {
         const NearLeaf nl = t.nleaf[lf];
         if constexpr (MF) {
