@@ -124,8 +124,14 @@ static imq_status upload_tree(imq_tree_s *t, const double *xy_dev)
 {
     const HostTree &h = t->h;
     imq_status st;
-    // the near field's leaf order (costs and a sort) on a second thread
-    std::future<std::vector<NearLeaf>> nleaf = std::async(std::launch::async, [&h] { return near_leaves(h); });
+    // the near field's leaf order (costs and a sort) on a second thread (on
+    // this one, when it is needed, where no thread can be started)
+    std::future<std::vector<NearLeaf>> nleaf;
+    try {
+        nleaf = std::async(std::launch::async, [&h] { return near_leaves(h); });
+    } catch (const std::exception &) {
+        nleaf = std::async(std::launch::deferred, [&h] { return near_leaves(h); });
+    }
 #define UP(field) if ((st = upload(t->field, h.field)) != IMQ_OK) return st
     UP(level); UP(set); UP(parent); UP(child0); UP(nchild); UP(pos);
     UP(begin); UP(end); UP(cx); UP(cy); UP(u_off); UP(u_idx); UP(v_off); UP(v_idx); UP(v_cls);

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <stdexcept>
 #include <thread>
 
 namespace imq {
@@ -148,9 +149,15 @@ imq_status check_tree_params(int nsets, const int64_t *off, const double *c, con
 imq_status finish_host_tree(HostTree &t, const std::vector<double> *leaf_r2)
 {
     // the flags and the batches write disjoint fields: built side by side
-    std::thread flags([&] { near_expansion_flags(t, leaf_r2); });
+    // (one after the other where no thread can be started)
+    std::thread flags;
+    try {
+        flags = std::thread([&] { near_expansion_flags(t, leaf_r2); });
+    } catch (const std::exception &) {
+        near_expansion_flags(t, leaf_r2);
+    }
     build_gemm_lists(t);
-    flags.join();
+    if (flags.joinable()) flags.join();
     const int nbox = int(t.level.size());
     auto npts = [&](int b) { return int64_t(t.end[b] - t.begin[b]); };
     for (int b = 0; b < nbox; ++b) {
