@@ -253,6 +253,32 @@ def test_near_field_forms_match_the_oracle(imq, c):
     tree.set_kernel_config()
 
 
+def test_near_field_workgroup_count_does_not_change_the_product(imq):
+    """The near field's leaf records are arranged for eight XCDs (runs of
+    equal cost of the Morton order, empty records padding the shorter runs)
+    and walked by however many workgroups the launch has.  Each leaf's sums
+    are made by one workgroup in a fixed order, so the product is the same
+    bit for bit at any workgroup count, including counts that are not a
+    multiple of 8 and counts above the number of records, and matches the
+    oracle."""
+    n = 20000
+    xy = W.mixture_points(n, W.rng(97, 1), W.rng(97, 3))
+    u = W.uniform_vector(n, W.rng(97, 2))
+    c = 0.03
+    tree = imq.build_tree(_dev(xy), c, leaf=32, p=12)
+    rows = np.arange(0, n, 53)
+    exact = oracle.matvec(xy, c, u, xy_targets=xy[rows])
+    for prec, tol in (("fp64", 1e-6), ("fp32", 1e-5)):
+        out = {}
+        for wg in (0, 8, 100, 1 << 16):
+            tree.set_kernel_config(p2p_wg=wg)
+            out[wg] = tree.matvec(_dev(u), prec).cpu().numpy()
+            assert _rel(out[wg][rows], exact) < tol, (prec, wg)
+        for wg in (8, 100, 1 << 16):
+            assert np.array_equal(out[wg], out[0]), (prec, wg)
+    tree.set_kernel_config()
+
+
 def test_caller_allocator_gives_the_same_products(imq):
     """A tree whose device memory comes from PyTorch's caching allocator
     (imq_build_tree_alloc) computes exactly what the default tree computes;
