@@ -232,6 +232,30 @@ def _tuned_run(tree, U, steps, nrows=300):
             "stage_ms": stages}
 
 
+def _leaf_tuned_run(build_kw, U, steps, leaves, p, nrows=300):
+    """Leaf capacity, per-level orders, precision and kernels by the tuner
+    (autotune.tune_leaf over `leaves`, FP64 and FP32 candidates), then time
+    `steps` products of the chosen tree; error over sampled rows of every
+    column.  Returns (tree, record)."""
+    import torch
+    from paper_2205_04194_amd import autotune
+    t0 = time.perf_counter()
+    tree, res, rec = autotune.tune_leaf(build_kw["xy"], build_kw["c"], U, leaves=leaves, p=p,
+                                        precisions=("fp64", "fp32"), **build_kw.get("extra", {}))
+    t_tune = time.perf_counter() - t0
+    n = U.shape[-1]
+    rows = torch.tensor(np.sort(np.random.default_rng(9).choice(n, min(nrows, n), replace=False)),
+                        device=U.device)
+    exact = tree.rows_exact(U, rows)
+    b = tree.matvec(U, res.precision)
+    err = float(torch.linalg.norm(b[..., rows] - exact) / torch.linalg.norm(exact))
+    ms, stages = time_products(tree, U, res.precision, steps, 2)
+    return tree, {"ms_per_step": ms, "rel_err_sampled_rows": err, "precision": res.precision,
+                  "leaf": res.leaf, "p": tree.info()["order_p"], "level_orders": res.level_orders,
+                  "m2l_mode": res.m2l_mode, "p2p_wg": res.p2p_wg, "tune_s": t_tune, "leaf_search": rec,
+                  "stage_ms": stages}
+
+
 def _graph_ms(tree, u, prec, steps):
     """ms per replay of the product captured in one HIP graph (torch.cuda.graph)."""
     import torch
@@ -256,6 +280,10 @@ def _graph_ms(tree, u, prec, steps):
     return e0.elapsed_time(e1) / steps
 
 
+# leaf capacities the tuner tries for the batched workloads
+LEAVES_BATCHED = (32, 48, 64, 96, 128)
+
+
 def batched_extras(dev, steps):
     """Batching: 64 right-hand sides on one tree, and 256 point sets in one forest."""
     import torch
@@ -264,26 +292,26 @@ def batched_extras(dev, steps):
     out = {}
     d = W.batched_rhs()
     U = torch.tensor(d["u"], device=dev)
-    t0 = time.perf_counter()
-    tree = imq.build_tree(torch.tensor(d["xy"], device=dev), d["c"], leaf=d["leaf"], p=d["p"])
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    r = _tuned_run(tree, U, steps)
+    xy = torch.tensor(d["xy"], device=dev)
+    tree, r = _leaf_tuned_run({"xy": xy, "c": d["c"]}, U, steps, LEAVES_BATCHED, d["p"])
+    tb = _warm_build_s(lambda: imq.build_tree(xy, d["c"], leaf=r["leaf"], p=r["p"]))
     r.update({"workload": "batched_rhs", "N": len(d["xy"]), "nrhs": int(U.shape[0]), "c": d["c"],
-              "tree_build_s": tb, "rhs_columns_per_s": U.shape[0] * 1e3 / r["ms_per_step"]})
+              "tree_build_warm_s": tb, "rhs_columns_per_s": U.shape[0] * 1e3 / r["ms_per_step"]})
     tree.close()
     out["rhs64"] = r
     log(f"batched 64 RHS: {r['ms_per_step']:.3f} ms, {r['rhs_columns_per_s']:.0f} columns/s, err {r['rel_err_sampled_rows']:.2e}")
     d = W.batched_sets()
     u = torch.tensor(d["u"], device=dev)
+    xy = torch.tensor(d["xy"], device=dev)
     t0 = time.perf_counter()
-    tree = imq.build_tree(torch.tensor(d["xy"], device=dev), list(d["c"]), leaf=d["leaf"], p=d["p"],
-                          set_offsets=list(d["offsets"]))
+    tree0 = imq.build_tree(xy, list(d["c"]), leaf=d["leaf"], p=d["p"], set_offsets=list(d["offsets"]))
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    tb_warm = _warm_build_s(lambda: imq.build_tree(torch.tensor(d["xy"], device=dev), list(d["c"]), leaf=d["leaf"],
-                                                   p=d["p"], set_offsets=list(d["offsets"])))
-    r = _tuned_run(tree, u, steps)
+    tree0.close()
+    tree, r = _leaf_tuned_run({"xy": xy, "c": list(d["c"]), "extra": {"set_offsets": list(d["offsets"])}}, u,
+                              steps, LEAVES_BATCHED, d["p"])
+    tb_warm = _warm_build_s(lambda: imq.build_tree(xy, list(d["c"]), leaf=r["leaf"], p=r["p"],
+                                                   set_offsets=list(d["offsets"])))
     r.update({"workload": "batched_sets", "nsets": len(d["c"]), "N_total": len(d["xy"]),
               "tree_build_s": tb, "tree_build_warm_s": tb_warm, "products_per_s": 1e3 / r["ms_per_step"]})
     r["graph_ms_per_step"] = _graph_ms(tree, u, r["precision"], steps)

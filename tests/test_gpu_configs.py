@@ -102,10 +102,11 @@ def _per_set_errors(b, ref, offs):
 
 
 @pytest.mark.timeout(600)
-def test_256_sets_every_set_against_the_oracle(imq, sets256):
+@pytest.mark.parametrize("leaf", [32, 128])
+def test_256_sets_every_set_against_the_oracle(imq, sets256, leaf):
     d, ref = sets256
     offs = d["offsets"]
-    tree = imq.build_tree(_dev(d["xy"]), list(d["c"]), leaf=d["leaf"], p=d["p"], set_offsets=list(offs))
+    tree = imq.build_tree(_dev(d["xy"]), list(d["c"]), leaf=leaf, p=d["p"], set_offsets=list(offs))
     u = _dev(d["u"])
     for prec, bar in (("fp64", 1e-6), ("fp32", 1e-5)):
         b = tree.matvec(u, prec).cpu().numpy()
@@ -116,11 +117,36 @@ def test_256_sets_every_set_against_the_oracle(imq, sets256):
     tree.close()
 
 
-@pytest.mark.timeout(600)
-def test_256_sets_graph_replays_against_the_oracle(imq, sets256):
+@pytest.mark.timeout(900)
+def test_256_sets_leaf_tuned_product_against_the_oracle(imq, sets256):
+    """The benchmark times the forest at the leaf capacity, per-level orders,
+    precision and kernels the tuner picks (autotune.tune_leaf over the leaf
+    capacities 32, 48, 64, 96 and 128, FP64 and FP32 candidates, on the
+    benchmark's weights).  Every row of that product against the oracle: the
+    whole vector to the tuner's 1e-6 target with the 1.5x margin of the other
+    tuned tests (the tuner measures sampled rows), and every set to the FP32
+    path's bar."""
+    from paper_2205_04194_amd import autotune
     d, ref = sets256
     offs = d["offsets"]
-    tree = imq.build_tree(_dev(d["xy"]), list(d["c"]), leaf=d["leaf"], p=d["p"], set_offsets=list(offs))
+    tree, res, rec = autotune.tune_leaf(_dev(d["xy"]), list(d["c"]), _dev(d["u"]), leaves=(32, 48, 64, 96, 128),
+                                        p=d["p"], precisions=("fp64", "fp32"), set_offsets=list(offs))
+    b = tree.matvec(_dev(d["u"]), res.precision).cpu().numpy()
+    errs = _per_set_errors(b, ref, offs)
+    whole = _rel(b, ref)
+    print(f"tuned forest: leaf {res.leaf}, {res.precision}, orders {res.level_orders}; whole vector "
+          f"{whole:.2e}, worst set {errs.max():.2e} (set {int(errs.argmax())}); search {rec}", flush=True)
+    assert whole <= 1.5e-6
+    assert errs.max() <= 1e-5
+    tree.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("leaf", [32, 128])
+def test_256_sets_graph_replays_against_the_oracle(imq, sets256, leaf):
+    d, ref = sets256
+    offs = d["offsets"]
+    tree = imq.build_tree(_dev(d["xy"]), list(d["c"]), leaf=leaf, p=d["p"], set_offsets=list(offs))
     u_static = torch.zeros(len(d["xy"]), dtype=torch.float64, device="cuda:0")
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
