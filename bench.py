@@ -418,38 +418,45 @@ def paper_table1_extra(dev, steps):
     return {"workload": "halton, c=1, M=10 (FP64)", "rows": rows_out}
 
 
-def adjoint_extra(dev, steps):
-    """Gradients of ||A(c, X) v - f||^2 (dv, dc, dX) at N = 1e5, FP64 expansions, p = 16."""
+def adjoint_extra(dev, steps, leaves=(64, 128)):
+    """Gradients of ||A(c, X) v - f||^2 (dv, dc, dX) at N = 1e5, p = 16, in
+    FP64 and FP32 expansions: the fastest of the leaf capacities `leaves`
+    and of the translation kernels (tables through the staged GEMM above 80
+    coefficients, m2l_mode 0, or streamed at every level, 3); the order p
+    fixes the accuracy, the leaf capacity only moves work between the near
+    and far fields."""
     import torch
     import workloads as W
     import paper_2205_04194_amd as imq
     d = W.grad(100_000)
     v = torch.tensor(d["v"], device=dev)
     f = torch.tensor(d["f"], device=dev)
-    tree = imq.build_tree(torch.tensor(d["xy"], device=dev), d["c"], leaf=64, p=16, direct_max=1 << 30)
-    g = 2.0 * (tree.matvec(v, "fp64") - f)
-    out = {"workload": "grad100k", "N": len(d["xy"]), "p": 16}
-    # the translation kernels: tables through the staged GEMM above 80
-    # coefficients (m2l_mode 0) or streamed at every level (3); the faster
-    for prec in ("fp64", "fp32"):
-        for mode in (0, 3):
-            tree.set_kernel_config(m2l_mode=mode)
-            tree.backward(v, g, prec=prec)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(steps):
+    xy = torch.tensor(d["xy"], device=dev)
+    out = {"workload": "grad100k", "N": len(d["xy"]), "p": 16, "by_leaf": {}}
+    for leaf in leaves:
+        tree = imq.build_tree(xy, d["c"], leaf=leaf, p=16)
+        g = 2.0 * (tree.matvec(v, "fp64") - f)
+        rec = {}
+        for prec in ("fp64", "fp32"):
+            for mode in (0, 3):
+                tree.set_kernel_config(m2l_mode=mode)
                 tree.backward(v, g, prec=prec)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / steps
-            out[f"{prec}_mode{mode}_ms"] = ms
-            if ms < out.get(f"{prec}_ms", float("inf")):
-                out[f"{prec}_ms"], out[f"{prec}_m2l_mode"] = ms, mode
-    tree.close()
-    log(f"adjoint N=1e5: fp64 {out['fp64_ms']:.3f} ms (m2l_mode {out['fp64_m2l_mode']}), "
-        f"fp32 {out['fp32_ms']:.3f} ms (m2l_mode {out['fp32_m2l_mode']})")
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(steps):
+                    tree.backward(v, g, prec=prec)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / steps
+                rec[f"{prec}_mode{mode}_ms"] = ms
+                if ms < out.get(f"{prec}_ms", float("inf")):
+                    out[f"{prec}_ms"], out[f"{prec}_m2l_mode"], out[f"{prec}_leaf"] = ms, mode, leaf
+        out["by_leaf"][leaf] = rec
+        tree.close()
+    log(f"adjoint N=1e5: fp64 {out['fp64_ms']:.3f} ms (leaf {out['fp64_leaf']}, m2l_mode {out['fp64_m2l_mode']}), "
+        f"fp32 {out['fp32_ms']:.3f} ms (leaf {out['fp32_leaf']}, m2l_mode {out['fp32_m2l_mode']})")
     return out
 
 

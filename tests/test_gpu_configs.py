@@ -65,6 +65,19 @@ def test_adjoint_at_1e5_points_against_oracle_and_finite_differences(imq):
     e_dv, e_dc, e_dx = _rel(dv, ref_dv), abs(dc - ref_dc) / abs(ref_dc), _rel(dX, ref_dX)
     print(f"N=1e5 adjoint vs dense oracle: dv {e_dv:.2e} dc {e_dc:.2e} dX {e_dx:.2e}", flush=True)
     assert e_dv <= 1e-6 and e_dc <= 1e-6 and e_dx <= 1e-6
+    # the benchmark's configuration: leaf capacity 128 (its timing picks the
+    # leaf), W/X interactions through expansions where the tree has them,
+    # every translation streamed (m2l_mode 3); FP64 to the same bar, FP32 to
+    # the FP32 path's
+    tree = imq.build_tree(_dev(xy), c, leaf=128, p=16)
+    tree.set_kernel_config(m2l_mode=3)
+    for prec, bar in (("fp64", 1e-6), ("fp32", 1e-5)):
+        dv2, dc2, dX2 = tree.backward(_dev(v), _dev(g), prec=prec)
+        dv2, dc2, dX2 = dv2.cpu().numpy(), float(dc2[0]), dX2.cpu().numpy()
+        e2 = (_rel(dv2, ref_dv), abs(dc2 - ref_dc) / abs(ref_dc), _rel(dX2, ref_dX))
+        print(f"N=1e5 adjoint, leaf 128, {prec}: dv {e2[0]:.2e} dc {e2[1]:.2e} dX {e2[2]:.2e}", flush=True)
+        assert max(e2) <= bar, prec
+    tree.close()
     # dc: Richardson-extrapolated central differences of the oracle loss
     h = 1e-4
     fd1 = (oracle.loss(xy, c + h, v, f) - oracle.loss(xy, c - h, v, f)) / (2 * h)
